@@ -1,0 +1,251 @@
+"""Seeded synthetic inputs shared by the oracle tests, the GPU tests and bench.py.
+
+This module only *generates inputs*: cell-type masks, Lagrangian rest meshes,
+random populations and the parameter sets of the standard workloads.  It holds
+none of the method's arithmetic (no equilibrium, collision, streaming, 0D model
+or delta kernel); both the plain CPU oracle and the HIP path consume what it
+returns, and neither imports the other.
+
+Conventions (they are part of the library interface, `include/lbm0d3d.h`):
+
+* cell (x, y, z) has linear index x + nx*(y + ny*z); arrays are shaped
+  (nz, ny, nx) in numpy;
+* cell types: FLUID 0, SOLID 1 (halfway bounce-back wall), INLET 2 and OUTLET 3
+  (ghost nodes of the 0D-coupled boundary, planes z = 0 and z = nz-1), EXTP 4
+  (ghost node held at the exterior reference pressure);
+* all pressures are gauge pressures p = P - c_s^2 in lattice units, so that the
+  population sum is 1 + 3p;
+* time is counted in lattice steps (dt = 1), lengths in lattice units (dx = 1).
+
+Physical 0D parameters (mmHg, ml, s) are mapped to lattice units with three
+scales: sigma_t steps per second, sigma_V lattice volumes per ml and sigma_P
+lattice pressure per mmHg.  Then E_lu = E * sP/sV, R_lu = R * sP*st/sV,
+C_lu = C * sV/sP, Q_lu = Q * sV/st.
+"""
+from __future__ import annotations
+
+import math
+import numpy as np
+
+FLUID, SOLID, INLET, OUTLET, EXTP = 0, 1, 2, 3, 4
+
+# ----------------------------------------------------------------------------
+# geometry
+# ----------------------------------------------------------------------------
+
+def tube_flags(nx, ny, nz, cx, cy, r, elastic=False):
+    """Straight tube along z with the lumen (x-cx)^2 + (y-cy)^2 < r^2.
+
+    rigid (elastic=False): every cell outside the lumen is SOLID, the lumen
+    cells of z = 0 / z = nz-1 are INLET / OUTLET ghosts.
+    elastic=True: the whole box interior is fluid (the wall is an immersed
+    membrane); the box side faces are SOLID; on the end planes the lumen is
+    INLET / OUTLET and the rest EXTP (exterior fluid at a reference pressure).
+    """
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    lumen = (x - cx) ** 2 + (y - cy) ** 2 < r * r
+    side = (x == 0) | (x == nx - 1) | (y == 0) | (y == ny - 1)
+    f = np.full((nz, ny, nx), FLUID, dtype=np.uint8)
+    if elastic:
+        ends = (z == 0) | (z == nz - 1)
+        f[ends] = EXTP
+        f[(z == 0) & lumen] = INLET
+        f[(z == nz - 1) & lumen] = OUTLET
+        f[side] = SOLID
+    else:
+        f[~lumen] = SOLID
+        f[(z == 0) & lumen] = INLET
+        f[(z == nz - 1) & lumen] = OUTLET
+        f[side] = SOLID
+    return f
+
+
+def closed_box_flags(nx, ny, nz):
+    """Box whose six faces are SOLID walls (no open boundary)."""
+    f = np.full((nz, ny, nx), FLUID, dtype=np.uint8)
+    f[0, :, :] = f[-1, :, :] = SOLID
+    f[:, 0, :] = f[:, -1, :] = SOLID
+    f[:, :, 0] = f[:, :, -1] = SOLID
+    return f
+
+
+def random_flags(nx, ny, nz, seed, solid_frac=0.15, extp=True):
+    """Random geometry for brute-force and parity checks.
+
+    Side faces SOLID; end planes a random mix of INLET/OUTLET, EXTP and SOLID;
+    interior cells SOLID with probability solid_frac, otherwise FLUID.
+    """
+    rng = np.random.default_rng(seed)
+    f = np.where(rng.random((nz, ny, nx)) < solid_frac, SOLID, FLUID).astype(np.uint8)
+    for zz, code in ((0, INLET), (nz - 1, OUTLET)):
+        u = rng.random((ny, nx))
+        plane = np.full((ny, nx), code, dtype=np.uint8)
+        if extp:
+            plane[u < 0.25] = EXTP
+        plane[u > 0.85] = SOLID
+        f[zz] = plane
+    f[:, 0, :] = f[:, -1, :] = SOLID
+    f[:, :, 0] = f[:, :, -1] = SOLID
+    return f
+
+
+def cylinder_mesh(cx, cy, r, z0, z1, h):
+    """Structured Lagrangian mesh of a cylinder wall.
+
+    n_theta points around (periodic), n_z rings from z0 to z1 inclusive
+    (rings 0 and n_z-1 are the fixed ends).  Point index p = j + n_theta*k.
+    Returns dict with X0 (n, 3) float64, n_theta, n_z, ds_theta (rest chord
+    between ring neighbours), ds_z, area (wall area carried by one point).
+    """
+    n_theta = max(3, int(round(2.0 * math.pi * r / h)))
+    n_z = int(round((z1 - z0) / h)) + 1
+    ds_z = (z1 - z0) / (n_z - 1)
+    th = 2.0 * math.pi * np.arange(n_theta) / n_theta
+    zz = z0 + ds_z * np.arange(n_z)
+    X0 = np.empty((n_z, n_theta, 3))
+    X0[:, :, 0] = cx + r * np.cos(th)[None, :]
+    X0[:, :, 1] = cy + r * np.sin(th)[None, :]
+    X0[:, :, 2] = zz[:, None]
+    ds_theta = 2.0 * r * math.sin(math.pi / n_theta)
+    area = (2.0 * math.pi * r / n_theta) * ds_z
+    return dict(X0=X0.reshape(-1, 3), n_theta=n_theta, n_z=n_z,
+                ds_theta=ds_theta, ds_z=ds_z, area=area)
+
+
+# ----------------------------------------------------------------------------
+# random states
+# ----------------------------------------------------------------------------
+
+def random_populations(ncell, seed, amp=1e-3, q=19):
+    """Shifted populations g[cell][i] ~ amp * U(-1, 1), AoS (ncell, q) float64."""
+    rng = np.random.default_rng(seed)
+    return amp * (2.0 * rng.random((ncell, q)) - 1.0)
+
+
+def random_points(n, lo, hi, seed):
+    rng = np.random.default_rng(seed)
+    lo = np.asarray(lo, float); hi = np.asarray(hi, float)
+    return lo + (hi - lo) * rng.random((n, 3))
+
+
+# ----------------------------------------------------------------------------
+# 0D parameter sets (lattice units)
+# ----------------------------------------------------------------------------
+
+# boundary kinds (same codes as the C interface)
+BC_PRESSURE_CONST, BC_VELOCITY_CONST, BC_WINDKESSEL3, BC_LV_ELASTANCE = 0, 1, 2, 3
+
+# double-Hill elastance shape constants (published fit used for the LV
+# compliance curve): alpha1, n1, alpha2, n2 and the normalisation k
+HILL = dict(a1=0.7, n1=1.9, a2=1.17, n2=21.9, k=1.55)
+
+
+def scales(sigma_t=25000.0, sigma_V=8000.0, sigma_P=2.5e-6):
+    return dict(sigma_t=sigma_t, sigma_V=sigma_V, sigma_P=sigma_P)
+
+
+def lv_params(Emax, Emin, HR, P_ed_mmHg, Ls_seconds, sc):
+    """LV-elastance parameter vector in lattice units.
+
+    Layout: [Emax, Emin, Tc, Tmax, P_ed, N_S, k, a1, n1, a2, n2]
+    (Emax/Emin in mmHg/ml, HR in beats/min, P_ed in mmHg, Ls in s).
+    T_max = (0.2 + 0.15 * T_c[s]) seconds, the published double-Hill timing.
+    """
+    st, sV, sP = sc["sigma_t"], sc["sigma_V"], sc["sigma_P"]
+    Tc_s = 60.0 / HR
+    Tmax_s = 0.2 + 0.15 * Tc_s
+    return [Emax * sP / sV, Emin * sP / sV, Tc_s * st, Tmax_s * st,
+            P_ed_mmHg * sP, round(Ls_seconds * st), HILL["k"],
+            HILL["a1"], HILL["n1"], HILL["a2"], HILL["n2"]]
+
+
+def wk_params(Z, C, R, sc, coupling=0.0):
+    """3-element Windkessel [Rp, C, Rd, coupling] in lattice units from
+    (mmHg s/ml, ml/mmHg).  coupling 0: flux in, pressure out; 1: mean
+    pressure in, outflow out."""
+    st, sV, sP = sc["sigma_t"], sc["sigma_V"], sc["sigma_P"]
+    return [Z * sP * st / sV, C * sV / sP, R * sP * st / sV, coupling]
+
+
+# ----------------------------------------------------------------------------
+# standard workloads
+# ----------------------------------------------------------------------------
+
+def cfg0():
+    """Rigid tube r = 8 in 24x24x64, tau 0.8, FP64, constant inlet with
+    population sum 1.001, 3-element Windkessel outlet Rp 0.05, C 50, Rd 1.0
+    (lattice units), 1000 steps."""
+    nx, ny, nz = 24, 24, 64
+    return dict(
+        name="cfg0_rigid_tube_24x24x64",
+        nx=nx, ny=ny, nz=nz, tau=0.8,
+        flags=tube_flags(nx, ny, nz, 11.5, 11.5, 8.0, elastic=False),
+        inlet=(BC_PRESSURE_CONST, [0.001 / 3.0]),
+        # Rp = 0.05 is ~18x the tube's acoustic impedance rho c_s / A, so the
+        # Windkessel is coupled in the direction that is stable there: mean
+        # outlet pressure in, outflow out (coupling flag 1).
+        outlet=(BC_WINDKESSEL3, [0.05, 50.0, 1.0, 1.0]),
+        steps=1000,
+    )
+
+
+def _elastic_tube(nx, ny, nz, r, h, k, ei, sc, tau, Emax=2.0, Emin=0.06, HR=75.0,
+                  Z=0.05, C=1.5, R=1.0, P0_mmHg=80.0, mass=2.0,
+                  alpha=-0.05, beta=-0.5):
+    cx, cy = (nx - 1) / 2.0, (ny - 1) / 2.0
+    mesh = cylinder_mesh(cx, cy, r, 2.0, nz - 3.0, h)
+    p0 = P0_mmHg * sc["sigma_P"]
+    return dict(
+        nx=nx, ny=ny, nz=nz, tau=tau,
+        flags=tube_flags(nx, ny, nz, cx, cy, r, elastic=True),
+        inlet=(BC_LV_ELASTANCE, lv_params(Emax, Emin, HR, 8.0, 0.075, sc)),
+        outlet=(BC_WINDKESSEL3, wk_params(Z, C, R, sc)),
+        outlet_state=[p0],            # Windkessel chamber starts at P0
+        exterior=(BC_PRESSURE_CONST, [p0]),
+        p_init=p0,                    # uniform initial gauge pressure P0 != 0
+        mesh=mesh, k=k, ei=ei, mass=mass, alpha=alpha, beta=beta,
+        scales=sc,
+    )
+
+
+def cfg1(h=0.5):
+    """Elastic tube r = 48 in 128x128x512 (8.4 M cells), FP32, spring k 0.05,
+    bending 1e-3, Peskin 4-point kernel, LV-elastance inlet (Emax 2.0, Emin
+    0.06 mmHg/ml, HR 75) and Windkessel outlet (Z 0.05, C 1.5, R 1.0), one
+    cardiac cycle = 20 000 steps."""
+    sc = scales(25000.0, 8000.0, 2.5e-6)
+    c = _elastic_tube(128, 128, 512, 48.0, h, 0.05, 1e-3, sc, tau=0.52)
+    c.update(name="cfg1_fsi_tube_128x128x512", steps=20000)
+    return c
+
+
+def cfg2():
+    """cfg1 geometry at 64x64x256 (r = 24) for the 16-bit storage study."""
+    sc = scales(25000.0, 1000.0, 2.5e-6)
+    c = _elastic_tube(64, 64, 256, 24.0, 0.5, 0.05, 1e-3, sc, tau=0.52)
+    c.update(name="cfg2_fsi_tube_64x64x256", steps=60000)
+    return c
+
+
+def small_fsi(nx=24, ny=24, nz=40, r=7.0, h=0.7, tau=0.6, seed=None):
+    """Small elastic tube with the cfg1 boundary models, for parity tests."""
+    sc = scales(2500.0, 8000.0 * (r / 48.0) ** 2, 2.5e-6)
+    c = _elastic_tube(nx, ny, nz, r, h, 0.05, 1e-3, sc, tau=tau)
+    c.update(name=f"small_fsi_{nx}x{ny}x{nz}")
+    return c
+
+
+def ensemble(n=256, seed=3):
+    """Parameter draws of the batched ensemble (radius, length, LV, WK, wall)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        r = int(round(rng.uniform(6.0, 16.0)))
+        L = int(round(rng.uniform(48.0, 160.0)))
+        out.append(dict(
+            r=r, L=L,
+            Emax=rng.uniform(1.5, 3.0), Emin=rng.uniform(0.04, 0.08),
+            HR=rng.uniform(60.0, 100.0),
+            Z=0.05 * rng.uniform(0.7, 1.3), C=1.5 * rng.uniform(0.7, 1.3),
+            R=1.0 * rng.uniform(0.7, 1.3), k=rng.uniform(0.02, 0.1)))
+    return out

@@ -1,0 +1,292 @@
+"""Plain FP64 CPU oracle of the 0D-3D coupled LB / IB method (test infrastructure).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  It is the reference the HIP path is
+checked against and shares no code with it: ``lbm_oracle.c`` (built here with
+gcc) is the solver, ``brute.py`` an independent numpy re-derivation used to
+pin it on tiny lattices.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "lbm_oracle.c")
+_LIB = os.path.join(_HERE, "liblbm_oracle.so")
+NREC = 12
+Q = 19
+
+
+def build(force=True):
+    """Compile the oracle with gcc (-O2, OpenMP, no fast-math)."""
+    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
+        return _LIB
+    tmp = _LIB + ".tmp"
+    subprocess.check_call(["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared",
+                           "-Wall", "-Wno-unused-function", "-o", tmp, _SRC, "-lm"])
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build(force=False)
+        L = C.CDLL(_LIB)
+        vp, dp, ip, u8p = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int), C.POINTER(C.c_uint8)
+        L.orc_create.restype = vp
+        L.orc_create.argtypes = [C.c_int, C.c_int, C.c_int, C.c_double, u8p, C.c_int, C.c_int, C.c_int]
+        L.orc_destroy.argtypes = [vp]
+        L.orc_set_bc.argtypes = [vp, C.c_int, C.c_int, dp, C.c_int, dp, C.c_int]
+        L.orc_set_body_force.argtypes = [vp, C.c_double, C.c_double, C.c_double, C.c_double]
+        L.orc_set_pops.argtypes = [vp, dp]
+        L.orc_get_pops.argtypes = [vp, dp]
+        L.orc_set_rest.argtypes = [vp, C.c_double]
+        L.orc_set_membrane.argtypes = [vp, C.c_int, C.c_int, dp, C.c_double, C.c_double, C.c_double,
+                                       C.c_double, C.c_double, C.c_double, C.c_double, C.c_double]
+        L.orc_get_lagrangian.argtypes = [vp, dp, dp, dp, dp, dp]
+        L.orc_set_lagrangian.argtypes = [vp, dp, dp]
+        L.orc_ib_interp.argtypes = [vp, C.c_long, dp, dp, dp]
+        L.orc_ib_spread.argtypes = [vp, C.c_long, dp, dp, C.c_double, dp]
+        L.orc_membrane_force.argtypes = [vp, dp, dp]
+        L.orc_step.argtypes = [vp, C.c_long]
+        L.orc_get_fields.argtypes = [vp, dp, dp]
+        L.orc_get_force.argtypes = [vp, dp]
+        L.orc_get_waveforms.restype = C.c_long
+        L.orc_get_waveforms.argtypes = [vp, dp, C.c_long]
+        L.orc_get_step.restype = C.c_long
+        L.orc_get_step.argtypes = [vp]
+        L.orc_smooth_S.restype = C.c_double
+        L.orc_smooth_S.argtypes = [C.c_double, C.c_double, C.c_double]
+        L.orc_elastance.argtypes = [dp, C.c_double, dp, dp]
+        L.orc_phi4.restype = C.c_double
+        L.orc_phi4.argtypes = [C.c_double]
+        L.orc_lattice.argtypes = [ip, dp]
+        L.orc_feq.argtypes = [C.c_double, dp, dp]
+        L.orc_forcing.argtypes = [C.c_double, dp, dp, dp]
+        L.orc_bc_new.restype = vp
+        L.orc_bc_new.argtypes = [C.c_int, C.c_int, dp, C.c_int, dp, C.c_int]
+        L.orc_bc_free.argtypes = [vp]
+        L.orc_bc_update.argtypes = [vp, C.c_long, C.c_double, C.c_double, dp]
+        L.orc_filament_force.argtypes = [C.c_int, dp, C.c_double, C.c_double, C.c_double, dp]
+        L.orc_num_threads.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _d(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _dn(a):
+    if a is None:
+        return None, None
+    return _d(a)
+
+
+# ----------------------------------------------------------------------------
+# single-node formulas (exported for the pin tests)
+# ----------------------------------------------------------------------------
+
+def lattice():
+    e = np.zeros(57, dtype=np.int32)
+    w = np.zeros(19)
+    lib().orc_lattice(e.ctypes.data_as(C.POINTER(C.c_int)), w.ctypes.data_as(C.POINTER(C.c_double)))
+    return e.reshape(19, 3), w
+
+
+def feq(p_gauge, v):
+    out = np.zeros(19)
+    v, vp = _d(v)
+    lib().orc_feq(p_gauge, vp, out.ctypes.data_as(C.POINTER(C.c_double)))
+    return out
+
+
+def forcing(tau, v, b):
+    out = np.zeros(19)
+    v, vp = _d(v)
+    b, bp = _d(b)
+    lib().orc_forcing(tau, vp, bp, out.ctypes.data_as(C.POINTER(C.c_double)))
+    return out
+
+
+def smooth_S(t, t0, Ls):
+    return lib().orc_smooth_S(float(t), float(t0), float(Ls))
+
+
+def elastance(par, t):
+    par, pp = _d(par)
+    E = C.c_double(); dE = C.c_double()
+    lib().orc_elastance(pp, float(t), C.byref(E), C.byref(dE))
+    return E.value, dE.value
+
+
+def phi4(r):
+    return lib().orc_phi4(float(r))
+
+
+def filament_force(X, ds, Eh, EI):
+    X, xp = _d(X)
+    m = X.shape[0]
+    F = np.zeros((m, 3))
+    lib().orc_filament_force(m, xp, ds, Eh, EI, F.ctypes.data_as(C.POINTER(C.c_double)))
+    return F
+
+
+class ZeroD:
+    """One 0D boundary model advanced by hand (unit tests of the ODEs)."""
+
+    def __init__(self, boundary, kind, par, state=()):
+        par, pp = _d(par)
+        st = np.asarray(state, float) if len(state) else np.zeros(1)
+        st, sp = _d(st)
+        self._keep = (par, st)
+        self.h = lib().orc_bc_new(boundary, kind, pp, len(par), sp, len(state))
+
+    def update(self, n, Qp, Pbar):
+        out = np.zeros(8)
+        lib().orc_bc_update(self.h, n, Qp, Pbar, out.ctypes.data_as(C.POINTER(C.c_double)))
+        return dict(vmode=int(out[0]), pstar=out[1], S=out[2], Pv=out[3], Pw=out[4],
+                    open=int(out[5]), snap=int(out[6]), Td=int(out[7]))
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().orc_bc_free(self.h)
+            self.h = None
+
+
+# ----------------------------------------------------------------------------
+# the solver
+# ----------------------------------------------------------------------------
+
+class Oracle:
+    """FP64 two-lattice pull solver.  flags: uint8 array (nz, ny, nx)."""
+
+    def __init__(self, flags, tau, periodic=(0, 0, 0)):
+        flags = np.ascontiguousarray(flags, dtype=np.uint8)
+        self.nz, self.ny, self.nx = flags.shape
+        self.ncell = flags.size
+        self.flags = flags
+        self.tau = tau
+        self.h = lib().orc_create(self.nx, self.ny, self.nz, tau,
+                                  flags.ctypes.data_as(C.POINTER(C.c_uint8)), *periodic)
+        self.np = 0
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().orc_destroy(self.h)
+            self.h = None
+
+    def set_bc(self, boundary, kind, par, state=()):
+        par, pp = _d(par)
+        st = np.asarray(state, float) if len(state) else np.zeros(1)
+        st, sp = _d(st)
+        lib().orc_set_bc(self.h, boundary, kind, pp, len(par), sp, len(state))
+
+    def set_body_force(self, b, omega=0.0):
+        lib().orc_set_body_force(self.h, float(b[0]), float(b[1]), float(b[2]), float(omega))
+
+    def set_pops(self, g):
+        g, gp = _d(np.asarray(g).reshape(self.ncell, 19))
+        lib().orc_set_pops(self.h, gp)
+
+    def get_pops(self):
+        g = np.zeros((self.ncell, 19))
+        lib().orc_get_pops(self.h, g.ctypes.data_as(C.POINTER(C.c_double)))
+        return g
+
+    def set_rest(self, p_gauge):
+        lib().orc_set_rest(self.h, float(p_gauge))
+
+    def set_membrane(self, mesh, k, ei, mass, alpha, beta):
+        X0, xp = _d(mesh["X0"])
+        self.np = X0.shape[0]
+        lib().orc_set_membrane(self.h, mesh["n_theta"], mesh["n_z"], xp, mesh["ds_theta"],
+                               mesh["ds_z"], mesh["area"], k, ei, mass, alpha, beta)
+
+    def lagrangian(self):
+        out = [np.zeros((self.np, 3)) for _ in range(5)]
+        ptrs = [o.ctypes.data_as(C.POINTER(C.c_double)) for o in out]
+        lib().orc_get_lagrangian(self.h, *ptrs)
+        return dict(X=out[0], Xprev=out[1], slip=out[2], Vf=out[3], F=out[4])
+
+    def set_lagrangian(self, X, Xprev):
+        X, xp = _d(X)
+        Xprev, pp = _d(Xprev)
+        lib().orc_set_lagrangian(self.h, xp, pp)
+
+    def ib_interp(self, X, u):
+        X, xp = _d(X)
+        u, up = _d(np.asarray(u).reshape(self.ncell, 3))
+        V = np.zeros((X.shape[0], 3))
+        lib().orc_ib_interp(self.h, X.shape[0], xp, up, V.ctypes.data_as(C.POINTER(C.c_double)))
+        return V
+
+    def ib_spread(self, X, F, area):
+        X, xp = _d(X)
+        F, fp = _d(F)
+        b = np.zeros((self.ncell, 3))
+        lib().orc_ib_spread(self.h, X.shape[0], xp, fp, float(area), b.ctypes.data_as(C.POINTER(C.c_double)))
+        return b
+
+    def membrane_force(self, X):
+        X, xp = _d(X)
+        F = np.zeros_like(X)
+        lib().orc_membrane_force(self.h, xp, F.ctypes.data_as(C.POINTER(C.c_double)))
+        return F
+
+    def step(self, n=1):
+        lib().orc_step(self.h, int(n))
+
+    @property
+    def t(self):
+        return lib().orc_get_step(self.h)
+
+    def fields(self):
+        """(gauge pressure (nz,ny,nx), first moment sum e g (nz,ny,nx,3))."""
+        p = np.zeros(self.ncell)
+        u = np.zeros((self.ncell, 3))
+        lib().orc_get_fields(self.h, p.ctypes.data_as(C.POINTER(C.c_double)),
+                             u.ctypes.data_as(C.POINTER(C.c_double)))
+        return p.reshape(self.nz, self.ny, self.nx), u.reshape(self.nz, self.ny, self.nx, 3)
+
+    def force(self):
+        b = np.zeros((self.ncell, 3))
+        lib().orc_get_force(self.h, b.ctypes.data_as(C.POINTER(C.c_double)))
+        return b
+
+    def waveforms(self):
+        n = lib().orc_get_waveforms(self.h, None, 0)
+        out = np.zeros((n, NREC))
+        lib().orc_get_waveforms(self.h, out.ctypes.data_as(C.POINTER(C.c_double)), n)
+        return out
+
+
+def num_threads():
+    return lib().orc_num_threads()
+
+
+def from_config(cfg, pops=None):
+    """Oracle set up from one of the lbm_inputs workload dicts."""
+    o = Oracle(cfg["flags"], cfg["tau"])
+    if "inlet" in cfg:
+        o.set_bc(0, cfg["inlet"][0], cfg["inlet"][1], cfg.get("inlet_state", ()))
+    if "outlet" in cfg:
+        o.set_bc(1, cfg["outlet"][0], cfg["outlet"][1], cfg.get("outlet_state", ()))
+    if "exterior" in cfg:
+        o.set_bc(2, cfg["exterior"][0], cfg["exterior"][1])
+    if pops is not None:
+        o.set_pops(pops)
+    elif cfg.get("p_init", 0.0) != 0.0:
+        o.set_rest(cfg["p_init"])
+    if "mesh" in cfg:
+        o.set_membrane(cfg["mesh"], cfg["k"], cfg["ei"], cfg["mass"], cfg["alpha"], cfg["beta"])
+    return o

@@ -1,0 +1,183 @@
+"""Physics pins of the CPU oracle: flows and conservation laws with known answers.
+
+Poiseuille and Womersley profiles in a rigid periodic tube, exact mass and
+momentum balances, the steady 3-element Windkessel relation P = Q (Rp + Rd)
+on the small rigid-tube workload, fixed points of the non-equilibrium
+extrapolation, and the invariance of the incompressible model under a
+constant pressure offset.
+"""
+import numpy as np
+import pytest
+from scipy.special import jv
+
+import lbm_inputs as L
+
+
+def _periodic_tube(nx, ny, nz, cx, cy, r):
+    fl = L.tube_flags(nx, ny, nz, cx, cy, r)
+    fl[0] = fl[1]
+    fl[-1] = fl[1]
+    return fl
+
+
+def _radii(fl, cx, cy):
+    nz, ny, nx = fl.shape
+    y, x = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    r2 = (x - cx) ** 2 + (y - cy) ** 2
+    return r2, fl[0] == L.FLUID
+
+
+def test_poiseuille_curvature(oracle_mod):
+    tau, G, cx, R = 0.8, 1e-6, 9.5, 8.0
+    nu = (tau - 0.5) / 3.0
+    fl = _periodic_tube(20, 20, 4, cx, cx, R)
+    o = oracle_mod.Oracle(fl, tau, periodic=(0, 0, 1))
+    o.set_body_force([0.0, 0.0, G])
+    o.step(6000)
+    _, u = o.fields()
+    uz = u[2, :, :, 2] + 0.5 * G                       # v = sum e f + b/2
+    r2, lum = _radii(fl, cx, cx)
+    sel = lum & (r2 < 36.0)
+    A = np.stack([np.ones(sel.sum()), r2[sel]], 1)
+    (a, mb), res, *_ = np.linalg.lstsq(A, uz[sel], rcond=None)
+    assert abs(-mb / (G / (4 * nu)) - 1.0) < 0.01           # curvature G / (4 nu)
+    fit = a + mb * r2[sel]
+    assert np.abs(fit - uz[sel]).max() < 2e-3 * uz.max()      # parabolic
+    Reff = np.sqrt(a / -mb)
+    assert abs(Reff - R) < 0.5                                # staircase wall near r = R
+
+
+def test_womersley_profile(oracle_mod):
+    tau, G, cx, R = 0.8, 1e-6, 9.5, 8.0
+    nu = (tau - 0.5) / 3.0
+    fl = _periodic_tube(20, 20, 4, cx, cx, R)
+    # effective radius from the steady profile
+    o = oracle_mod.Oracle(fl, tau, periodic=(0, 0, 1))
+    o.set_body_force([0.0, 0.0, G])
+    o.step(6000)
+    _, u = o.fields()
+    r2, lum = _radii(fl, cx, cx)
+    sel = lum & (r2 < 36.0)
+    A = np.stack([np.ones(sel.sum()), r2[sel]], 1)
+    (a, mb), *_ = np.linalg.lstsq(A, u[2, :, :, 2][sel] + 0.5 * G, rcond=None)
+    Reff = np.sqrt(a / -mb)
+    # oscillating body force G cos(w t), Womersley number 4
+    w = 16.0 * nu / Reff ** 2
+    Wo = Reff * np.sqrt(w / nu)
+    o = oracle_mod.Oracle(fl, tau, periodic=(0, 0, 1))
+    o.set_body_force([0.0, 0.0, G], omega=w)
+    period = 2 * np.pi / w
+    o.step(int(4 * period))
+    r = np.sqrt(r2[lum])
+    k = 1j ** 1.5 * Wo
+    shape = 1.0 - jv(0, k * r / Reff) / jv(0, k)
+    core = r < Reff - 1.5                    # away from the staircase wall
+    num2 = den2 = 0.0
+    for _ in range(8):
+        o.step(int(period / 8))
+        n = o.t
+        _, u = o.fields()
+        num = u[2, :, :, 2][lum] + 0.5 * G * np.cos(w * n)
+        ana = np.real(G / (1j * w) * shape * np.exp(1j * w * n))
+        num2 += ((num - ana)[core] ** 2).sum()
+        den2 += (ana[core] ** 2).sum()
+    assert np.sqrt(num2 / den2) < 0.03
+
+
+def test_closed_box_conserves_mass(oracle_mod):
+    fl = L.closed_box_flags(10, 9, 8)
+    g = L.random_populations(fl.size, seed=11)
+    o = oracle_mod.Oracle(fl, 0.62)
+    o.set_pops(g)
+    m0 = o.get_pops()[fl.reshape(-1) == L.FLUID].sum()
+    o.step(500)
+    m1 = o.get_pops()[fl.reshape(-1) == L.FLUID].sum()
+    assert abs(m1 - m0) < 1e-15 * fl.size
+
+
+def test_periodic_box_momentum_grows_by_force(oracle_mod):
+    fl = np.zeros((4, 5, 6), np.uint8)
+    g = L.random_populations(fl.size, seed=12)
+    b = np.array([2e-5, -1e-5, 3e-5])
+    o = oracle_mod.Oracle(fl, 0.7, periodic=(1, 1, 1))
+    o.set_pops(g)
+    o.set_body_force(b)
+    _, u0 = o.fields()
+    o.step(7)
+    _, u1 = o.fields()
+    dj = u1.reshape(-1, 3).sum(0) - u0.reshape(-1, 3).sum(0)
+    assert np.abs(dj - 7 * fl.size * b).max() < 1e-16 * fl.size * 7
+
+
+def test_uniform_states_are_fixed_points(oracle_mod):
+    nx = ny = 5; nz = 8
+    fl = np.zeros((nz, ny, nx), np.uint8)
+    fl[0] = L.INLET
+    fl[-1] = L.OUTLET
+    v = np.array([0.0, 0.0, 0.02])
+    # uniform flow between two constant-velocity planes
+    o = oracle_mod.Oracle(fl, 0.7, periodic=(1, 1, 0))
+    g = np.tile(oracle_mod.feq(0.0, v), (fl.size, 1))
+    o.set_pops(g)
+    o.set_bc(0, L.BC_VELOCITY_CONST, [0.02])
+    o.set_bc(1, L.BC_VELOCITY_CONST, [0.02])
+    o.step(20)
+    assert np.abs(o.get_pops()[fl.reshape(-1) == 0] - g[0]).max() < 1e-17
+    # uniform flow between two planes held at the same pressure
+    o = oracle_mod.Oracle(fl, 0.7, periodic=(1, 1, 0))
+    g = np.tile(oracle_mod.feq(2e-4, v), (fl.size, 1))
+    o.set_pops(g)
+    o.set_bc(0, L.BC_PRESSURE_CONST, [2e-4])
+    o.set_bc(1, L.BC_PRESSURE_CONST, [2e-4])
+    o.step(20)
+    assert np.abs(o.get_pops()[fl.reshape(-1) == 0] - g[0]).max() < 1e-17
+
+
+def test_pressure_offset_invariance(oracle_mod):
+    """The incompressible model is linear in P: adding c to every pressure
+    (initial state and boundary values) shifts p by c and leaves j unchanged."""
+    fl = L.random_flags(9, 8, 10, seed=13)
+    g = L.random_populations(fl.size, seed=14)
+    c = 3e-4
+    runs = []
+    for off in (0.0, c):
+        o = oracle_mod.Oracle(fl, 0.75)
+        o.set_pops(g + np.tile(oracle_mod.feq(off, np.zeros(3)), (fl.size, 1)))
+        o.set_bc(0, L.BC_PRESSURE_CONST, [1e-4 + off])
+        o.set_bc(1, L.BC_PRESSURE_CONST, [-2e-4 + off])
+        o.set_bc(2, L.BC_PRESSURE_CONST, [0.5e-4 + off])
+        o.step(30)
+        runs.append(o.fields())
+    (p0, u0), (p1, u1) = runs
+    fluid = fl == L.FLUID
+    assert np.abs(u1 - u0)[fluid].max() < 1e-16
+    assert np.abs((p1 - p0)[fluid] - c).max() < 1e-16
+
+
+@pytest.mark.slow
+def test_small_tube_steady_windkessel(oracle_mod):
+    """Rigid tube r = 8 with a constant inlet pressure and a Windkessel
+    outlet: at steady state the mean outlet pressure is Q (Rp + Rd), the
+    inlet and outlet fluxes agree, and the profile mid-tube is Poiseuille."""
+    c = L.cfg0()
+    o = oracle_mod.from_config(c)
+    o.step(5000)
+    w = o.waveforms()
+    Qin, Pin, Qout, Pout = w[-1, 1:5]
+    Rp, Cw, Rd = c["outlet"][1][:3]
+    assert abs(Qout - Qin) < 1e-4 * Qin                     # still settling at 1e-5
+    assert abs(Pout / (Qout * (Rp + Rd)) - 1.0) < 5e-3      # flux-correction offset ~0.3 %
+    # history is settled: last 500 steps vary by < 1e-4
+    assert np.abs(w[-500:, 3] - Qout).max() < 1e-4 * Qout
+    p, u = o.fields()
+    fl = c["flags"]
+    lum = fl[32] == L.FLUID
+    pz = np.array([p[z][lum].mean() for z in range(16, 49)])
+    slope = np.polyfit(np.arange(16, 49), pz, 1)[0]
+    nu = (c["tau"] - 0.5) / 3.0
+    y, x = np.meshgrid(np.arange(24), np.arange(24), indexing="ij")
+    r2 = (x - 11.5) ** 2 + (y - 11.5) ** 2
+    sel = lum & (r2 < 30.0)
+    A = np.stack([np.ones(sel.sum()), r2[sel]], 1)
+    (a, mb), *_ = np.linalg.lstsq(A, u[32, :, :, 2][sel], rcond=None)
+    assert abs(mb / (slope / (4 * nu)) - 1.0) < 0.02
