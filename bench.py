@@ -1,0 +1,213 @@
+"""Benchmark of the 0D-3D coupled lattice Boltzmann step on one MI355X.
+
+Default workload: the FP32 fluid-structure run, an elastic tube r = 48 lu
+(immersed membrane at 0.5 lu spacing, spring 0.05, bending 1e-3, Peskin
+4-point kernel) in a 128x128x512 box (8.4 M cells), LV-elastance inlet and
+3-element Windkessel outlet.  A step is the whole path: boundary reductions
+and 0D update, band moments, wall interpolation / penalty / spreading /
+membrane update, fused collide-stream.  The same workload is then run with
+FP16 storage (FP32 collide) for the storage-precision comparison.
+
+Prints ONE JSON line.  `value` = fluid-cell updates per second (MLUPS) of the
+FP32 path over the timed steps, inputs resident in HBM.  `roofline` is the
+collide-stream kernel's algorithmic bytes per launch over its average
+duration (HIP events on the solver's stream, same timed region) against
+8 TB/s.  `cpu_baseline` is the FP64 CPU oracle on a bounded sample of the
+same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PMC_FILE = os.path.join(ROOT, "profiles", "collide_cfg1_fp32_pmc.txt")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=40)
+    ap.add_argument("--workload", default="cfg1", choices=["cfg1", "cfg1_coarse_wall", "cfg0", "channel256"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-fp16", action="store_true", help="skip the FP16-storage run")
+    ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "fp16s", "bf16s"])
+    return ap.parse_args()
+
+
+def workload(name):
+    import lbm_inputs as L
+    if name == "cfg1":
+        c = L.cfg1(h=0.5)
+        desc = ("elastic tube r=48 lu in 128x128x512 (8.4M cells), membrane at 0.5 lu "
+                "(%d points), k=0.05, EI=1e-3, Peskin 4-point, LV-elastance inlet "
+                "(Emax 2.0, Emin 0.06 mmHg/ml, HR 75), 3-element Windkessel outlet" % c["mesh"]["X0"].shape[0])
+    elif name == "cfg1_coarse_wall":
+        c = L.cfg1(h=0.9)
+        desc = "cfg1 box with the membrane at 0.9 lu (%d points)" % c["mesh"]["X0"].shape[0]
+    elif name == "cfg0":
+        c = L.cfg0()
+        desc = "rigid tube r=8 in 24x24x64, constant inlet, Windkessel outlet"
+    else:
+        n = 256
+        c = dict(name="channel256", nx=n, ny=n, nz=512, tau=0.6,
+                 flags=L.tube_flags(n, n, 512, (n - 1) / 2, (n - 1) / 2, 1e9),
+                 inlet=(L.BC_PRESSURE_CONST, [1e-4]), outlet=(L.BC_PRESSURE_CONST, [0.0]), p_ref=5e-5)
+        desc = "rigid square channel 256x256x512 (33.5M cells), pressure-driven"
+    return c, desc
+
+
+def run_gpu(cfg, precision, steps, warmup):
+    import numpy as np
+    import torch
+    import lbm_inputs as L
+    import paper_2112_05258_amd as amd
+
+    prec = {"fp64": amd.FP64, "fp32": amd.FP32, "fp16s": amd.FP16S, "bf16s": amd.BF16S}[precision]
+    s = amd.solver_from_config(cfg, precision=prec)
+    fl = cfg["flags"]
+    nfluid = int((fl == L.FLUID).sum())
+    s.step(warmup)
+    s.sync()
+    s.set_timing(True)                      # per-kernel HIP events on the solver stream
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(s.stream)
+    s.step(steps)
+    e1.record(s.stream)
+    e1.synchronize()
+    torch.cuda.synchronize()
+    total_ms = e0.elapsed_time(e1)
+    s.sync()
+    kt = {k: s.kernel_time(k) for k in range(4)}
+    s.set_timing(False)
+    es = {amd.FP64: 8, amd.FP32: 4, amd.FP16S: 2, amd.BF16S: 2}[prec]
+    r4 = 32 if prec == amd.FP64 else 16
+    nband = 0
+    if "mesh" in cfg:
+        nband = int(s.fsi[0][0].numel() > 0 and _band_cells(cfg))
+    bytes_collide = nfluid * (2 * 19 * es + 1) + nband * r4
+    n_launch, ms_collide = kt[0]
+    avg_ms = ms_collide / max(n_launch, 1)
+    w = s.waveforms(cap=4)
+    finite = bool(np.isfinite(w[:, 1:5]).all())
+    s.close()
+    return dict(total_ms=total_ms, nfluid=nfluid, kt=kt, avg_collide_ms=avg_ms,
+                bytes_collide=bytes_collide, finite=finite, es=es)
+
+
+def _band_cells(cfg):
+    """Band cells of the wall (same rule as the library: stencil + 2-cell margin, fluid only)."""
+    import numpy as np
+    import lbm_inputs as L
+    X = cfg["mesh"]["X0"]
+    nz, ny, nx = cfg["flags"].shape
+    mark = np.zeros((nz, ny, nx), bool)
+    b = np.floor(X).astype(int) - 1
+    for dz in range(-2, 6):
+        for dy in range(-2, 6):
+            for dx in range(-2, 6):
+                z = np.clip(b[:, 2] + dz, 0, nz - 1)
+                y = np.clip(b[:, 1] + dy, 0, ny - 1)
+                x = np.clip(b[:, 0] + dx, 0, nx - 1)
+                mark[z, y, x] = True
+    return int((mark & (cfg["flags"] == L.FLUID)).sum())
+
+
+def cpu_baseline(cfg, budget_s=20.0):
+    import oracle
+    o = oracle.from_config(cfg)
+    import lbm_inputs as L
+    nfluid = int((cfg["flags"] == L.FLUID).sum())
+    o.step(1)                                # first step outside the clock
+    n, t0 = 0, time.perf_counter()
+    while True:
+        o.step(1)
+        n += 1
+        dt = time.perf_counter() - t0
+        if dt > budget_s or n >= 50:
+            break
+    return dict(value=nfluid * n / dt / 1e6, unit="MLUPS", cores=oracle.num_threads(), kind="oracle",
+                sample=f"{n} steps of the full workload (FP64, {nfluid} fluid cells), {dt:.1f} s")
+
+
+def traffic_from_profile(bytes_alg):
+    """HBM bytes per collide launch from the committed rocprofv3 PMC summary
+    (FETCH_SIZE + WRITE_SIZE in KiB, scaled by the copy-kernel calibration)."""
+    if not os.path.exists(PMC_FILE):
+        return None
+    vals = {}
+    for line in open(PMC_FILE):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            try:
+                vals[k.strip()] = float(v.split()[0])
+            except ValueError:
+                pass
+    if "collide_bytes_per_launch" in vals:
+        return vals["collide_bytes_per_launch"]
+    return None
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the method's multi-GPU sharding is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    cfg, desc = workload(args.workload)
+    t_setup = time.perf_counter()
+    r = run_gpu(cfg, args.precision, args.steps, args.warmup)
+    print(f"# {args.precision} run: {r['total_ms']:.2f} ms for {args.steps} steps, "
+          f"collide avg {r['avg_collide_ms']*1e3:.1f} us, setup+run {time.perf_counter()-t_setup:.1f} s",
+          file=sys.stderr, flush=True)
+    ms_step = r["total_ms"] / args.steps
+    mlups = r["nfluid"] * args.steps / (r["total_ms"] * 1e-3) / 1e6
+    achieved = r["bytes_collide"] / (r["avg_collide_ms"] * 1e-3) / 1e9
+    out = {
+        "metric": "MLUPS & % HBM peak (FP32 vs FP16-store); surrogate waveforms/s at <=2% error",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "fp16s": "f32 (f16 storage)", "bf16s": "f32 (bf16 storage)"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {desc}", "fluid_cells": r["nfluid"],
+                   "precision": args.precision, "step": "reduce+0D, band, wall, collide-stream"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic_from_profile(r["bytes_collide"]),
+                     "kernel": "k_collide", "bytes_per_launch": r["bytes_collide"],
+                     "avg_launch_us": round(r["avg_collide_ms"] * 1e3, 2)},
+        "kernels_ms_per_step": {name: round(r["kt"][k][1] / max(r["kt"][k][0], 1), 5)
+                                for k, name in enumerate(["collide", "reduce_0d", "band", "wall"])},
+        "finite": r["finite"],
+    }
+    if not args.no_fp16 and args.precision == "fp32":
+        r16 = run_gpu(cfg, "fp16s", args.steps, args.warmup)
+        m16 = r16["nfluid"] * args.steps / (r16["total_ms"] * 1e-3) / 1e6
+        a16 = r16["bytes_collide"] / (r16["avg_collide_ms"] * 1e-3) / 1e9
+        out["fp16s"] = {"value": round(m16, 1), "unit": "MLUPS", "ratio_vs_fp32": round(m16 / mlups, 3),
+                        "collide_achieved_GBs": round(a16, 1), "collide_frac": round(a16 / HBM_PEAK_GBS, 4)}
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(cfg)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,239 @@
+/*
+ * lbm0d3d.h -- C interface of the MI355X (gfx950) 0D-3D coupled lattice
+ * Boltzmann library: incompressible D3Q19 BGK with forcing, non-equilibrium
+ * extrapolation at 0D-coupled planes, penalty immersed boundary with an
+ * elastic membrane wall (Wei, Amlani & Pahlevan, arXiv 2112.05258).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Lattice units: dx = dt = 1, c_s^2 = 1/3, rho_0 = 1.
+ * - Cell (x, y, z) of an instance has index x + nx*(y + ny*z).
+ * - Populations are handled shifted, g_i = f_i - w_i, in this velocity order
+ *   (weights 1/3, 1/18 for the 6 faces, 1/36 for the 12 edges):
+ *     0 (0,0,0)  1 (1,0,0)  2 (-1,0,0)  3 (0,1,0)  4 (0,-1,0)  5 (0,0,1)
+ *     6 (0,0,-1) 7 (1,1,0)  8 (-1,-1,0) 9 (1,-1,0) 10 (-1,1,0) 11 (1,0,1)
+ *     12 (-1,0,-1) 13 (1,0,-1) 14 (-1,0,1) 15 (0,1,1) 16 (0,-1,-1)
+ *     17 (0,1,-1) 18 (0,-1,1)
+ * - Pressures are gauge, p = P - c_s^2 (so sum f = 1 + 3p).
+ * - Cell types (the flags array): FLUID 0, SOLID 1 (halfway bounce-back),
+ *   INLET 2 (ghost of boundary 0, only on the plane z = 0), OUTLET 3 (ghost
+ *   of boundary 1, only on z = nz-1), EXTP 4 (ghost of boundary 2, the
+ *   exterior, anywhere on the box faces).  Every cell on the box faces must
+ *   be non-FLUID.
+ *
+ * Memory and streams: the caller owns every device buffer (allocate with any
+ * allocator, e.g. torch) and the HIP stream.  A context only borrows them;
+ * they must outlive it.  Calls that only enqueue work are asynchronous on the
+ * stream; calls that return data synchronise the stream first.  lbm_destroy
+ * frees host memory only.  One context per host thread.
+ *
+ * Errors: every call returns an lbm_status; nothing throws across the
+ * interface; lbm_last_error() gives a message for the last failure of a
+ * context.
+ */
+#ifndef LBM0D3D_H
+#define LBM0D3D_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx lbm_ctx;
+
+typedef enum {
+  LBM_OK = 0,
+  LBM_E_INVAL = -1,       /* bad argument, size or geometry */
+  LBM_E_DEVICE = -2,      /* a HIP call failed */
+  LBM_E_UNSTABLE = -3,    /* a boundary flux or pressure became non-finite */
+  LBM_E_STATE = -4,       /* call not valid in the current state */
+  LBM_E_UNSUPPORTED = -5, /* option not built into this library */
+  LBM_E_BAND = -6         /* a wall point left the band of cells set up for it */
+} lbm_status;
+
+typedef enum {
+  LBM_FP64 = 0,  /* populations stored and collided in FP64 */
+  LBM_FP32 = 1,  /* stored and collided in FP32 */
+  LBM_FP16S = 2, /* stored as FP16 of s*g (s = power of two), collided in FP32 */
+  LBM_BF16S = 3  /* stored as BF16 of g, collided in FP32 */
+} lbm_precision;
+
+enum { LBM_CELL_FLUID = 0, LBM_CELL_SOLID = 1, LBM_CELL_INLET = 2, LBM_CELL_OUTLET = 3, LBM_CELL_EXTP = 4 };
+
+/* 0D boundary models (Sec. 2.1.2 and 2.2 of the paper).  Parameters, all in
+ * lattice units:
+ *  PRESSURE_CONST  [p]                 pressure-type coupling, P* = c_s^2 + p
+ *  VELOCITY_CONST  [vz]                velocity-type coupling, v* = (0, 0, vz)
+ *  WINDKESSEL3     [Rp, C, Rd, mode]   3-element Windkessel, Eqs. rightbc and
+ *                  rightQ marched by forward Euler.  mode 0: the flux Q
+ *                  leaving the domain drives the model, P* = Pw + Rp Q
+ *                  (explicit coupling: stable for Rp below the acoustic
+ *                  impedance c_s / A of the layer and C above A / c_s);
+ *                  mode 1: the mean boundary pressure drives it and the
+ *                  outflow (P - Pw)/Rp is imposed as v* = v(x_f) + dv e_z with
+ *                  dv = (Q_0D - Q_3D)/A (stable for Rp above c_s / A).
+ *                  state: [Pw]
+ *  LV_ELASTANCE    [Emax, Emin, Tc, Tmax, P_ed, N_S, k, a1, n1, a2, n2]
+ *                  hybrid ODE-Dirichlet left ventricle (Eq. LVE) with the
+ *                  double-Hill elastance E(t) = (Emax-Emin) k h1 h2 + Emin,
+ *                  h1 = (tn/a1)^n1 / (1 + (tn/a1)^n1), h2 = 1/(1 + (tn/a2)^n2),
+ *                  tn = (t mod Tc)/Tmax, C_v = 1/E.  The valve opens when
+ *                  P_v exceeds the mean inlet pressure (at most once a beat),
+ *                  closes on the first step with inflow Q < 0; then
+ *                  v* = v0(x_f, T_d) S(t, T_d, N_S) (Eqs. SmoothFunction and
+ *                  vnew).  Each beat starts closed with P_v = P_ed.  Inlet only.
+ *                  state: [Pv]                                           */
+typedef enum {
+  LBM_BC_PRESSURE_CONST = 0,
+  LBM_BC_VELOCITY_CONST = 1,
+  LBM_BC_WINDKESSEL3 = 2,
+  LBM_BC_LV_ELASTANCE = 3
+} lbm_bc_kind;
+
+typedef struct {
+  int32_t nx, ny, nz;    /* box size, each >= 3 */
+  double tau;            /* BGK relaxation time (Eq. tau), > 0.5 */
+  int32_t precision;     /* lbm_precision */
+  double store_scale;    /* FP16S only: s (power of two), 0 = 256 */
+  const uint8_t* flags;  /* host, nx*ny*nz cell types; copied by lbm_init */
+  int32_t wave_cap;      /* waveform ring capacity in steps, 0 = 4096 */
+  double p_ref;          /* reference gauge pressure of the stored populations:
+                            the device keeps f_i - w_i (1 + 3 p_ref), an exact
+                            change of variables (f_eq is linear in P) that keeps
+                            the stored values small where the pressure sits near
+                            p_ref; every value handed in or out is still g = f - w */
+} lbm_config;
+
+typedef struct {
+  void* pop;        /* device, >= pop_bytes from lbm_query_sizes */
+  size_t pop_bytes;
+  void* work;       /* device, >= work_bytes from lbm_query_sizes */
+  size_t work_bytes;
+} lbm_buffers;
+
+/* Sizes of the device buffers for n instances (n = 1: one box).  All
+ * instances of one context share the precision of cfgs[0].
+ * Errors: LBM_E_INVAL for bad sizes, tau, flags or a NULL pointer. */
+lbm_status lbm_query_sizes(const lbm_config* cfgs, int32_t n, size_t* pop_bytes, size_t* work_bytes);
+
+/* Create a context over n independent instances (the batched ensemble when
+ * n > 1) on the caller's device buffers and HIP stream (NULL = default
+ * stream).  Sets every population to rest (g = 0: u = 0, p = 0, as in the
+ * paper's initialisation U_0 = 0, Q_0 = 0), every boundary to
+ * PRESSURE_CONST 0, the step counter to 0.  Enqueues host-to-device copies
+ * on the stream.  Errors: LBM_E_INVAL (see lbm_query_sizes; buffers too
+ * small), LBM_E_DEVICE. */
+lbm_status lbm_init(const lbm_config* cfgs, int32_t n, const lbm_buffers* buf, void* hip_stream,
+                    lbm_ctx** out);
+
+/* Advance every instance by nsteps full steps (Algorithm 1): boundary
+ * reductions and 0D update, IB force (if a wall is registered), fused
+ * collide-stream.  Asynchronous.  Errors: LBM_E_INVAL (nsteps < 0). */
+lbm_status lbm_step(lbm_ctx* ctx, int64_t nsteps);
+
+/* Set the 0D model of boundary b (0 inlet, 1 outlet, 2 exterior) of instance
+ * inst: kind, params (see lbm_bc_kind), optional initial state.  Synchronises
+ * the stream.  Errors: LBM_E_INVAL (kind/boundary mismatch, too few params:
+ * PRESSURE/VELOCITY need 1, WINDKESSEL3 3 or 4, LV 11). */
+lbm_status lbm_couple_0d(lbm_ctx* ctx, int32_t inst, int32_t boundary, int32_t kind,
+                         const double* params, int32_t nparams, const double* state, int32_t nstate);
+
+/* Read the 0D state of one boundary: out[0..7] = [vmode, p*, S, Pv, Pw,
+ * valve_open, T_d, dv_or_vz].  Synchronises. */
+lbm_status lbm_get_0d(lbm_ctx* ctx, int32_t inst, int32_t boundary, double* out);
+
+/* Elastic wall (Sec. 2.3.2): a structured cylinder membrane of n_theta
+ * (periodic) x n_z points (rings 0 and n_z-1 fixed, simply supported), point
+ * p = j + n_theta*k.  Forces: penalty IB (Eq. LagForce, force on the fluid
+ * F = alpha int(Vf - Vs) + beta (Vf - Vs), alpha, beta < 0; the wall gets -F),
+ * Peskin 4-point delta for interpolation (Eq. interpolation) and spreading
+ * (Eq. EulForce, b = sum F area delta), membrane stretching and bending by
+ * the staggered differences of Eqs. tension and bending along both mesh
+ * directions (bending acts on X - X0), central difference in time with
+ * areal mass `mass`.  X0_host: 3*n_points doubles (x,y,z per point), rest
+ * = initial shape.  band_margin: extra cells kept around the wall
+ * (default 2); a point whose stencil leaves the band raises LBM_E_BAND at
+ * the next lbm_sync. */
+typedef struct {
+  int32_t n_theta, n_z;
+  const double* X0_host;
+  double ds_theta, ds_z, area;
+  double k_stretch, ei_bend, mass, alpha, beta;
+  int32_t band_margin;
+} lbm_wall_desc;
+
+/* Device bytes the wall of one instance needs (Lagrangian state + dense
+ * velocity / force fields of the instance's cells + band list). */
+lbm_status lbm_fsi_query_sizes(lbm_ctx* ctx, int32_t inst, const lbm_wall_desc* wall, size_t* bytes);
+
+/* Register (or replace) the wall of instance inst on the caller's device
+ * buffer fsi_buf (>= bytes from lbm_fsi_query_sizes).  From the next step
+ * on, every step exchanges velocity and force with the wall.  Synchronises.
+ * Errors: LBM_E_INVAL (sizes, a point outside the box or a stencil touching
+ * the box faces). */
+lbm_status lbm_fsi_exchange(lbm_ctx* ctx, int32_t inst, const lbm_wall_desc* wall, void* fsi_buf,
+                            size_t fsi_bytes);
+
+/* Read the wall state: X, Xprev (positions at t_n, t_{n-1}), slip integral,
+ * interpolated fluid velocity Vf and force on the fluid F of the last step;
+ * each 3*n_points doubles, any pointer may be NULL.  Synchronises. */
+lbm_status lbm_read_wall(lbm_ctx* ctx, int32_t inst, double* X, double* Xprev, double* slip,
+                         double* Vf, double* F);
+
+/* Overwrite the populations of instance inst: g (host, [cell][19] doubles,
+ * shifted) for FLUID cells.  Only between an even number of steps.  Converts
+ * to the storage precision (round to nearest even).  Synchronises. */
+lbm_status lbm_write_populations(lbm_ctx* ctx, int32_t inst, const double* g_host);
+
+/* Uniform rest state at gauge pressure p for every FLUID cell of instance
+ * inst (the paper's arbitrary initial P_0).  Asynchronous. */
+lbm_status lbm_set_rest(lbm_ctx* ctx, int32_t inst, double p);
+
+/* Read the populations (host [cell][19] doubles, shifted, 0 off-fluid) of
+ * instance inst at the current step.  Synchronises. */
+lbm_status lbm_read_populations(lbm_ctx* ctx, int32_t inst, double* g_host);
+
+/* Read gauge pressure p = c_s^2 sum g (ncell doubles) and first moment
+ * sum e_i g_i (3*ncell doubles) of instance inst; either may be NULL.
+ * Synchronises. */
+lbm_status lbm_read_fields(lbm_ctx* ctx, int32_t inst, double* p_host, double* u_host);
+
+/* Per-step boundary waveforms of instance inst, 12 doubles per step:
+ * [n, Q_in, p_in, Q_out, p_out, in_mode, in_value, out_mode, out_value, Pv,
+ *  Pw_out, valve] (value = p* in pressure mode, S for the LV and the axial v*
+ * or correction otherwise).  Writes the last min(cap, steps, wave_cap)
+ * records, oldest first, and sets *n to that count.  Synchronises. */
+lbm_status lbm_read_waveforms(lbm_ctx* ctx, int32_t inst, double* out, int64_t cap, int64_t* n);
+
+/* Wait for the stream; LBM_E_UNSTABLE if a boundary flux or pressure became
+ * non-finite, LBM_E_BAND if a wall point left its band. */
+lbm_status lbm_sync(lbm_ctx* ctx);
+
+/* Steps taken so far. */
+int64_t lbm_steps(const lbm_ctx* ctx);
+
+/* Kernel timing with HIP events on the context's stream: when on, every
+ * launch of the collide-stream kernel (id 0), the boundary/0D kernel (1), the
+ * band-moment kernel (2) and the wall kernel (3) is bracketed by events.
+ * lbm_kernel_time synchronises and returns launches and total milliseconds
+ * since timing was switched on. */
+lbm_status lbm_set_timing(lbm_ctx* ctx, int32_t on);
+lbm_status lbm_kernel_time(lbm_ctx* ctx, int32_t kernel, int64_t* launches, double* total_ms);
+
+/* Replay steps from a captured HIP graph (one even + one odd step) instead
+ * of launching kernels one by one (default on; turned off while timing). */
+lbm_status lbm_set_graph(lbm_ctx* ctx, int32_t on);
+
+const char* lbm_last_error(const lbm_ctx* ctx);
+void lbm_destroy(lbm_ctx* ctx);
+
+/* Number of cells / population bytes per cell of instance inst. */
+int64_t lbm_num_cells(const lbm_ctx* ctx, int32_t inst);
+int32_t lbm_bytes_per_population(const lbm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM0D3D_H */

@@ -174,17 +174,23 @@ def wk_params(Z, C, R, sc, coupling=0.0):
 def cfg0():
     """Rigid tube r = 8 in 24x24x64, tau 0.8, FP64, constant inlet with
     population sum 1.001, 3-element Windkessel outlet Rp 0.05, C 50, Rd 1.0
-    (lattice units), 1000 steps."""
+    (lattice units), 1000 steps, starting at rest at the inlet pressure."""
     nx, ny, nz = 24, 24, 64
     return dict(
         name="cfg0_rigid_tube_24x24x64",
         nx=nx, ny=ny, nz=nz, tau=0.8,
         flags=tube_flags(nx, ny, nz, 11.5, 11.5, 8.0, elastic=False),
         inlet=(BC_PRESSURE_CONST, [0.001 / 3.0]),
+        p_ref=0.001 / 3.0,            # storage reference (exact change of variables)
         # Rp = 0.05 is ~18x the tube's acoustic impedance rho c_s / A, so the
         # Windkessel is coupled in the direction that is stable there: mean
         # outlet pressure in, outflow out (coupling flag 1).
         outlet=(BC_WINDKESSEL3, [0.05, 50.0, 1.0, 1.0]),
+        # the paper's initialisation U0 = 0, Q0 = 0, P0 != 0: fluid at rest at
+        # the inlet pressure, Windkessel chamber at the same pressure (no
+        # initial outflow)
+        p_init=0.001 / 3.0,
+        outlet_state=[0.001 / 3.0],
         steps=1000,
     )
 
@@ -203,6 +209,7 @@ def _elastic_tube(nx, ny, nz, r, h, k, ei, sc, tau, Emax=2.0, Emin=0.06, HR=75.0
         outlet_state=[p0],            # Windkessel chamber starts at P0
         exterior=(BC_PRESSURE_CONST, [p0]),
         p_init=p0,                    # uniform initial gauge pressure P0 != 0
+        p_ref=p0,                     # storage reference (exact change of variables)
         mesh=mesh, k=k, ei=ei, mass=mass, alpha=alpha, beta=beta,
         scales=sc,
     )

@@ -1,4 +1,5 @@
-"""Plain FP64 CPU oracle of the 0D-3D coupled LB / IB method (test infrastructure).
+"""Plain CPU oracle (FP64; long-double build as the FP64-bar reference) of the
+0D-3D coupled LB / IB method (test infrastructure).
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 ``bench.py`` may import this package.  It is the reference the HIP path is
@@ -16,30 +17,35 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lbm_oracle.c")
-_LIB = os.path.join(_HERE, "liblbm_oracle.so")
+_LIBS = {False: os.path.join(_HERE, "liblbm_oracle.so"),       # real = double
+         True: os.path.join(_HERE, "liblbm_oracle_ext.so")}    # real = long double
 NREC = 12
 Q = 19
 
 
 def build(force=True):
-    """Compile the oracle with gcc (-O2, OpenMP, no fast-math)."""
-    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
-        return _LIB
-    tmp = _LIB + ".tmp"
-    subprocess.check_call(["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared",
-                           "-Wall", "-Wno-unused-function", "-o", tmp, _SRC, "-lm"])
-    os.replace(tmp, _LIB)
-    return _LIB
+    """Compile the oracle with gcc (-O2, OpenMP, no fast-math), in FP64 and
+    in extended precision (long double, the reference for the FP64 bar)."""
+    for ext, path in _LIBS.items():
+        if not force and os.path.exists(path) and os.path.getmtime(path) >= os.path.getmtime(_SRC):
+            continue
+        tmp = path + ".tmp"
+        cmd = ["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared", "-Wall",
+               "-Wno-unused-function", "-o", tmp, _SRC, "-lm"]
+        if ext:
+            cmd.insert(1, "-DORC_EXTENDED")
+        subprocess.check_call(cmd)
+        os.replace(tmp, path)
+    return _LIBS[False]
 
 
-_lib = None
+_lib = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
+def lib(extended=False):
+    if extended not in _lib:
         build(force=False)
-        L = C.CDLL(_LIB)
+        L = C.CDLL(_LIBS[extended])
         vp, dp, ip, u8p = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int), C.POINTER(C.c_uint8)
         L.orc_create.restype = vp
         L.orc_create.argtypes = [C.c_int, C.c_int, C.c_int, C.c_double, u8p, C.c_int, C.c_int, C.c_int]
@@ -52,7 +58,7 @@ def lib():
         L.orc_set_membrane.argtypes = [vp, C.c_int, C.c_int, dp, C.c_double, C.c_double, C.c_double,
                                        C.c_double, C.c_double, C.c_double, C.c_double, C.c_double]
         L.orc_get_lagrangian.argtypes = [vp, dp, dp, dp, dp, dp]
-        L.orc_set_lagrangian.argtypes = [vp, dp, dp]
+        L.orc_get_displacement.argtypes = [vp, dp, dp]
         L.orc_ib_interp.argtypes = [vp, C.c_long, dp, dp, dp]
         L.orc_ib_spread.argtypes = [vp, C.c_long, dp, dp, C.c_double, dp]
         L.orc_membrane_force.argtypes = [vp, dp, dp]
@@ -77,8 +83,9 @@ def lib():
         L.orc_bc_update.argtypes = [vp, C.c_long, C.c_double, C.c_double, dp]
         L.orc_filament_force.argtypes = [C.c_int, dp, C.c_double, C.c_double, C.c_double, dp]
         L.orc_num_threads.restype = C.c_int
-        _lib = L
-    return _lib
+        L.orc_is_extended.restype = C.c_int
+        _lib[extended] = L
+    return _lib[extended]
 
 
 def _d(a):
@@ -168,105 +175,108 @@ class ZeroD:
 # ----------------------------------------------------------------------------
 
 class Oracle:
-    """FP64 two-lattice pull solver.  flags: uint8 array (nz, ny, nx)."""
+    """Two-lattice pull solver (FP64, or long double with extended=True).
+    flags: uint8 array (nz, ny, nx)."""
 
-    def __init__(self, flags, tau, periodic=(0, 0, 0)):
+    def __init__(self, flags, tau, periodic=(0, 0, 0), extended=False):
         flags = np.ascontiguousarray(flags, dtype=np.uint8)
         self.nz, self.ny, self.nx = flags.shape
         self.ncell = flags.size
         self.flags = flags
         self.tau = tau
-        self.h = lib().orc_create(self.nx, self.ny, self.nz, tau,
-                                  flags.ctypes.data_as(C.POINTER(C.c_uint8)), *periodic)
+        self.L = lib(extended)
+        self.h = self.L.orc_create(self.nx, self.ny, self.nz, tau,
+                                   flags.ctypes.data_as(C.POINTER(C.c_uint8)), *periodic)
         self.np = 0
 
     def __del__(self):
         if getattr(self, "h", None):
-            lib().orc_destroy(self.h)
+            self.L.orc_destroy(self.h)
             self.h = None
 
     def set_bc(self, boundary, kind, par, state=()):
         par, pp = _d(par)
         st = np.asarray(state, float) if len(state) else np.zeros(1)
         st, sp = _d(st)
-        lib().orc_set_bc(self.h, boundary, kind, pp, len(par), sp, len(state))
+        self.L.orc_set_bc(self.h, boundary, kind, pp, len(par), sp, len(state))
 
     def set_body_force(self, b, omega=0.0):
-        lib().orc_set_body_force(self.h, float(b[0]), float(b[1]), float(b[2]), float(omega))
+        self.L.orc_set_body_force(self.h, float(b[0]), float(b[1]), float(b[2]), float(omega))
 
     def set_pops(self, g):
         g, gp = _d(np.asarray(g).reshape(self.ncell, 19))
-        lib().orc_set_pops(self.h, gp)
+        self.L.orc_set_pops(self.h, gp)
 
     def get_pops(self):
         g = np.zeros((self.ncell, 19))
-        lib().orc_get_pops(self.h, g.ctypes.data_as(C.POINTER(C.c_double)))
+        self.L.orc_get_pops(self.h, g.ctypes.data_as(C.POINTER(C.c_double)))
         return g
 
     def set_rest(self, p_gauge):
-        lib().orc_set_rest(self.h, float(p_gauge))
+        self.L.orc_set_rest(self.h, float(p_gauge))
 
     def set_membrane(self, mesh, k, ei, mass, alpha, beta):
         X0, xp = _d(mesh["X0"])
         self.np = X0.shape[0]
-        lib().orc_set_membrane(self.h, mesh["n_theta"], mesh["n_z"], xp, mesh["ds_theta"],
+        self.L.orc_set_membrane(self.h, mesh["n_theta"], mesh["n_z"], xp, mesh["ds_theta"],
                                mesh["ds_z"], mesh["area"], k, ei, mass, alpha, beta)
 
     def lagrangian(self):
         out = [np.zeros((self.np, 3)) for _ in range(5)]
         ptrs = [o.ctypes.data_as(C.POINTER(C.c_double)) for o in out]
-        lib().orc_get_lagrangian(self.h, *ptrs)
+        self.L.orc_get_lagrangian(self.h, *ptrs)
         return dict(X=out[0], Xprev=out[1], slip=out[2], Vf=out[3], F=out[4])
 
-    def set_lagrangian(self, X, Xprev):
-        X, xp = _d(X)
-        Xprev, pp = _d(Xprev)
-        lib().orc_set_lagrangian(self.h, xp, pp)
+    def displacement(self):
+        """(D^n, D^{n-1}) = wall positions minus the rest shape."""
+        out = [np.zeros((self.np, 3)) for _ in range(2)]
+        self.L.orc_get_displacement(self.h, *[o.ctypes.data_as(C.POINTER(C.c_double)) for o in out])
+        return out
 
     def ib_interp(self, X, u):
         X, xp = _d(X)
         u, up = _d(np.asarray(u).reshape(self.ncell, 3))
         V = np.zeros((X.shape[0], 3))
-        lib().orc_ib_interp(self.h, X.shape[0], xp, up, V.ctypes.data_as(C.POINTER(C.c_double)))
+        self.L.orc_ib_interp(self.h, X.shape[0], xp, up, V.ctypes.data_as(C.POINTER(C.c_double)))
         return V
 
     def ib_spread(self, X, F, area):
         X, xp = _d(X)
         F, fp = _d(F)
         b = np.zeros((self.ncell, 3))
-        lib().orc_ib_spread(self.h, X.shape[0], xp, fp, float(area), b.ctypes.data_as(C.POINTER(C.c_double)))
+        self.L.orc_ib_spread(self.h, X.shape[0], xp, fp, float(area), b.ctypes.data_as(C.POINTER(C.c_double)))
         return b
 
     def membrane_force(self, X):
         X, xp = _d(X)
         F = np.zeros_like(X)
-        lib().orc_membrane_force(self.h, xp, F.ctypes.data_as(C.POINTER(C.c_double)))
+        self.L.orc_membrane_force(self.h, xp, F.ctypes.data_as(C.POINTER(C.c_double)))
         return F
 
     def step(self, n=1):
-        lib().orc_step(self.h, int(n))
+        self.L.orc_step(self.h, int(n))
 
     @property
     def t(self):
-        return lib().orc_get_step(self.h)
+        return self.L.orc_get_step(self.h)
 
     def fields(self):
         """(gauge pressure (nz,ny,nx), first moment sum e g (nz,ny,nx,3))."""
         p = np.zeros(self.ncell)
         u = np.zeros((self.ncell, 3))
-        lib().orc_get_fields(self.h, p.ctypes.data_as(C.POINTER(C.c_double)),
+        self.L.orc_get_fields(self.h, p.ctypes.data_as(C.POINTER(C.c_double)),
                              u.ctypes.data_as(C.POINTER(C.c_double)))
         return p.reshape(self.nz, self.ny, self.nx), u.reshape(self.nz, self.ny, self.nx, 3)
 
     def force(self):
         b = np.zeros((self.ncell, 3))
-        lib().orc_get_force(self.h, b.ctypes.data_as(C.POINTER(C.c_double)))
+        self.L.orc_get_force(self.h, b.ctypes.data_as(C.POINTER(C.c_double)))
         return b
 
     def waveforms(self):
-        n = lib().orc_get_waveforms(self.h, None, 0)
+        n = self.L.orc_get_waveforms(self.h, None, 0)
         out = np.zeros((n, NREC))
-        lib().orc_get_waveforms(self.h, out.ctypes.data_as(C.POINTER(C.c_double)), n)
+        self.L.orc_get_waveforms(self.h, out.ctypes.data_as(C.POINTER(C.c_double)), n)
         return out
 
 
@@ -274,9 +284,9 @@ def num_threads():
     return lib().orc_num_threads()
 
 
-def from_config(cfg, pops=None):
+def from_config(cfg, pops=None, extended=False):
     """Oracle set up from one of the lbm_inputs workload dicts."""
-    o = Oracle(cfg["flags"], cfg["tau"])
+    o = Oracle(cfg["flags"], cfg["tau"], extended=extended)
     if "inlet" in cfg:
         o.set_bc(0, cfg["inlet"][0], cfg["inlet"][1], cfg.get("inlet_state", ()))
     if "outlet" in cfg:

@@ -1,0 +1,256 @@
+"""MI355X-native 0D-3D coupled lattice Boltzmann / immersed-boundary solver.
+
+Python binding of ``liblbm0d3d.so`` (C interface in ``include/lbm0d3d.h``).
+This module only marshals arguments: every step of the method runs in the
+library's HIP kernels.  torch supplies device memory and the stream.  There
+is no CPU fallback: if the library is missing, importing ``lib()`` raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbm0d3d.so")
+NQ = 19
+NREC = 12
+FP64, FP32, FP16S, BF16S = 0, 1, 2, 3
+KERNEL_COLLIDE, KERNEL_REDUCE, KERNEL_BAND, KERNEL_WALL = 0, 1, 2, 3
+
+STATUS = {0: "OK", -1: "E_INVAL", -2: "E_DEVICE", -3: "E_UNSTABLE", -4: "E_STATE",
+          -5: "E_UNSUPPORTED", -6: "E_BAND"}
+
+
+class LbmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Config(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("tau", C.c_double),
+                ("precision", C.c_int32), ("store_scale", C.c_double),
+                ("flags", C.POINTER(C.c_uint8)), ("wave_cap", C.c_int32), ("p_ref", C.c_double)]
+
+
+class Buffers(C.Structure):
+    _fields_ = [("pop", C.c_void_p), ("pop_bytes", C.c_size_t),
+                ("work", C.c_void_p), ("work_bytes", C.c_size_t)]
+
+
+class WallDesc(C.Structure):
+    _fields_ = [("n_theta", C.c_int32), ("n_z", C.c_int32), ("X0_host", C.POINTER(C.c_double)),
+                ("ds_theta", C.c_double), ("ds_z", C.c_double), ("area", C.c_double),
+                ("k_stretch", C.c_double), ("ei_bend", C.c_double), ("mass", C.c_double),
+                ("alpha", C.c_double), ("beta", C.c_double), ("band_margin", C.c_int32)]
+
+
+SYMBOLS = {
+    "lbm_query_sizes": (C.c_int, [C.POINTER(Config), C.c_int32, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
+    "lbm_init": (C.c_int, [C.POINTER(Config), C.c_int32, C.POINTER(Buffers), C.c_void_p, C.POINTER(C.c_void_p)]),
+    "lbm_step": (C.c_int, [C.c_void_p, C.c_int64]),
+    "lbm_couple_0d": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_double), C.c_int32,
+                                C.POINTER(C.c_double), C.c_int32]),
+    "lbm_get_0d": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_double)]),
+    "lbm_fsi_query_sizes": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(WallDesc), C.POINTER(C.c_size_t)]),
+    "lbm_fsi_exchange": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(WallDesc), C.c_void_p, C.c_size_t]),
+    "lbm_read_wall": (C.c_int, [C.c_void_p, C.c_int32] + [C.POINTER(C.c_double)] * 5),
+    "lbm_write_populations": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_double)]),
+    "lbm_set_rest": (C.c_int, [C.c_void_p, C.c_int32, C.c_double]),
+    "lbm_read_populations": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_double)]),
+    "lbm_read_fields": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "lbm_read_waveforms": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.c_int64,
+                                     C.POINTER(C.c_int64)]),
+    "lbm_sync": (C.c_int, [C.c_void_p]),
+    "lbm_steps": (C.c_int64, [C.c_void_p]),
+    "lbm_set_timing": (C.c_int, [C.c_void_p, C.c_int32]),
+    "lbm_kernel_time": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
+    "lbm_set_graph": (C.c_int, [C.c_void_p, C.c_int32]),
+    "lbm_last_error": (C.c_char_p, [C.c_void_p]),
+    "lbm_destroy": (None, [C.c_void_p]),
+    "lbm_num_cells": (C.c_int64, [C.c_void_p, C.c_int32]),
+    "lbm_bytes_per_population": (C.c_int32, [C.c_void_p]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load liblbm0d3d.so (built by paper_2112_05258_amd.build); raise if absent."""
+    global _lib
+    if _lib is None:
+        # torch first: its bundled HIP runtime must be the one the library
+        # binds to (same SONAME), so that one runtime owns the device, the
+        # torch-allocated buffers and the streams.
+        import torch  # noqa: F401
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run python -m paper_2112_05258_amd.build")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SYMBOLS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double)) if a is not None else None
+
+
+class Solver:
+    """One context over one or more lattice instances on the current GPU.
+
+    boxes: list of dicts with nx, ny, nz, tau, flags (uint8 (nz, ny, nx)).
+    """
+
+    def __init__(self, boxes, precision=FP32, store_scale=0.0, wave_cap=4096, device="cuda:0"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        if isinstance(boxes, dict):
+            boxes = [boxes]
+        self.boxes = boxes
+        self.n = len(boxes)
+        self._flags = [np.ascontiguousarray(b["flags"], dtype=np.uint8) for b in boxes]
+        cfgs = (Config * self.n)()
+        for k, b in enumerate(boxes):
+            cfgs[k] = Config(b["nx"], b["ny"], b["nz"], float(b["tau"]), precision, float(store_scale),
+                             self._flags[k].ctypes.data_as(C.POINTER(C.c_uint8)), wave_cap,
+                             float(b.get("p_ref", 0.0)))
+        self._cfgs = cfgs
+        pb, wb = C.c_size_t(), C.c_size_t()
+        self._check(lib().lbm_query_sizes(cfgs, self.n, C.byref(pb), C.byref(wb)), None)
+        self.pop = torch.empty(pb.value, dtype=torch.uint8, device=self.device)
+        self.work = torch.empty(wb.value, dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.Stream(device=self.device)
+        buf = Buffers(self.pop.data_ptr(), pb.value, self.work.data_ptr(), wb.value)
+        h = C.c_void_p()
+        self._check(lib().lbm_init(cfgs, self.n, C.byref(buf), C.c_void_p(self.stream.cuda_stream), C.byref(h)), None)
+        self.h = h
+        self.fsi = {}
+        self.precision = precision
+
+    # ------------------------------------------------------------------
+    def _check(self, code, h="self"):
+        if code != 0:
+            hh = self.h if h == "self" else h
+            msg = lib().lbm_last_error(hh).decode()
+            raise LbmError(code, msg)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().lbm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------
+    def step(self, n=1):
+        self._check(lib().lbm_step(self.h, int(n)))
+
+    @property
+    def t(self):
+        return lib().lbm_steps(self.h)
+
+    def sync(self):
+        self._check(lib().lbm_sync(self.h))
+
+    def couple_0d(self, inst, boundary, kind, params, state=()):
+        p = np.ascontiguousarray(params, dtype=np.float64)
+        s = np.ascontiguousarray(state, dtype=np.float64) if len(state) else None
+        self._check(lib().lbm_couple_0d(self.h, inst, boundary, kind, _dp(p), len(p), _dp(s),
+                                        0 if s is None else len(s)))
+
+    def get_0d(self, inst, boundary):
+        out = np.zeros(8)
+        self._check(lib().lbm_get_0d(self.h, inst, boundary, _dp(out)))
+        return dict(vmode=int(out[0]), pstar=out[1], S=out[2], Pv=out[3], Pw=out[4],
+                    open=int(out[5]), Td=int(out[6]), vz=out[7])
+
+    def _wall_desc(self, mesh, k, ei, mass, alpha, beta, margin):
+        X0 = np.ascontiguousarray(mesh["X0"], dtype=np.float64).reshape(-1)
+        d = WallDesc(mesh["n_theta"], mesh["n_z"], _dp(X0), mesh["ds_theta"], mesh["ds_z"], mesh["area"],
+                     k, ei, mass, alpha, beta, margin)
+        return d, X0
+
+    def fsi_exchange(self, inst, mesh, k, ei, mass, alpha, beta, margin=2):
+        d, X0 = self._wall_desc(mesh, k, ei, mass, alpha, beta, margin)
+        nb = C.c_size_t()
+        self._check(lib().lbm_fsi_query_sizes(self.h, inst, C.byref(d), C.byref(nb)))
+        buf = self.torch.empty(nb.value, dtype=self.torch.uint8, device=self.device)
+        self._check(lib().lbm_fsi_exchange(self.h, inst, C.byref(d), C.c_void_p(buf.data_ptr()), nb.value))
+        self.fsi[inst] = (buf, mesh["n_theta"] * mesh["n_z"])
+
+    def read_wall(self, inst=0):
+        n = self.fsi[inst][1]
+        out = [np.zeros((n, 3)) for _ in range(5)]
+        self._check(lib().lbm_read_wall(self.h, inst, *[_dp(o) for o in out]))
+        return dict(X=out[0], Xprev=out[1], slip=out[2], Vf=out[3], F=out[4])
+
+    def ncell(self, inst=0):
+        return lib().lbm_num_cells(self.h, inst)
+
+    def write_populations(self, g, inst=0):
+        g = np.ascontiguousarray(g, dtype=np.float64).reshape(-1)
+        self._check(lib().lbm_write_populations(self.h, inst, _dp(g)))
+
+    def set_rest(self, p, inst=0):
+        self._check(lib().lbm_set_rest(self.h, inst, float(p)))
+
+    def read_populations(self, inst=0):
+        g = np.zeros((self.ncell(inst), NQ))
+        self._check(lib().lbm_read_populations(self.h, inst, _dp(g)))
+        return g
+
+    def fields(self, inst=0):
+        """(gauge pressure (nz,ny,nx), first moment sum e g (nz,ny,nx,3))."""
+        b = self.boxes[inst]
+        nc = self.ncell(inst)
+        p = np.zeros(nc)
+        u = np.zeros((nc, 3))
+        self._check(lib().lbm_read_fields(self.h, inst, _dp(p), _dp(u)))
+        return p.reshape(b["nz"], b["ny"], b["nx"]), u.reshape(b["nz"], b["ny"], b["nx"], 3)
+
+    def waveforms(self, inst=0, cap=1 << 30):
+        cap = min(cap, self.t)
+        out = np.zeros((max(cap, 1), NREC))
+        n = C.c_int64()
+        self._check(lib().lbm_read_waveforms(self.h, inst, _dp(out), cap, C.byref(n)))
+        return out[: n.value]
+
+    def set_timing(self, on):
+        self._check(lib().lbm_set_timing(self.h, 1 if on else 0))
+
+    def kernel_time(self, kernel):
+        n = C.c_int64()
+        ms = C.c_double()
+        self._check(lib().lbm_kernel_time(self.h, kernel, C.byref(n), C.byref(ms)))
+        return n.value, ms.value
+
+    def set_graph(self, on):
+        self._check(lib().lbm_set_graph(self.h, 1 if on else 0))
+
+
+def solver_from_config(cfg, precision=FP32, pops=None, store_scale=0.0, wave_cap=4096):
+    """Solver for one workload dict (see lbm_inputs): box, 0D models, initial
+    state and wall are passed through the C interface unchanged."""
+    s = Solver(dict(nx=cfg["nx"], ny=cfg["ny"], nz=cfg["nz"], tau=cfg["tau"], flags=cfg["flags"],
+                    p_ref=cfg.get("p_ref", 0.0)),
+               precision=precision, store_scale=store_scale, wave_cap=wave_cap)
+    for b, key in ((0, "inlet"), (1, "outlet"), (2, "exterior")):
+        if key in cfg:
+            s.couple_0d(0, b, cfg[key][0], cfg[key][1], cfg.get(key + "_state", ()))
+    if pops is not None:
+        s.write_populations(pops)
+    elif cfg.get("p_init", 0.0) != 0.0:
+        s.set_rest(cfg["p_init"])
+    if "mesh" in cfg:
+        s.fsi_exchange(0, cfg["mesh"], cfg["k"], cfg["ei"], cfg["mass"], cfg["alpha"], cfg["beta"])
+    return s

@@ -1,0 +1,825 @@
+// lbm_api.cpp -- host side of the C interface declared in include/lbm0d3d.h.
+//
+// Validates geometry and parameters, lays out the caller's device buffers,
+// builds the per-instance tables the kernels read (block -> instance,
+// boundary-layer cell lists, reduction work table, wall band), enqueues the
+// kernels of every step on the caller's stream (eagerly or from a captured
+// HIP graph of one even + one odd step) and converts populations between the
+// storage precision and host FP64 for read-back.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/lbm0d3d.h"
+#include "lbm_internal.h"
+
+using namespace lbm;
+
+namespace {
+
+constexpr int EXh[NQ] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+constexpr int EYh[NQ] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+constexpr int EZh[NQ] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+constexpr int OPPh[NQ] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
+constexpr double W[NQ] = {1.0 / 3,  1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18,
+                          1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36,
+                          1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+int elem_size(int prec) { return prec == 0 ? 8 : (prec == 1 ? 4 : 2); }
+int r4_size(int prec) { return prec == 0 ? 32 : 16; }
+
+// -------- host conversions to and from the storage precision --------------
+uint16_t f32_to_bf16_rne(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+float bf16_to_f32(uint16_t h) {
+  uint32_t u = (uint32_t)h << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+uint16_t f32_to_f16_rne(float f) {
+  _Float16 h = (_Float16)f;
+  uint16_t u;
+  std::memcpy(&u, &h, 2);
+  return u;
+}
+float f16_to_f32(uint16_t u) {
+  _Float16 h;
+  std::memcpy(&h, &u, 2);
+  return (float)h;
+}
+
+struct Geometry {
+  int nx, ny, nz;
+  int64_t ncell;
+  std::vector<uint8_t> flags;        // with F_NEAR (and F_BAND) bits
+  std::vector<int32_t> lay[2];
+};
+
+// Checks the cell types and derives NEAR bits and boundary-layer lists.
+bool build_geometry(const lbm_config& c, Geometry& g, std::string& err) {
+  if (c.nx < 3 || c.ny < 3 || c.nz < 3) { err = "box dimensions must be >= 3"; return false; }
+  if (!(c.tau > 0.5)) { err = "tau must be > 0.5"; return false; }
+  if (!c.flags) { err = "flags is NULL"; return false; }
+  g.nx = c.nx; g.ny = c.ny; g.nz = c.nz;
+  g.ncell = (int64_t)c.nx * c.ny * c.nz;
+  if (g.ncell > (int64_t)1 << 31) { err = "instance too large"; return false; }
+  g.flags.assign(c.flags, c.flags + g.ncell);
+  auto at = [&](int x, int y, int z) -> uint8_t& { return g.flags[x + (int64_t)g.nx * (y + (int64_t)g.ny * z)]; };
+  for (int z = 0; z < g.nz; ++z)
+    for (int y = 0; y < g.ny; ++y)
+      for (int x = 0; x < g.nx; ++x) {
+        const uint8_t t = at(x, y, z);
+        const bool face = x == 0 || y == 0 || z == 0 || x == g.nx - 1 || y == g.ny - 1 || z == g.nz - 1;
+        if (t > T_EXTP) { err = "cell type out of range"; return false; }
+        if (face && t == T_FLUID) { err = "FLUID cell on the box boundary"; return false; }
+        if (t == T_INLET && z != 0) { err = "INLET cell off the plane z = 0"; return false; }
+        if (t == T_OUTLET && z != g.nz - 1) { err = "OUTLET cell off the plane z = nz-1"; return false; }
+        if (t == T_EXTP && !face) { err = "EXTP cell inside the box"; return false; }
+      }
+  for (int z = 1; z < g.nz - 1; ++z)
+    for (int y = 1; y < g.ny - 1; ++y)
+      for (int x = 1; x < g.nx - 1; ++x) {
+        uint8_t& t = at(x, y, z);
+        if (t != T_FLUID) continue;
+        for (int i = 1; i < NQ; ++i)
+          if (at(x + EXh[i], y + EYh[i], z + EZh[i]) != T_FLUID) { t |= F_NEAR; break; }
+      }
+  for (int pl = 0; pl < 2; ++pl) {
+    g.lay[pl].clear();
+    const int zl = pl == 0 ? 1 : g.nz - 2, zg = pl == 0 ? 0 : g.nz - 1;
+    const uint8_t gt = pl == 0 ? T_INLET : T_OUTLET;
+    for (int y = 0; y < g.ny; ++y)
+      for (int x = 0; x < g.nx; ++x)
+        if ((at(x, y, zl) & TYPE_MASK) == T_FLUID && at(x, y, zg) == gt)
+          g.lay[pl].push_back(x + g.nx * (y + g.ny * zl));
+  }
+  return true;
+}
+
+struct Layout {
+  size_t flags, inst, blk_inst, lay, red, red_part, bc, st, wave, v0, err, walls, total;
+  int64_t NT;
+  int nblk, nred, nlay, wave_cap;
+  int64_t nv0;
+};
+
+void plan(const std::vector<Geometry>& G, int prec, int wave_cap, Layout& L, std::vector<InstDesc>* inst,
+          std::vector<int32_t>* blk, std::vector<int32_t>* lay, std::vector<RedTab>* red) {
+  L.NT = 0; L.nblk = 0; L.nred = 0; L.nlay = 0; L.nv0 = 0; L.wave_cap = wave_cap;
+  for (size_t k = 0; k < G.size(); ++k) {
+    const Geometry& g = G[k];
+    InstDesc d;
+    std::memset(&d, 0, sizeof d);
+    d.nx = g.nx; d.ny = g.ny; d.nz = g.nz;
+    d.cell0 = L.NT; d.ncell = g.ncell;
+    d.blk0 = L.nblk;
+    d.nblk = (int32_t)((g.ncell + BLOCK - 1) / BLOCK);
+    d.v0_off = L.nv0;
+    d.red0 = L.nred;
+    int nr = 0;
+    for (int pl = 0; pl < 2; ++pl) {
+      d.lay_off[pl] = L.nlay;
+      d.lay_n[pl] = (int32_t)g.lay[pl].size();
+      if (lay) lay->insert(lay->end(), g.lay[pl].begin(), g.lay[pl].end());
+      L.nlay += d.lay_n[pl];
+      for (int s = 0; s < d.lay_n[pl]; s += RCHUNK) {
+        if (red) red->push_back(RedTab{(int32_t)k, pl, s, std::min(RCHUNK, d.lay_n[pl] - s)});
+        ++nr;
+      }
+    }
+    if (nr == 0) {  // the 0D models still advance every step
+      if (red) red->push_back(RedTab{(int32_t)k, 0, 0, 0});
+      nr = 1;
+    }
+    d.nred = nr;
+    L.nred += nr;
+    if (blk) blk->insert(blk->end(), d.nblk, (int32_t)k);
+    L.nblk += d.nblk;
+    L.NT += g.ncell;
+    L.nv0 += (int64_t)g.nx * g.ny;
+    if (inst) inst->push_back(d);
+  }
+  const size_t n = G.size();
+  size_t o = 0;
+  L.flags = o; o = align256(o + L.NT);
+  L.inst = o; o = align256(o + n * sizeof(InstDesc));
+  L.blk_inst = o; o = align256(o + (size_t)L.nblk * 4);
+  L.lay = o; o = align256(o + (size_t)std::max(L.nlay, 1) * 4);
+  L.red = o; o = align256(o + (size_t)L.nred * sizeof(RedTab));
+  L.red_part = o; o = align256(o + (size_t)L.nred * 16);
+  L.bc = o; o = align256(o + 3 * n * sizeof(BcDev));
+  L.st = o; o = align256(o + n * sizeof(InstState));
+  L.wave = o; o = align256(o + n * (size_t)wave_cap * NREC * 8);
+  L.v0 = o; o = align256(o + (size_t)L.nv0 * r4_size(prec));
+  L.err = o; o = align256(o + 4);
+  L.walls = o; o = align256(o + n * 4);
+  L.total = o;
+  (void)prec;
+}
+
+struct EventPair {
+  hipEvent_t a, b;
+};
+
+struct Wall {
+  bool on = false;
+  int64_t np = 0;
+  int nband = 0;
+  std::vector<int32_t> band;
+};
+
+}  // namespace
+
+struct lbm_ctx {
+  int n = 0, prec = 1;
+  float scale = 1.0f;
+  std::vector<Geometry> geo;
+  std::vector<InstDesc> inst;
+  Layout L;
+  hipStream_t stream = nullptr;
+  char* work = nullptr;
+  void* pop = nullptr;
+  Dev dev;
+  int64_t step = 0;
+  std::string err;
+  std::vector<Wall> wall;
+  std::vector<int32_t> walls;
+  // timing
+  bool timing = false;
+  std::vector<EventPair> pool;
+  std::vector<std::pair<int, EventPair>> recorded;
+  int64_t t_launch[4] = {0, 0, 0, 0};
+  double t_ms[4] = {0, 0, 0, 0};
+  // graph
+  bool use_graph = true;
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+};
+
+namespace {
+
+thread_local std::string g_init_err;  // message of the last failed lbm_init / query
+
+lbm_status fail(lbm_ctx* c, lbm_status s, const std::string& m) {
+  if (c) c->err = m;
+  return s;
+}
+
+#define HIPCHK(ctx, call)                                                         \
+  do {                                                                           \
+    hipError_t e_ = (call);                                                      \
+    if (e_ != hipSuccess) return fail(ctx, LBM_E_DEVICE, std::string(#call ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+void drop_graph(lbm_ctx* c) {
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  c->gexec = nullptr;
+  c->graph = nullptr;
+}
+
+EventPair get_pair(lbm_ctx* c) {
+  if (!c->pool.empty()) {
+    EventPair p = c->pool.back();
+    c->pool.pop_back();
+    return p;
+  }
+  EventPair p;
+  (void)hipEventCreate(&p.a);
+  (void)hipEventCreate(&p.b);
+  return p;
+}
+
+hipError_t enqueue_step(lbm_ctx* c, int parity, bool timed) {
+  hipError_t e;
+  EventPair ev[4];
+  auto pre = [&](int k) {
+    if (timed) { ev[k] = get_pair(c); (void)hipEventRecord(ev[k].a, c->stream); }
+  };
+  auto post = [&](int k) {
+    if (timed) { (void)hipEventRecord(ev[k].b, c->stream); c->recorded.push_back({k, ev[k]}); }
+  };
+  pre(1);
+  e = launch_reduce(c->dev, c->prec, parity, c->L.nred, c->stream);
+  if (e != hipSuccess) return e;
+  post(1);
+  if (c->dev.nwall > 0) {
+    pre(2);
+    e = launch_band(c->dev, c->prec, parity, c->stream);
+    if (e != hipSuccess) return e;
+    post(2);
+    pre(3);
+    e = launch_wall(c->dev, c->prec, parity, c->stream);
+    if (e != hipSuccess) return e;
+    post(3);
+  }
+  pre(0);
+  e = launch_collide(c->dev, c->prec, parity, c->L.nblk, c->stream);
+  if (e != hipSuccess) return e;
+  post(0);
+  return hipSuccess;
+}
+
+void collect_times(lbm_ctx* c) {
+  for (auto& r : c->recorded) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.second.a, r.second.b) == hipSuccess) {
+      c->t_ms[r.first] += ms;
+      c->t_launch[r.first] += 1;
+    }
+    c->pool.push_back(r.second);
+  }
+  c->recorded.clear();
+}
+
+template <class T>
+lbm_status h2d(lbm_ctx* c, size_t off, const T* src, size_t count) {
+  if (count == 0) return LBM_OK;
+  HIPCHK(c, hipMemcpyAsync(c->work + off, src, count * sizeof(T), hipMemcpyHostToDevice, c->stream));
+  return LBM_OK;
+}
+
+// Read the raw storage of instance k into host doubles, AoS [cell][19],
+// undoing the AA parity permutation.
+lbm_status read_pops(lbm_ctx* c, int k, std::vector<double>& out) {
+  const Geometry& g = c->geo[k];
+  const InstDesc& d = c->inst[k];
+  const int es = elem_size(c->prec);
+  std::vector<char> raw((size_t)NQ * g.ncell * es);
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (int i = 0; i < NQ; ++i)
+    HIPCHK(c, hipMemcpy(raw.data() + (size_t)i * g.ncell * es,
+                        (char*)c->pop + ((size_t)i * c->L.NT + d.cell0) * es, (size_t)g.ncell * es,
+                        hipMemcpyDeviceToHost));
+  auto val = [&](int i, int64_t cell) -> double {
+    const char* p = raw.data() + ((size_t)i * g.ncell + cell) * es;
+    switch (c->prec) {
+      case 0: { double v; std::memcpy(&v, p, 8); return v; }
+      case 1: { float v; std::memcpy(&v, p, 4); return v; }
+      case 2: { uint16_t u; std::memcpy(&u, p, 2); return (double)(f16_to_f32(u) * (1.0f / c->scale)); }
+      default: { uint16_t u; std::memcpy(&u, p, 2); return (double)(bf16_to_f32(u) * (1.0f / c->scale)); }
+    }
+  };
+  const int64_t sy = g.nx, sz = (int64_t)g.nx * g.ny;
+  const bool odd = c->step & 1;
+  out.assign((size_t)g.ncell * NQ, 0.0);
+  for (int64_t cell = 0; cell < g.ncell; ++cell) {
+    if ((g.flags[cell] & TYPE_MASK) != T_FLUID) continue;
+    for (int i = 0; i < NQ; ++i) {
+      double v;
+      if (!odd) {
+        v = val(i, cell);
+      } else {
+        const int64_t src = cell - (EXh[i] + EYh[i] * sy + EZh[i] * sz);
+        v = (i != 0 && (g.flags[src] & TYPE_MASK) == T_SOLID) ? val(i, cell) : val(OPPh[i], src);
+      }
+      out[(size_t)cell * NQ + i] = v + W[i] * d.dref;
+    }
+  }
+  return LBM_OK;
+}
+
+bool wall_band(const lbm_ctx* c, int k, const lbm_wall_desc* w, std::vector<int32_t>& band, std::string& err) {
+  const Geometry& g = c->geo[k];
+  const int64_t np = (int64_t)w->n_theta * w->n_z;
+  const int m = w->band_margin > 0 ? w->band_margin : 2;
+  std::vector<uint8_t> mark(g.ncell, 0);
+  for (int64_t p = 0; p < np; ++p) {
+    const double* X = w->X0_host + 3 * p;
+    int b[3];
+    const int n3[3] = {g.nx, g.ny, g.nz};
+    for (int a = 0; a < 3; ++a) {
+      if (!std::isfinite(X[a])) { err = "non-finite wall point"; return false; }
+      b[a] = (int)std::floor(X[a]) - 1;
+      if (b[a] < 0 || b[a] + 3 > n3[a] - 1) { err = "wall stencil touches the box faces"; return false; }
+    }
+    for (int z = std::max(0, b[2] - m); z <= std::min(g.nz - 1, b[2] + 3 + m); ++z)
+      for (int y = std::max(0, b[1] - m); y <= std::min(g.ny - 1, b[1] + 3 + m); ++y)
+        for (int x = std::max(0, b[0] - m); x <= std::min(g.nx - 1, b[0] + 3 + m); ++x)
+          mark[x + (int64_t)g.nx * (y + (int64_t)g.ny * z)] = 1;
+  }
+  band.clear();
+  for (int64_t cell = 0; cell < g.ncell; ++cell)
+    if (mark[cell] && (g.flags[cell] & TYPE_MASK) == T_FLUID) band.push_back((int32_t)cell);
+  return true;
+}
+
+struct FsiLayout {
+  size_t u4, b4, X0, Xa, Xb, slip, Vf, Fp, band, total;
+};
+FsiLayout fsi_plan(int64_t ncell, int64_t np, int64_t nband, int prec) {
+  FsiLayout f;
+  const size_t r4 = r4_size(prec);
+  size_t o = 0;
+  f.u4 = o; o = align256(o + ncell * r4);
+  f.b4 = o; o = align256(o + ncell * r4);
+  f.X0 = o; o = align256(o + np * 32);
+  f.Xa = o; o = align256(o + np * 32);
+  f.Xb = o; o = align256(o + np * 32);
+  f.slip = o; o = align256(o + np * 32);
+  f.Vf = o; o = align256(o + np * r4);
+  f.Fp = o; o = align256(o + np * r4);
+  f.band = o; o = align256(o + std::max<int64_t>(nband, 1) * 4);
+  f.total = o;
+  return f;
+}
+
+bool valid_wall(const lbm_wall_desc* w, std::string& err) {
+  if (!w || !w->X0_host) { err = "wall descriptor or X0 is NULL"; return false; }
+  if (w->n_theta < 3 || w->n_z < 2) { err = "wall mesh needs n_theta >= 3 and n_z >= 2"; return false; }
+  if (!(w->ds_theta > 0 && w->ds_z > 0 && w->area > 0 && w->mass > 0)) {
+    err = "wall spacings, area and mass must be positive";
+    return false;
+  }
+  return true;
+}
+
+}  // namespace
+
+// ===========================================================================
+extern "C" {
+
+lbm_status lbm_query_sizes(const lbm_config* cfgs, int32_t n, size_t* pop_bytes, size_t* work_bytes) {
+  if (!cfgs || n <= 0 || !pop_bytes || !work_bytes) return LBM_E_INVAL;
+  std::vector<Geometry> G(n);
+  for (int k = 0; k < n; ++k)
+    if (!build_geometry(cfgs[k], G[k], g_init_err)) return LBM_E_INVAL;
+  const int prec = cfgs[0].precision;
+  if (prec < 0 || prec > 3) return LBM_E_INVAL;
+  Layout L;
+  plan(G, prec, cfgs[0].wave_cap > 0 ? cfgs[0].wave_cap : 4096, L, nullptr, nullptr, nullptr, nullptr);
+  *pop_bytes = (size_t)NQ * L.NT * elem_size(prec);
+  *work_bytes = L.total;
+  return LBM_OK;
+}
+
+lbm_status lbm_init(const lbm_config* cfgs, int32_t n, const lbm_buffers* buf, void* hip_stream, lbm_ctx** out) {
+  if (!out) return LBM_E_INVAL;
+  *out = nullptr;
+  if (!cfgs || n <= 0 || !buf || !buf->pop || !buf->work) return LBM_E_INVAL;
+  lbm_ctx* c = new lbm_ctx();
+  c->n = n;
+  c->prec = cfgs[0].precision;
+  if (c->prec < 0 || c->prec > 3) { delete c; return LBM_E_INVAL; }
+  for (int k = 1; k < n; ++k)
+    if (cfgs[k].precision != c->prec) { delete c; return LBM_E_INVAL; }
+  c->geo.resize(n);
+  for (int k = 0; k < n; ++k)
+    if (!build_geometry(cfgs[k], c->geo[k], g_init_err)) { delete c; return LBM_E_INVAL; }
+  double s = cfgs[0].store_scale;
+  if (c->prec == 2 && s == 0.0) s = 256.0;
+  if (c->prec <= 1 || s == 0.0) s = 1.0;
+  int ex;
+  if (std::frexp(s, &ex) != 0.5) { delete c; return LBM_E_INVAL; }  // power of two only
+  c->scale = (float)s;
+  std::vector<int32_t> blk, lay;
+  std::vector<RedTab> red;
+  plan(c->geo, c->prec, cfgs[0].wave_cap > 0 ? cfgs[0].wave_cap : 4096, c->L, &c->inst, &blk, &lay, &red);
+  for (int k = 0; k < n; ++k) {
+    c->inst[k].tau = cfgs[k].tau;
+    c->inst[k].dref = 3.0 * cfgs[k].p_ref;
+  }
+  if (buf->pop_bytes < (size_t)NQ * c->L.NT * elem_size(c->prec) || buf->work_bytes < c->L.total) {
+    delete c;
+    return LBM_E_INVAL;
+  }
+  c->stream = (hipStream_t)hip_stream;
+  c->work = (char*)buf->work;
+  c->pop = buf->pop;
+  c->wall.resize(n);
+
+  Dev& d = c->dev;
+  std::memset(&d, 0, sizeof d);
+  d.pop = c->pop;
+  d.NT = c->L.NT;
+  d.scale = c->scale;
+  d.inv_scale = 1.0f / c->scale;
+  d.flags = (const uint8_t*)(c->work + c->L.flags);
+  d.inst = (const InstDesc*)(c->work + c->L.inst);
+  d.blk_inst = (const int32_t*)(c->work + c->L.blk_inst);
+  d.lay = (const int32_t*)(c->work + c->L.lay);
+  d.red = (const RedTab*)(c->work + c->L.red);
+  d.red_part = (double*)(c->work + c->L.red_part);
+  d.bc = (BcDev*)(c->work + c->L.bc);
+  d.st = (InstState*)(c->work + c->L.st);
+  d.wave = (double*)(c->work + c->L.wave);
+  d.wave_cap = c->L.wave_cap;
+  d.v0 = c->work + c->L.v0;
+  d.err = (uint32_t*)(c->work + c->L.err);
+  d.walls = (const int32_t*)(c->work + c->L.walls);
+  d.nwall = 0;
+
+  std::vector<uint8_t> flags(c->L.NT);
+  for (int k = 0; k < n; ++k)
+    std::memcpy(flags.data() + c->inst[k].cell0, c->geo[k].flags.data(), c->geo[k].ncell);
+  std::vector<BcDev> bc(3 * n);
+  for (int k = 0; k < 3 * n; ++k) {
+    std::memset(&bc[k], 0, sizeof(BcDev));
+    bc[k].kind = BC_PRESSURE;
+    bc[k].boundary = k % 3;
+    bc[k].Td = -1;
+  }
+  std::vector<InstState> st(n);
+  std::memset(st.data(), 0, n * sizeof(InstState));
+  // Tables go up with synchronous copies (init is not on the hot path, and
+  // the host vectors die with this call); then clear and fill on the stream.
+  auto up = [&](size_t off, const void* src, size_t bytes) -> hipError_t {
+    return bytes ? hipMemcpy(c->work + off, src, bytes, hipMemcpyHostToDevice) : hipSuccess;
+  };
+  hipError_t e = hipStreamSynchronize(c->stream);
+  const char* what = "hipStreamSynchronize";
+  if (e == hipSuccess) { e = up(c->L.flags, flags.data(), flags.size()); what = "flags upload"; }
+  if (e == hipSuccess) { e = up(c->L.inst, c->inst.data(), c->inst.size() * sizeof(InstDesc)); what = "instance upload"; }
+  if (e == hipSuccess) { e = up(c->L.blk_inst, blk.data(), blk.size() * 4); what = "block table upload"; }
+  if (e == hipSuccess) { e = up(c->L.lay, lay.data(), lay.size() * 4); what = "layer upload"; }
+  if (e == hipSuccess) { e = up(c->L.red, red.data(), red.size() * sizeof(RedTab)); what = "reduction table upload"; }
+  if (e == hipSuccess) { e = up(c->L.bc, bc.data(), bc.size() * sizeof(BcDev)); what = "0D state upload"; }
+  if (e == hipSuccess) { e = up(c->L.st, st.data(), st.size() * sizeof(InstState)); what = "step state upload"; }
+  if (e == hipSuccess) { e = hipMemset(c->work + c->L.err, 0, 4); what = "error flag clear"; }
+  if (e == hipSuccess) { e = hipMemset(c->work + c->L.v0, 0, (size_t)c->L.nv0 * r4_size(c->prec)); what = "snapshot clear"; }
+  if (e == hipSuccess) { e = hipMemset(c->work + c->L.wave, 0, (size_t)n * c->L.wave_cap * NREC * 8); what = "waveform clear"; }
+  for (int k = 0; k < n && e == hipSuccess; ++k) {
+    e = launch_fill_rest(d, c->prec, c->inst[k].cell0, c->inst[k].ncell, -c->inst[k].dref, c->stream);
+    what = "rest-state fill launch";
+  }
+  if (e != hipSuccess) {
+    g_init_err = std::string(what) + ": " + hipGetErrorString(e);
+    (void)hipStreamSynchronize(c->stream);
+    delete c;
+    return LBM_E_DEVICE;
+  }
+  *out = c;
+  return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_ctx* c, int64_t nsteps) {
+  if (!c) return LBM_E_INVAL;
+  if (nsteps < 0) return fail(c, LBM_E_INVAL, "nsteps < 0");
+  int64_t left = nsteps;
+  const bool graph = c->use_graph && !c->timing;
+  if (graph && left >= 2) {
+    if ((c->step & 1) && left > 0) {
+      HIPCHK(c, enqueue_step(c, 1, false));
+      c->step++;
+      left--;
+    }
+    if (!c->gexec && left >= 2) {
+      HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+      hipError_t e0 = enqueue_step(c, 0, false);
+      hipError_t e1 = enqueue_step(c, 1, false);
+      hipGraph_t gr = nullptr;
+      hipError_t e2 = hipStreamEndCapture(c->stream, &gr);
+      if (e0 != hipSuccess || e1 != hipSuccess || e2 != hipSuccess)
+        return fail(c, LBM_E_DEVICE, "graph capture failed");
+      c->graph = gr;
+      HIPCHK(c, hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+    }
+    while (left >= 2) {
+      HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
+      c->step += 2;
+      left -= 2;
+    }
+  }
+  while (left > 0) {
+    HIPCHK(c, enqueue_step(c, (int)(c->step & 1), c->timing));
+    c->step++;
+    left--;
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_couple_0d(lbm_ctx* c, int32_t inst, int32_t b, int32_t kind, const double* params, int32_t np,
+                         const double* state, int32_t nst) {
+  if (!c) return LBM_E_INVAL;
+  if (inst < 0 || inst >= c->n || b < 0 || b > 2) return fail(c, LBM_E_INVAL, "bad instance or boundary");
+  if (!params && np > 0) return fail(c, LBM_E_INVAL, "params NULL");
+  int need = kind == BC_PRESSURE || kind == BC_VELOCITY ? 1 : (kind == BC_WK3 ? 3 : (kind == BC_LV ? 11 : -1));
+  if (need < 0) return fail(c, LBM_E_INVAL, "unknown 0D kind");
+  if (np < need || np > 16) return fail(c, LBM_E_INVAL, "wrong number of 0D parameters");
+  if (kind == BC_LV && b != 0) return fail(c, LBM_E_INVAL, "the LV model couples to the inlet only");
+  if (kind == BC_WK3 && b == 2) return fail(c, LBM_E_INVAL, "the exterior takes constant models only");
+  if (kind == BC_WK3 && !(params[0] > 0 && params[1] > 0 && params[2] > 0))
+    return fail(c, LBM_E_INVAL, "Windkessel Rp, C, Rd must be positive");
+  if (kind == BC_LV && !(params[1] > 0 && params[2] > 0 && params[3] > 0 && params[5] > 0))
+    return fail(c, LBM_E_INVAL, "LV Emin, Tc, Tmax, N_S must be positive");
+  BcDev B;
+  std::memset(&B, 0, sizeof B);
+  B.kind = kind;
+  B.boundary = b;
+  for (int k = 0; k < np; ++k) B.par[k] = params[k];
+  B.Td = -1;
+  if (kind == BC_WK3) B.Pw = (state && nst > 0) ? state[0] : 0.0;
+  if (kind == BC_LV) B.Pv = (state && nst > 0) ? state[0] : params[4];
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipMemcpy(c->work + c->L.bc + (3 * (size_t)inst + b) * sizeof(BcDev), &B, sizeof B,
+                      hipMemcpyHostToDevice));
+  return LBM_OK;
+}
+
+lbm_status lbm_get_0d(lbm_ctx* c, int32_t inst, int32_t b, double* out) {
+  if (!c || !out || inst < 0 || inst >= c->n || b < 0 || b > 2) return LBM_E_INVAL;
+  BcDev B;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipMemcpy(&B, c->work + c->L.bc + (3 * (size_t)inst + b) * sizeof(BcDev), sizeof B,
+                      hipMemcpyDeviceToHost));
+  out[0] = B.vmode; out[1] = B.pstar; out[2] = B.S; out[3] = B.Pv;
+  out[4] = B.Pw; out[5] = B.open; out[6] = (double)B.Td; out[7] = B.vz;
+  return LBM_OK;
+}
+
+lbm_status lbm_fsi_query_sizes(lbm_ctx* c, int32_t k, const lbm_wall_desc* w, size_t* bytes) {
+  if (!c || !bytes || k < 0 || k >= c->n) return LBM_E_INVAL;
+  if (!valid_wall(w, c->err)) return LBM_E_INVAL;
+  std::vector<int32_t> band;
+  if (!wall_band(c, k, w, band, c->err)) return LBM_E_INVAL;
+  *bytes = fsi_plan(c->geo[k].ncell, (int64_t)w->n_theta * w->n_z, (int64_t)band.size(), c->prec).total;
+  return LBM_OK;
+}
+
+lbm_status lbm_fsi_exchange(lbm_ctx* c, int32_t k, const lbm_wall_desc* w, void* fsi, size_t fsi_bytes) {
+  if (!c || k < 0 || k >= c->n || !fsi) return LBM_E_INVAL;
+  if (!valid_wall(w, c->err)) return LBM_E_INVAL;
+  std::vector<int32_t> band;
+  if (!wall_band(c, k, w, band, c->err)) return LBM_E_INVAL;
+  Geometry& g = c->geo[k];
+  const int64_t np = (int64_t)w->n_theta * w->n_z;
+  const FsiLayout f = fsi_plan(g.ncell, np, (int64_t)band.size(), c->prec);
+  if (fsi_bytes < f.total) return fail(c, LBM_E_INVAL, "wall buffer too small");
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  drop_graph(c);
+  // band bits
+  for (auto& t : g.flags) t &= (uint8_t)~F_BAND;
+  for (int32_t cell : band) g.flags[cell] |= F_BAND;
+  char* F = (char*)fsi;
+  InstDesc& d = c->inst[k];
+  d.has_wall = 1;
+  d.nth = w->n_theta;
+  d.nzl = w->n_z;
+  d.np = np;
+  d.nband = (int32_t)band.size();
+  d.u4 = F + f.u4;
+  d.b4 = F + f.b4;
+  d.X0 = (double*)(F + f.X0);
+  d.Xab[0] = (double*)(F + f.Xa);
+  d.Xab[1] = (double*)(F + f.Xb);
+  d.slip = (double*)(F + f.slip);
+  d.Vf = F + f.Vf;
+  d.Fp = F + f.Fp;
+  d.band = (int32_t*)(F + f.band);
+  d.ds_th = w->ds_theta; d.ds_z = w->ds_z; d.area = w->area;
+  d.ks = w->k_stretch; d.ei = w->ei_bend; d.mass = w->mass; d.alpha = w->alpha; d.beta = w->beta;
+  std::vector<double> X4((size_t)np * 4, 0.0);
+  for (int64_t p = 0; p < np; ++p)
+    for (int a = 0; a < 3; ++a) X4[4 * p + a] = w->X0_host[3 * p + a];
+  HIPCHK(c, hipMemset(F, 0, f.total));  // displacements D^n = D^{n-1} = 0, slip 0, fields 0
+  HIPCHK(c, hipMemcpy(F + f.X0, X4.data(), X4.size() * 8, hipMemcpyHostToDevice));
+  if (!band.empty()) HIPCHK(c, hipMemcpy(F + f.band, band.data(), band.size() * 4, hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->work + c->L.flags + d.cell0, g.flags.data(), g.ncell, hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->work + c->L.inst + k * sizeof(InstDesc), &d, sizeof d, hipMemcpyHostToDevice));
+  c->wall[k].on = true;
+  c->wall[k].np = np;
+  c->wall[k].nband = d.nband;
+  c->walls.clear();
+  int maxb = 0;
+  int64_t maxp = 0;
+  for (int q = 0; q < c->n; ++q)
+    if (c->wall[q].on) {
+      c->walls.push_back(q);
+      maxb = std::max(maxb, c->wall[q].nband);
+      maxp = std::max(maxp, c->wall[q].np);
+    }
+  HIPCHK(c, hipMemcpy(c->work + c->L.walls, c->walls.data(), c->walls.size() * 4, hipMemcpyHostToDevice));
+  c->dev.nwall = (int32_t)c->walls.size();
+  c->dev.max_band = maxb;
+  c->dev.max_np = (int32_t)maxp;
+  return LBM_OK;
+}
+
+lbm_status lbm_read_wall(lbm_ctx* c, int32_t k, double* X, double* Xp, double* slip, double* Vf, double* Fp) {
+  if (!c || k < 0 || k >= c->n || !c->wall[k].on) return LBM_E_INVAL;
+  const InstDesc& d = c->inst[k];
+  const int64_t np = d.np;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  std::vector<double> tmp((size_t)np * 4);
+  auto get4 = [&](const void* src, double* dst) -> lbm_status {
+    if (!dst) return LBM_OK;
+    HIPCHK(c, hipMemcpy(tmp.data(), src, (size_t)np * 32, hipMemcpyDeviceToHost));
+    for (int64_t p = 0; p < np; ++p)
+      for (int a = 0; a < 3; ++a) dst[3 * p + a] = tmp[4 * p + a];
+    return LBM_OK;
+  };
+  auto getr4 = [&](const void* src, double* dst) -> lbm_status {
+    if (!dst) return LBM_OK;
+    if (c->prec == 0) return get4(src, dst);
+    std::vector<float> t((size_t)np * 4);
+    HIPCHK(c, hipMemcpy(t.data(), src, (size_t)np * 16, hipMemcpyDeviceToHost));
+    for (int64_t p = 0; p < np; ++p)
+      for (int a = 0; a < 3; ++a) dst[3 * p + a] = t[4 * p + a];
+    return LBM_OK;
+  };
+  const int par = (int)(c->step & 1);
+  std::vector<double> x0((size_t)np * 3);
+  lbm_status r;
+  if ((r = get4(d.X0, x0.data())) != LBM_OK) return r;
+  auto add_x0 = [&](double* dst) {
+    if (dst) for (size_t q = 0; q < x0.size(); ++q) dst[q] += x0[q];
+  };
+  if ((r = get4(d.Xab[par], X)) != LBM_OK || (r = get4(d.Xab[par ^ 1], Xp)) != LBM_OK ||
+      (r = get4(d.slip, slip)) != LBM_OK || (r = getr4(d.Vf, Vf)) != LBM_OK || (r = getr4(d.Fp, Fp)) != LBM_OK)
+    return r;
+  add_x0(X);
+  add_x0(Xp);
+  return LBM_OK;
+}
+
+lbm_status lbm_write_populations(lbm_ctx* c, int32_t k, const double* g) {
+  if (!c || !g || k < 0 || k >= c->n) return LBM_E_INVAL;
+  if (c->step & 1) return fail(c, LBM_E_STATE, "populations can only be written after an even number of steps");
+  const Geometry& geo = c->geo[k];
+  const InstDesc& d = c->inst[k];
+  const int es = elem_size(c->prec);
+  std::vector<char> raw((size_t)NQ * geo.ncell * es, 0);
+  for (int64_t cell = 0; cell < geo.ncell; ++cell) {
+    const bool fl = (geo.flags[cell] & TYPE_MASK) == T_FLUID;
+    for (int i = 0; i < NQ; ++i) {
+      const double v = fl ? g[(size_t)cell * NQ + i] - W[i] * d.dref : 0.0;
+      char* p = raw.data() + ((size_t)i * geo.ncell + cell) * es;
+      switch (c->prec) {
+        case 0: std::memcpy(p, &v, 8); break;
+        case 1: { float f = (float)v; std::memcpy(p, &f, 4); break; }
+        case 2: { uint16_t u = f32_to_f16_rne((float)v * c->scale); std::memcpy(p, &u, 2); break; }
+        default: { uint16_t u = f32_to_bf16_rne((float)v * c->scale); std::memcpy(p, &u, 2); break; }
+      }
+    }
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (int i = 0; i < NQ; ++i)
+    HIPCHK(c, hipMemcpy((char*)c->pop + ((size_t)i * c->L.NT + d.cell0) * es, raw.data() + (size_t)i * geo.ncell * es,
+                        (size_t)geo.ncell * es, hipMemcpyHostToDevice));
+  return LBM_OK;
+}
+
+lbm_status lbm_set_rest(lbm_ctx* c, int32_t k, double p) {
+  if (!c || k < 0 || k >= c->n) return LBM_E_INVAL;
+  if (c->step & 1) return fail(c, LBM_E_STATE, "rest state can only be set after an even number of steps");
+  HIPCHK(c, launch_fill_rest(c->dev, c->prec, c->inst[k].cell0, c->inst[k].ncell, 3.0 * p - c->inst[k].dref,
+                             c->stream));
+  return LBM_OK;
+}
+
+lbm_status lbm_read_populations(lbm_ctx* c, int32_t k, double* g) {
+  if (!c || !g || k < 0 || k >= c->n) return LBM_E_INVAL;
+  std::vector<double> v;
+  lbm_status r = read_pops(c, k, v);
+  if (r != LBM_OK) return r;
+  std::memcpy(g, v.data(), v.size() * 8);
+  return LBM_OK;
+}
+
+lbm_status lbm_read_fields(lbm_ctx* c, int32_t k, double* p, double* u) {
+  if (!c || k < 0 || k >= c->n) return LBM_E_INVAL;
+  std::vector<double> v;
+  lbm_status r = read_pops(c, k, v);
+  if (r != LBM_OK) return r;
+  const int64_t nc = c->geo[k].ncell;
+  for (int64_t cell = 0; cell < nc; ++cell) {
+    double s = 0, j[3] = {0, 0, 0};
+    for (int i = 0; i < NQ; ++i) {
+      const double g = v[(size_t)cell * NQ + i];
+      s += g;
+      j[0] += EXh[i] * g; j[1] += EYh[i] * g; j[2] += EZh[i] * g;
+    }
+    if (p) p[cell] = s / 3.0;
+    if (u) for (int a = 0; a < 3; ++a) u[3 * cell + a] = j[a];
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_read_waveforms(lbm_ctx* c, int32_t k, double* out, int64_t cap, int64_t* n) {
+  if (!c || !n || k < 0 || k >= c->n || cap < 0 || (!out && cap > 0)) return LBM_E_INVAL;
+  const int64_t W = c->L.wave_cap;
+  const int64_t have = std::min<int64_t>(c->step, W);
+  const int64_t cnt = std::min<int64_t>(have, cap);
+  *n = cnt;
+  if (cnt == 0) return LBM_OK;
+  std::vector<double> ring((size_t)W * NREC);
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipMemcpy(ring.data(), c->work + c->L.wave + (size_t)k * W * NREC * 8, ring.size() * 8,
+                      hipMemcpyDeviceToHost));
+  for (int64_t q = 0; q < cnt; ++q) {
+    const int64_t step = c->step - cnt + q;
+    std::memcpy(out + q * NREC, ring.data() + (step % W) * NREC, NREC * 8);
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_sync(lbm_ctx* c) {
+  if (!c) return LBM_E_INVAL;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  uint32_t e = 0;
+  HIPCHK(c, hipMemcpy(&e, c->work + c->L.err, 4, hipMemcpyDeviceToHost));
+  if (e & ERR_NONFINITE) return fail(c, LBM_E_UNSTABLE, "boundary flux or pressure became non-finite");
+  if (e & ERR_BAND) return fail(c, LBM_E_BAND, "a wall point left its band of cells");
+  return LBM_OK;
+}
+
+int64_t lbm_steps(const lbm_ctx* c) { return c ? c->step : -1; }
+
+lbm_status lbm_set_timing(lbm_ctx* c, int32_t on) {
+  if (!c) return LBM_E_INVAL;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  collect_times(c);
+  for (int k = 0; k < 4; ++k) { c->t_ms[k] = 0; c->t_launch[k] = 0; }
+  c->timing = on != 0;
+  return LBM_OK;
+}
+
+lbm_status lbm_kernel_time(lbm_ctx* c, int32_t kernel, int64_t* launches, double* ms) {
+  if (!c || kernel < 0 || kernel > 3 || !launches || !ms) return LBM_E_INVAL;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  collect_times(c);
+  *launches = c->t_launch[kernel];
+  *ms = c->t_ms[kernel];
+  return LBM_OK;
+}
+
+lbm_status lbm_set_graph(lbm_ctx* c, int32_t on) {
+  if (!c) return LBM_E_INVAL;
+  c->use_graph = on != 0;
+  return LBM_OK;
+}
+
+const char* lbm_last_error(const lbm_ctx* c) { return c ? c->err.c_str() : g_init_err.c_str(); }
+
+void lbm_destroy(lbm_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  collect_times(c);
+  for (auto& p : c->pool) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  drop_graph(c);
+  delete c;
+}
+
+int64_t lbm_num_cells(const lbm_ctx* c, int32_t k) {
+  if (!c || k < 0 || k >= c->n) return -1;
+  return c->geo[k].ncell;
+}
+
+int32_t lbm_bytes_per_population(const lbm_ctx* c) { return c ? elem_size(c->prec) : -1; }
+
+}  // extern "C"

@@ -1,0 +1,117 @@
+// lbm_internal.h -- device-side data layout of the gfx950 library (private).
+//
+// One context holds n instances (n = 1 for a single box).  Every per-cell
+// array is concatenated over the instances; the populations are one
+// structure-of-arrays block A[19][NT] (NT = total cells), updated in place with
+// the AA pattern: an even step reads and writes a cell's own slots (writing
+// direction i into slot opp(i)), an odd step reads from and writes to the
+// neighbours.  Everything a kernel needs about an instance sits in its
+// InstDesc, found from the block index through a block->instance table.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+constexpr int NQ = 19;
+constexpr int NREC = 12;          // doubles per waveform record
+constexpr int BLOCK = 256;        // collide-stream workgroup (4 wave64)
+constexpr int RBLOCK = 256;       // boundary-reduction workgroup
+constexpr int RCHUNK = 256;       // layer cells per reduction workgroup (one per lane)
+constexpr int WBLOCK = 256;       // wall / band workgroups
+
+enum : uint8_t { T_FLUID = 0, T_SOLID = 1, T_INLET = 2, T_OUTLET = 3, T_EXTP = 4 };
+constexpr uint8_t TYPE_MASK = 7;
+constexpr uint8_t F_NEAR = 8;     // FLUID cell with at least one non-FLUID neighbour
+constexpr uint8_t F_BAND = 16;    // FLUID cell inside a wall's band (may carry force)
+
+enum : int32_t { BC_PRESSURE = 0, BC_VELOCITY = 1, BC_WK3 = 2, BC_LV = 3 };
+enum : int32_t { VK_CONST = 0, VK_CORRECT = 1, VK_SNAPSHOT = 2 };
+
+enum : uint32_t { ERR_NONFINITE = 1u, ERR_BAND = 2u };
+
+// 0D boundary model: configuration, state, and what it hands the collide
+// kernel for the current step.
+struct BcDev {
+  int32_t kind, boundary;
+  double par[16];
+  double area;             // layer cells (flux -> mean velocity)
+  // state
+  double Pw, Pv;
+  int64_t Td, cycle;
+  int32_t open;
+  // output of the last update (valid for the step being taken)
+  int32_t vmode;           // 0 pressure type, 1 velocity type
+  int32_t vkind;           // VK_*
+  int32_t snap;            // 1 on the step the valve closes
+  double pstar;            // gauge P*
+  double dstar;            // 3 P* (shifted density target)
+  double vz;               // constant axial v*, or the axial correction dv
+  double S;                // smoothing factor (LV)
+};
+
+struct InstDesc {
+  int32_t nx, ny, nz;
+  int32_t blk0, nblk;      // collide-stream blocks [blk0, blk0 + nblk)
+  int32_t red0, nred;      // reduction blocks
+  int32_t lay_off[2], lay_n[2];   // inlet / outlet layer lists in the lay array
+  int64_t cell0, ncell;
+  int64_t v0_off;          // first entry of this instance's inlet snapshot (nx*ny)
+  double tau;
+  double dref;             // 3 p_ref: stored populations are g - w_i dref
+  // wall (has_wall = 0: none)
+  int32_t has_wall, nth, nzl, nband;
+  int64_t np;
+  void* u4;                // R4 per local cell: unforced velocity (band cells)
+  void* b4;                // R4 per local cell: IB force density (band cells)
+  double* X0;              // double4 per point
+  double* Xab[2];          // double4 per point, ping-pong D^n / D^{n-1}, D = X - X0
+  double* slip;            // double4 per point
+  void* Vf;                // R4 per point (last step, for read-back)
+  void* Fp;                // R4 per point (last step, for read-back)
+  int32_t* band;           // local cell ids of the band
+  double ds_th, ds_z, area, ks, ei, mass, alpha, beta;
+};
+
+struct InstState {
+  int64_t step;
+  uint32_t counter;        // finished reduction blocks of the current step
+  uint32_t pad;
+};
+
+struct RedTab {
+  int32_t inst, plane, start, count;
+};
+
+// Everything a launch needs (passed by value as the kernel argument).
+struct Dev {
+  void* pop;
+  int64_t NT;
+  float scale, inv_scale;          // 16-bit storage scale
+  const uint8_t* flags;
+  const InstDesc* inst;
+  const int32_t* blk_inst;         // collide block -> instance
+  const int32_t* lay;              // layer cell lists (local cell ids)
+  const RedTab* red;
+  double* red_part;                // 2 doubles per reduction block
+  BcDev* bc;                       // 3 per instance
+  InstState* st;
+  double* wave;                    // [inst][wave_cap][NREC]
+  int32_t wave_cap;
+  int32_t nwall;
+  void* v0;                        // R4 per snapshot entry
+  uint32_t* err;
+  const int32_t* walls;            // instance ids with a wall
+  int32_t max_band, max_np;
+};
+
+}  // namespace lbm
+
+// launchers (lbm_kernels.hip)
+namespace lbm {
+hipError_t launch_reduce(const Dev& d, int prec, int parity, int nred, hipStream_t s);
+hipError_t launch_collide(const Dev& d, int prec, int parity, int nblk, hipStream_t s);
+hipError_t launch_band(const Dev& d, int prec, int parity, hipStream_t s);
+hipError_t launch_wall(const Dev& d, int prec, int parity, hipStream_t s);
+hipError_t launch_fill_rest(const Dev& d, int prec, int64_t cell0, int64_t ncell, double dshift, hipStream_t s);
+}  // namespace lbm

@@ -1,0 +1,681 @@
+// lbm_kernels.hip -- gfx950 kernels of the 0D-3D coupled lattice Boltzmann
+// step (Wei, Amlani & Pahlevan, arXiv 2112.05258, Algorithm 1).
+//
+// Per step, on one stream:
+//   k_reduce    boundary layers: flux Q = sum j_z / sum f and mean gauge
+//               pressure (Sec. 2.1.2) in FP64, fixed-order tree reductions;
+//               the last workgroup of an instance advances its 0D models one
+//               forward-Euler step (Eqs. LVE, rightbc, rightQ, SmoothFunction)
+//               and writes the waveform record
+//   k_band      unforced velocity of the wall's band cells, clears the force
+//   k_wall      per wall point: interpolation (Eq. interpolation), penalty
+//               force (Eq. LagForce), spreading (Eq. EulForce), membrane
+//               forces (Eqs. tension, bending) and the time step of the wall
+//   k_collide   fused BGK collide-stream (Eqs. fi, feq, f, rho, v) in the AA
+//               in-place pattern with halfway bounce-back and the
+//               non-equilibrium extrapolation of Eq. Non-equilibrium3 at
+//               0D-coupled ghost nodes
+// The lattice work is HBM-bound (no contraction): one cell per lane,
+// 19 coalesced loads and 19 coalesced stores per cell.
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include "lbm_internal.h"
+
+namespace lbm {
+
+// D3Q19 in the interface order.
+__device__ constexpr int EX[NQ] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+__device__ constexpr int EY[NQ] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+__device__ constexpr int EZ[NQ] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+__device__ constexpr int OPP[NQ] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
+
+template <class R>
+__device__ __forceinline__ R wgt(int i) {
+  return i == 0 ? R(1) / R(3) : (i < 7 ? R(1) / R(18) : R(1) / R(36));
+}
+
+// ---------------------------------------------------------------------------
+// storage types: value stored = scale * g (scale used by the 16-bit modes)
+// ---------------------------------------------------------------------------
+template <class S> struct Store;
+template <> struct Store<double> {
+  using R = double;
+  __device__ static R ld(const double* p, float) { return *p; }
+  __device__ static void st(double* p, R v, float) { *p = v; }
+};
+template <> struct Store<float> {
+  using R = float;
+  __device__ static R ld(const float* p, float) { return *p; }
+  __device__ static void st(float* p, R v, float) { *p = v; }
+};
+template <> struct Store<__half> {
+  using R = float;
+  __device__ static R ld(const __half* p, float inv) { return __half2float(*p) * inv; }
+  __device__ static void st(__half* p, R v, float s) { *p = __float2half_rn(v * s); }
+};
+template <> struct Store<__hip_bfloat16> {
+  using R = float;
+  __device__ static R ld(const __hip_bfloat16* p, float inv) { return __bfloat162float(*p) * inv; }
+  __device__ static void st(__hip_bfloat16* p, R v, float s) { *p = __float2bfloat16(v * s); }
+};
+
+template <class R> struct V4;
+template <> struct V4<float> { using T = float4; };
+template <> struct V4<double> { using T = double4; };
+
+__device__ __forceinline__ void dir_offsets(int64_t sy, int64_t sz, int64_t off[NQ]) {
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) off[i] = EX[i] + EY[i] * sy + EZ[i] * sz;
+}
+
+// Populations of cell c at the current step (parity = step & 1), AA layout:
+// even: g_i = A[i][c]; odd: g_i = A[opp i][c - e_i], or A[i][c] when c - e_i
+// is SOLID (the bounce-back slot written by c itself).
+template <class S, bool ODD>
+__device__ __forceinline__ void load_cell(const S* __restrict__ A, int64_t NT, const uint8_t* __restrict__ flags,
+                                          int64_t c, bool near, const int64_t off[NQ], float inv,
+                                          typename Store<S>::R g[NQ]) {
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) {
+    if (!ODD) {
+      g[i] = Store<S>::ld(A + i * NT + c, inv);
+    } else {
+      const bool bb = near && i != 0 && ((flags[c - off[i]] & TYPE_MASK) == T_SOLID);
+      g[i] = bb ? Store<S>::ld(A + i * NT + c, inv) : Store<S>::ld(A + OPP[i] * NT + c - off[i], inv);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 0D models (FP64, one thread per boundary)
+// ---------------------------------------------------------------------------
+__device__ double smooth_S(double t, double t0, double L) {
+  if (t < t0) return 1.0;
+  if (t >= t0 + L) return 0.0;
+  const double u = (t - t0) / L;
+  return exp(2.0 * exp(-1.0 / u) / (u - 1.0));
+}
+
+// Double-Hill elastance and its time derivative at time t (steps) in the beat.
+__device__ void elastance(const double* p, double t, double& E, double& dE) {
+  const double tn = t / p[3];
+  const double x1 = tn / p[7], x2 = tn / p[9];
+  const double a = pow(x1, p[8]), b = pow(x2, p[10]);
+  const double h1 = a / (1.0 + a), h2 = 1.0 / (1.0 + b);
+  double dh1 = 0.0, dh2 = 0.0;
+  if (tn > 0.0) {
+    dh1 = p[8] * a / (x1 * p[7]) / ((1.0 + a) * (1.0 + a));
+    dh2 = -p[10] * b / (x2 * p[9]) / ((1.0 + b) * (1.0 + b));
+  }
+  const double amp = (p[0] - p[1]) * p[6];
+  E = amp * h1 * h2 + p[1];
+  dE = amp * (dh1 * h2 + h1 * dh2) / p[3];
+}
+
+__device__ void zerod_update(BcDev& b, int64_t n, double Qp, double Pbar) {
+  b.snap = 0;
+  switch (b.kind) {
+    case BC_PRESSURE:
+      b.vmode = 0;
+      b.pstar = b.par[0];
+      break;
+    case BC_VELOCITY:
+      b.vmode = 1;
+      b.vkind = VK_CONST;
+      b.vz = b.par[0];
+      break;
+    case BC_WK3: {
+      const double Z = b.par[0], C = b.par[1], R = b.par[2];
+      if (b.par[3] == 0.0) {
+        // flux-driven: C dPw/dt = Q - Pw/R, P* = Pw + Z Q
+        const double Q = b.boundary == 0 ? -Qp : Qp;
+        b.Pw += (Q - b.Pw / R) / C;
+        b.vmode = 0;
+        b.pstar = b.Pw + Z * Q;
+      } else {
+        // pressure-driven: C dPw/dt = (P - Pw)/Z - Pw/R, outflow (P - Pw)/Z
+        b.Pw += ((Pbar - b.Pw) / Z - b.Pw / R) / C;
+        const double Q = (Pbar - b.Pw) / Z;
+        const double want = b.boundary == 0 ? -Q : Q;
+        b.vmode = 1;
+        b.vkind = VK_CORRECT;
+        b.vz = (want - Qp) / (b.area > 0.0 ? b.area : 1.0);
+      }
+      break;
+    }
+    case BC_LV: {
+      const double* p = b.par;
+      const int64_t cyc = (int64_t)floor((double)n / p[2]);
+      if (cyc != b.cycle) {
+        b.cycle = cyc;
+        b.Pv = p[4];
+        b.open = 0;
+        b.Td = -1;
+      }
+      double E, dE;
+      elastance(p, (double)n - (double)cyc * p[2], E, dE);
+      if (b.open && Qp < 0.0) {
+        b.open = 0;
+        b.Td = n;
+        b.snap = 1;
+      } else if (!b.open && b.Td < 0 && b.Pv > Pbar) {
+        b.open = 1;
+      }
+      const double Q = b.open ? Qp : 0.0;
+      // dPv/dt = -(C' Pv + Q)/C with C = 1/E  <=>  dPv/dt = (E'/E) Pv - E Q
+      b.Pv += (dE / E) * b.Pv - E * Q;
+      if (b.open) {
+        b.vmode = 0;
+        b.pstar = b.Pv;
+      } else {
+        b.vmode = 1;
+        b.vkind = VK_SNAPSHOT;
+        b.S = b.Td < 0 ? 0.0 : smooth_S((double)(n + 1), (double)b.Td, p[5]);
+      }
+      break;
+    }
+    default:
+      break;
+  }
+  b.dstar = 3.0 * b.pstar;
+}
+
+// ---------------------------------------------------------------------------
+// k_reduce: layer flux / pressure, then (last block) the 0D update
+// ---------------------------------------------------------------------------
+template <class S, bool ODD>
+__global__ __launch_bounds__(RBLOCK) void k_reduce(Dev d) {
+  using R = typename Store<S>::R;
+  __shared__ double sq[RBLOCK], sp[RBLOCK];
+  __shared__ int last;
+  const RedTab t = d.red[blockIdx.x];
+  const InstDesc& I = d.inst[t.inst];
+  const int64_t sy = I.nx, sz = (int64_t)I.nx * I.ny;
+  int64_t off[NQ];
+  dir_offsets(sy, sz, off);
+  const S* A = (const S*)d.pop;
+  double q = 0.0, ps = 0.0;
+  for (int k = threadIdx.x; k < t.count; k += RBLOCK) {
+    const int64_t c = I.cell0 + d.lay[I.lay_off[t.plane] + t.start + k];
+    const bool near = d.flags[c] & F_NEAR;
+    R g[NQ];
+    load_cell<S, ODD>(A, d.NT, d.flags, c, near, off, d.inv_scale, g);
+    double s = I.dref, jz = 0.0;
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+      s += (double)g[i];
+      jz += EZ[i] * (double)g[i];
+    }
+    q += jz / (1.0 + s);
+    ps += s / 3.0;
+  }
+  sq[threadIdx.x] = q;
+  sp[threadIdx.x] = ps;
+  __syncthreads();
+  for (int w = RBLOCK / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      sq[threadIdx.x] += sq[threadIdx.x + w];
+      sp[threadIdx.x] += sp[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    d.red_part[2 * blockIdx.x] = sq[0];
+    d.red_part[2 * blockIdx.x + 1] = sp[0];
+    InstState* st = d.st + t.inst;
+    const uint32_t done =
+        __hip_atomic_fetch_add(&st->counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    last = (done == (uint32_t)(I.nred - 1));
+  }
+  __syncthreads();
+  if (!last || threadIdx.x != 0) return;
+
+  // ---- last block of this instance: finish the sums in a fixed order ----
+  InstState* st = d.st + t.inst;
+  double Q[2] = {0.0, 0.0}, P[2] = {0.0, 0.0};
+  for (int b = I.red0; b < I.red0 + I.nred; ++b) {
+    const RedTab tb = d.red[b];
+    Q[tb.plane] += __hip_atomic_load(&d.red_part[2 * b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    P[tb.plane] += __hip_atomic_load(&d.red_part[2 * b + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  for (int pl = 0; pl < 2; ++pl) P[pl] = I.lay_n[pl] ? P[pl] / (double)I.lay_n[pl] : 0.0;
+  if (!isfinite(Q[0]) || !isfinite(Q[1]) || !isfinite(P[0]) || !isfinite(P[1]))
+    atomicOr(d.err, ERR_NONFINITE);
+  const int64_t n = st->step;
+  BcDev* bc = d.bc + 3 * t.inst;
+  bc[0].area = (double)I.lay_n[0];
+  bc[1].area = (double)I.lay_n[1];
+  zerod_update(bc[0], n, Q[0], P[0]);
+  zerod_update(bc[1], n, Q[1], P[1]);
+  zerod_update(bc[2], n, 0.0, 0.0);
+  double* r = d.wave + ((int64_t)t.inst * d.wave_cap + (n % d.wave_cap)) * NREC;
+  r[0] = (double)n;
+  r[1] = Q[0]; r[2] = P[0]; r[3] = Q[1]; r[4] = P[1];
+  r[5] = bc[0].vmode;
+  r[6] = bc[0].vmode == 0 ? bc[0].pstar : (bc[0].kind == BC_LV ? bc[0].S : bc[0].vz);
+  r[7] = bc[1].vmode;
+  r[8] = bc[1].vmode == 0 ? bc[1].pstar : bc[1].vz;
+  r[9] = bc[0].kind == BC_LV ? bc[0].Pv : 0.0;
+  r[10] = bc[1].kind == BC_WK3 ? bc[1].Pw : 0.0;
+  r[11] = bc[0].kind == BC_LV ? (double)bc[0].open : 0.0;
+  st->step = n + 1;
+  __hip_atomic_store(&st->counter, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---------------------------------------------------------------------------
+// k_collide: fused collide-stream
+// ---------------------------------------------------------------------------
+
+// g_eq(delta, v*) - g_eq(delta, v) for the velocity-type coupling.
+template <class R>
+__device__ __forceinline__ R deq_velocity(int i, R vx, R vy, R vz, R sx, R sy, R sz) {
+  const R eu = EX[i] * vx + EY[i] * vy + EZ[i] * vz;
+  const R es = EX[i] * sx + EY[i] * sy + EZ[i] * sz;
+  const R uu = vx * vx + vy * vy + vz * vz;
+  const R ss = sx * sx + sy * sy + sz * sz;
+  return wgt<R>(i) * (R(3) * (es - eu) + R(4.5) * (es * es - eu * eu) - R(1.5) * (ss - uu));
+}
+
+template <class S, bool ODD>
+__global__ __launch_bounds__(BLOCK) void k_collide(Dev d) {
+  using R = typename Store<S>::R;
+  using R4 = typename V4<R>::T;
+  const int inst = d.blk_inst[blockIdx.x];
+  const InstDesc& I = d.inst[inst];
+  const int64_t local = (int64_t)(blockIdx.x - I.blk0) * BLOCK + threadIdx.x;
+  if (local >= I.ncell) return;
+  const int64_t c = I.cell0 + local;
+  const uint8_t fl = d.flags[c];
+  if ((fl & TYPE_MASK) != T_FLUID) return;
+  const int64_t sy = I.nx, sz = (int64_t)I.nx * I.ny;
+  const int64_t NT = d.NT;
+  int64_t off[NQ];
+  dir_offsets(sy, sz, off);
+  S* __restrict__ A = (S*)d.pop;
+  const bool near = fl & F_NEAR;
+
+  R g[NQ];
+  load_cell<S, ODD>(A, NT, d.flags, c, near, off, d.inv_scale, g);
+
+  // moments (Eqs. rho, v): dl = sum g - dref (= delta - 3 p_ref), j = sum e g
+  R dl = 0, jx = 0, jy = 0, jz = 0;
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) {
+    dl += g[i];
+    jx += EX[i] * g[i];
+    jy += EY[i] * g[i];
+    jz += EZ[i] * g[i];
+  }
+  R bx = 0, by = 0, bz = 0;
+  const bool band = fl & F_BAND;
+  if (band) {
+    const R4 b = ((const R4*)I.b4)[local];
+    bx = b.x; by = b.y; bz = b.z;
+  }
+  const R vx = jx + R(0.5) * bx, vy = jy + R(0.5) * by, vz = jz + R(0.5) * bz;
+  const R uu = vx * vx + vy * vy + vz * vz;
+  const R om = R(1) / R(I.tau);
+  const R cf = R(1) - R(0.5) * om;
+  const R vb = vx * bx + vy * by + vz * bz;
+
+  // collision (Eqs. fi, feq, f)
+  R gs[NQ];
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) {
+    const R eu = EX[i] * vx + EY[i] * vy + EZ[i] * vz;
+    const R geq = wgt<R>(i) * (dl + R(3) * eu + R(4.5) * eu * eu - R(1.5) * uu);
+    R v = g[i] - om * (g[i] - geq);
+    if (band) {
+      const R eb = EX[i] * bx + EY[i] * by + EZ[i] * bz;
+      v += cf * wgt<R>(i) * (R(3) * (eb - vb) + R(9) * eu * eb);
+    }
+    gs[i] = v;
+  }
+
+  // source cell types (only cells next to walls or ghosts look)
+  uint8_t nt[NQ];
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) nt[i] = T_FLUID;
+  if (near) {
+#pragma unroll
+    for (int i = 1; i < NQ; ++i) nt[i] = d.flags[c - off[i]] & TYPE_MASK;
+  }
+
+  // streaming
+  if (!ODD) {
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) Store<S>::st(A + OPP[i] * NT + c, gs[i], d.scale);
+  } else {
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+      const uint8_t td = nt[OPP[i]];  // type of c + e_i
+      if (td == T_FLUID) Store<S>::st(A + i * NT + c + off[i], gs[i], d.scale);
+      else if (td == T_SOLID) Store<S>::st(A + OPP[i] * NT + c, gs[i], d.scale);
+    }
+  }
+
+  // non-equilibrium extrapolation: the ghost x = c - e_i hands c the value
+  // g*_i(c) + g_eq(P*, v*) - g_eq(P(c), v(c))  (Eq. Non-equilibrium3, x_f = c)
+  if (near) {
+    R4 v0 = {0, 0, 0, 0};
+    bool have_v0 = false;
+#pragma unroll
+    for (int i = 1; i < NQ; ++i) {
+      if (nt[i] < T_INLET) continue;
+      const BcDev& B = d.bc[3 * inst + (nt[i] - T_INLET)];
+      R out;
+      if (B.vmode == 0) {
+        out = gs[i] + wgt<R>(i) * (R(B.dstar - I.dref) - dl);
+      } else {
+        R sx, s_y, s_z;
+        if (B.vkind == VK_SNAPSHOT) {
+          if (!have_v0) {
+            R4* vp = (R4*)d.v0 + I.v0_off + (local % sz);
+            if (B.snap) {
+              v0 = R4{jx, jy, jz, R(0)};
+              *vp = v0;
+            } else {
+              v0 = *vp;
+            }
+            have_v0 = true;
+          }
+          const R Sf = R(B.S);
+          sx = v0.x * Sf; s_y = v0.y * Sf; s_z = v0.z * Sf;
+        } else if (B.vkind == VK_CORRECT) {
+          sx = vx; s_y = vy; s_z = vz + R(B.vz);
+        } else {
+          sx = 0; s_y = 0; s_z = R(B.vz);
+        }
+        out = gs[i] + deq_velocity<R>(i, vx, vy, vz, sx, s_y, s_z);
+      }
+      if (!ODD) Store<S>::st(A + OPP[i] * NT + c - off[i], out, d.scale);
+      else Store<S>::st(A + i * NT + c, out, d.scale);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_band: unforced velocity of band cells, force cleared
+// ---------------------------------------------------------------------------
+template <class S, bool ODD>
+__global__ __launch_bounds__(WBLOCK) void k_band(Dev d) {
+  using R = typename Store<S>::R;
+  using R4 = typename V4<R>::T;
+  const int inst = d.walls[blockIdx.y];
+  const InstDesc& I = d.inst[inst];
+  const int k = blockIdx.x * WBLOCK + threadIdx.x;
+  if (k >= I.nband) return;
+  const int64_t lc = I.band[k];
+  const int64_t c = I.cell0 + lc;
+  int64_t off[NQ];
+  dir_offsets(I.nx, (int64_t)I.nx * I.ny, off);
+  R g[NQ];
+  load_cell<S, ODD>((const S*)d.pop, d.NT, d.flags, c, d.flags[c] & F_NEAR, off, d.inv_scale, g);
+  R jx = 0, jy = 0, jz = 0;
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) {
+    jx += EX[i] * g[i];
+    jy += EY[i] * g[i];
+    jz += EZ[i] * g[i];
+  }
+  ((R4*)I.u4)[lc] = R4{jx, jy, jz, R(0)};
+  ((R4*)I.b4)[lc] = R4{0, 0, 0, 0};
+}
+
+// ---------------------------------------------------------------------------
+// k_wall: one lane per wall point
+// ---------------------------------------------------------------------------
+template <class R>
+__device__ __forceinline__ R phi4(R r) {
+  r = fabs(r);
+  if (r <= R(1)) return (R(3) - R(2) * r + sqrt(R(1) + R(4) * r - R(4) * r * r)) * R(0.125);
+  if (r < R(2)) return (R(5) - R(2) * r - sqrt(R(-7) + R(12) * r - R(4) * r * r)) * R(0.125);
+  return R(0);
+}
+
+__device__ __forceinline__ double3 ld3(const double* p, int64_t k) {
+  const double4 v = ((const double4*)p)[k];
+  return make_double3(v.x, v.y, v.z);
+}
+
+// tension vector T D0 X on a half edge with edge vector e (Eq. tension)
+__device__ __forceinline__ double3 tension(double3 e, double ds, double ks) {
+  const double dx = e.x / ds, dy = e.y / ds, dz = e.z / ds;
+  const double T = ks * (sqrt(dx * dx + dy * dy + dz * dz) - 1.0);
+  return make_double3(T * dx, T * dy, T * dz);
+}
+
+template <class R>
+__global__ __launch_bounds__(WBLOCK) void k_wall(Dev d, int parity) {
+  using R4 = typename V4<R>::T;
+  const int inst = d.walls[blockIdx.y];
+  const InstDesc& I = d.inst[inst];
+  const int64_t p = (int64_t)blockIdx.x * WBLOCK + threadIdx.x;
+  if (p >= I.np) return;
+  // the wall is carried as displacement D = X - X0 (ping-pong D^n / D^{n-1})
+  const double* Dc = I.Xab[parity];
+  double* Dn = I.Xab[parity ^ 1];
+  const double3 X0 = ld3(I.X0, p), D = ld3(Dc, p), Dm = ld3(Dn, p);
+
+  // interpolation of the unforced velocity over the 4x4x4 stencil
+  const int bx0 = (int)floor(X0.x + D.x) - 1, by0 = (int)floor(X0.y + D.y) - 1, bz0 = (int)floor(X0.z + D.z) - 1;
+  R wx[4], wy[4], wz[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    wx[a] = phi4<R>((R)(((double)(bx0 + a) - X0.x) - D.x));
+    wy[a] = phi4<R>((R)(((double)(by0 + a) - X0.y) - D.y));
+    wz[a] = phi4<R>((R)(((double)(bz0 + a) - X0.z) - D.z));
+  }
+  const R4* U = (const R4*)I.u4;
+  R Vx = 0, Vy = 0, Vz = 0;
+  bool outside = false;
+  for (int cz = 0; cz < 4; ++cz) {
+    const int z = bz0 + cz;
+    if (z < 0 || z >= I.nz) continue;
+    for (int cy = 0; cy < 4; ++cy) {
+      const int y = by0 + cy;
+      if (y < 0 || y >= I.ny) continue;
+      const R wyz = wy[cy] * wz[cz];
+      for (int cx = 0; cx < 4; ++cx) {
+        const int x = bx0 + cx;
+        if (x < 0 || x >= I.nx) continue;
+        const int64_t lc = x + (int64_t)I.nx * (y + (int64_t)I.ny * z);
+        const uint8_t f = d.flags[I.cell0 + lc];
+        if ((f & TYPE_MASK) != T_FLUID) continue;
+        const R w = wx[cx] * wyz;
+        if (!(f & F_BAND)) {
+          if (w != R(0)) outside = true;
+          continue;
+        }
+        const R4 u = U[lc];
+        Vx += u.x * w; Vy += u.y * w; Vz += u.z * w;
+      }
+    }
+  }
+  if (outside) atomicOr(d.err, ERR_BAND);
+
+  // penalty force on the fluid (Eq. LagForce): alpha int (Vf - Vs) + beta (Vf - Vs)
+  const double dxv = (double)Vx - (D.x - Dm.x);
+  const double dyv = (double)Vy - (D.y - Dm.y);
+  const double dzv = (double)Vz - (D.z - Dm.z);
+  double4* SL = (double4*)I.slip;
+  double4 sl = SL[p];
+  sl.x += dxv; sl.y += dyv; sl.z += dzv;
+  SL[p] = sl;
+  const double Fx = I.alpha * sl.x + I.beta * dxv;
+  const double Fy = I.alpha * sl.y + I.beta * dyv;
+  const double Fz = I.alpha * sl.z + I.beta * dzv;
+  ((R4*)I.Vf)[p] = R4{Vx, Vy, Vz, R(0)};
+  ((R4*)I.Fp)[p] = R4{(R)Fx, (R)Fy, (R)Fz, R(0)};
+
+  // spreading (Eq. EulForce): b(node) += F area delta
+  R* B = (R*)I.b4;
+  const R fx = (R)(Fx * I.area), fy = (R)(Fy * I.area), fz = (R)(Fz * I.area);
+  for (int cz = 0; cz < 4; ++cz) {
+    const int z = bz0 + cz;
+    if (z < 0 || z >= I.nz) continue;
+    for (int cy = 0; cy < 4; ++cy) {
+      const int y = by0 + cy;
+      if (y < 0 || y >= I.ny) continue;
+      const R wyz = wy[cy] * wz[cz];
+      for (int cx = 0; cx < 4; ++cx) {
+        const int x = bx0 + cx;
+        if (x < 0 || x >= I.nx) continue;
+        const int64_t lc = x + (int64_t)I.nx * (y + (int64_t)I.ny * z);
+        const uint8_t f = d.flags[I.cell0 + lc];
+        if ((f & TYPE_MASK) != T_FLUID || !(f & F_BAND)) continue;
+        const R w = wx[cx] * wyz;
+        if (w == R(0)) continue;
+        atomicAdd(B + 4 * lc + 0, fx * w);
+        atomicAdd(B + 4 * lc + 1, fy * w);
+        atomicAdd(B + 4 * lc + 2, fz * w);
+      }
+    }
+  }
+
+  // membrane forces (Eqs. tension and bending along theta and z)
+  const int nth = I.nth, nzl = I.nzl;
+  const int j = (int)(p % nth), k = (int)(p / nth);
+  auto P = [&](int jj, int kk) -> int64_t { return (int64_t)((jj % nth + nth) % nth) + (int64_t)nth * kk; };
+  // edge vector X_b - X_a = (X0_b - X0_a) + (D_b - D_a)
+  auto edge = [&](int64_t a, int64_t b) -> double3 {
+    const double3 xa = ld3(I.X0, a), xb = ld3(I.X0, b), da = ld3(Dc, a), db = ld3(Dc, b);
+    return make_double3((xb.x - xa.x) + (db.x - da.x), (xb.y - xa.y) + (db.y - da.y),
+                        (xb.z - xa.z) + (db.z - da.z));
+  };
+  const double dt2 = I.ds_th * I.ds_th, dz2 = I.ds_z * I.ds_z;
+  double3 f = make_double3(0.0, 0.0, 0.0);
+  {
+    const double3 tp = tension(edge(p, P(j + 1, k)), I.ds_th, I.ks);
+    const double3 tm = tension(edge(P(j - 1, k), p), I.ds_th, I.ks);
+    f.x += (tp.x - tm.x) / I.ds_th; f.y += (tp.y - tm.y) / I.ds_th; f.z += (tp.z - tm.z) / I.ds_th;
+    const double3 y2m = ld3(Dc, P(j - 2, k)), y1m = ld3(Dc, P(j - 1, k)), y0 = D, y1p = ld3(Dc, P(j + 1, k)),
+                  y2p = ld3(Dc, P(j + 2, k));
+    // curvature at j-1, j, j+1, then its second difference
+    const double kmx = (y0.x - 2.0 * y1m.x + y2m.x) / dt2, kcx = (y1p.x - 2.0 * y0.x + y1m.x) / dt2,
+                 kpx = (y2p.x - 2.0 * y1p.x + y0.x) / dt2;
+    const double kmy = (y0.y - 2.0 * y1m.y + y2m.y) / dt2, kcy = (y1p.y - 2.0 * y0.y + y1m.y) / dt2,
+                 kpy = (y2p.y - 2.0 * y1p.y + y0.y) / dt2;
+    const double kmz = (y0.z - 2.0 * y1m.z + y2m.z) / dt2, kcz = (y1p.z - 2.0 * y0.z + y1m.z) / dt2,
+                 kpz = (y2p.z - 2.0 * y1p.z + y0.z) / dt2;
+    f.x -= I.ei * (kpx - 2.0 * kcx + kmx) / dt2;
+    f.y -= I.ei * (kpy - 2.0 * kcy + kmy) / dt2;
+    f.z -= I.ei * (kpz - 2.0 * kcz + kmz) / dt2;
+  }
+  const bool interior = k > 0 && k < nzl - 1;
+  if (interior) {
+    const double3 tp = tension(edge(p, P(j, k + 1)), I.ds_z, I.ks);
+    const double3 tm = tension(edge(P(j, k - 1), p), I.ds_z, I.ks);
+    f.x += (tp.x - tm.x) / I.ds_z; f.y += (tp.y - tm.y) / I.ds_z; f.z += (tp.z - tm.z) / I.ds_z;
+    // curvature along z, zero on the end rings (simply supported)
+    auto kap = [&](int kk) -> double3 {
+      if (kk <= 0 || kk >= nzl - 1) return make_double3(0.0, 0.0, 0.0);
+      const double3 a = ld3(Dc, P(j, kk - 1)), b = ld3(Dc, P(j, kk)), c = ld3(Dc, P(j, kk + 1));
+      return make_double3((c.x - 2.0 * b.x + a.x) / dz2, (c.y - 2.0 * b.y + a.y) / dz2,
+                          (c.z - 2.0 * b.z + a.z) / dz2);
+    };
+    const double3 km = kap(k - 1), kc = kap(k), kp = kap(k + 1);
+    f.x -= I.ei * (kp.x - 2.0 * kc.x + km.x) / dz2;
+    f.y -= I.ei * (kp.y - 2.0 * kc.y + km.y) / dz2;
+    f.z -= I.ei * (kp.z - 2.0 * kc.z + km.z) / dz2;
+  }
+
+  // central difference in time; the wall receives -F
+  double4 out;
+  if (interior) {
+    out.x = 2.0 * D.x - Dm.x + (f.x - Fx) / I.mass;
+    out.y = 2.0 * D.y - Dm.y + (f.y - Fy) / I.mass;
+    out.z = 2.0 * D.z - Dm.z + (f.z - Fz) / I.mass;
+  } else {
+    out.x = D.x; out.y = D.y; out.z = D.z;
+  }
+  out.w = 0.0;
+  ((double4*)Dn)[p] = out;
+}
+
+// ---------------------------------------------------------------------------
+// rest state fill: stored g = w_i dshift (dshift = 3 p - dref)
+// ---------------------------------------------------------------------------
+template <class S>
+__global__ void k_fill_rest(Dev d, int64_t cell0, int64_t ncell, double dshift) {
+  using R = typename Store<S>::R;
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= ncell) return;
+  const int64_t c = cell0 + k;
+  const bool fl = (d.flags[c] & TYPE_MASK) == T_FLUID;
+  S* A = (S*)d.pop;
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) Store<S>::st(A + i * d.NT + c, fl ? (R)(wgt<double>(i) * dshift) : R(0), d.scale);
+}
+
+// ---------------------------------------------------------------------------
+// launchers: hipLaunchKernel returns the launch status itself, so a stale
+// error left in the thread by an unrelated runtime call is never reported.
+// ---------------------------------------------------------------------------
+namespace {
+template <class... P>
+hipError_t launch(void (*k)(P...), dim3 g, dim3 b, hipStream_t s, P... a) {
+  void* args[] = {(void*)&a...};
+  return hipLaunchKernel((const void*)k, g, b, args, 0, s);
+}
+}  // namespace
+
+#define LBM_DISPATCH(prec, F)                     \
+  switch (prec) {                                 \
+    case 0: F(double); break;                     \
+    case 1: F(float); break;                      \
+    case 2: F(__half); break;                     \
+    case 3: F(__hip_bfloat16); break;             \
+    default: return hipErrorInvalidValue;         \
+  }
+
+hipError_t launch_reduce(const Dev& d, int prec, int parity, int nred, hipStream_t s) {
+  if (nred <= 0) return hipSuccess;
+#define F(T)                                                                              \
+  return parity ? launch(k_reduce<T, true>, dim3(nred), dim3(RBLOCK), s, Dev(d))          \
+                : launch(k_reduce<T, false>, dim3(nred), dim3(RBLOCK), s, Dev(d));
+  LBM_DISPATCH(prec, F)
+#undef F
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_collide(const Dev& d, int prec, int parity, int nblk, hipStream_t s) {
+  if (nblk <= 0) return hipSuccess;
+#define F(T)                                                                              \
+  return parity ? launch(k_collide<T, true>, dim3(nblk), dim3(BLOCK), s, Dev(d))          \
+                : launch(k_collide<T, false>, dim3(nblk), dim3(BLOCK), s, Dev(d));
+  LBM_DISPATCH(prec, F)
+#undef F
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_band(const Dev& d, int prec, int parity, hipStream_t s) {
+  if (d.nwall <= 0 || d.max_band <= 0) return hipSuccess;
+  const dim3 grid((d.max_band + WBLOCK - 1) / WBLOCK, d.nwall);
+#define F(T)                                                                              \
+  return parity ? launch(k_band<T, true>, grid, dim3(WBLOCK), s, Dev(d))                  \
+                : launch(k_band<T, false>, grid, dim3(WBLOCK), s, Dev(d));
+  LBM_DISPATCH(prec, F)
+#undef F
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_wall(const Dev& d, int prec, int parity, hipStream_t s) {
+  if (d.nwall <= 0 || d.max_np <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((d.max_np + WBLOCK - 1) / WBLOCK), d.nwall);
+  if (prec == 0) return launch(k_wall<double>, grid, dim3(WBLOCK), s, Dev(d), int(parity));
+  return launch(k_wall<float>, grid, dim3(WBLOCK), s, Dev(d), int(parity));
+}
+
+hipError_t launch_fill_rest(const Dev& d, int prec, int64_t cell0, int64_t ncell, double dshift, hipStream_t s) {
+  if (ncell <= 0) return hipSuccess;
+  const unsigned nb = (unsigned)((ncell + 255) / 256);
+#define F(T) return launch(k_fill_rest<T>, dim3(nb), dim3(256), s, Dev(d), int64_t(cell0), int64_t(ncell), double(dshift));
+  LBM_DISPATCH(prec, F)
+#undef F
+  return hipErrorInvalidValue;
+}
+
+}  // namespace lbm

@@ -181,3 +181,21 @@ def test_small_tube_steady_windkessel(oracle_mod):
     A = np.stack([np.ones(sel.sum()), r2[sel]], 1)
     (a, mb), *_ = np.linalg.lstsq(A, u[32, :, :, 2][sel], rcond=None)
     assert abs(mb / (slope / (4 * nu)) - 1.0) < 0.02
+
+
+def test_oracle_noise_floor(oracle_mod):
+    """FP64 oracle against its long-double build on the small rigid tube: the
+    FP64 build's own rounding sets a floor of ~1e-12 on the slow (3e-6 lu)
+    velocity, which is why the FP64 bar is checked against the long-double
+    build."""
+    c = L.cfg0()
+    a = oracle_mod.from_config(c)
+    b = oracle_mod.from_config(c, extended=True)
+    assert oracle_mod.lib(True).orc_is_extended() == 1
+    a.step(300)
+    b.step(300)
+    (pa, ua), (pb, ub) = a.fields(), b.fields()
+    fl = c["flags"] == L.FLUID
+    e = np.linalg.norm(ua[fl] - ub[fl]) / np.linalg.norm(ub[fl])
+    print("FP64 oracle vs long double: rel-L2 u %.2e" % e)
+    assert 1e-16 < e < 1e-10
