@@ -370,7 +370,7 @@ FsiLayout fsi_plan(int64_t ncell, int64_t np, int64_t nband, int prec) {
   f.Xb = o; o = align256(o + np * 32);
   f.slip = o; o = align256(o + np * 32);
   f.Vf = o; o = align256(o + np * r4);
-  f.Fp = o; o = align256(o + np * r4);
+  f.Fp = o; o = align256(o + np * 32);
   f.band = o; o = align256(o + std::max<int64_t>(nband, 1) * 4);
   f.total = o;
   return f;
@@ -632,18 +632,21 @@ lbm_status lbm_fsi_exchange(lbm_ctx* c, int32_t k, const lbm_wall_desc* w, void*
   c->wall[k].np = np;
   c->wall[k].nband = d.nband;
   c->walls.clear();
-  int maxb = 0;
+  int maxb = 0, maxt = 0;
   int64_t maxp = 0;
   for (int q = 0; q < c->n; ++q)
     if (c->wall[q].on) {
       c->walls.push_back(q);
       maxb = std::max(maxb, c->wall[q].nband);
       maxp = std::max(maxp, c->wall[q].np);
+      const InstDesc& dq = c->inst[q];
+      maxt = std::max(maxt, ((dq.nth + 15) / 16) * ((dq.nzl + 15) / 16));
     }
   HIPCHK(c, hipMemcpy(c->work + c->L.walls, c->walls.data(), c->walls.size() * 4, hipMemcpyHostToDevice));
   c->dev.nwall = (int32_t)c->walls.size();
   c->dev.max_band = maxb;
   c->dev.max_np = (int32_t)maxp;
+  c->dev.max_tiles = maxt;
   return LBM_OK;
 }
 
@@ -677,7 +680,7 @@ lbm_status lbm_read_wall(lbm_ctx* c, int32_t k, double* X, double* Xp, double* s
     if (dst) for (size_t q = 0; q < x0.size(); ++q) dst[q] += x0[q];
   };
   if ((r = get4(d.Xab[par], X)) != LBM_OK || (r = get4(d.Xab[par ^ 1], Xp)) != LBM_OK ||
-      (r = get4(d.slip, slip)) != LBM_OK || (r = getr4(d.Vf, Vf)) != LBM_OK || (r = getr4(d.Fp, Fp)) != LBM_OK)
+      (r = get4(d.slip, slip)) != LBM_OK || (r = getr4(d.Vf, Vf)) != LBM_OK || (r = get4(d.Fp, Fp)) != LBM_OK)
     return r;
   add_x0(X);
   add_x0(Xp);

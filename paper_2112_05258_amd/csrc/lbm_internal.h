@@ -68,7 +68,7 @@ struct InstDesc {
   double* Xab[2];          // double4 per point, ping-pong D^n / D^{n-1}, D = X - X0
   double* slip;            // double4 per point
   void* Vf;                // R4 per point (last step, for read-back)
-  void* Fp;                // R4 per point (last step, for read-back)
+  void* Fp;                // double4 per point: penalty force on the fluid (last step)
   int32_t* band;           // local cell ids of the band
   double ds_th, ds_z, area, ks, ei, mass, alpha, beta;
 };
@@ -103,6 +103,7 @@ struct Dev {
   uint32_t* err;
   const int32_t* walls;            // instance ids with a wall
   int32_t max_band, max_np;
+  int32_t max_tiles;               // wall tiles (16 x 16 points) of the largest wall
 };
 
 }  // namespace lbm

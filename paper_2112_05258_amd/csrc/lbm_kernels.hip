@@ -286,18 +286,39 @@ __global__ __launch_bounds__(BLOCK) void k_collide(Dev d) {
   const InstDesc& I = d.inst[inst];
   const int64_t local = (int64_t)(blockIdx.x - I.blk0) * BLOCK + threadIdx.x;
   if (local >= I.ncell) return;
-  const int64_t c = I.cell0 + local;
+  // global cell index fits 32 bits (NT < 2^31); per-direction arrays are
+  // addressed as uniform base + 32-bit lane offset
+  const uint32_t c = (uint32_t)(I.cell0 + local);
   const uint8_t fl = d.flags[c];
   if ((fl & TYPE_MASK) != T_FLUID) return;
-  const int64_t sy = I.nx, sz = (int64_t)I.nx * I.ny;
-  const int64_t NT = d.NT;
-  int64_t off[NQ];
-  dir_offsets(sy, sz, off);
+  const int32_t sy = I.nx, sz = I.nx * I.ny;
+  int32_t off[NQ];
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) off[i] = EX[i] + EY[i] * sy + EZ[i] * sz;
   S* __restrict__ A = (S*)d.pop;
+  const int64_t NT = d.NT;
   const bool near = fl & F_NEAR;
 
+  // source cell types (only cells next to walls or ghosts look)
+  uint8_t nt[NQ];
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) nt[i] = T_FLUID;
+  if (near) {
+#pragma unroll
+    for (int i = 1; i < NQ; ++i) nt[i] = d.flags[c - off[i]] & TYPE_MASK;
+  }
+
   R g[NQ];
-  load_cell<S, ODD>(A, NT, d.flags, c, near, off, d.inv_scale, g);
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) {
+    if (!ODD) {
+      g[i] = Store<S>::ld(A + i * NT + c, d.inv_scale);
+    } else if (nt[i] == T_SOLID) {
+      g[i] = Store<S>::ld(A + i * NT + c, d.inv_scale);
+    } else {
+      g[i] = Store<S>::ld(A + OPP[i] * NT + (uint32_t)(c - off[i]), d.inv_scale);
+    }
+  }
 
   // moments (Eqs. rho, v): dl = sum g - dref (= delta - 3 p_ref), j = sum e g
   R dl = 0, jx = 0, jy = 0, jz = 0;
@@ -320,7 +341,7 @@ __global__ __launch_bounds__(BLOCK) void k_collide(Dev d) {
   const R cf = R(1) - R(0.5) * om;
   const R vb = vx * bx + vy * by + vz * bz;
 
-  // collision (Eqs. fi, feq, f)
+  // collision (Eqs. fi, feq, f) and streaming, direction by direction
   R gs[NQ];
 #pragma unroll
   for (int i = 0; i < NQ; ++i) {
@@ -332,27 +353,12 @@ __global__ __launch_bounds__(BLOCK) void k_collide(Dev d) {
       v += cf * wgt<R>(i) * (R(3) * (eb - vb) + R(9) * eu * eb);
     }
     gs[i] = v;
-  }
-
-  // source cell types (only cells next to walls or ghosts look)
-  uint8_t nt[NQ];
-#pragma unroll
-  for (int i = 0; i < NQ; ++i) nt[i] = T_FLUID;
-  if (near) {
-#pragma unroll
-    for (int i = 1; i < NQ; ++i) nt[i] = d.flags[c - off[i]] & TYPE_MASK;
-  }
-
-  // streaming
-  if (!ODD) {
-#pragma unroll
-    for (int i = 0; i < NQ; ++i) Store<S>::st(A + OPP[i] * NT + c, gs[i], d.scale);
-  } else {
-#pragma unroll
-    for (int i = 0; i < NQ; ++i) {
+    if (!ODD) {
+      Store<S>::st(A + OPP[i] * NT + c, v, d.scale);
+    } else {
       const uint8_t td = nt[OPP[i]];  // type of c + e_i
-      if (td == T_FLUID) Store<S>::st(A + i * NT + c + off[i], gs[i], d.scale);
-      else if (td == T_SOLID) Store<S>::st(A + OPP[i] * NT + c, gs[i], d.scale);
+      if (td == T_FLUID) Store<S>::st(A + i * NT + (uint32_t)(c + off[i]), v, d.scale);
+      else if (td == T_SOLID) Store<S>::st(A + OPP[i] * NT + c, v, d.scale);
     }
   }
 
@@ -390,7 +396,7 @@ __global__ __launch_bounds__(BLOCK) void k_collide(Dev d) {
         }
         out = gs[i] + deq_velocity<R>(i, vx, vy, vz, sx, s_y, s_z);
       }
-      if (!ODD) Store<S>::st(A + OPP[i] * NT + c - off[i], out, d.scale);
+      if (!ODD) Store<S>::st(A + OPP[i] * NT + (uint32_t)(c - off[i]), out, d.scale);
       else Store<S>::st(A + i * NT + c, out, d.scale);
     }
   }
@@ -447,19 +453,61 @@ __device__ __forceinline__ double3 tension(double3 e, double ds, double ks) {
   return make_double3(T * dx, T * dy, T * dz);
 }
 
+// fixed-point accumulator type for the LDS spreading: same width as R
+template <class R> struct FixOf;
+template <> struct FixOf<float> {
+  using T = int;
+  static constexpr int M = 23;
+  __device__ static void add(int* p, float v) { atomicAdd(p, __float2int_rn(v)); }
+};
+template <> struct FixOf<double> {
+  using T = long long;
+  static constexpr int M = 52;
+  __device__ static void add(long long* p, double v) {
+    atomicAdd((unsigned long long*)p, (unsigned long long)__double2ll_rn(v));
+  }
+};
+
+// Wall points are processed in tiles of TJ x TK mesh points (theta x z), one
+// tile per 256-lane workgroup.  The tile's stencils span a small box of
+// lattice cells; when it fits in LDS the band velocity of the box is staged
+// there for the interpolation, and the same LDS then accumulates the spread
+// force with LDS atomics before one flush of the box's non-zero cells with
+// global atomics (instead of 64 x 3 global atomics per point).
+constexpr int TJ = 16, TK = 16;
+
 template <class R>
 __global__ __launch_bounds__(WBLOCK) void k_wall(Dev d, int parity) {
   using R4 = typename V4<R>::T;
+  // box cells; a 16 x 16 tile at 0.5 lu spans <= ~1000 (LDS stays < 64 KB)
+  constexpr int BOXCAP = sizeof(R) == 8 ? 1024 : 2048;
+  __shared__ R sbox[3 * BOXCAP];
+  __shared__ uint8_t sfl[BOXCAP];
+  __shared__ int smin[3], smax[3];
+  __shared__ int semax;
   const int inst = d.walls[blockIdx.y];
   const InstDesc& I = d.inst[inst];
-  const int64_t p = (int64_t)blockIdx.x * WBLOCK + threadIdx.x;
-  if (p >= I.np) return;
+  const int nth = I.nth, nzl = I.nzl;
+  const int ntj = (nth + TJ - 1) / TJ;
+  if ((int)blockIdx.x >= ntj * ((nzl + TK - 1) / TK)) return;  // whole block leaves
+  // wave w takes the parity sub-lattice (w & 1, w >> 1) of the 16 x 16 patch:
+  // its 8 x 8 points are >= 1 lu apart, so for a given stencil offset the 64
+  // lanes mostly hit distinct cells and the LDS atomics do not serialise.
+  const int wv = (int)threadIdx.x >> 6, ln = (int)threadIdx.x & 63;
+  const int j = ((int)blockIdx.x % ntj) * TJ + 2 * (ln & 7) + (wv & 1);
+  const int k = ((int)blockIdx.x / ntj) * TK + 2 * (ln >> 3) + (wv >> 1);
+  const bool valid = j < nth && k < nzl;
+  const int64_t p = valid ? j + (int64_t)nth * k : 0;
   // the wall is carried as displacement D = X - X0 (ping-pong D^n / D^{n-1})
   const double* Dc = I.Xab[parity];
   double* Dn = I.Xab[parity ^ 1];
   const double3 X0 = ld3(I.X0, p), D = ld3(Dc, p), Dm = ld3(Dn, p);
 
-  // interpolation of the unforced velocity over the 4x4x4 stencil
+  if (threadIdx.x < 3) {
+    smin[threadIdx.x] = 0x7fffffff;
+    smax[threadIdx.x] = -0x7fffffff;
+  }
+  __syncthreads();
   const int bx0 = (int)floor(X0.x + D.x) - 1, by0 = (int)floor(X0.y + D.y) - 1, bz0 = (int)floor(X0.z + D.z) - 1;
   R wx[4], wy[4], wz[4];
 #pragma unroll
@@ -468,76 +516,178 @@ __global__ __launch_bounds__(WBLOCK) void k_wall(Dev d, int parity) {
     wy[a] = phi4<R>((R)(((double)(by0 + a) - X0.y) - D.y));
     wz[a] = phi4<R>((R)(((double)(bz0 + a) - X0.z) - D.z));
   }
+  if (valid) {
+    atomicMin(&smin[0], bx0); atomicMin(&smin[1], by0); atomicMin(&smin[2], bz0);
+    atomicMax(&smax[0], bx0); atomicMax(&smax[1], by0); atomicMax(&smax[2], bz0);
+  }
+  __syncthreads();
+  const int ox = smin[0], oy = smin[1], oz = smin[2];
+  const int ex = smax[0] - ox + 4, ey = smax[1] - oy + 4, ez = smax[2] - oz + 4;
+  const int64_t vol = (int64_t)ex * ey * ez;
+  const bool staged = vol <= BOXCAP;          // uniform over the block
   const R4* U = (const R4*)I.u4;
+  auto box_cell = [&](int q, int& x, int& y, int& z) {
+    x = ox + q % ex;
+    y = oy + (q / ex) % ey;
+    z = oz + q / (ex * ey);
+  };
+  auto in_box = [&](int x, int y, int z) { return x >= 0 && y >= 0 && z >= 0 && x < I.nx && y < I.ny && z < I.nz; };
+
+  // ---- interpolation of the unforced velocity over the 4x4x4 stencil ----
+  if (staged) {
+    for (int q = threadIdx.x; q < (int)vol; q += WBLOCK) {
+      int x, y, z;
+      box_cell(q, x, y, z);
+      uint8_t f = T_SOLID;
+      R4 u = {0, 0, 0, 0};
+      if (in_box(x, y, z)) {
+        const int64_t lc = x + (int64_t)I.nx * (y + (int64_t)I.ny * z);
+        f = d.flags[I.cell0 + lc];
+        u = U[lc];  // only read where (f is FLUID and BAND)
+      }
+      sfl[q] = f;
+      sbox[3 * q] = u.x; sbox[3 * q + 1] = u.y; sbox[3 * q + 2] = u.z;
+    }
+    __syncthreads();
+  }
   R Vx = 0, Vy = 0, Vz = 0;
   bool outside = false;
-  for (int cz = 0; cz < 4; ++cz) {
-    const int z = bz0 + cz;
-    if (z < 0 || z >= I.nz) continue;
-    for (int cy = 0; cy < 4; ++cy) {
-      const int y = by0 + cy;
-      if (y < 0 || y >= I.ny) continue;
-      const R wyz = wy[cy] * wz[cz];
-      for (int cx = 0; cx < 4; ++cx) {
-        const int x = bx0 + cx;
-        if (x < 0 || x >= I.nx) continue;
-        const int64_t lc = x + (int64_t)I.nx * (y + (int64_t)I.ny * z);
-        const uint8_t f = d.flags[I.cell0 + lc];
-        if ((f & TYPE_MASK) != T_FLUID) continue;
-        const R w = wx[cx] * wyz;
-        if (!(f & F_BAND)) {
-          if (w != R(0)) outside = true;
-          continue;
+  if (valid) {
+    for (int cz = 0; cz < 4; ++cz)
+      for (int cy = 0; cy < 4; ++cy) {
+        const R wyz = wy[cy] * wz[cz];
+        for (int cx = 0; cx < 4; ++cx) {
+          const int x = bx0 + cx, y = by0 + cy, z = bz0 + cz;
+          uint8_t f;
+          R ux, uy, uz;
+          if (staged) {
+            const int q = (x - ox) + ex * ((y - oy) + ey * (z - oz));
+            f = sfl[q];
+            ux = sbox[3 * q]; uy = sbox[3 * q + 1]; uz = sbox[3 * q + 2];
+          } else {
+            if (!in_box(x, y, z)) continue;
+            const int64_t lc = x + (int64_t)I.nx * (y + (int64_t)I.ny * z);
+            f = d.flags[I.cell0 + lc];
+            ux = uy = uz = 0;
+            if ((f & TYPE_MASK) == T_FLUID && (f & F_BAND)) {
+              const R4 u = U[lc];
+              ux = u.x; uy = u.y; uz = u.z;
+            }
+          }
+          if ((f & TYPE_MASK) != T_FLUID) continue;
+          const R w = wx[cx] * wyz;
+          if (!(f & F_BAND)) {
+            if (w != R(0)) outside = true;
+            continue;
+          }
+          Vx += ux * w; Vy += uy * w; Vz += uz * w;
         }
-        const R4 u = U[lc];
-        Vx += u.x * w; Vy += u.y * w; Vz += u.z * w;
       }
-    }
   }
   if (outside) atomicOr(d.err, ERR_BAND);
 
-  // penalty force on the fluid (Eq. LagForce): alpha int (Vf - Vs) + beta (Vf - Vs)
-  const double dxv = (double)Vx - (D.x - Dm.x);
-  const double dyv = (double)Vy - (D.y - Dm.y);
-  const double dzv = (double)Vz - (D.z - Dm.z);
-  double4* SL = (double4*)I.slip;
-  double4 sl = SL[p];
-  sl.x += dxv; sl.y += dyv; sl.z += dzv;
-  SL[p] = sl;
-  const double Fx = I.alpha * sl.x + I.beta * dxv;
-  const double Fy = I.alpha * sl.y + I.beta * dyv;
-  const double Fz = I.alpha * sl.z + I.beta * dzv;
-  ((R4*)I.Vf)[p] = R4{Vx, Vy, Vz, R(0)};
-  ((R4*)I.Fp)[p] = R4{(R)Fx, (R)Fy, (R)Fz, R(0)};
-
-  // spreading (Eq. EulForce): b(node) += F area delta
-  R* B = (R*)I.b4;
-  const R fx = (R)(Fx * I.area), fy = (R)(Fy * I.area), fz = (R)(Fz * I.area);
-  for (int cz = 0; cz < 4; ++cz) {
-    const int z = bz0 + cz;
-    if (z < 0 || z >= I.nz) continue;
-    for (int cy = 0; cy < 4; ++cy) {
-      const int y = by0 + cy;
-      if (y < 0 || y >= I.ny) continue;
-      const R wyz = wy[cy] * wz[cz];
-      for (int cx = 0; cx < 4; ++cx) {
-        const int x = bx0 + cx;
-        if (x < 0 || x >= I.nx) continue;
-        const int64_t lc = x + (int64_t)I.nx * (y + (int64_t)I.ny * z);
-        const uint8_t f = d.flags[I.cell0 + lc];
-        if ((f & TYPE_MASK) != T_FLUID || !(f & F_BAND)) continue;
-        const R w = wx[cx] * wyz;
-        if (w == R(0)) continue;
-        atomicAdd(B + 4 * lc + 0, fx * w);
-        atomicAdd(B + 4 * lc + 1, fy * w);
-        atomicAdd(B + 4 * lc + 2, fz * w);
-      }
-    }
+  // ---- penalty force on the fluid (Eq. LagForce) ----
+  double Fx = 0, Fy = 0, Fz = 0;
+  if (valid) {
+    const double dxv = (double)Vx - (D.x - Dm.x);
+    const double dyv = (double)Vy - (D.y - Dm.y);
+    const double dzv = (double)Vz - (D.z - Dm.z);
+    double4* SL = (double4*)I.slip;
+    double4 sl = SL[p];
+    sl.x += dxv; sl.y += dyv; sl.z += dzv;
+    SL[p] = sl;
+    Fx = I.alpha * sl.x + I.beta * dxv;
+    Fy = I.alpha * sl.y + I.beta * dyv;
+    Fz = I.alpha * sl.z + I.beta * dzv;
+    ((R4*)I.Vf)[p] = R4{Vx, Vy, Vz, R(0)};
+    ((double4*)I.Fp)[p] = double4{Fx, Fy, Fz, 0.0};
   }
 
-  // membrane forces (Eqs. tension and bending along theta and z)
+  // ---- spreading (Eq. EulForce): b(node) += F area delta ----
+  R* B = (R*)I.b4;
+  const R fx = (R)(Fx * I.area), fy = (R)(Fy * I.area), fz = (R)(Fz * I.area);
+  // Spreading into the LDS box in fixed point: integer LDS atomics run at
+  // full rate where float ones do not, and an integer sum is exact, so the
+  // result does not depend on the order of the tile's contributions.  The
+  // scale is a power of two per tile, 2^(M - e) with e the exponent of the
+  // tile's largest |F area| and M the significand width of R (headroom of
+  // 2^7 resp. 2^10 for the sums).
+  using Fix = typename FixOf<R>::T;
+  if (staged) {
+    if (threadIdx.x == 0) semax = -100000;
+    __syncthreads();  // everyone is done reading the staged velocity
+    Fix* acc = (Fix*)sbox;
+    for (int q = threadIdx.x; q < 3 * (int)vol; q += WBLOCK) acc[q] = 0;
+    if (valid) {
+      const R m = fmax(fabs(fx), fmax(fabs(fy), fabs(fz)));
+      if (m > R(0)) atomicMax(&semax, (int)ilogb(m));
+    }
+    __syncthreads();
+    const int e = semax < -1000 ? 0 : semax;
+    const R S = ldexp(R(1), FixOf<R>::M - e), invS = ldexp(R(1), e - FixOf<R>::M);
+    if (valid) {
+      const R sx = fx * S, sy = fy * S, sz = fz * S;
+      for (int cz = 0; cz < 4; ++cz)
+        for (int cy = 0; cy < 4; ++cy) {
+          const R wyz = wy[cy] * wz[cz];
+          const int q0 = (bx0 - ox) + ex * ((by0 + cy - oy) + ey * (bz0 + cz - oz));
+          for (int cx = 0; cx < 4; ++cx) {
+            const R w = wx[cx] * wyz;
+            FixOf<R>::add(&acc[3 * (q0 + cx)], sx * w);
+            FixOf<R>::add(&acc[3 * (q0 + cx) + 1], sy * w);
+            FixOf<R>::add(&acc[3 * (q0 + cx) + 2], sz * w);
+          }
+        }
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < (int)vol; q += WBLOCK) {
+      const uint8_t f = sfl[q];
+      if ((f & TYPE_MASK) != T_FLUID || !(f & F_BAND)) continue;
+      int x, y, z;
+      box_cell(q, x, y, z);
+      const int64_t lc = x + (int64_t)I.nx * (y + (int64_t)I.ny * z);
+#pragma unroll
+      for (int c3 = 0; c3 < 3; ++c3) {
+        const Fix a = acc[3 * q + c3];
+        if (a != 0) atomicAdd(B + 4 * lc + c3, (R)a * invS);
+      }
+    }
+  } else if (valid) {
+    for (int cz = 0; cz < 4; ++cz)
+      for (int cy = 0; cy < 4; ++cy) {
+        const R wyz = wy[cy] * wz[cz];
+        for (int cx = 0; cx < 4; ++cx) {
+          const int x = bx0 + cx, y = by0 + cy, z = bz0 + cz;
+          if (!in_box(x, y, z)) continue;
+          const int64_t lc = x + (int64_t)I.nx * (y + (int64_t)I.ny * z);
+          const uint8_t f = d.flags[I.cell0 + lc];
+          if ((f & TYPE_MASK) != T_FLUID || !(f & F_BAND)) continue;
+          const R w = wx[cx] * wyz;
+          if (w == R(0)) continue;
+          atomicAdd(B + 4 * lc + 0, fx * w);
+          atomicAdd(B + 4 * lc + 1, fy * w);
+          atomicAdd(B + 4 * lc + 2, fz * w);
+        }
+      }
+  }
+}
+
+// k_membrane: membrane forces (Eqs. tension and bending along theta and z)
+// and the wall's central-difference step, one lane per point, after k_wall
+// has produced this step's penalty force.
+__global__ __launch_bounds__(WBLOCK) void k_membrane(Dev d, int parity) {
+  const int inst = d.walls[blockIdx.y];
+  const InstDesc& I = d.inst[inst];
+  const int64_t p = (int64_t)blockIdx.x * WBLOCK + threadIdx.x;
+  if (p >= I.np) return;
   const int nth = I.nth, nzl = I.nzl;
   const int j = (int)(p % nth), k = (int)(p / nth);
+  const double* Dc = I.Xab[parity];
+  double* Dn = I.Xab[parity ^ 1];
+  const double3 D = ld3(Dc, p), Dm = ld3(Dn, p);
+  const double4 Fw = ((const double4*)I.Fp)[p];
+  const double Fx = Fw.x, Fy = Fw.y, Fz = Fw.z;
+  // membrane forces (Eqs. tension and bending along theta and z)
   auto P = [&](int jj, int kk) -> int64_t { return (int64_t)((jj % nth + nth) % nth) + (int64_t)nth * kk; };
   // edge vector X_b - X_a = (X0_b - X0_a) + (D_b - D_a)
   auto edge = [&](int64_t a, int64_t b) -> double3 {
@@ -663,10 +813,13 @@ hipError_t launch_band(const Dev& d, int prec, int parity, hipStream_t s) {
 }
 
 hipError_t launch_wall(const Dev& d, int prec, int parity, hipStream_t s) {
-  if (d.nwall <= 0 || d.max_np <= 0) return hipSuccess;
-  const dim3 grid((unsigned)((d.max_np + WBLOCK - 1) / WBLOCK), d.nwall);
-  if (prec == 0) return launch(k_wall<double>, grid, dim3(WBLOCK), s, Dev(d), int(parity));
-  return launch(k_wall<float>, grid, dim3(WBLOCK), s, Dev(d), int(parity));
+  if (d.nwall <= 0 || d.max_tiles <= 0) return hipSuccess;
+  const dim3 grid((unsigned)d.max_tiles, d.nwall);
+  hipError_t e = prec == 0 ? launch(k_wall<double>, grid, dim3(WBLOCK), s, Dev(d), int(parity))
+                           : launch(k_wall<float>, grid, dim3(WBLOCK), s, Dev(d), int(parity));
+  if (e != hipSuccess) return e;
+  const dim3 g2((unsigned)((d.max_np + WBLOCK - 1) / WBLOCK), d.nwall);
+  return launch(k_membrane, g2, dim3(WBLOCK), s, Dev(d), int(parity));
 }
 
 hipError_t launch_fill_rest(const Dev& d, int prec, int64_t cell0, int64_t ncell, double dshift, hipStream_t s) {
