@@ -39,7 +39,23 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp16", action="store_true", help="skip the FP16-storage run")
     ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "fp16s", "bf16s"])
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain device copy of 1 GiB (calibration of the HBM byte counters)")
     return ap.parse_args()
+
+
+def copy_probe(reps=5, nbytes=1 << 30):
+    """A plain device-to-device copy of known size: the per-dispatch
+    FETCH_SIZE / WRITE_SIZE it reports calibrates the counters."""
+    import torch
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": nbytes, "reps": reps}), flush=True)
 
 
 def workload(name):
@@ -139,26 +155,31 @@ def cpu_baseline(cfg, budget_s=20.0):
                 sample=f"{n} steps of the full workload (FP64, {nfluid} fluid cells), {dt:.1f} s")
 
 
-def traffic_from_profile(bytes_alg):
+def traffic_from_profile(precision):
     """HBM bytes per collide launch from the committed rocprofv3 PMC summary
-    (FETCH_SIZE + WRITE_SIZE in KiB, scaled by the copy-kernel calibration)."""
-    if not os.path.exists(PMC_FILE):
+    (FETCH_SIZE and WRITE_SIZE scaled by the copy-kernel calibration), or
+    None when it does not apply: another precision, or the kernel source has
+    changed since the counters were taken."""
+    import hashlib
+    if precision != "fp32" or not os.path.exists(PMC_FILE):
         return None
     vals = {}
     for line in open(PMC_FILE):
         if "=" in line and not line.startswith("#"):
             k, v = line.split("=", 1)
-            try:
-                vals[k.strip()] = float(v.split()[0])
-            except ValueError:
-                pass
-    if "collide_bytes_per_launch" in vals:
-        return vals["collide_bytes_per_launch"]
-    return None
+            vals[k.strip()] = v.strip()
+    src = os.path.join(ROOT, "paper_2112_05258_amd", "csrc", "lbm_kernels.hip")
+    now = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if vals.get("kernel_source_sha256_16") != now or "collide_bytes_per_launch" not in vals:
+        return None
+    return float(vals["collide_bytes_per_launch"])
 
 
 def main():
     args = parse()
+    if args.copy_probe:
+        copy_probe()
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the method's multi-GPU sharding is described in DESIGN.md)", file=sys.stderr)
@@ -191,7 +212,7 @@ def main():
                    "precision": args.precision, "step": "reduce+0D, band, wall, collide-stream"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic_from_profile(r["bytes_collide"]),
+                     "traffic": traffic_from_profile(args.precision),
                      "kernel": "k_collide", "bytes_per_launch": r["bytes_collide"],
                      "avg_launch_us": round(r["avg_collide_ms"] * 1e3, 2)},
         "kernels_ms_per_step": {name: round(r["kt"][k][1] / max(r["kt"][k][0], 1), 5)
