@@ -243,7 +243,11 @@ def small_fsi(nx=24, ny=24, nz=40, r=7.0, h=0.7, tau=0.6, seed=None):
 
 
 def ensemble(n=256, seed=3):
-    """Parameter draws of the batched ensemble (radius, length, LV, WK, wall)."""
+    """Parameter draws of the batched ensemble (radius, length, LV, WK, wall):
+    r ~ U[6, 16] lu and L ~ U[48, 160] lu (rounded), Emax ~ U[1.5, 3.0],
+    Emin ~ U[0.04, 0.08] mmHg/ml, HR ~ U[60, 100] bpm, Windkessel Z, C, R
+    each the reference set (Z 0.05, C 1.5, R 1.0) times U[0.7, 1.3],
+    membrane stiffness k ~ U[0.02, 0.1]."""
     rng = np.random.default_rng(seed)
     out = []
     for _ in range(n):
@@ -256,3 +260,16 @@ def ensemble(n=256, seed=3):
             Z=0.05 * rng.uniform(0.7, 1.3), C=1.5 * rng.uniform(0.7, 1.3),
             R=1.0 * rng.uniform(0.7, 1.3), k=rng.uniform(0.02, 0.1)))
     return out
+
+
+def ensemble_config(p, h=0.5, tau=0.52):
+    """Workload dict of one ensemble member: an elastic tube of radius r in a
+    (2r + 8)^2 x (L + 2) box with the member's LV, Windkessel and wall.
+    Volume scale sigma_V ~ r^2 keeps peak velocities near the large tube's."""
+    r, L = p["r"], p["L"]
+    n = 2 * r + 8
+    sc = scales(25000.0, 8000.0 * (r / 48.0) ** 2, 2.5e-6)
+    c = _elastic_tube(n, n, L + 2, float(r), h, p["k"], 1e-3, sc, tau=tau, Emax=p["Emax"], Emin=p["Emin"],
+                      HR=p["HR"], Z=p["Z"], C=p["C"], R=p["R"])
+    c.update(name=f"ensemble_r{r}_L{L}")
+    return c

@@ -254,3 +254,20 @@ def solver_from_config(cfg, precision=FP32, pops=None, store_scale=0.0, wave_cap
     if "mesh" in cfg:
         s.fsi_exchange(0, cfg["mesh"], cfg["k"], cfg["ei"], cfg["mass"], cfg["alpha"], cfg["beta"])
     return s
+
+
+def solver_from_configs(cfgs, precision=FP32, store_scale=0.0, wave_cap=4096):
+    """One batched context over several workload dicts (the ensemble): one
+    launch per kernel per step advances every instance."""
+    boxes = [dict(nx=c["nx"], ny=c["ny"], nz=c["nz"], tau=c["tau"], flags=c["flags"],
+                  p_ref=c.get("p_ref", 0.0)) for c in cfgs]
+    s = Solver(boxes, precision=precision, store_scale=store_scale, wave_cap=wave_cap)
+    for k, cfg in enumerate(cfgs):
+        for b, key in ((0, "inlet"), (1, "outlet"), (2, "exterior")):
+            if key in cfg:
+                s.couple_0d(k, b, cfg[key][0], cfg[key][1], cfg.get(key + "_state", ()))
+        if cfg.get("p_init", 0.0) != 0.0:
+            s.set_rest(cfg["p_init"], inst=k)
+        if "mesh" in cfg:
+            s.fsi_exchange(k, cfg["mesh"], cfg["k"], cfg["ei"], cfg["mass"], cfg["alpha"], cfg["beta"])
+    return s
