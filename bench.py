@@ -122,6 +122,36 @@ def run_gpu(cfg, precision, steps, warmup):
                 bytes_collide=bytes_collide, finite=finite, es=es)
 
 
+def precision_study_errors():
+    """Run the 16-bit storage study workload (three beats) in FP16S and BF16S
+    and compare with the FP64 oracle's stored record (tests/golden): the
+    pointwise inlet-pressure error over the pulse pressure, the error of each
+    beat's systolic peak, and the relative L2 of the inlet flux."""
+    import numpy as np
+    import lbm_inputs as L
+    import paper_2112_05258_amd as amd
+    here = os.path.dirname(os.path.abspath(__file__))
+    wr = np.loadtxt(os.path.join(here, "tests", "golden", "precision_study_waveforms.txt"))
+    c = L.precision_study()
+    beat = c["steps"] // 3
+    out = {"workload": c["name"], "steps": c["steps"]}
+    for name, prec in (("fp16s", amd.FP16S), ("bf16s", amd.BF16S)):
+        s = amd.solver_from_config(c, precision=prec, wave_cap=c["steps"])
+        s.step(c["steps"])
+        s.sync()
+        w = s.waveforms()[7::8][:, (0, 1, 2, 3, 4, 9, 10, 11)]
+        s.close()
+        P, Pr = w[:, 2], wr[:, 2]
+        peaks = []
+        for b in range(3):
+            m = (wr[:, 0] >= b * beat) & (wr[:, 0] < (b + 1) * beat)
+            peaks.append(abs(P[m].max() - Pr[m].max()) / Pr[m].max())
+        out[name] = {"pressure_max_err_over_pulse": float(f"{np.abs(P - Pr).max() / (Pr.max() - Pr.min()):.3e}"),
+                     "peak_pressure_rel_err": float(f"{max(peaks):.3e}"),
+                     "inlet_flux_rel_l2": float(f"{np.linalg.norm(w[:, 1] - wr[:, 1]) / np.linalg.norm(wr[:, 1]):.3e}")}
+    return out
+
+
 def _band_cells(cfg):
     """Band cells of the wall (same rule as the library: stencil + 2-cell margin, fluid only)."""
     import numpy as np
@@ -263,7 +293,9 @@ def main():
         m16 = r16["nfluid"] * args.steps / (r16["total_ms"] * 1e-3) / 1e6
         a16 = r16["bytes_collide"] / (r16["avg_collide_ms"] * 1e-3) / 1e9
         out["fp16s"] = {"value": round(m16, 1), "unit": "MLUPS", "ratio_vs_fp32": round(m16 / mlups, 3),
+                        "collide_ratio_vs_fp32": round(r["avg_collide_ms"] / r16["avg_collide_ms"], 3),
                         "collide_achieved_GBs": round(a16, 1), "collide_frac": round(a16 / HBM_PEAK_GBS, 4)}
+        out["fp16s"]["waveform_error_vs_fp64_oracle"] = precision_study_errors()
     if not args.no_ensemble and args.workload == "cfg1" and args.precision == "fp32":
         out["ensemble"] = run_ensemble(args.ensemble_steps, 10)
     if not args.no_cpu:

@@ -234,6 +234,25 @@ def cfg2():
     return c
 
 
+def precision_study(r=12.0):
+    """Workload of the 16-bit storage study: elastic tube r = 12 in a
+    32 x 32 x 128 box with the cfg1 boundary models, three beats of 1600
+    steps (sigma_t = 2000 /s at 75 bpm; sigma_V keeps the peak velocities of
+    the large tube).  tau = 0.6: at tau = 0.52 the pressure-type inlet
+    becomes unstable late in systole on this compressed time scale, when the
+    ventricle pressure falls under the downstream pressure while the valve
+    is still open.  Bending stiffness 1e-2 (not 1e-3): in diastole the tube
+    pressure drops under the exterior's P0 and a thinner wall buckles inwards
+    a little further every beat."""
+    st = 2000.0
+    sc = scales(st, 8000.0 * (r / 48.0) ** 2 * (st / 25000.0), 2.5e-6)
+    n = int(round(8 * r / 3))
+    nz = int(round(32 * r / 3))
+    c = _elastic_tube(n, n, nz, r, 0.5, 0.05, 1e-2, sc, tau=0.6)
+    c.update(name=f"precision_study_{n}x{n}x{nz}", steps=3 * int(round(60.0 / 75.0 * st)))
+    return c
+
+
 def small_fsi(nx=24, ny=24, nz=40, r=7.0, h=0.7, tau=0.6, seed=None):
     """Small elastic tube with the cfg1 boundary models, for parity tests."""
     sc = scales(2500.0, 8000.0 * (r / 48.0) ** 2, 2.5e-6)
@@ -273,3 +292,49 @@ def ensemble_config(p, h=0.5, tau=0.52):
                       HR=p["HR"], Z=p["Z"], C=p["C"], R=p["R"])
     c.update(name=f"ensemble_r{r}_L{L}")
     return c
+
+
+# ----------------------------------------------------------------------------
+# learned surrogate: parameter draws and initial weights
+# ----------------------------------------------------------------------------
+
+# the 7 surrogate inputs and the box they are drawn from (the ensemble's
+# ranges): Emax, Emin (mmHg/ml), HR (bpm), Windkessel Z, C, R (the reference
+# set 0.05, 1.5, 1.0 times U[0.7, 1.3]) and the membrane stiffness k
+SURROGATE_NAMES = ("Emax", "Emin", "HR", "Z", "C", "R", "k")
+SURROGATE_LO = np.array([1.5, 0.04, 60.0, 0.05 * 0.7, 1.5 * 0.7, 1.0 * 0.7, 0.02])
+SURROGATE_HI = np.array([3.0, 0.08, 100.0, 0.05 * 1.3, 1.5 * 1.3, 1.0 * 1.3, 0.1])
+
+
+def surrogate_params(n, seed, lo=SURROGATE_LO, hi=SURROGATE_HI):
+    """n parameter vectors drawn uniformly from the box [lo, hi]."""
+    rng = np.random.default_rng(seed)
+    return lo + (hi - lo) * rng.random((n, len(lo)))
+
+
+def surrogate_config(p, r=11, L=104, st=2000.0):
+    """Elastic tube of fixed geometry (r = 11, length 104: the midpoints of
+    the ensemble's ranges) driven by the parameter vector p (the 7 inputs),
+    with the 16-bit study's time scale and wall (tau 0.6, bending 1e-2).
+    steps: three beats at the vector's heart rate."""
+    Emax, Emin, HR, Z, C, R, k = (float(v) for v in p)
+    n = 2 * r + 8
+    sc = scales(st, 8000.0 * (r / 48.0) ** 2 * (st / 25000.0), 2.5e-6)
+    c = _elastic_tube(n, n, L + 2, float(r), 0.5, k, 1e-2, sc, tau=0.6, Emax=Emax, Emin=Emin, HR=HR,
+                      Z=Z, C=C, R=R)
+    beat = 60.0 / HR * st
+    c.update(name=f"surrogate_r{r}_L{L}", beat=beat, steps=int(math.ceil(3 * beat)) + 1)
+    return c
+
+
+def mlp_init(dims, seed):
+    """Flat FP64 initial parameters of an MLP with layer widths dims: for each
+    layer W (out x in, row-major) then b, both U(-1/sqrt(in), 1/sqrt(in))."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for k in range(len(dims) - 1):
+        fan_in, fan_out = dims[k], dims[k + 1]
+        a = 1.0 / np.sqrt(fan_in)
+        parts.append(rng.uniform(-a, a, fan_out * fan_in))
+        parts.append(rng.uniform(-a, a, fan_out))
+    return np.concatenate(parts)

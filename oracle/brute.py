@@ -98,7 +98,7 @@ class Boundary:
         self.which, self.kind, self.par = which, kind, list(par) + [0.0] * 16
         self.Pw = state[0] if (kind == 2 and len(state)) else 0.0
         self.Pv = (state[0] if len(state) else self.par[4]) if kind == 3 else 0.0
-        self.open, self.Td, self.cycle = False, -1, 0
+        self.open, self.inflow, self.Td, self.cycle = False, False, -1, 0
         self.mode, self.pstar, self.vc, self.S, self.snap, self.area = 0, 0.0, 0.0, 1.0, False, 1.0
 
     def advance(self, n, Qp, Pbar):
@@ -124,12 +124,15 @@ class Boundary:
             Tc, NS = p[2], p[5]
             cyc = int(math.floor(n / Tc))
             if cyc != self.cycle:
-                self.cycle, self.Pv, self.open, self.Td = cyc, p[4], False, -1
+                self.cycle, self.Pv, self.open, self.inflow, self.Td = cyc, p[4], False, False, -1
             Ev, dEv = elastance(p, n - cyc * Tc)
-            if self.open and Qp < 0.0:
+            # closes once inflow, having started, turns negative
+            if self.open and self.inflow and Qp < 0.0:
                 self.open, self.Td, self.snap = False, n, True
-            elif (not self.open) and self.Td < 0 and self.Pv > Pbar:
-                self.open = True
+            elif self.open:
+                self.inflow = self.inflow or Qp > 0.0
+            elif self.Td < 0 and self.Pv > Pbar:
+                self.open, self.inflow = True, False
             Q = Qp if self.open else 0.0
             # dPv/dt = (E'/E) Pv - E Q  (Eq. LVE with C_v = 1/E)
             self.Pv = self.Pv + (dEv / Ev) * self.Pv - Ev * Q

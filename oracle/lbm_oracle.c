@@ -190,6 +190,7 @@ typedef struct {
   /* state */
   real Pw, Pv;
   int open;
+  int inflow;     /* inflow (Q > 0) seen since the valve opened */
   long Td, cycle;
   /* result of the last update */
   int vmode;      /* 0: pressure-type coupling, 1: velocity-type */
@@ -263,17 +264,25 @@ static void bc_update(orc_bc* c, long n, real Qp, real Pbar) {
         c->cycle = cyc;
         c->Pv = p[4];
         c->open = 0;
+        c->inflow = 0;
         c->Td = -1;
       }
       real E, dE;
       elastance(p, (real)n - (real)cyc * Tc, &E, &dE);
       real Cv = 1 / E, dCv = -dE / (E * E);
-      if (c->open && Qp < 0) { /* inflow reached zero: valve closes */
+      /* The valve closes when the inflow, after ejection has begun, drops
+       * below zero; the flux of the first steps after opening still carries
+       * the closed valve's small residual (either sign), which does not
+       * count as the inflow reaching zero. */
+      if (c->open && c->inflow && Qp < 0) { /* inflow reached zero: valve closes */
         c->open = 0;
         c->Td = n;
         c->snap = 1;
-      } else if (!c->open && c->Td < 0 && c->Pv > Pbar) { /* P_v above aortic */
+      } else if (c->open) {
+        if (Qp > 0) c->inflow = 1;
+      } else if (c->Td < 0 && c->Pv > Pbar) { /* P_v above aortic */
         c->open = 1;
+        c->inflow = 0;
       }
       real Q = c->open ? Qp : 0;
       /* Eq. LVE, forward Euler */

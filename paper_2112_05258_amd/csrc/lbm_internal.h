@@ -40,6 +40,7 @@ struct BcDev {
   double Pw, Pv;
   int64_t Td, cycle;
   int32_t open;
+  int32_t inflow;          // inflow seen since the valve opened (LV)
   // output of the last update (valid for the step being taken)
   int32_t vmode;           // 0 pressure type, 1 velocity type
   int32_t vkind;           // VK_*

@@ -152,16 +152,22 @@ __device__ void zerod_update(BcDev& b, int64_t n, double Qp, double Pbar) {
         b.cycle = cyc;
         b.Pv = p[4];
         b.open = 0;
+        b.inflow = 0;
         b.Td = -1;
       }
       double E, dE;
       elastance(p, (double)n - (double)cyc * p[2], E, dE);
-      if (b.open && Qp < 0.0) {
+      // closes when the inflow turns negative after ejection has begun (the
+      // residual flux of the first steps after opening does not count)
+      if (b.open && b.inflow && Qp < 0.0) {
         b.open = 0;
         b.Td = n;
         b.snap = 1;
-      } else if (!b.open && b.Td < 0 && b.Pv > Pbar) {
+      } else if (b.open) {
+        if (Qp > 0.0) b.inflow = 1;
+      } else if (b.Td < 0 && b.Pv > Pbar) {
         b.open = 1;
+        b.inflow = 0;
       }
       const double Q = b.open ? Qp : 0.0;
       // dPv/dt = -(C' Pv + Q)/C with C = 1/E  <=>  dPv/dt = (E'/E) Pv - E Q
@@ -496,19 +502,29 @@ __global__ __launch_bounds__(WBLOCK) void k_wall(Dev d, int parity) {
   const int wv = (int)threadIdx.x >> 6, ln = (int)threadIdx.x & 63;
   const int j = ((int)blockIdx.x % ntj) * TJ + 2 * (ln & 7) + (wv & 1);
   const int k = ((int)blockIdx.x / ntj) * TK + 2 * (ln >> 3) + (wv >> 1);
-  const bool valid = j < nth && k < nzl;
-  const int64_t p = valid ? j + (int64_t)nth * k : 0;
+  const bool point = j < nth && k < nzl;
+  const int64_t p = point ? j + (int64_t)nth * k : 0;
   // the wall is carried as displacement D = X - X0 (ping-pong D^n / D^{n-1})
   const double* Dc = I.Xab[parity];
   double* Dn = I.Xab[parity ^ 1];
   const double3 X0 = ld3(I.X0, p), D = ld3(Dc, p), Dm = ld3(Dn, p);
+  // A point that is not finite or has left the lattice box (a run that has
+  // blown up) cannot be in its band: it is flagged and takes no part, so
+  // that no stencil index is ever formed from it (the comparisons are false
+  // for NaN).
+  const double px = X0.x + D.x, py = X0.y + D.y, pz = X0.z + D.z;
+  const bool inside = px >= -1.0 && py >= -1.0 && pz >= -1.0 && px <= (double)I.nx &&
+                      py <= (double)I.ny && pz <= (double)I.nz;
+  if (point && !inside) atomicOr(d.err, ERR_BAND);
+  const bool valid = point && inside;
 
   if (threadIdx.x < 3) {
     smin[threadIdx.x] = 0x7fffffff;
     smax[threadIdx.x] = -0x7fffffff;
   }
   __syncthreads();
-  const int bx0 = (int)floor(X0.x + D.x) - 1, by0 = (int)floor(X0.y + D.y) - 1, bz0 = (int)floor(X0.z + D.z) - 1;
+  const int bx0 = valid ? (int)floor(px) - 1 : 0, by0 = valid ? (int)floor(py) - 1 : 0,
+            bz0 = valid ? (int)floor(pz) - 1 : 0;
   R wx[4], wy[4], wz[4];
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
@@ -521,10 +537,13 @@ __global__ __launch_bounds__(WBLOCK) void k_wall(Dev d, int parity) {
     atomicMax(&smax[0], bx0); atomicMax(&smax[1], by0); atomicMax(&smax[2], bz0);
   }
   __syncthreads();
+  // every valid point has its stencil base in [-2, n], so the extents are
+  // small and positive; a tile without a valid point has smin > smax
   const int ox = smin[0], oy = smin[1], oz = smin[2];
-  const int ex = smax[0] - ox + 4, ey = smax[1] - oy + 4, ez = smax[2] - oz + 4;
+  const bool any = smin[0] <= smax[0];
+  const int ex = any ? smax[0] - ox + 4 : 0, ey = any ? smax[1] - oy + 4 : 0, ez = any ? smax[2] - oz + 4 : 0;
   const int64_t vol = (int64_t)ex * ey * ez;
-  const bool staged = vol <= BOXCAP;          // uniform over the block
+  const bool staged = any && vol <= BOXCAP;   // uniform over the block
   const R4* U = (const R4*)I.u4;
   auto box_cell = [&](int q, int& x, int& y, int& z) {
     x = ox + q % ex;

@@ -1,0 +1,96 @@
+"""16-bit shifted storage (FP16S, BF16S) against the FP64 oracle.
+
+Workload: lbm_inputs.precision_study, an elastic tube driven by the
+LV-elastance inlet with a Windkessel outlet, three beats (4800 steps).  The
+oracle's record (boundary waveforms every 8 steps, mid-length velocity at
+two instants) is stored under tests/golden, written by
+tests/golden/make_precision_study.py, which calls only the oracle.
+
+Error measures (P is the mean inlet pressure, Q the inlet flux):
+  pulse  max_t |P - P_ref| / (max P_ref - min P_ref): pointwise pressure
+         error relative to the pulse pressure
+  peak   max over beats of |max_beat P - max_beat P_ref| / max_beat P_ref:
+         error of the systolic peak (P in the model's absolute units)
+  Q, u   relative L2 of the inlet flux waveform and of the velocity slices
+The stored-as-16-bit populations are collided in FP32, the 0D models and
+boundary reductions run in FP64.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import lbm_inputs as L
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+EVERY = 8
+COLS = (0, 1, 2, 3, 4, 9, 10, 11)
+
+
+@pytest.fixture(scope="module")
+def amd():
+    import paper_2112_05258_amd as amd
+    amd.lib()
+    return amd
+
+
+@pytest.fixture(scope="module")
+def golden():
+    w = np.loadtxt(os.path.join(HERE, "golden", "precision_study_waveforms.txt"))
+    s = np.loadtxt(os.path.join(HERE, "golden", "precision_study_midplane.txt"))
+    return w, s
+
+
+def study_errors(w, s, wr, sr, beat):
+    """Error measures of a run (w, s) against the reference (wr, sr)."""
+    P, Pr = w[:, 2], wr[:, 2]
+    out = {"pulse": np.abs(P - Pr).max() / (Pr.max() - Pr.min())}
+    nb = int(round(wr[-1, 0] + 1)) // beat
+    peaks = []
+    for b in range(nb):
+        m = (wr[:, 0] >= b * beat) & (wr[:, 0] < (b + 1) * beat)
+        peaks.append(abs(P[m].max() - Pr[m].max()) / Pr[m].max())
+    out["peak"] = max(peaks)
+    out["Q"] = np.linalg.norm(w[:, 1] - wr[:, 1]) / np.linalg.norm(wr[:, 1])
+    out["u"] = np.linalg.norm(s[:, 3:] - sr[:, 3:]) / np.linalg.norm(sr[:, 3:])
+    return out
+
+
+def run_study(amd, precision):
+    c = L.precision_study()
+    s = amd.solver_from_config(c, precision=precision, wave_cap=c["steps"])
+    zmid = c["nz"] // 2
+    yy, xx = np.mgrid[0:c["ny"], 0:c["nx"]]
+    cx, cy = (c["nx"] - 1) / 2.0, (c["ny"] - 1) / 2.0
+    fl = (c["flags"][zmid] == L.FLUID) & (np.hypot(xx - cx, yy - cy) < 12.0)
+    slices = []
+    for t in (3840, 4800):
+        s.step(t - s.t)
+        s.sync()
+        _, u = s.fields()
+        ys, xs = np.nonzero(fl)
+        slices.append(np.column_stack([np.full(len(xs), t), xs, ys, u[zmid][fl]]))
+    w = s.waveforms()[EVERY - 1::EVERY][:, COLS]
+    s.close()
+    return w, np.vstack(slices), c
+
+
+@pytest.mark.parametrize("precision,bars", [
+    ("FP64", dict(pulse=1e-8, peak=1e-8, Q=1e-8, u=1e-8)),
+    ("FP32", dict(pulse=1e-3, peak=1e-3, Q=1e-3, u=1e-3)),
+    ("FP16S", dict(pulse=1e-2, peak=1e-2, Q=2e-2, u=2e-2)),
+    ("BF16S", dict(pulse=5e-2, peak=5e-2, Q=1e-1, u=1e-1)),
+])
+def test_storage_precision_vs_oracle(amd, golden, precision, bars):
+    wr, sr = golden
+    w, s, c = run_study(amd, getattr(amd, precision))
+    assert w.shape == wr.shape and np.array_equal(w[:, 0], wr[:, 0])
+    assert np.array_equal(s[:, :3], sr[:, :3])
+    e = study_errors(w, s, wr, sr, beat=int(round(c["steps"] / 3)))
+    opens = [int((np.diff(x[:, 7]) == 1).sum()) for x in (w, wr)]
+    print(precision, {k: f"{v:.2e}" for k, v in e.items()}, "valve openings", opens, flush=True)
+    assert opens[0] == opens[1] == 3
+    for k, v in bars.items():
+        assert e[k] <= v, (k, e[k], v)

@@ -186,6 +186,11 @@ def test_lv_valve_switching(oracle_mod):
     assert r["open"] == 0 and r["vmode"] == 1
     r = z.update(1, 0.0, -1.0)                              # P_v > P_bar: opens
     assert r["open"] == 1 and r["vmode"] == 0 and r["pstar"] == r["Pv"]
+    r = z.update(2, -1e-9, -1.0)        # residual backflow before any inflow: stays open
+    assert r["open"] == 1 and r["snap"] == 0
+    z = oracle_mod.ZeroD(0, L.BC_LV_ELASTANCE, par)
+    z.update(0, 0.0, 1.0)
+    r = z.update(1, 0.0, -1.0)
     Pv = r["Pv"]
     E, dE = oracle_mod.elastance(par, 2.0)
     r = z.update(2, 1e-3, -1.0)                             # ejecting: P_v follows Eq. LVE
