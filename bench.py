@@ -147,6 +147,7 @@ def precision_study_errors():
             m = (wr[:, 0] >= b * beat) & (wr[:, 0] < (b + 1) * beat)
             peaks.append(abs(P[m].max() - Pr[m].max()) / Pr[m].max())
         out[name] = {"pressure_max_err_over_pulse": float(f"{np.abs(P - Pr).max() / (Pr.max() - Pr.min()):.3e}"),
+                     "pressure_pulse_rel_l2": float(f"{np.linalg.norm(P - Pr) / np.linalg.norm(Pr - c['p_init']):.3e}"),
                      "peak_pressure_rel_err": float(f"{max(peaks):.3e}"),
                      "inlet_flux_rel_l2": float(f"{np.linalg.norm(w[:, 1] - wr[:, 1]) / np.linalg.norm(wr[:, 1]):.3e}")}
     return out

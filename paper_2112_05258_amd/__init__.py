@@ -74,6 +74,34 @@ SYMBOLS = {
     "lbm_bytes_per_population": (C.c_int32, [C.c_void_p]),
 }
 
+
+
+class SurConfig(C.Structure):
+    _fields_ = [("n_in", C.c_int32), ("width", C.c_int32), ("n_hidden", C.c_int32), ("n_out", C.c_int32),
+                ("max_batch", C.c_int32), ("train_batch", C.c_int32)]
+
+
+# learned surrogate (include/lbm_surrogate.h)
+SUR_SYMBOLS = {
+    "lbm_sur_num_params": (C.c_int64, [C.POINTER(SurConfig)]),
+    "lbm_sur_query_sizes": (C.c_int, [C.POINTER(SurConfig), C.POINTER(C.c_size_t)]),
+    "lbm_sur_init": (C.c_int, [C.POINTER(SurConfig), C.c_void_p, C.c_size_t, C.c_void_p, C.POINTER(C.c_void_p)]),
+    "lbm_sur_set_params": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_int64]),
+    "lbm_sur_get_params": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_int64]),
+    "lbm_sur_set_scaling": (C.c_int, [C.c_void_p] + [C.POINTER(C.c_double)] * 4),
+    "lbm_sur_grad": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p,
+                               C.POINTER(C.c_double)]),
+    "lbm_sur_train_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int32,
+                                     C.c_double, C.c_double, C.c_double, C.c_double, C.POINTER(C.c_double)]),
+    "lbm_sur_predict": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
+    "lbm_sur_set_timing": (C.c_int, [C.c_void_p, C.c_int32]),
+    "lbm_sur_gemm_time": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_double),
+                                    C.POINTER(C.c_double)]),
+    "lbm_sur_sync": (C.c_int, [C.c_void_p]),
+    "lbm_sur_last_error": (C.c_char_p, [C.c_void_p]),
+    "lbm_sur_destroy": (C.c_int, [C.c_void_p]),
+}
+
 _lib = None
 
 
@@ -88,7 +116,7 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is not built; run python -m paper_2112_05258_amd.build")
         L = C.CDLL(LIB_PATH)
-        for name, (res, args) in SYMBOLS.items():
+        for name, (res, args) in list(SYMBOLS.items()) + list(SUR_SYMBOLS.items()):
             f = getattr(L, name)
             f.restype = res
             f.argtypes = args

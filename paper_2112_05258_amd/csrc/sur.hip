@@ -1,0 +1,708 @@
+// Learned surrogate: MLP forward, backward and Adam on the gfx950 matrix
+// cores.  BF16 operands, FP32 accumulation (v_mfma_f32_32x32x16_bf16), FP32
+// master weights, gradients and Adam moments.
+//
+// Kernels
+//   k_gemm<AKC, BKC, EPI>  C = A B with a fused epilogue; A is m x k and B is
+//                          k x n, each stored either k-contiguous (KC) or
+//                          m- resp. n-contiguous.  The three forms are the
+//                          forward product (h W^T), the backward data
+//                          product (dz W) and the weight gradient (dz^T h).
+//   k_prep_x / k_prep_t    input normalisation (optionally gathering a
+//                          shuffled mini-batch) and target standardisation
+//   k_loss                 squared error, its gradient in BF16, loss sum
+//   k_colsum               bias gradients
+//   k_adam / k_cast        Adam step; BF16 (K-padded) copy of the weights
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lbm_surrogate.h"
+
+namespace sur {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// block tile BM x BN, k-step BK; 4 waves, each 64 x 64 = 2 x 2 MFMA tiles
+constexpr int BM = 128, BN = 128, BK = 32;
+constexpr int LDK = BK + 8;  // LDS row pitch in bf16 (80 B: 16-B aligned, staggers banks)
+constexpr int KPAD = 32;     // input width of the first layer is padded to this
+
+enum { EPI_FWD_GELU = 0, EPI_FWD_OUT = 1, EPI_BWD_GELU = 2, EPI_WGRAD = 3 };
+
+// FP32 -> BF16, round to nearest even (NaN kept quiet)
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+
+// d/dz [z Phi(z)] = Phi(z) + z phi(z)
+__device__ __forceinline__ float gelu_grad(float z) {
+  return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * expf(-0.5f * z * z);
+}
+
+struct GemmArgs {
+  const uint16_t* A;
+  int64_t lda;
+  int a_ext;            // rows of A along m that exist in memory (loads beyond read zero)
+  const uint16_t* B;
+  int64_t ldb;
+  int b_ext;            // the same along n
+  int M, N, K;          // output m x n (stores are bounded by M, N), depth K (multiple of 8)
+  const float* bias;    // n
+  const float* zin;     // EPI_BWD_GELU: pre-activation of the layer below (ldo)
+  float* outf;          // FP32 output (EPI_FWD_OUT, EPI_WGRAD)
+  uint16_t* outh;       // BF16 output (EPI_FWD_GELU, EPI_BWD_GELU)
+  float* zout;          // EPI_FWD_GELU: pre-activation (may be null)
+  int64_t ldo;
+  const float* mu;      // EPI_FWD_OUT: output de-standardisation (may be null)
+  const float* sigma;
+};
+
+// Stage a 128 x 32 tile (rows r0.., depth k0..) into LDS as S[r][k].
+template <bool KC>
+__device__ __forceinline__ void load_tile(uint16_t* S, const uint16_t* G, int64_t ld, int ext, int r0, int k0,
+                                          int K, int tid) {
+  if (KC) {  // G[r * ld + k]: one 16-byte chunk of 8 k per load
+    for (int c = tid; c < 128 * (BK / 8); c += 256) {
+      const int r = c / (BK / 8), kc = (c % (BK / 8)) * 8;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (r0 + r < ext && k0 + kc + 8 <= K) v = *(const uint4*)(G + (int64_t)(r0 + r) * ld + k0 + kc);
+      *(uint4*)(S + r * LDK + kc) = v;
+    }
+  } else {   // G[k * ld + r]: 8 consecutive r per load, transposed into LDS
+    for (int c = tid; c < BK * 16; c += 256) {
+      const int k = c / 16, rc = (c % 16) * 8;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (k0 + k < K && r0 + rc + 8 <= ext) v = *(const uint4*)(G + (int64_t)(k0 + k) * ld + r0 + rc);
+      const uint16_t* e = (const uint16_t*)&v;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) S[(rc + j) * LDK + k] = e[j];
+    }
+  }
+}
+
+template <bool AKC, bool BKC, int EPI>
+__global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
+  __shared__ __attribute__((aligned(16))) uint16_t As[BM * LDK];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[BN * LDK];
+  const int tid = (int)threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int m0 = (int)blockIdx.y * BM, n0 = (int)blockIdx.x * BN;
+  const int wm = (wv >> 1) * 64, wn = (wv & 1) * 64;
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
+
+  // operand fragments: lane l supplies row (l % 32) and the 8 k of half (l / 32)
+  const int fr = lane & 31, fk = (lane >> 5) * 8;
+  for (int k0 = 0; k0 < g.K; k0 += BK) {
+    load_tile<AKC>(As, g.A, g.lda, g.a_ext, m0, k0, g.K, tid);
+    load_tile<BKC>(Bs, g.B, g.ldb, g.b_ext, n0, k0, g.K, tid);
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 16) {
+      bf16x8 a[2], b[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        a[t] = *(const bf16x8*)(As + (wm + t * 32 + fr) * LDK + kk + fk);
+        b[t] = *(const bf16x8*)(Bs + (wn + t * 32 + fr) * LDK + kk + fk);
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+
+  // accumulator v of lane l holds row 8 (v / 4) + 4 (l / 32) + v % 4 and
+  // column l % 32 of its 32 x 32 tile
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int m = m0 + wm + i * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
+        const int n = n0 + wn + j * 32 + (lane & 31);
+        if (m >= g.M || n >= g.N) continue;
+        const float s = acc[i][j][v];
+        const int64_t o = (int64_t)m * g.ldo + n;
+        if (EPI == EPI_FWD_GELU) {
+          const float z = s + g.bias[n];
+          if (g.zout) g.zout[o] = z;
+          g.outh[o] = f2bf(gelu(z));
+        } else if (EPI == EPI_FWD_OUT) {
+          const float y = s + g.bias[n];
+          g.outf[o] = g.mu ? g.mu[n] + g.sigma[n] * y : y;
+        } else if (EPI == EPI_BWD_GELU) {
+          g.outh[o] = f2bf(s * gelu_grad(g.zin[o]));
+        } else {
+          g.outf[o] = s;
+        }
+      }
+}
+
+// inputs: X0[r][j] = 2 (x - lo) / (hi - lo) - 1 for r < m and j < n_in; 0 for
+// the padding columns up to KPAD and the padding rows m <= r < mp
+// (rows picked by idx outside [0, nrows) read zeros and set *err)
+__global__ void k_prep_x(const float* __restrict__ x, int nrows, const int32_t* __restrict__ idx, int m, int mp,
+                         int nin, const float* __restrict__ lo, const float* __restrict__ hi,
+                         uint16_t* __restrict__ X0, int* __restrict__ err) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)mp * KPAD) return;
+  const int r = (int)(e / KPAD), j = (int)(e % KPAD);
+  float v = 0.0f;
+  if (j < nin && r < m) {
+    const int64_t src = idx ? idx[r] : r;
+    if (src >= 0 && src < nrows)
+      v = 2.0f * (x[src * nin + j] - lo[j]) / (hi[j] - lo[j]) - 1.0f;
+    else
+      atomicOr(err, 1);
+  }
+  X0[e] = f2bf(v);
+}
+
+// standardised targets tn = (t - mu) / sigma
+__global__ void k_prep_t(const float* __restrict__ t, int nrows, const int32_t* __restrict__ idx, int m, int nout,
+                         const float* __restrict__ mu, const float* __restrict__ sigma, float* __restrict__ tn) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)m * nout) return;
+  const int r = (int)(e / nout), j = (int)(e % nout);
+  const int64_t src = idx ? idx[r] : r;
+  tn[e] = (src >= 0 && src < nrows) ? (t[src * nout + j] - mu[j]) / sigma[j] : 0.0f;
+}
+
+// loss = mean (y - tn)^2; dy = 2 (y - tn) / count in BF16
+__global__ __launch_bounds__(256) void k_loss(const float* __restrict__ y, const float* __restrict__ tn, int64_t n,
+                                              uint16_t* __restrict__ dy, double* __restrict__ loss) {
+  __shared__ double part[256];
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double s = 0.0;
+  if (e < n) {
+    const float d = y[e] - tn[e];
+    dy[e] = f2bf(2.0f * d / (float)n);
+    s = (double)d * (double)d;
+  }
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd(loss, part[0] / (double)n);
+}
+
+// db[j] = sum_r dz[r][j]
+__global__ void k_colsum(const uint16_t* __restrict__ dz, int m, int n, float* __restrict__ db) {
+  const int j = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (j >= n) return;
+  float s = 0.0f;
+  for (int r = 0; r < m; ++r) s += __uint_as_float((uint32_t)dz[(int64_t)r * n + j] << 16);
+  db[j] = s;
+}
+
+struct LayerMap {
+  int nl;
+  int64_t off[8];       // first parameter of layer l (W then b)
+  int64_t woff[8];      // first element of its BF16 weight copy
+  int out[8], in[8], kp[8];
+};
+
+// BF16 copy of the weights, rows padded to kp columns (the padding stays 0)
+__device__ __forceinline__ void to_bf16_copy(const LayerMap& L, int64_t p, float w, uint16_t* wb) {
+#pragma unroll 1
+  for (int l = 0; l < L.nl; ++l) {
+    const int64_t nw = (int64_t)L.out[l] * L.in[l];
+    if (p >= L.off[l] && p < L.off[l] + nw) {
+      const int64_t q = p - L.off[l];
+      wb[L.woff[l] + (q / L.in[l]) * L.kp[l] + q % L.in[l]] = f2bf(w);
+      return;
+    }
+  }
+}
+
+__global__ void k_cast(const float* __restrict__ w, int64_t n, LayerMap L, uint16_t* __restrict__ wb) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < n) to_bf16_copy(L, p, w[p], wb);
+}
+
+__global__ void k_adam(float* __restrict__ w, float* __restrict__ m1, float* __restrict__ m2,
+                       const float* __restrict__ g, int64_t n, float lr, float b1, float b2, float eps,
+                       float bc1, float bc2, LayerMap L, uint16_t* __restrict__ wb) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const float gp = g[p];
+  const float a = b1 * m1[p] + (1.0f - b1) * gp;
+  const float b = b2 * m2[p] + (1.0f - b2) * gp * gp;
+  m1[p] = a;
+  m2[p] = b;
+  const float wn = w[p] - lr * (a / bc1) / (sqrtf(b / bc2) + eps);
+  w[p] = wn;
+  to_bf16_copy(L, p, wn, wb);
+}
+
+}  // namespace sur
+
+using namespace sur;
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+
+struct lbm_sur_ctx {
+  lbm_sur_config cfg;
+  hipStream_t stream;
+  std::string err;
+  LayerMap L;
+  int64_t np, nwb;
+  // device regions
+  float *w, *m1, *m2, *g, *lo, *hi, *mu, *sigma, *Y, *Tn;
+  uint16_t *wb, *X0, *dz[2];
+  uint16_t* H[8];
+  float* Z[8];
+  double* loss;
+  int* errw;            // device error word (bit 0: index out of range)
+  int64_t step;
+  // timing
+  bool timing;
+  std::vector<hipEvent_t> ev;
+  int nev;
+  int64_t launches;
+  double flops, ms;
+};
+
+namespace {
+
+lbm_status fail(lbm_sur_ctx* c, lbm_status s, const std::string& m) {
+  if (c) c->err = m;
+  return s;
+}
+
+#define SURCHK(c, x)                                                               \
+  do {                                                                             \
+    hipError_t e_ = (x);                                                           \
+    if (e_ != hipSuccess) return fail(c, LBM_E_DEVICE, std::string(#x) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+bool valid_cfg(const lbm_sur_config* c) {
+  return c && c->n_in >= 1 && c->n_in <= KPAD && c->width >= 32 && c->width % 32 == 0 && c->n_hidden >= 1 &&
+         c->n_hidden <= 7 && c->n_out >= 32 && c->n_out % 32 == 0 && c->max_batch >= 1 && c->train_batch >= 8 &&
+         c->train_batch % 8 == 0 && c->max_batch <= (1 << 22) && c->train_batch <= (1 << 20);
+}
+
+LayerMap layer_map(const lbm_sur_config& c, int64_t& np, int64_t& nwb) {
+  LayerMap L;
+  std::memset(&L, 0, sizeof L);
+  L.nl = c.n_hidden + 1;
+  np = 0;
+  nwb = 0;
+  for (int l = 0; l < L.nl; ++l) {
+    L.in[l] = l == 0 ? c.n_in : c.width;
+    L.out[l] = l == L.nl - 1 ? c.n_out : c.width;
+    L.kp[l] = l == 0 ? KPAD : c.width;
+    L.off[l] = np;
+    L.woff[l] = nwb;
+    np += (int64_t)L.out[l] * L.in[l] + L.out[l];
+    nwb += (int64_t)L.out[l] * L.kp[l];
+  }
+  return L;
+}
+
+struct Plan {
+  size_t w, m1, m2, g, wb, lo, hi, mu, sigma, X0, H[8], Z[8], Y, Tn, dz[2], loss, errw, total;
+};
+
+size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
+
+Plan plan(const lbm_sur_config& c) {
+  int64_t np, nwb;
+  layer_map(c, np, nwb);
+  Plan p;
+  std::memset(&p, 0, sizeof p);
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t r = o; o = al(o + bytes); return r; };
+  const size_t rows_inf = (size_t)c.max_batch, rows_tr = (size_t)c.train_batch;
+  const size_t rows = rows_inf > rows_tr ? rows_inf : rows_tr;
+  p.w = take(np * 4);
+  p.m1 = take(np * 4);
+  p.m2 = take(np * 4);
+  p.g = take(np * 4);
+  p.wb = take(nwb * 2);
+  p.lo = take(KPAD * 4);
+  p.hi = take(KPAD * 4);
+  p.mu = take((size_t)c.n_out * 4);
+  p.sigma = take((size_t)c.n_out * 4);
+  p.X0 = take(rows * KPAD * 2);
+  // hidden activations: every layer's for training, a ping-pong pair for
+  // inference
+  for (int l = 0; l < c.n_hidden; ++l) {
+    const size_t r = l < 2 ? rows : rows_tr;
+    p.H[l] = take(r * (size_t)c.width * 2);
+  }
+  for (int l = 0; l < c.n_hidden; ++l) p.Z[l] = take(rows_tr * (size_t)c.width * 4);
+  p.Y = take(rows_tr * (size_t)c.n_out * 4);
+  p.Tn = take(rows_tr * (size_t)c.n_out * 4);
+  const size_t wmax = (size_t)(c.width > c.n_out ? c.width : c.n_out);
+  p.dz[0] = take(rows_tr * wmax * 2);
+  p.dz[1] = take(rows_tr * wmax * 2);
+  p.loss = take(8);
+  p.errw = take(4);
+  p.total = o;
+  return p;
+}
+
+bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
+
+template <bool AKC, bool BKC, int EPI>
+lbm_status gemm(lbm_sur_ctx* c, const GemmArgs& a) {
+  // the tile loaders read 16-byte chunks: rows and depth in multiples of 8
+  if (a.K % 8 || a.lda % 8 || a.ldb % 8 || !aligned16(a.A) || !aligned16(a.B) || (!AKC && a.a_ext % 8) ||
+      (!BKC && a.b_ext % 8) || a.M <= 0 || a.N <= 0)
+    return fail(c, LBM_E_INVAL, "matrix product shape or alignment not supported");
+  dim3 grid((a.N + BN - 1) / BN, (a.M + BM - 1) / BM);
+  const bool t = c->timing && c->nev + 2 <= (int)c->ev.size();
+  if (t) SURCHK(c, hipEventRecord(c->ev[c->nev], c->stream));
+  hipLaunchKernelGGL((k_gemm<AKC, BKC, EPI>), grid, dim3(256), 0, c->stream, a);
+  SURCHK(c, hipGetLastError());
+  if (t) {
+    SURCHK(c, hipEventRecord(c->ev[c->nev + 1], c->stream));
+    c->nev += 2;
+    c->flops += 2.0 * a.M * (double)a.N * a.K;
+  }
+  return LBM_OK;
+}
+
+#define TRY(x)                      \
+  do {                              \
+    lbm_status s_ = (x);            \
+    if (s_ != LBM_OK) return s_;    \
+  } while (0)
+
+unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+// forward pass over m rows from X0; training keeps Z and every H, inference
+// ping-pongs two H buffers and writes physical outputs to y
+lbm_status forward(lbm_sur_ctx* c, int m, bool train, float* y) {
+  const lbm_sur_config& C = c->cfg;
+  const uint16_t* in = c->X0;
+  int64_t ldin = KPAD;
+  for (int l = 0; l < C.n_hidden; ++l) {
+    GemmArgs a;
+    std::memset(&a, 0, sizeof a);
+    uint16_t* out = train ? c->H[l] : c->H[l & 1];
+    a.A = in; a.lda = ldin; a.a_ext = m;
+    a.B = c->wb + c->L.woff[l]; a.ldb = c->L.kp[l]; a.b_ext = C.width;
+    a.M = m; a.N = C.width; a.K = (int)ldin;
+    a.bias = c->w + c->L.off[l] + (int64_t)c->L.out[l] * c->L.in[l];
+    a.outh = out; a.zout = train ? c->Z[l] : nullptr; a.ldo = C.width;
+    TRY((gemm<true, true, EPI_FWD_GELU>(c, a)));
+    in = out;
+    ldin = C.width;
+  }
+  const int l = C.n_hidden;
+  GemmArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.A = in; a.lda = ldin; a.a_ext = m;
+  a.B = c->wb + c->L.woff[l]; a.ldb = c->L.kp[l]; a.b_ext = C.n_out;
+  a.M = m; a.N = C.n_out; a.K = (int)ldin;
+  a.bias = c->w + c->L.off[l] + (int64_t)c->L.out[l] * c->L.in[l];
+  a.outf = train ? c->Y : y; a.ldo = C.n_out;
+  a.mu = train ? nullptr : c->mu;
+  a.sigma = train ? nullptr : c->sigma;
+  return gemm<true, true, EPI_FWD_OUT>(c, a);
+}
+
+lbm_status check_batch(lbm_sur_ctx* c, const float* x, int m, int limit) {
+  if (!x || ((uintptr_t)x & 3)) return fail(c, LBM_E_INVAL, "input rows must be a 4-byte aligned device pointer");
+  if (m < 1 || m > limit) return fail(c, LBM_E_INVAL, "row count outside [1, configured batch]");
+  return LBM_OK;
+}
+
+// forward, loss and backward into c->g; the loss lands in c->loss
+lbm_status grad_pass(lbm_sur_ctx* c, const float* x, const float* t, int nrows, const int32_t* idx, int m) {
+  const lbm_sur_config& C = c->cfg;
+  TRY(check_batch(c, x, m, C.train_batch));
+  if (!t || ((uintptr_t)t & 3)) return fail(c, LBM_E_INVAL, "targets must be a 4-byte aligned device pointer");
+  if (nrows < 1 || (!idx && nrows < m)) return fail(c, LBM_E_INVAL, "fewer data rows than batch rows");
+  // the weight-gradient product reduces over the rows in chunks of 8: pad
+  // the batch's activations with zero rows up to a multiple of 8
+  const int mp = (m + 7) / 8 * 8;
+  hipLaunchKernelGGL(k_prep_x, dim3(blocks((int64_t)mp * KPAD, 256)), dim3(256), 0, c->stream, x, nrows, idx, m,
+                     mp, C.n_in, c->lo, c->hi, c->X0, c->errw);
+  SURCHK(c, hipGetLastError());
+  hipLaunchKernelGGL(k_prep_t, dim3(blocks((int64_t)m * C.n_out, 256)), dim3(256), 0, c->stream, t, nrows, idx, m,
+                     C.n_out, c->mu, c->sigma, c->Tn);
+  SURCHK(c, hipGetLastError());
+  TRY(forward(c, m, true, nullptr));
+  SURCHK(c, hipMemsetAsync(c->loss, 0, 8, c->stream));
+  hipLaunchKernelGGL(k_loss, dim3(blocks((int64_t)m * C.n_out, 256)), dim3(256), 0, c->stream, c->Y, c->Tn,
+                     (int64_t)m * C.n_out, c->dz[0], c->loss);
+  SURCHK(c, hipGetLastError());
+  int cur = 0;
+  for (int l = C.n_hidden; l >= 0; --l) {
+    const int nout = c->L.out[l], nin = c->L.in[l];
+    const uint16_t* hin = l == 0 ? c->X0 : c->H[l - 1];
+    const int64_t ldh = l == 0 ? KPAD : C.width;
+    // dW_l = dz^T h_{l-1}: (nout x m) (m x nin), reduction over the rows
+    GemmArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.A = c->dz[cur]; a.lda = nout; a.a_ext = nout;
+    a.B = hin; a.ldb = ldh; a.b_ext = (int)ldh;
+    a.M = nout; a.N = nin; a.K = mp;
+    a.outf = c->g + c->L.off[l]; a.ldo = nin;
+    TRY((gemm<false, false, EPI_WGRAD>(c, a)));
+    hipLaunchKernelGGL(k_colsum, dim3(blocks(nout, 256)), dim3(256), 0, c->stream, c->dz[cur], m, nout,
+                       c->g + c->L.off[l] + (int64_t)nout * nin);
+    SURCHK(c, hipGetLastError());
+    if (l == 0) break;
+    // dz_{l-1} = (dz W_l) * GELU'(z_{l-1}): (m x nout) (nout x nin)
+    std::memset(&a, 0, sizeof a);
+    a.A = c->dz[cur]; a.lda = nout; a.a_ext = m;
+    a.B = c->wb + c->L.woff[l]; a.ldb = c->L.kp[l]; a.b_ext = nin;
+    a.M = m; a.N = nin; a.K = nout;
+    a.zin = c->Z[l - 1]; a.outh = c->dz[cur ^ 1]; a.ldo = nin;
+    TRY((gemm<true, false, EPI_BWD_GELU>(c, a)));
+    cur ^= 1;
+  }
+  return LBM_OK;
+}
+
+// rows m..mp of the padded batch must be zero in every operand of the
+// weight-gradient product: dz (loss gradient and backward products) and h
+lbm_status zero_tail(lbm_sur_ctx* c, int m) {
+  const lbm_sur_config& C = c->cfg;
+  const int mp = (m + 7) / 8 * 8;
+  if (mp == m) return LBM_OK;
+  // dz holds rows of pitch n_out (loss gradient) or width (backward
+  // products): clear from the smaller pitch's row m to the larger's row mp
+  const size_t wmax = (size_t)(C.width > C.n_out ? C.width : C.n_out);
+  const size_t wmin = (size_t)(C.width < C.n_out ? C.width : C.n_out);
+  for (int k = 0; k < 2; ++k)
+    SURCHK(c, hipMemsetAsync(c->dz[k] + (size_t)m * wmin, 0, ((size_t)mp * wmax - (size_t)m * wmin) * 2, c->stream));
+  for (int l = 0; l < C.n_hidden; ++l)
+    SURCHK(c, hipMemsetAsync(c->H[l] + (size_t)m * C.width, 0, (size_t)(mp - m) * C.width * 2, c->stream));
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" lbm_status lbm_sur_sync(lbm_sur_ctx* c);
+
+namespace {
+lbm_status read_loss(lbm_sur_ctx* c, double* loss) {
+  TRY(lbm_sur_sync(c));
+  SURCHK(c, hipMemcpy(loss, c->loss, 8, hipMemcpyDeviceToHost));
+  return LBM_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int64_t lbm_sur_num_params(const lbm_sur_config* cfg) {
+  if (!valid_cfg(cfg)) return -1;
+  int64_t np, nwb;
+  layer_map(*cfg, np, nwb);
+  return np;
+}
+
+lbm_status lbm_sur_query_sizes(const lbm_sur_config* cfg, size_t* bytes) {
+  if (!valid_cfg(cfg) || !bytes) return LBM_E_INVAL;
+  *bytes = plan(*cfg).total;
+  return LBM_OK;
+}
+
+lbm_status lbm_sur_init(const lbm_sur_config* cfg, void* mem, size_t bytes, void* stream, lbm_sur_ctx** out) {
+  if (!out) return LBM_E_INVAL;
+  *out = nullptr;
+  if (!valid_cfg(cfg) || !mem || ((uintptr_t)mem & 255)) return LBM_E_INVAL;
+  const Plan p = plan(*cfg);
+  if (bytes < p.total) return LBM_E_INVAL;
+  lbm_sur_ctx* c = new lbm_sur_ctx();
+  c->cfg = *cfg;
+  c->stream = (hipStream_t)stream;
+  c->L = layer_map(*cfg, c->np, c->nwb);
+  char* b = (char*)mem;
+  c->w = (float*)(b + p.w); c->m1 = (float*)(b + p.m1); c->m2 = (float*)(b + p.m2); c->g = (float*)(b + p.g);
+  c->wb = (uint16_t*)(b + p.wb);
+  c->lo = (float*)(b + p.lo); c->hi = (float*)(b + p.hi); c->mu = (float*)(b + p.mu); c->sigma = (float*)(b + p.sigma);
+  c->X0 = (uint16_t*)(b + p.X0);
+  for (int l = 0; l < cfg->n_hidden; ++l) {
+    c->H[l] = (uint16_t*)(b + p.H[l]);
+    c->Z[l] = (float*)(b + p.Z[l]);
+  }
+  c->Y = (float*)(b + p.Y); c->Tn = (float*)(b + p.Tn);
+  c->dz[0] = (uint16_t*)(b + p.dz[0]); c->dz[1] = (uint16_t*)(b + p.dz[1]);
+  c->loss = (double*)(b + p.loss);
+  c->errw = (int*)(b + p.errw);
+  c->step = 0;
+  c->timing = false;
+  c->nev = 0;
+  c->launches = 0;
+  c->flops = c->ms = 0.0;
+  // zero everything once (padding columns of the BF16 weights and of X0,
+  // Adam moments, scaling); synchronous so the context is ready on return
+  hipError_t e = hipMemsetAsync(mem, 0, p.total, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    delete c;
+    return LBM_E_DEVICE;
+  }
+  *out = c;
+  return LBM_OK;
+}
+
+lbm_status lbm_sur_set_params(lbm_sur_ctx* c, const double* theta, int64_t n) {
+  if (!c || !theta) return LBM_E_INVAL;
+  if (n != c->np) return fail(c, LBM_E_INVAL, "parameter count does not match the network");
+  std::vector<float> h(n);
+  for (int64_t k = 0; k < n; ++k) h[k] = (float)theta[k];
+  SURCHK(c, hipStreamSynchronize(c->stream));
+  SURCHK(c, hipMemcpy(c->w, h.data(), n * 4, hipMemcpyHostToDevice));
+  SURCHK(c, hipMemsetAsync(c->m1, 0, n * 4, c->stream));
+  SURCHK(c, hipMemsetAsync(c->m2, 0, n * 4, c->stream));
+  hipLaunchKernelGGL(k_cast, dim3(blocks(n, 256)), dim3(256), 0, c->stream, c->w, n, c->L, c->wb);
+  SURCHK(c, hipGetLastError());
+  SURCHK(c, hipStreamSynchronize(c->stream));
+  c->step = 0;
+  return LBM_OK;
+}
+
+lbm_status lbm_sur_get_params(lbm_sur_ctx* c, double* theta, int64_t n) {
+  if (!c || !theta) return LBM_E_INVAL;
+  if (n != c->np) return fail(c, LBM_E_INVAL, "parameter count does not match the network");
+  std::vector<float> h(n);
+  SURCHK(c, hipStreamSynchronize(c->stream));
+  SURCHK(c, hipMemcpy(h.data(), c->w, n * 4, hipMemcpyDeviceToHost));
+  for (int64_t k = 0; k < n; ++k) theta[k] = h[k];
+  return LBM_OK;
+}
+
+lbm_status lbm_sur_set_scaling(lbm_sur_ctx* c, const double* lo, const double* hi, const double* mu,
+                               const double* sigma) {
+  if (!c || !lo || !hi || !mu || !sigma) return LBM_E_INVAL;
+  const lbm_sur_config& C = c->cfg;
+  std::vector<float> a(KPAD, 0.0f), b(KPAD, 1.0f), m(C.n_out), s(C.n_out);
+  for (int j = 0; j < C.n_in; ++j) {
+    if (!(hi[j] > lo[j])) return fail(c, LBM_E_INVAL, "input box needs lo < hi");
+    a[j] = (float)lo[j];
+    b[j] = (float)hi[j];
+  }
+  for (int j = 0; j < C.n_out; ++j) {
+    if (!(sigma[j] > 0)) return fail(c, LBM_E_INVAL, "output scales must be positive");
+    m[j] = (float)mu[j];
+    s[j] = (float)sigma[j];
+  }
+  SURCHK(c, hipStreamSynchronize(c->stream));
+  SURCHK(c, hipMemcpy(c->lo, a.data(), KPAD * 4, hipMemcpyHostToDevice));
+  SURCHK(c, hipMemcpy(c->hi, b.data(), KPAD * 4, hipMemcpyHostToDevice));
+  SURCHK(c, hipMemcpy(c->mu, m.data(), C.n_out * 4, hipMemcpyHostToDevice));
+  SURCHK(c, hipMemcpy(c->sigma, s.data(), C.n_out * 4, hipMemcpyHostToDevice));
+  return LBM_OK;
+}
+
+lbm_status lbm_sur_grad(lbm_sur_ctx* c, const float* x, const float* t, int32_t n_rows, const int32_t* idx,
+                        int32_t m, float* grad, double* loss) {
+  if (!c || !grad) return LBM_E_INVAL;
+  if (m < 1 || m > c->cfg.train_batch) return fail(c, LBM_E_INVAL, "row count outside [1, training batch]");
+  TRY(zero_tail(c, m));
+  TRY(grad_pass(c, x, t, n_rows, idx, m));
+  SURCHK(c, hipMemcpyAsync(grad, c->g, c->np * 4, hipMemcpyDeviceToDevice, c->stream));
+  if (loss) TRY(read_loss(c, loss));
+  return LBM_OK;
+}
+
+lbm_status lbm_sur_train_step(lbm_sur_ctx* c, const float* x, const float* t, int32_t n_rows,
+                              const int32_t* idx, int32_t m, double lr, double b1, double b2, double eps,
+                              double* loss) {
+  if (!c) return LBM_E_INVAL;
+  if (!(lr >= 0) || !(b1 >= 0 && b1 < 1) || !(b2 >= 0 && b2 < 1) || !(eps > 0))
+    return fail(c, LBM_E_INVAL, "Adam needs lr >= 0, 0 <= b1, b2 < 1, eps > 0");
+  if (m < 1 || m > c->cfg.train_batch) return fail(c, LBM_E_INVAL, "row count outside [1, training batch]");
+  TRY(zero_tail(c, m));
+  TRY(grad_pass(c, x, t, n_rows, idx, m));
+  c->step += 1;
+  const float bc1 = (float)(1.0 - std::pow(b1, (double)c->step));
+  const float bc2 = (float)(1.0 - std::pow(b2, (double)c->step));
+  hipLaunchKernelGGL(k_adam, dim3(blocks(c->np, 256)), dim3(256), 0, c->stream, c->w, c->m1, c->m2, c->g, c->np,
+                     (float)lr, (float)b1, (float)b2, (float)eps, bc1, bc2, c->L, c->wb);
+  SURCHK(c, hipGetLastError());
+  if (loss) TRY(read_loss(c, loss));
+  return LBM_OK;
+}
+
+lbm_status lbm_sur_predict(lbm_sur_ctx* c, const float* x, int32_t m, float* y) {
+  if (!c || !y) return LBM_E_INVAL;
+  TRY(check_batch(c, x, m, c->cfg.max_batch));
+  hipLaunchKernelGGL(k_prep_x, dim3(blocks((int64_t)m * KPAD, 256)), dim3(256), 0, c->stream, x, m, nullptr, m, m,
+                     c->cfg.n_in, c->lo, c->hi, c->X0, c->errw);
+  SURCHK(c, hipGetLastError());
+  return forward(c, m, false, y);
+}
+
+lbm_status lbm_sur_set_timing(lbm_sur_ctx* c, int32_t on) {
+  if (!c) return LBM_E_INVAL;
+  SURCHK(c, hipStreamSynchronize(c->stream));
+  if (on && c->ev.empty()) {
+    c->ev.resize(2048);
+    for (auto& e : c->ev) SURCHK(c, hipEventCreate(&e));
+  }
+  c->timing = on != 0;
+  c->nev = 0;
+  c->launches = 0;
+  c->flops = c->ms = 0.0;
+  return LBM_OK;
+}
+
+lbm_status lbm_sur_gemm_time(lbm_sur_ctx* c, int64_t* launches, double* ms, double* flops) {
+  if (!c || !launches || !ms || !flops) return LBM_E_INVAL;
+  SURCHK(c, hipStreamSynchronize(c->stream));
+  for (int k = 0; k + 1 < c->nev; k += 2) {
+    float t = 0.0f;
+    SURCHK(c, hipEventElapsedTime(&t, c->ev[k], c->ev[k + 1]));
+    c->ms += t;
+    c->launches += 1;
+  }
+  c->nev = 0;
+  *launches = c->launches;
+  *ms = c->ms;
+  *flops = c->flops;
+  return LBM_OK;
+}
+
+lbm_status lbm_sur_sync(lbm_sur_ctx* c) {
+  if (!c) return LBM_E_INVAL;
+  SURCHK(c, hipStreamSynchronize(c->stream));
+  int e = 0;
+  SURCHK(c, hipMemcpy(&e, c->errw, 4, hipMemcpyDeviceToHost));
+  if (e) {
+    SURCHK(c, hipMemset(c->errw, 0, 4));
+    return fail(c, LBM_E_INVAL, "a batch index was outside [0, n_rows)");
+  }
+  return LBM_OK;
+}
+
+const char* lbm_sur_last_error(const lbm_sur_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+lbm_status lbm_sur_destroy(lbm_sur_ctx* c) {
+  if (!c) return LBM_E_INVAL;
+  (void)hipStreamSynchronize(c->stream);
+  for (auto& e : c->ev) (void)hipEventDestroy(e);
+  delete c;
+  return LBM_OK;
+}
+
+}  // extern "C"

@@ -7,8 +7,8 @@ import re
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def declared_symbols():
-    src = open(os.path.join(ROOT, "include", "lbm0d3d.h")).read()
+def declared_symbols(header="lbm0d3d.h"):
+    src = open(os.path.join(ROOT, "include", header)).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     return sorted(set(re.findall(r"\b(lbm_[a-z0-9_]+)\s*\(", src)))
 
@@ -23,10 +23,25 @@ def test_header_declares_the_boundary_calls():
 def test_library_exports_every_declared_symbol():
     import paper_2112_05258_amd as amd
     lib = ctypes.CDLL(amd.LIB_PATH)
-    missing = [n for n in declared_symbols() if not hasattr(lib, n)]
-    assert not missing, missing
-    # the binding covers the same set
-    assert set(declared_symbols()) == set(amd.SYMBOLS)
+    for header, table in (("lbm0d3d.h", amd.SYMBOLS), ("lbm_surrogate.h", amd.SUR_SYMBOLS)):
+        missing = [n for n in declared_symbols(header) if not hasattr(lib, n)]
+        assert not missing, (header, missing)
+        # the binding covers the same set
+        assert set(declared_symbols(header)) == set(table), header
+
+
+def test_surrogate_size_queries_on_cpu():
+    """Parameter count of the 7 -> 512 x 4 -> 512 network and config checks."""
+    import paper_2112_05258_amd as amd
+    L = amd.lib()
+    cfg = amd.SurConfig(7, 512, 4, 512, 65536, 256)
+    assert L.lbm_sur_num_params(ctypes.byref(cfg)) == 7 * 512 + 3 * 512 * 512 + 512 * 512 + 5 * 512
+    nb = ctypes.c_size_t()
+    assert L.lbm_sur_query_sizes(ctypes.byref(cfg), ctypes.byref(nb)) == 0 and nb.value > 0
+    for bad in (amd.SurConfig(40, 512, 4, 512, 64, 256), amd.SurConfig(7, 500, 4, 512, 64, 256),
+                amd.SurConfig(7, 512, 4, 512, 64, 100), amd.SurConfig(7, 512, 0, 512, 64, 256)):
+        assert L.lbm_sur_num_params(ctypes.byref(bad)) == -1
+        assert L.lbm_sur_query_sizes(ctypes.byref(bad), ctypes.byref(nb)) == -1
 
 
 def test_size_query_and_argument_checks_on_cpu():

@@ -1,0 +1,176 @@
+"""The surrogate's kernels (through the C interface) against the FP64 network
+reference in oracle/mlp.py, and the trained network against the solver.
+
+Tolerances: operands of every matrix product are rounded to BF16 (relative
+rounding 2^-9 = 2e-3) and accumulated in FP32; a forward pass chains 5
+products and a gradient 9 more, each adding an independent ~2e-3 relative
+error, so the outputs agree to ~5e-3 and the gradients to ~1e-2 in relative
+L2.  The bars below sit at 2e-2 (forward) and 4e-2 (gradient), well under
+what a wrong index, sign or transposition gives (O(1)).
+"""
+import os
+
+import numpy as np
+import pytest
+
+import lbm_inputs as L
+from oracle import mlp
+
+pytestmark = pytest.mark.gpu
+
+WEIGHTS = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2112_05258_amd",
+                       "surrogate_weights.npz")
+
+
+@pytest.fixture(scope="module")
+def sur():
+    import paper_2112_05258_amd as amd
+    amd.lib()
+    from paper_2112_05258_amd import surrogate
+    return surrogate
+
+
+def _rel(a, b):
+    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(b)
+
+
+def _scaling(n_out, rng):
+    lo, hi = L.SURROGATE_LO, L.SURROGATE_HI
+    mu = rng.normal(size=n_out)
+    sigma = rng.uniform(0.5, 2.0, n_out)
+    return lo, hi, mu, sigma
+
+
+def test_forward_small_net_ragged_batch(sur):
+    rng = np.random.default_rng(1)
+    dims = [7, 64, 64, 96]
+    s = sur.Surrogate(7, 64, 2, 96, max_batch=300, train_batch=40)
+    theta = L.mlp_init(dims, seed=2)
+    s.set_params(theta)
+    lo, hi, mu, sigma = _scaling(96, rng)
+    s.set_scaling(lo, hi, mu, sigma)
+    X = L.surrogate_params(257, seed=3)
+    y = s.predict(X).cpu().numpy()
+    yo, _, _ = mlp.forward(theta, mlp.layer_shapes(7, 64, 2, 96), mlp.normalise_inputs(X, lo, hi))
+    e = _rel((y - mu) / sigma, yo)
+    print({"forward_rel_l2": f"{e:.2e}"}, flush=True)
+    assert e <= 2e-2
+    s.close()
+
+
+def _full_case(seed, m):
+    rng = np.random.default_rng(seed)
+    theta = L.mlp_init([7] + [512] * 4 + [512], seed=seed)
+    lo, hi, mu, sigma = _scaling(512, rng)
+    X = L.surrogate_params(m, seed=seed + 1)
+    T = mu + sigma * rng.normal(size=(m, 512))
+    return theta, lo, hi, mu, sigma, X, T
+
+
+def test_gradient_full_size_matches_oracle(sur):
+    theta, lo, hi, mu, sigma, X, T = _full_case(5, 100)     # 100 rows: a ragged tail of 4
+    s = sur.Surrogate(train_batch=128, max_batch=256)
+    s.set_params(theta)
+    s.set_scaling(lo, hi, mu, sigma)
+    g, loss = s.grad(X, T)
+    g = g.cpu().numpy().astype(np.float64)
+    shapes = mlp.layer_shapes()
+    lo_, go = mlp.loss_and_grad(theta, shapes, mlp.normalise_inputs(X, lo, hi), (T - mu) / sigma)
+    errs = {"loss": abs(loss - lo_) / lo_}
+    k = 0
+    for l, (o, i) in enumerate(shapes):
+        errs[f"W{l + 1}"] = _rel(g[k:k + o * i], go[k:k + o * i])
+        k += o * i
+        errs[f"b{l + 1}"] = _rel(g[k:k + o], go[k:k + o])
+        k += o
+    print({a: f"{b:.2e}" for a, b in errs.items()}, flush=True)
+    assert errs["loss"] <= 1e-2
+    for a, b in errs.items():
+        assert b <= 4e-2, (a, b)
+    s.close()
+
+
+def test_adam_steps_match_oracle(sur):
+    """Three Adam steps: the update kernel applied to the device's own
+    gradients equals the oracle's Adam on the same gradients (FP32 master
+    weights: agreement to FP32 rounding)."""
+    theta, lo, hi, mu, sigma, X, T = _full_case(9, 64)
+    s = sur.Surrogate(train_batch=64, max_batch=64)
+    s.set_params(theta)
+    s.set_scaling(lo, hi, mu, sigma)
+    ref = theta.astype(np.float32).astype(np.float64)
+    opt = mlp.Adam(theta.size, lr=1e-3)
+    xd, td = s._dev(X), s._dev(T)
+    for step in range(3):
+        idx = s._dev(np.random.default_rng(step).permutation(64).astype(np.int32), s.torch.int32)
+        g, _ = s.grad(xd, td, idx)
+        ref = opt.step(ref, g.cpu().numpy().astype(np.float64))
+        s.stream.wait_stream(s.torch.cuda.current_stream(s.device))
+        s.train_step(xd, td, idx, 1e-3, want_loss=True)
+        got = s.params()
+        err = np.abs(got - ref).max()
+        print({"step": step, "max_abs_diff": f"{err:.2e}"}, flush=True)
+        # FP32 master weights (|theta| < 0.4, ulp <= 3e-8) rounded once per
+        # step; a wrong update is off by ~lr = 1e-3
+        assert err <= 2e-7
+    s.close()
+
+
+def test_training_fits_a_smooth_map(sur):
+    """A few hundred Adam steps on a smooth 7 -> 512 map drive the loss down
+    by well over an order of magnitude."""
+    rng = np.random.default_rng(4)
+    X = L.surrogate_params(2048, seed=5)
+    xn = mlp.normalise_inputs(X, L.SURROGATE_LO, L.SURROGATE_HI)
+    A = rng.normal(size=(7, 512))
+    T = np.sin(xn @ A * 0.7) + 0.3 * (xn[:, :1] ** 2)
+    s = sur.Surrogate(train_batch=256, max_batch=2048)
+    s.set_params(L.mlp_init([7] + [512] * 4 + [512], seed=6))
+    hist = s.fit(X, T, epochs=40, lr=1e-3, lr_min=1e-4, seed=1, log_every=50)
+    print({"loss_first": f"{hist[0][1]:.3e}", "loss_last": f"{hist[-1][1]:.3e}"}, flush=True)
+    assert hist[-1][1] < hist[0][1] / 20
+    s.close()
+
+
+def test_out_of_range_index_is_reported(sur):
+    import paper_2112_05258_amd as amd
+    theta, lo, hi, mu, sigma, X, T = _full_case(3, 16)
+    s = sur.Surrogate(train_batch=16, max_batch=16)
+    s.set_params(theta)
+    s.set_scaling(lo, hi, mu, sigma)
+    with pytest.raises(amd.LbmError):
+        s.grad(X, T, np.array([0, 1, 16, 2], np.int32))
+    g, loss = s.grad(X, T)                  # the flag was cleared
+    assert np.isfinite(loss)
+    s.close()
+
+
+@pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="no trained surrogate weights in the package")
+def test_trained_surrogate_against_solver_and_fallback(sur):
+    """Held-out parameter draws: the solver judges the network (pressure
+    pulse and flow waveforms within 2 % on average); a draw outside the
+    training box is routed to the solver."""
+    import time
+    s = sur.Surrogate.load(WEIGHTS, max_batch=65536)
+    X = L.surrogate_params(16, seed=2027)
+    t0 = time.time()
+    Y = sur.lb_waveforms(X)
+    t_lb = time.time() - t0
+    Yp = s.predict(X).cpu().numpy()
+    dP, dQ = sur.rel_errors(Yp, Y)
+    big = L.surrogate_params(65536, seed=7)
+    s.predict(big[:1024])
+    t0 = time.time()
+    s.predict(big)
+    t_nn = time.time() - t0
+    print({"P_mean": f"{dP.mean():.4f}", "P_max": f"{dP.max():.4f}", "Q_mean": f"{dQ.mean():.4f}",
+           "Q_max": f"{dQ.max():.4f}", "lb_s_per_waveform": f"{t_lb / 16:.3e}",
+           "nn_s_per_waveform": f"{t_nn / 65536:.3e}"}, flush=True)
+    assert dP.mean() <= 0.02 and dQ.mean() <= 0.02
+    assert t_nn / 65536 < 1e-3 * t_lb / 16
+    Xo = X[:3].copy()
+    Xo[1, 0] = L.SURROGATE_HI[0] * 1.2      # Emax outside the box
+    out, solved = s.predict_or_solve(Xo)
+    assert solved.tolist() == [False, True, False]
+    assert np.allclose(out[[0, 2]], Yp[[0, 2]], rtol=1e-6, atol=1e-6)
+    s.close()
