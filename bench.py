@@ -38,6 +38,9 @@ def parse():
     ap.add_argument("--workload", default="cfg1", choices=["cfg1", "cfg1_coarse_wall", "cfg0", "channel256"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp16", action="store_true", help="skip the FP16-storage run")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the learned-surrogate leg")
+    ap.add_argument("--surrogate-only", action="store_true",
+                    help="only the learned-surrogate leg (for profiling its kernels)")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble run")
     ap.add_argument("--ensemble-steps", type=int, default=100)
     ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "fp16s", "bf16s"])
@@ -153,6 +156,56 @@ def precision_study_errors():
     return out
 
 
+def run_surrogate(n_check=64, reps=20, batch=65536):
+    """Trained surrogate: error against fresh solver runs on held-out
+    parameter draws (the solver is the judge), inference throughput at the
+    given batch, and the matrix products' MFMA rate (HIP events on the
+    context's stream)."""
+    import numpy as np
+    import torch
+    import lbm_inputs as L
+    from paper_2112_05258_amd import surrogate as S
+    here = os.path.dirname(os.path.abspath(__file__))
+    s = S.Surrogate.load(os.path.join(here, "paper_2112_05258_amd", "surrogate_weights.npz"), max_batch=batch)
+    X = L.surrogate_params(n_check, seed=2026)
+    t0 = time.perf_counter()
+    Y = S.lb_waveforms(X)
+    t_lb = time.perf_counter() - t0
+    dP, dQ = S.rel_errors(s.predict(X).cpu().numpy(), Y)
+    xb = s._dev(L.surrogate_params(batch, seed=7))
+    yb = torch.empty((batch, s.cfg.n_out), dtype=torch.float32, device=s.device)
+    s.stream.wait_stream(torch.cuda.current_stream(s.device))
+    for _ in range(3):
+        s.predict_into(xb, yb)
+    s.sync()
+    s.set_timing(True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(s.stream)
+    for _ in range(reps):
+        s.predict_into(xb, yb)
+    e1.record(s.stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    n, gms, _ = s.gemm_time()
+    s.set_timing(False)
+    # algorithmic FLOP of one sample: 2 (7*512 + 3*512*512 + 512*512)
+    w, nh, nin, nout = s.cfg.width, s.cfg.n_hidden, s.cfg.n_in, s.cfg.n_out
+    flop = 2.0 * batch * (nin * w + (nh - 1) * w * w + w * nout)
+    achieved = flop * reps / (gms * 1e-3) / 1e12
+    s.close()
+    return {"value": round(batch / (ms * 1e-3), 1), "unit": "waveforms/s", "batch": batch,
+            "ms_per_batch": round(ms, 4),
+            "held_out": n_check, "pressure_pulse_rel_l2_mean": round(float(dP.mean()), 5),
+            "pressure_pulse_rel_l2_max": round(float(dP.max()), 5),
+            "flow_rel_l2_mean": round(float(dQ.mean()), 5), "flow_rel_l2_max": round(float(dQ.max()), 5),
+            "solver_waveforms_per_s": round(n_check / t_lb, 2),
+            "roofline": {"bound": "mfma", "kernel": "k_gemm (5 products per batch)",
+                         "achieved": round(achieved, 1), "peak": 2500.0, "unit": "TFLOP/s",
+                         "frac": round(achieved / 2500.0, 4), "gemm_launches": n,
+                         "avg_launch_us": round(gms / max(n, 1) * 1e3, 2)}}
+
+
 def _band_cells(cfg):
     """Band cells of the wall (same rule as the library: stencil + 2-cell margin, fluid only)."""
     import numpy as np
@@ -187,25 +240,40 @@ def run_ensemble(steps, warmup, n=256, seed=3):
     nfluid = sum(int((c["flags"] == L.FLUID).sum()) for c in cfgs)
     s.step(warmup)
     s.sync()
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(s.stream)
-    s.step(steps)
-    e1.record(s.stream)
-    e1.synchronize()
-    ms = e0.elapsed_time(e1)
-    s.sync()
+
+    def timed():
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(s.stream)
+        s.step(steps)
+        e1.record(s.stream)
+        e1.synchronize()
+        s.sync()
+        return e0.elapsed_time(e1)
+
+    ms_default = timed()
+    # launch shapes per size class (box-volume quartiles) from the autotuner
+    # (its trial steps are ordinary steps); the figure is the tuned run
+    t0 = time.perf_counter()
+    tuned_steps = s.autotune(trial_steps=8)
+    t_tune = time.perf_counter() - t0
+    ms = timed()
     steps_per_s = steps / (ms * 1e-3)
     # one waveform = one cardiac cycle of one tube (T_c steps)
     wf = sum(steps_per_s / c["inlet"][1][2] for c in cfgs)
     finite = all(bool(np.isfinite(s.waveforms(k, cap=2)[:, 1:5]).all()) for k in range(n))
+    classes = s.classes()
     s.close()
     return {"instances": n, "cells": int(sum(c["nx"] * c["ny"] * c["nz"] for c in cfgs)), "fluid_cells": nfluid,
             "wall_points": int(sum(c["mesh"]["X0"].shape[0] for c in cfgs)),
             "value": round(nfluid * steps / (ms * 1e-3) / 1e6, 1), "unit": "MLUPS",
             "ms_per_step": round(ms / steps, 4), "waveforms_per_s": round(wf, 3),
-            "setup_s": round(t_setup, 1), "steps": steps, "finite": finite}
+            "setup_s": round(t_setup, 1), "steps": steps, "finite": finite,
+            "default_launch_ms_per_step": round(ms_default / steps, 4),
+            "autotune": {"steps": tuned_steps, "s": round(t_tune, 2),
+                         "classes": [{k: c[k] for k in ("instances", "cells", "block", "cells_per_lane",
+                                                        "wall_tile_theta")} for c in classes]}}
 
 
 def cpu_baseline(cfg, budget_s=20.0):
@@ -256,6 +324,9 @@ def main():
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.surrogate_only:
+        print(json.dumps({"surrogate": run_surrogate()}), flush=True)
+        return
     cfg, desc = workload(args.workload)
     t_setup = time.perf_counter()
     r = run_gpu(cfg, args.precision, args.steps, args.warmup)
@@ -299,6 +370,8 @@ def main():
         out["fp16s"]["waveform_error_vs_fp64_oracle"] = precision_study_errors()
     if not args.no_ensemble and args.workload == "cfg1" and args.precision == "fp32":
         out["ensemble"] = run_ensemble(args.ensemble_steps, 10)
+    if not args.no_surrogate and args.workload == "cfg1" and args.precision == "fp32":
+        out["surrogate"] = run_surrogate()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cfg)
     print(json.dumps(out), flush=True)

@@ -81,7 +81,8 @@ enum { LBM_CELL_FLUID = 0, LBM_CELL_SOLID = 1, LBM_CELL_INLET = 2, LBM_CELL_OUTL
  *                  h1 = (tn/a1)^n1 / (1 + (tn/a1)^n1), h2 = 1/(1 + (tn/a2)^n2),
  *                  tn = (t mod Tc)/Tmax, C_v = 1/E.  The valve opens when
  *                  P_v exceeds the mean inlet pressure (at most once a beat),
- *                  closes on the first step with inflow Q < 0; then
+ *                  closes on the first step with Q < 0 after inflow (Q > 0)
+ *                  has begun since the opening; then
  *                  v* = v0(x_f, T_d) S(t, T_d, N_S) (Eqs. SmoothFunction and
  *                  vnew).  Each beat starts closed with P_v = P_ed.  Inlet only.
  *                  state: [Pv]                                           */
@@ -114,8 +115,12 @@ typedef struct {
 } lbm_buffers;
 
 /* Sizes of the device buffers for n instances (n = 1: one box).  All
- * instances of one context share the precision of cfgs[0].
- * Errors: LBM_E_INVAL for bad sizes, tau, flags or a NULL pointer. */
+ * instances of one context share the precision of cfgs[0].  Limits of one
+ * context: fewer than 2^31 cells in all, and one direction's populations
+ * under 4 GiB (FP64: 2^29 cells, FP32: 2^30; the kernels address each
+ * direction with 32-bit byte offsets).
+ * Errors: LBM_E_INVAL for bad sizes, tau, flags, a NULL pointer or a
+ * context past those limits. */
 lbm_status lbm_query_sizes(const lbm_config* cfgs, int32_t n, size_t* pop_bytes, size_t* work_bytes);
 
 /* Create a context over n independent instances (the batched ensemble when
@@ -225,6 +230,35 @@ lbm_status lbm_kernel_time(lbm_ctx* ctx, int32_t kernel, int64_t* launches, doub
 /* Replay steps from a captured HIP graph (one even + one odd step) instead
  * of launching kernels one by one (default on; turned off while timing). */
 lbm_status lbm_set_graph(lbm_ctx* ctx, int32_t on);
+
+/* Launch shapes per size class.  The instances of a context are grouped by
+ * cell count into size classes (quartiles from 8 instances on, else one
+ * class); each class has its own collide-stream launch (workgroup size and
+ * cells per lane, over a table of tiles of consecutive cells of one
+ * instance) and wall launch (tiles of wall_tile_theta x 256/wall_tile_theta
+ * mesh points).  Results do not depend on the shapes, except for the
+ * rounding order of the wall force's float additions. */
+typedef struct {
+  int32_t block;            /* collide workgroup: 128, 256 or 512 lanes */
+  int32_t cells_per_lane;   /* 1 or 2 */
+  int32_t wall_tile_theta;  /* 8, 16 or 32 mesh points along theta */
+} lbm_launch;
+
+int32_t lbm_num_classes(lbm_ctx* ctx);
+/* Instances, cells and wall points of class cls (any pointer may be NULL). */
+lbm_status lbm_class_info(lbm_ctx* ctx, int32_t cls, int32_t* instances, int64_t* cells, int64_t* wall_points);
+lbm_status lbm_get_launch(lbm_ctx* ctx, int32_t cls, lbm_launch* out);
+/* Set a class's shapes (LBM_E_INVAL outside the values above); synchronises
+ * and drops the captured step graph. */
+lbm_status lbm_set_launch(lbm_ctx* ctx, int32_t cls, const lbm_launch* launch);
+
+/* Autotuner: times every collide shape (6) and then every wall tile (3, if
+ * walls are registered) over trial_steps steps each (rounded up to even,
+ * after 2 untimed steps), per class with HIP events, and keeps each class's
+ * fastest.  The trial steps are ordinary steps of the method: the state
+ * advances by *advanced steps (may be NULL).  Call after the 0D couplings
+ * and walls are set. */
+lbm_status lbm_autotune(lbm_ctx* ctx, int32_t trial_steps, int64_t* advanced);
 
 const char* lbm_last_error(const lbm_ctx* ctx);
 void lbm_destroy(lbm_ctx* ctx);

@@ -47,6 +47,10 @@ class WallDesc(C.Structure):
                 ("alpha", C.c_double), ("beta", C.c_double), ("band_margin", C.c_int32)]
 
 
+class Launch(C.Structure):
+    _fields_ = [("block", C.c_int32), ("cells_per_lane", C.c_int32), ("wall_tile_theta", C.c_int32)]
+
+
 SYMBOLS = {
     "lbm_query_sizes": (C.c_int, [C.POINTER(Config), C.c_int32, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
     "lbm_init": (C.c_int, [C.POINTER(Config), C.c_int32, C.POINTER(Buffers), C.c_void_p, C.POINTER(C.c_void_p)]),
@@ -68,6 +72,12 @@ SYMBOLS = {
     "lbm_set_timing": (C.c_int, [C.c_void_p, C.c_int32]),
     "lbm_kernel_time": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
     "lbm_set_graph": (C.c_int, [C.c_void_p, C.c_int32]),
+    "lbm_num_classes": (C.c_int32, [C.c_void_p]),
+    "lbm_class_info": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int64),
+                                 C.POINTER(C.c_int64)]),
+    "lbm_get_launch": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(Launch)]),
+    "lbm_set_launch": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(Launch)]),
+    "lbm_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64)]),
     "lbm_last_error": (C.c_char_p, [C.c_void_p]),
     "lbm_destroy": (None, [C.c_void_p]),
     "lbm_num_cells": (C.c_int64, [C.c_void_p, C.c_int32]),
@@ -264,6 +274,74 @@ class Solver:
 
     def set_graph(self, on):
         self._check(lib().lbm_set_graph(self.h, 1 if on else 0))
+
+    # ---- launch shapes per size class (autotuner) ----------------------
+    def classes(self):
+        """Per size class: dict(instances, cells, wall_points, block,
+        cells_per_lane, wall_tile_theta)."""
+        out = []
+        for q in range(lib().lbm_num_classes(self.h)):
+            ni, nc, npt = C.c_int32(), C.c_int64(), C.c_int64()
+            self._check(lib().lbm_class_info(self.h, q, C.byref(ni), C.byref(nc), C.byref(npt)))
+            la = Launch()
+            self._check(lib().lbm_get_launch(self.h, q, C.byref(la)))
+            out.append(dict(instances=ni.value, cells=nc.value, wall_points=npt.value, block=la.block,
+                            cells_per_lane=la.cells_per_lane, wall_tile_theta=la.wall_tile_theta))
+        return out
+
+    def set_launch(self, cls, block, cells_per_lane, wall_tile_theta):
+        la = Launch(block, cells_per_lane, wall_tile_theta)
+        self._check(lib().lbm_set_launch(self.h, cls, C.byref(la)))
+
+    def _class_keys(self):
+        """Cache key of each size class: GPU, storage precision, and the
+        class's mean cells and wall points per instance (powers of two)."""
+        arch = self.torch.cuda.get_device_properties(self.device).gcnArchName.split(":")[0]
+        keys = []
+        for c in self.classes():
+            n = max(c["instances"], 1)
+            cb = int(round(np.log2(max(c["cells"] / n, 1))))
+            pb = int(round(np.log2(c["wall_points"] / n))) if c["wall_points"] else -1
+            keys.append(f"{arch}|p{self.precision}|cells2^{cb}|wall2^{pb}")
+        return keys
+
+    def autotune(self, trial_steps=8, cache=None):
+        """Launch shapes per size class: taken from the JSON file cache when
+        it holds every class's key, else measured by the library's autotuner
+        (which advances the state by ordinary steps) and written back.
+        Returns the number of steps taken."""
+        import json
+        import os
+        keys = self._class_keys()
+        table = {}
+        if cache and os.path.exists(cache):
+            with open(cache) as f:
+                table = json.load(f).get("classes", {})
+        if keys and all(k in table for k in keys):
+            for q, k in enumerate(keys):
+                e = table[k]
+                self.set_launch(q, e["block"], e["cells_per_lane"], e["wall_tile_theta"])
+            return 0
+        adv = C.c_int64()
+        self._check(lib().lbm_autotune(self.h, int(trial_steps), C.byref(adv)))
+        # classes with the same key take the shapes of the largest of them
+        # (small classes time noisily), so that the cache reproduces them
+        cls = self.classes()
+        pick = {}
+        for q, (k, c) in enumerate(zip(keys, cls)):
+            if k not in pick or c["cells"] > cls[pick[k]]["cells"]:
+                pick[k] = q
+        for q, k in enumerate(keys):
+            c = cls[pick[k]]
+            if pick[k] != q:
+                self.set_launch(q, c["block"], c["cells_per_lane"], c["wall_tile_theta"])
+            table[k] = {a: c[a] for a in ("block", "cells_per_lane", "wall_tile_theta")}
+        if cache:
+            tmp = cache + ".tmp"
+            with open(tmp, "w") as f:
+                json.dump({"version": 1, "classes": table}, f, indent=1, sort_keys=True)
+            os.replace(tmp, cache)
+        return adv.value
 
 
 def solver_from_config(cfg, precision=FP32, pops=None, store_scale=0.0, wave_cap=4096):

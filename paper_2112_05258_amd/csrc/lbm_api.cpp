@@ -109,23 +109,23 @@ bool build_geometry(const lbm_config& c, Geometry& g, std::string& err) {
 }
 
 struct Layout {
-  size_t flags, inst, blk_inst, lay, red, red_part, bc, st, wave, v0, err, walls, total;
+  size_t flags, inst, ctab, lay, red, red_part, bc, st, wave, v0, err, walls, cwalls, total;
   int64_t NT;
-  int nblk, nred, nlay, wave_cap;
+  int ntile_max, nred, nlay, wave_cap;
   int64_t nv0;
 };
 
 void plan(const std::vector<Geometry>& G, int prec, int wave_cap, Layout& L, std::vector<InstDesc>* inst,
-          std::vector<int32_t>* blk, std::vector<int32_t>* lay, std::vector<RedTab>* red) {
-  L.NT = 0; L.nblk = 0; L.nred = 0; L.nlay = 0; L.nv0 = 0; L.wave_cap = wave_cap;
+          std::vector<int32_t>* lay, std::vector<RedTab>* red) {
+  L.NT = 0; L.ntile_max = 0; L.nred = 0; L.nlay = 0; L.nv0 = 0; L.wave_cap = wave_cap;
   for (size_t k = 0; k < G.size(); ++k) {
     const Geometry& g = G[k];
     InstDesc d;
     std::memset(&d, 0, sizeof d);
     d.nx = g.nx; d.ny = g.ny; d.nz = g.nz;
     d.cell0 = L.NT; d.ncell = g.ncell;
-    d.blk0 = L.nblk;
-    d.nblk = (int32_t)((g.ncell + BLOCK - 1) / BLOCK);
+    // collide tiles: at most one per MIN_TILE cells, whatever the launch shape
+    L.ntile_max += (int)((g.ncell + MIN_TILE - 1) / MIN_TILE);
     d.v0_off = L.nv0;
     d.red0 = L.nred;
     int nr = 0;
@@ -145,8 +145,6 @@ void plan(const std::vector<Geometry>& G, int prec, int wave_cap, Layout& L, std
     }
     d.nred = nr;
     L.nred += nr;
-    if (blk) blk->insert(blk->end(), d.nblk, (int32_t)k);
-    L.nblk += d.nblk;
     L.NT += g.ncell;
     L.nv0 += (int64_t)g.nx * g.ny;
     if (inst) inst->push_back(d);
@@ -155,7 +153,7 @@ void plan(const std::vector<Geometry>& G, int prec, int wave_cap, Layout& L, std
   size_t o = 0;
   L.flags = o; o = align256(o + L.NT);
   L.inst = o; o = align256(o + n * sizeof(InstDesc));
-  L.blk_inst = o; o = align256(o + (size_t)L.nblk * 4);
+  L.ctab = o; o = align256(o + (size_t)std::max(L.ntile_max, 1) * sizeof(CTile));
   L.lay = o; o = align256(o + (size_t)std::max(L.nlay, 1) * 4);
   L.red = o; o = align256(o + (size_t)L.nred * sizeof(RedTab));
   L.red_part = o; o = align256(o + (size_t)L.nred * 16);
@@ -165,6 +163,7 @@ void plan(const std::vector<Geometry>& G, int prec, int wave_cap, Layout& L, std
   L.v0 = o; o = align256(o + (size_t)L.nv0 * r4_size(prec));
   L.err = o; o = align256(o + 4);
   L.walls = o; o = align256(o + n * 4);
+  L.cwalls = o; o = align256(o + n * 4);
   L.total = o;
   (void)prec;
 }
@@ -178,6 +177,23 @@ struct Wall {
   int64_t np = 0;
   int nband = 0;
   std::vector<int32_t> band;
+};
+
+// Instances of similar box volume share launch shapes, chosen by the
+// autotuner: collide workgroup size and cells per lane, wall tile width.
+struct SizeClass {
+  std::vector<int32_t> inst;   // instance ids, ascending (memory order)
+  int bs = 256, cpt = 1, tj = 16;
+};
+
+// One launch: the classes that share a shape (or one class while tuning),
+// with their slice of the packed tile table or wall list.
+struct LaunchGroup {
+  int bs = 256, cpt = 1, tj = 16;
+  int cls = -1;                // the class timed by this launch while tuning
+  size_t off = 0;              // first tile / wall entry
+  int count = 0;               // tiles / walls
+  int wall_tiles = 0;          // tiles of the group's largest wall
 };
 
 }  // namespace
@@ -196,6 +212,11 @@ struct lbm_ctx {
   std::string err;
   std::vector<Wall> wall;
   std::vector<int32_t> walls;
+  std::vector<SizeClass> cls;
+  std::vector<LaunchGroup> cgroups, wgroups;
+  // per-class kernel events while tuning: (class, kind 0 collide / 1 wall)
+  bool tuning = false;
+  std::vector<std::pair<std::pair<int, int>, EventPair>> tune_rec;
   // timing
   bool timing = false;
   std::vector<EventPair> pool;
@@ -251,6 +272,14 @@ hipError_t enqueue_step(lbm_ctx* c, int parity, bool timed) {
   auto post = [&](int k) {
     if (timed) { (void)hipEventRecord(ev[k].b, c->stream); c->recorded.push_back({k, ev[k]}); }
   };
+  auto tpre = [&](EventPair& p) {
+    if (c->tuning) { p = get_pair(c); (void)hipEventRecord(p.a, c->stream); }
+  };
+  auto tpost = [&](EventPair& p, int q, int kind) {
+    if (c->tuning) { (void)hipEventRecord(p.b, c->stream); c->tune_rec.push_back({{q, kind}, p}); }
+  };
+  const CTile* tab = (const CTile*)(c->work + c->L.ctab);
+  const int32_t* cw = (const int32_t*)(c->work + c->L.cwalls);
   pre(1);
   e = launch_reduce(c->dev, c->prec, parity, c->L.nred, c->stream);
   if (e != hipSuccess) return e;
@@ -261,13 +290,25 @@ hipError_t enqueue_step(lbm_ctx* c, int parity, bool timed) {
     if (e != hipSuccess) return e;
     post(2);
     pre(3);
-    e = launch_wall(c->dev, c->prec, parity, c->stream);
+    for (const LaunchGroup& G : c->wgroups) {
+      EventPair p;
+      tpre(p);
+      e = launch_wall(c->dev, c->prec, parity, G.tj, cw + G.off, G.count, G.wall_tiles, c->stream);
+      if (e != hipSuccess) return e;
+      tpost(p, G.cls, 1);
+    }
+    e = launch_membrane(c->dev, parity, c->stream);
     if (e != hipSuccess) return e;
     post(3);
   }
   pre(0);
-  e = launch_collide(c->dev, c->prec, parity, c->L.nblk, c->stream);
-  if (e != hipSuccess) return e;
+  for (const LaunchGroup& G : c->cgroups) {
+    EventPair p;
+    tpre(p);
+    e = launch_collide(c->dev, c->prec, parity, G.bs, G.cpt, tab + G.off, G.count, c->stream);
+    if (e != hipSuccess) return e;
+    tpost(p, G.cls, 0);
+  }
   post(0);
   return hipSuccess;
 }
@@ -282,6 +323,79 @@ void collect_times(lbm_ctx* c) {
     c->pool.push_back(r.second);
   }
   c->recorded.clear();
+}
+
+// Size classes: instances sorted by cell count, split into quartiles (a
+// single class below 8 instances).
+void make_classes(lbm_ctx* c) {
+  const int n = c->n;
+  std::vector<int32_t> order(n);
+  for (int k = 0; k < n; ++k) order[k] = k;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int32_t a, int32_t b) { return c->inst[a].ncell < c->inst[b].ncell; });
+  const int nc = n >= 8 ? 4 : 1;
+  c->cls.assign(nc, SizeClass());
+  for (int q = 0; q < nc; ++q) {
+    SizeClass& K = c->cls[q];
+    for (int r = q * n / nc; r < (q + 1) * n / nc; ++r) K.inst.push_back(order[r]);
+    std::sort(K.inst.begin(), K.inst.end());
+  }
+}
+
+// Launch groups from the classes' shapes: one collide launch per distinct
+// (workgroup, cells per lane) and one wall launch per distinct tile width,
+// or one of each per class (per_class, for timing them apart).  Packs and
+// uploads the tile table and the wall list.
+lbm_status build_groups(lbm_ctx* c, bool per_class) {
+  const int nc = (int)c->cls.size();
+  std::vector<CTile> tab;
+  std::vector<int32_t> walls;
+  c->cgroups.clear();
+  c->wgroups.clear();
+  std::vector<bool> done(nc, false), wdone(nc, false);
+  for (int q = 0; q < nc; ++q) {
+    if (done[q]) continue;
+    LaunchGroup G;
+    G.bs = c->cls[q].bs;
+    G.cpt = c->cls[q].cpt;
+    G.cls = q;
+    G.off = tab.size();
+    const int64_t span = (int64_t)G.bs * G.cpt;
+    for (int r = q; r < nc; ++r) {
+      if (done[r] || (r != q && (per_class || c->cls[r].bs != G.bs || c->cls[r].cpt != G.cpt))) continue;
+      done[r] = true;
+      for (int32_t i : c->cls[r].inst)
+        for (int64_t s = 0; s < c->inst[i].ncell; s += span) tab.push_back(CTile{i, (int32_t)s});
+    }
+    G.count = (int)(tab.size() - G.off);
+    if (G.count > 0) c->cgroups.push_back(G);
+  }
+  for (int q = 0; q < nc; ++q) {
+    if (wdone[q]) continue;
+    LaunchGroup G;
+    G.tj = c->cls[q].tj;
+    G.cls = q;
+    G.off = walls.size();
+    const int tk = 256 / G.tj;
+    for (int r = q; r < nc; ++r) {
+      if (wdone[r] || (r != q && (per_class || c->cls[r].tj != G.tj))) continue;
+      wdone[r] = true;
+      for (int32_t i : c->cls[r].inst)
+        if (c->wall[i].on) {
+          walls.push_back(i);
+          const InstDesc& d = c->inst[i];
+          G.wall_tiles = std::max(G.wall_tiles, ((d.nth + G.tj - 1) / G.tj) * ((d.nzl + tk - 1) / tk));
+        }
+    }
+    G.count = (int)(walls.size() - G.off);
+    if (G.count > 0) c->wgroups.push_back(G);
+  }
+  if ((int64_t)tab.size() > c->L.ntile_max) return fail(c, LBM_E_STATE, "tile table overflow");
+  if (!tab.empty())
+    HIPCHK(c, hipMemcpy(c->work + c->L.ctab, tab.data(), tab.size() * sizeof(CTile), hipMemcpyHostToDevice));
+  if (!walls.empty())
+    HIPCHK(c, hipMemcpy(c->work + c->L.cwalls, walls.data(), walls.size() * 4, hipMemcpyHostToDevice));
+  return LBM_OK;
 }
 
 template <class T>
@@ -399,7 +513,15 @@ lbm_status lbm_query_sizes(const lbm_config* cfgs, int32_t n, size_t* pop_bytes,
   const int prec = cfgs[0].precision;
   if (prec < 0 || prec > 3) return LBM_E_INVAL;
   Layout L;
-  plan(G, prec, cfgs[0].wave_cap > 0 ? cfgs[0].wave_cap : 4096, L, nullptr, nullptr, nullptr, nullptr);
+  plan(G, prec, cfgs[0].wave_cap > 0 ? cfgs[0].wave_cap : 4096, L, nullptr, nullptr, nullptr);
+  if (L.NT >= ((int64_t)1 << 31)) {  // the kernels index cells with 32 bits
+    g_init_err = "more than 2^31 - 1 cells in one context";
+    return LBM_E_INVAL;
+  }
+  if (L.NT * elem_size(prec) >= ((int64_t)1 << 32)) {  // 32-bit byte offsets per direction
+    g_init_err = "one direction's populations exceed 4 GiB";
+    return LBM_E_INVAL;
+  }
   *pop_bytes = (size_t)NQ * L.NT * elem_size(prec);
   *work_bytes = L.total;
   return LBM_OK;
@@ -424,9 +546,19 @@ lbm_status lbm_init(const lbm_config* cfgs, int32_t n, const lbm_buffers* buf, v
   int ex;
   if (std::frexp(s, &ex) != 0.5) { delete c; return LBM_E_INVAL; }  // power of two only
   c->scale = (float)s;
-  std::vector<int32_t> blk, lay;
+  std::vector<int32_t> lay;
   std::vector<RedTab> red;
-  plan(c->geo, c->prec, cfgs[0].wave_cap > 0 ? cfgs[0].wave_cap : 4096, c->L, &c->inst, &blk, &lay, &red);
+  plan(c->geo, c->prec, cfgs[0].wave_cap > 0 ? cfgs[0].wave_cap : 4096, c->L, &c->inst, &lay, &red);
+  if (c->L.NT >= ((int64_t)1 << 31)) {  // the kernels index cells with 32 bits
+    g_init_err = "more than 2^31 - 1 cells in one context";
+    delete c;
+    return LBM_E_INVAL;
+  }
+  if (c->L.NT * elem_size(c->prec) >= ((int64_t)1 << 32)) {  // 32-bit byte offsets per direction
+    g_init_err = "one direction's populations exceed 4 GiB";
+    delete c;
+    return LBM_E_INVAL;
+  }
   for (int k = 0; k < n; ++k) {
     c->inst[k].tau = cfgs[k].tau;
     c->inst[k].dref = 3.0 * cfgs[k].p_ref;
@@ -448,7 +580,6 @@ lbm_status lbm_init(const lbm_config* cfgs, int32_t n, const lbm_buffers* buf, v
   d.inv_scale = 1.0f / c->scale;
   d.flags = (const uint8_t*)(c->work + c->L.flags);
   d.inst = (const InstDesc*)(c->work + c->L.inst);
-  d.blk_inst = (const int32_t*)(c->work + c->L.blk_inst);
   d.lay = (const int32_t*)(c->work + c->L.lay);
   d.red = (const RedTab*)(c->work + c->L.red);
   d.red_part = (double*)(c->work + c->L.red_part);
@@ -482,7 +613,6 @@ lbm_status lbm_init(const lbm_config* cfgs, int32_t n, const lbm_buffers* buf, v
   const char* what = "hipStreamSynchronize";
   if (e == hipSuccess) { e = up(c->L.flags, flags.data(), flags.size()); what = "flags upload"; }
   if (e == hipSuccess) { e = up(c->L.inst, c->inst.data(), c->inst.size() * sizeof(InstDesc)); what = "instance upload"; }
-  if (e == hipSuccess) { e = up(c->L.blk_inst, blk.data(), blk.size() * 4); what = "block table upload"; }
   if (e == hipSuccess) { e = up(c->L.lay, lay.data(), lay.size() * 4); what = "layer upload"; }
   if (e == hipSuccess) { e = up(c->L.red, red.data(), red.size() * sizeof(RedTab)); what = "reduction table upload"; }
   if (e == hipSuccess) { e = up(c->L.bc, bc.data(), bc.size() * sizeof(BcDev)); what = "0D state upload"; }
@@ -500,6 +630,13 @@ lbm_status lbm_init(const lbm_config* cfgs, int32_t n, const lbm_buffers* buf, v
     delete c;
     return LBM_E_DEVICE;
   }
+  make_classes(c);
+  if (build_groups(c, false) != LBM_OK) {
+    g_init_err = c->err;
+    (void)hipStreamSynchronize(c->stream);
+    delete c;
+    return LBM_E_DEVICE;
+  }
   *out = c;
   return LBM_OK;
 }
@@ -508,7 +645,7 @@ lbm_status lbm_step(lbm_ctx* c, int64_t nsteps) {
   if (!c) return LBM_E_INVAL;
   if (nsteps < 0) return fail(c, LBM_E_INVAL, "nsteps < 0");
   int64_t left = nsteps;
-  const bool graph = c->use_graph && !c->timing;
+  const bool graph = c->use_graph && !c->timing && !c->tuning;
   if (graph && left >= 2) {
     if ((c->step & 1) && left > 0) {
       HIPCHK(c, enqueue_step(c, 1, false));
@@ -537,6 +674,135 @@ lbm_status lbm_step(lbm_ctx* c, int64_t nsteps) {
     c->step++;
     left--;
   }
+  return LBM_OK;
+}
+
+int32_t lbm_num_classes(lbm_ctx* c) { return c ? (int32_t)c->cls.size() : -1; }
+
+lbm_status lbm_class_info(lbm_ctx* c, int32_t q, int32_t* instances, int64_t* cells, int64_t* wall_points) {
+  if (!c || q < 0 || q >= (int)c->cls.size()) return LBM_E_INVAL;
+  const SizeClass& K = c->cls[q];
+  int64_t nc = 0, np = 0;
+  for (int32_t i : K.inst) {
+    nc += c->inst[i].ncell;
+    if (c->wall[i].on) np += c->wall[i].np;
+  }
+  if (instances) *instances = (int32_t)K.inst.size();
+  if (cells) *cells = nc;
+  if (wall_points) *wall_points = np;
+  return LBM_OK;
+}
+
+lbm_status lbm_get_launch(lbm_ctx* c, int32_t q, lbm_launch* out) {
+  if (!c || !out || q < 0 || q >= (int)c->cls.size()) return LBM_E_INVAL;
+  out->block = c->cls[q].bs;
+  out->cells_per_lane = c->cls[q].cpt;
+  out->wall_tile_theta = c->cls[q].tj;
+  return LBM_OK;
+}
+
+namespace {
+bool valid_launch(const lbm_launch* l) {
+  return l && (l->block == 128 || l->block == 256 || l->block == 512) &&
+         (l->cells_per_lane == 1 || l->cells_per_lane == 2) &&
+         (l->wall_tile_theta == 8 || l->wall_tile_theta == 16 || l->wall_tile_theta == 32);
+}
+
+void apply_launch(lbm_ctx* c, int q, const lbm_launch& l) {
+  SizeClass& K = c->cls[q];
+  K.bs = l.block;
+  K.cpt = l.cells_per_lane;
+  K.tj = l.wall_tile_theta;
+}
+}  // namespace
+
+lbm_status lbm_set_launch(lbm_ctx* c, int32_t q, const lbm_launch* l) {
+  if (!c || q < 0 || q >= (int)c->cls.size()) return LBM_E_INVAL;
+  if (!valid_launch(l)) return fail(c, LBM_E_INVAL, "block 128/256/512, 1-2 cells per lane, wall tile 8/16/32");
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  drop_graph(c);
+  apply_launch(c, q, *l);
+  return build_groups(c, false);
+}
+
+lbm_status lbm_autotune(lbm_ctx* c, int32_t trial_steps, int64_t* advanced) {
+  if (!c) return LBM_E_INVAL;
+  if (trial_steps < 2) return fail(c, LBM_E_INVAL, "trial_steps < 2");
+  trial_steps += trial_steps & 1;   // whole even/odd pairs
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  drop_graph(c);
+  const int nc = (int)c->cls.size();
+  std::vector<lbm_launch> best(nc);
+  for (int q = 0; q < nc; ++q) lbm_get_launch(c, q, &best[q]);
+  int64_t ran = 0;
+  // time every candidate over trial_steps ordinary steps (after two
+  // untimed ones), per class and kernel; phase 0 tunes the collide shape,
+  // phase 1 the wall tile with the chosen collide shape
+  auto trial = [&](const lbm_launch& cand, int kind, std::vector<double>& ms) -> lbm_status {
+    for (int q = 0; q < nc; ++q) {
+      lbm_launch l = best[q];
+      if (kind == 0) { l.block = cand.block; l.cells_per_lane = cand.cells_per_lane; }
+      else l.wall_tile_theta = cand.wall_tile_theta;
+      apply_launch(c, q, l);
+    }
+    lbm_status s = build_groups(c, true);   // one launch per class, timed apart
+    if (s != LBM_OK) return s;
+    for (int k = 0; k < 2; ++k) {
+      HIPCHK(c, enqueue_step(c, (int)(c->step & 1), false));
+      c->step++;
+    }
+    c->tuning = true;
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < trial_steps && e == hipSuccess; ++k) {
+      e = enqueue_step(c, (int)(c->step & 1), false);
+      c->step++;
+    }
+    c->tuning = false;
+    ran += 2 + trial_steps;
+    HIPCHK(c, e);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    ms.assign(nc, 0.0);
+    for (auto& r : c->tune_rec) {
+      float t = 0.f;
+      if (r.first.second == kind && hipEventElapsedTime(&t, r.second.a, r.second.b) == hipSuccess)
+        ms[r.first.first] += t;
+      c->pool.push_back(r.second);
+    }
+    c->tune_rec.clear();
+    return LBM_OK;
+  };
+  const int shapes[6][2] = {{128, 1}, {128, 2}, {256, 1}, {256, 2}, {512, 1}, {512, 2}};
+  std::vector<double> bms(nc, 1e300), ms;
+  std::vector<lbm_launch> pick = best;
+  for (auto& sh : shapes) {
+    lbm_launch cand = best[0];
+    cand.block = sh[0];
+    cand.cells_per_lane = sh[1];
+    lbm_status s = trial(cand, 0, ms);
+    if (s != LBM_OK) return s;
+    for (int q = 0; q < nc; ++q)
+      if (ms[q] < bms[q]) { bms[q] = ms[q]; pick[q].block = sh[0]; pick[q].cells_per_lane = sh[1]; }
+  }
+  for (int q = 0; q < nc; ++q) { best[q].block = pick[q].block; best[q].cells_per_lane = pick[q].cells_per_lane; }
+  if (c->dev.nwall > 0) {
+    std::vector<bool> has_wall(nc, false);
+    for (int q = 0; q < nc; ++q)
+      for (int32_t i : c->cls[q].inst) has_wall[q] = has_wall[q] || c->wall[i].on;
+    std::fill(bms.begin(), bms.end(), 1e300);
+    for (int tj : {8, 16, 32}) {
+      lbm_launch cand = best[0];
+      cand.wall_tile_theta = tj;
+      lbm_status s = trial(cand, 1, ms);
+      if (s != LBM_OK) return s;
+      for (int q = 0; q < nc; ++q)
+        if (has_wall[q] && ms[q] < bms[q]) { bms[q] = ms[q]; pick[q].wall_tile_theta = tj; }
+    }
+    for (int q = 0; q < nc; ++q) best[q].wall_tile_theta = pick[q].wall_tile_theta;
+  }
+  for (int q = 0; q < nc; ++q) apply_launch(c, q, best[q]);
+  lbm_status s = build_groups(c, false);
+  if (s != LBM_OK) return s;
+  if (advanced) *advanced = ran;
   return LBM_OK;
 }
 
@@ -632,22 +898,19 @@ lbm_status lbm_fsi_exchange(lbm_ctx* c, int32_t k, const lbm_wall_desc* w, void*
   c->wall[k].np = np;
   c->wall[k].nband = d.nband;
   c->walls.clear();
-  int maxb = 0, maxt = 0;
+  int maxb = 0;
   int64_t maxp = 0;
   for (int q = 0; q < c->n; ++q)
     if (c->wall[q].on) {
       c->walls.push_back(q);
       maxb = std::max(maxb, c->wall[q].nband);
       maxp = std::max(maxp, c->wall[q].np);
-      const InstDesc& dq = c->inst[q];
-      maxt = std::max(maxt, ((dq.nth + 15) / 16) * ((dq.nzl + 15) / 16));
     }
   HIPCHK(c, hipMemcpy(c->work + c->L.walls, c->walls.data(), c->walls.size() * 4, hipMemcpyHostToDevice));
   c->dev.nwall = (int32_t)c->walls.size();
   c->dev.max_band = maxb;
   c->dev.max_np = (int32_t)maxp;
-  c->dev.max_tiles = maxt;
-  return LBM_OK;
+  return build_groups(c, false);
 }
 
 lbm_status lbm_read_wall(lbm_ctx* c, int32_t k, double* X, double* Xp, double* slip, double* Vf, double* Fp) {

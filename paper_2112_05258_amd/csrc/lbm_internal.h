@@ -15,7 +15,7 @@ namespace lbm {
 
 constexpr int NQ = 19;
 constexpr int NREC = 12;          // doubles per waveform record
-constexpr int BLOCK = 256;        // collide-stream workgroup (4 wave64)
+constexpr int MIN_TILE = 128;     // smallest collide tile (workgroup 128, 1 cell per lane)
 constexpr int RBLOCK = 256;       // boundary-reduction workgroup
 constexpr int RCHUNK = 256;       // layer cells per reduction workgroup (one per lane)
 constexpr int WBLOCK = 256;       // wall / band workgroups
@@ -53,7 +53,6 @@ struct BcDev {
 
 struct InstDesc {
   int32_t nx, ny, nz;
-  int32_t blk0, nblk;      // collide-stream blocks [blk0, blk0 + nblk)
   int32_t red0, nred;      // reduction blocks
   int32_t lay_off[2], lay_n[2];   // inlet / outlet layer lists in the lay array
   int64_t cell0, ncell;
@@ -91,7 +90,6 @@ struct Dev {
   float scale, inv_scale;          // 16-bit storage scale
   const uint8_t* flags;
   const InstDesc* inst;
-  const int32_t* blk_inst;         // collide block -> instance
   const int32_t* lay;              // layer cell lists (local cell ids)
   const RedTab* red;
   double* red_part;                // 2 doubles per reduction block
@@ -104,7 +102,12 @@ struct Dev {
   uint32_t* err;
   const int32_t* walls;            // instance ids with a wall
   int32_t max_band, max_np;
-  int32_t max_tiles;               // wall tiles (16 x 16 points) of the largest wall
+};
+
+// collide tile: BS * CPT consecutive local cells of one instance
+struct CTile {
+  int32_t inst;
+  int32_t start;
 };
 
 }  // namespace lbm
@@ -112,8 +115,15 @@ struct Dev {
 // launchers (lbm_kernels.hip)
 namespace lbm {
 hipError_t launch_reduce(const Dev& d, int prec, int parity, int nred, hipStream_t s);
-hipError_t launch_collide(const Dev& d, int prec, int parity, int nblk, hipStream_t s);
+// collide-stream over a size class: ntile tiles of the table tab, workgroup
+// size bs (128, 256, 512) and cpt (1, 2) cells per lane
+hipError_t launch_collide(const Dev& d, int prec, int parity, int bs, int cpt, const CTile* tab, int ntile,
+                          hipStream_t s);
 hipError_t launch_band(const Dev& d, int prec, int parity, hipStream_t s);
-hipError_t launch_wall(const Dev& d, int prec, int parity, hipStream_t s);
+// wall exchange over the walls of a size class, tiles of tj x (256 / tj)
+// points (tj = 8, 16, 32); tiles = tile count of the class's largest wall
+hipError_t launch_wall(const Dev& d, int prec, int parity, int tj, const int32_t* walls, int nwall, int tiles,
+                       hipStream_t s);
+hipError_t launch_membrane(const Dev& d, int parity, hipStream_t s);
 hipError_t launch_fill_rest(const Dev& d, int prec, int64_t cell0, int64_t ncell, double dshift, hipStream_t s);
 }  // namespace lbm

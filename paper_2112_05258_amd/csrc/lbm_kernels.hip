@@ -61,6 +61,49 @@ template <> struct Store<__hip_bfloat16> {
   __device__ static void st(__hip_bfloat16* p, R v, float s) { *p = __float2bfloat16(v * s); }
 };
 
+// Buffer addressing of one direction's array: a uniform descriptor (base,
+// size in bytes; accesses at or past the size read 0 and write nothing) and a
+// 32-bit byte offset per lane, instead of a 64-bit address per lane and
+// direction.  Needs NT * sizeof(S) < 2^32 (checked at init).
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+__device__ __forceinline__ Rsrc dir_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+template <class S> struct BufIO;
+template <> struct BufIO<double> {
+  __device__ static double ld(Rsrc r, uint32_t o, float) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, o, 0, 0));
+  }
+  __device__ static void st(Rsrc r, uint32_t o, double v, float) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, v), r, o, 0, 0);
+  }
+};
+template <> struct BufIO<float> {
+  __device__ static float ld(Rsrc r, uint32_t o, float) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, o, 0, 0));
+  }
+  __device__ static void st(Rsrc r, uint32_t o, float v, float) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, o, 0, 0);
+  }
+};
+template <> struct BufIO<__half> {
+  __device__ static float ld(Rsrc r, uint32_t o, float inv) {
+    return __half2float(__builtin_bit_cast(__half, __builtin_amdgcn_raw_buffer_load_b16(r, o, 0, 0))) * inv;
+  }
+  __device__ static void st(Rsrc r, uint32_t o, float v, float s) {
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, __float2half_rn(v * s)), r, o, 0, 0);
+  }
+};
+template <> struct BufIO<__hip_bfloat16> {
+  __device__ static float ld(Rsrc r, uint32_t o, float inv) {
+    return __bfloat162float(__builtin_bit_cast(__hip_bfloat16, __builtin_amdgcn_raw_buffer_load_b16(r, o, 0, 0))) *
+           inv;
+  }
+  __device__ static void st(Rsrc r, uint32_t o, float v, float s) {
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, __float2bfloat16(v * s)), r, o, 0, 0);
+  }
+};
+
 template <class R> struct V4;
 template <> struct V4<float> { using T = float4; };
 template <> struct V4<double> { using T = double4; };
@@ -284,13 +327,12 @@ __device__ __forceinline__ R deq_velocity(int i, R vx, R vy, R vz, R sx, R sy, R
   return wgt<R>(i) * (R(3) * (es - eu) + R(4.5) * (es * es - eu * eu) - R(1.5) * (ss - uu));
 }
 
+// one lattice cell (local index of instance inst) of the collide-stream step
 template <class S, bool ODD>
-__global__ __launch_bounds__(BLOCK) void k_collide(Dev d) {
+__device__ __forceinline__ void collide_cell(const Dev& d, const int inst, const int64_t local) {
   using R = typename Store<S>::R;
   using R4 = typename V4<R>::T;
-  const int inst = d.blk_inst[blockIdx.x];
   const InstDesc& I = d.inst[inst];
-  const int64_t local = (int64_t)(blockIdx.x - I.blk0) * BLOCK + threadIdx.x;
   if (local >= I.ncell) return;
   // global cell index fits 32 bits (NT < 2^31); per-direction arrays are
   // addressed as uniform base + 32-bit lane offset
@@ -306,23 +348,26 @@ __global__ __launch_bounds__(BLOCK) void k_collide(Dev d) {
   const bool near = fl & F_NEAR;
 
   // source cell types (only cells next to walls or ghosts look)
-  uint8_t nt[NQ];
-#pragma unroll
-  for (int i = 0; i < NQ; ++i) nt[i] = T_FLUID;
+  // (3 bits per direction in one 64-bit word: two registers, not 19)
+  uint64_t ntb = 0;
   if (near) {
 #pragma unroll
-    for (int i = 1; i < NQ; ++i) nt[i] = d.flags[c - off[i]] & TYPE_MASK;
+    for (int i = 1; i < NQ; ++i) ntb |= (uint64_t)(d.flags[c - off[i]] & TYPE_MASK) << (3 * i);
   }
+  auto nt = [&](int i) -> uint32_t { return (uint32_t)(ntb >> (3 * i)) & 7u; };
 
+  constexpr uint32_t ES = sizeof(S);
+  const uint32_t dir_bytes = (uint32_t)(NT * ES);
+  auto rs = [&](int i) { return dir_rsrc(A + i * NT, dir_bytes); };
   R g[NQ];
 #pragma unroll
   for (int i = 0; i < NQ; ++i) {
     if (!ODD) {
-      g[i] = Store<S>::ld(A + i * NT + c, d.inv_scale);
-    } else if (nt[i] == T_SOLID) {
-      g[i] = Store<S>::ld(A + i * NT + c, d.inv_scale);
+      g[i] = BufIO<S>::ld(rs(i), c * ES, d.inv_scale);
+    } else if (nt(i) == T_SOLID) {
+      g[i] = BufIO<S>::ld(rs(i), c * ES, d.inv_scale);
     } else {
-      g[i] = Store<S>::ld(A + OPP[i] * NT + (uint32_t)(c - off[i]), d.inv_scale);
+      g[i] = BufIO<S>::ld(rs(OPP[i]), (uint32_t)(c - off[i]) * ES, d.inv_scale);
     }
   }
 
@@ -347,8 +392,13 @@ __global__ __launch_bounds__(BLOCK) void k_collide(Dev d) {
   const R cf = R(1) - R(0.5) * om;
   const R vb = vx * bx + vy * by + vz * bz;
 
-  // collision (Eqs. fi, feq, f) and streaming, direction by direction
-  R gs[NQ];
+  // collision (Eqs. fi, feq, f) and streaming, direction by direction.
+  // At a cell next to a 0D-coupled ghost x = c - e_i, the ghost hands c the
+  // value g*_i(c) + g_eq(P*, v*) - g_eq(P(c), v(c)) (Eq. Non-equilibrium3,
+  // x_f = c); it is formed right after g*_i, so that the post-collision
+  // values need not stay live (the two stores go to different slots).
+  R4 v0 = {0, 0, 0, 0};
+  bool have_v0 = false;
 #pragma unroll
   for (int i = 0; i < NQ; ++i) {
     const R eu = EX[i] * vx + EY[i] * vy + EZ[i] * vz;
@@ -358,28 +408,18 @@ __global__ __launch_bounds__(BLOCK) void k_collide(Dev d) {
       const R eb = EX[i] * bx + EY[i] * by + EZ[i] * bz;
       v += cf * wgt<R>(i) * (R(3) * (eb - vb) + R(9) * eu * eb);
     }
-    gs[i] = v;
     if (!ODD) {
-      Store<S>::st(A + OPP[i] * NT + c, v, d.scale);
+      BufIO<S>::st(rs(OPP[i]), c * ES, v, d.scale);
     } else {
-      const uint8_t td = nt[OPP[i]];  // type of c + e_i
-      if (td == T_FLUID) Store<S>::st(A + i * NT + (uint32_t)(c + off[i]), v, d.scale);
-      else if (td == T_SOLID) Store<S>::st(A + OPP[i] * NT + c, v, d.scale);
+      const uint32_t td = nt(OPP[i]);  // type of c + e_i
+      if (td == T_FLUID) BufIO<S>::st(rs(i), (uint32_t)(c + off[i]) * ES, v, d.scale);
+      else if (td == T_SOLID) BufIO<S>::st(rs(OPP[i]), c * ES, v, d.scale);
     }
-  }
-
-  // non-equilibrium extrapolation: the ghost x = c - e_i hands c the value
-  // g*_i(c) + g_eq(P*, v*) - g_eq(P(c), v(c))  (Eq. Non-equilibrium3, x_f = c)
-  if (near) {
-    R4 v0 = {0, 0, 0, 0};
-    bool have_v0 = false;
-#pragma unroll
-    for (int i = 1; i < NQ; ++i) {
-      if (nt[i] < T_INLET) continue;
-      const BcDev& B = d.bc[3 * inst + (nt[i] - T_INLET)];
+    if (i > 0 && nt(i) >= T_INLET) {
+      const BcDev& B = d.bc[3 * inst + (nt(i) - T_INLET)];
       R out;
       if (B.vmode == 0) {
-        out = gs[i] + wgt<R>(i) * (R(B.dstar - I.dref) - dl);
+        out = v + wgt<R>(i) * (R(B.dstar - I.dref) - dl);
       } else {
         R sx, s_y, s_z;
         if (B.vkind == VK_SNAPSHOT) {
@@ -400,12 +440,23 @@ __global__ __launch_bounds__(BLOCK) void k_collide(Dev d) {
         } else {
           sx = 0; s_y = 0; s_z = R(B.vz);
         }
-        out = gs[i] + deq_velocity<R>(i, vx, vy, vz, sx, s_y, s_z);
+        out = v + deq_velocity<R>(i, vx, vy, vz, sx, s_y, s_z);
       }
-      if (!ODD) Store<S>::st(A + OPP[i] * NT + (uint32_t)(c - off[i]), out, d.scale);
-      else Store<S>::st(A + i * NT + c, out, d.scale);
+      if (!ODD) BufIO<S>::st(rs(OPP[i]), (uint32_t)(c - off[i]) * ES, out, d.scale);
+      else BufIO<S>::st(rs(i), c * ES, out, d.scale);
     }
   }
+}
+
+// One workgroup of BS lanes per tile of BS * CPT consecutive cells of one
+// instance (the tile table of a size class); lane t takes cells start + t,
+// start + t + BS, ... so every load and store stays coalesced.  BS and CPT
+// are chosen per size class by the autotuner.
+template <class S, bool ODD, int BS, int CPT>
+__global__ __launch_bounds__(BS) void k_collide(Dev d, const CTile* __restrict__ tab) {
+  const CTile t = tab[blockIdx.x];
+#pragma unroll
+  for (int q = 0; q < CPT; ++q) collide_cell<S, ODD>(d, t.inst, (int64_t)t.start + q * BS + (int)threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -480,10 +531,11 @@ template <> struct FixOf<double> {
 // there for the interpolation, and the same LDS then accumulates the spread
 // force with LDS atomics before one flush of the box's non-zero cells with
 // global atomics (instead of 64 x 3 global atomics per point).
-constexpr int TJ = 16, TK = 16;
-
-template <class R>
-__global__ __launch_bounds__(WBLOCK) void k_wall(Dev d, int parity) {
+// The tile shape TJ x TK (TJ * TK = 256) is chosen per size class by the
+// autotuner: wide in theta (32 x 8), square (16 x 16) or long in z (8 x 32).
+template <class R, int TJ>
+__global__ __launch_bounds__(WBLOCK) void k_wall(Dev d, const int32_t* __restrict__ walls, int parity) {
+  constexpr int TK = (WBLOCK / 64) * 64 / TJ;
   using R4 = typename V4<R>::T;
   // box cells; a 16 x 16 tile at 0.5 lu spans <= ~1000 (LDS stays < 64 KB)
   constexpr int BOXCAP = sizeof(R) == 8 ? 1024 : 2048;
@@ -491,17 +543,18 @@ __global__ __launch_bounds__(WBLOCK) void k_wall(Dev d, int parity) {
   __shared__ uint8_t sfl[BOXCAP];
   __shared__ int smin[3], smax[3];
   __shared__ int semax;
-  const int inst = d.walls[blockIdx.y];
+  const int inst = walls[blockIdx.y];
   const InstDesc& I = d.inst[inst];
   const int nth = I.nth, nzl = I.nzl;
   const int ntj = (nth + TJ - 1) / TJ;
   if ((int)blockIdx.x >= ntj * ((nzl + TK - 1) / TK)) return;  // whole block leaves
-  // wave w takes the parity sub-lattice (w & 1, w >> 1) of the 16 x 16 patch:
-  // its 8 x 8 points are >= 1 lu apart, so for a given stencil offset the 64
-  // lanes mostly hit distinct cells and the LDS atomics do not serialise.
+  // wave w takes the parity sub-lattice (w & 1, w >> 1) of the TJ x TK patch:
+  // its (TJ/2) x (TK/2) points are >= 1 lu apart, so for a given stencil
+  // offset the 64 lanes mostly hit distinct cells and the LDS atomics do not
+  // serialise.
   const int wv = (int)threadIdx.x >> 6, ln = (int)threadIdx.x & 63;
-  const int j = ((int)blockIdx.x % ntj) * TJ + 2 * (ln & 7) + (wv & 1);
-  const int k = ((int)blockIdx.x / ntj) * TK + 2 * (ln >> 3) + (wv >> 1);
+  const int j = ((int)blockIdx.x % ntj) * TJ + 2 * (ln % (TJ / 2)) + (wv & 1);
+  const int k = ((int)blockIdx.x / ntj) * TK + 2 * (ln / (TJ / 2)) + (wv >> 1);
   const bool point = j < nth && k < nzl;
   const int64_t p = point ? j + (int64_t)nth * k : 0;
   // the wall is carried as displacement D = X - X0 (ping-pong D^n / D^{n-1})
@@ -810,11 +863,30 @@ hipError_t launch_reduce(const Dev& d, int prec, int parity, int nred, hipStream
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_collide(const Dev& d, int prec, int parity, int nblk, hipStream_t s) {
-  if (nblk <= 0) return hipSuccess;
-#define F(T)                                                                              \
-  return parity ? launch(k_collide<T, true>, dim3(nblk), dim3(BLOCK), s, Dev(d))          \
-                : launch(k_collide<T, false>, dim3(nblk), dim3(BLOCK), s, Dev(d));
+namespace {
+template <class T, int BS, int CPT>
+hipError_t collide_bs(const Dev& d, int parity, const CTile* tab, int ntile, hipStream_t s) {
+  return parity ? launch(k_collide<T, true, BS, CPT>, dim3(ntile), dim3(BS), s, Dev(d), tab)
+                : launch(k_collide<T, false, BS, CPT>, dim3(ntile), dim3(BS), s, Dev(d), tab);
+}
+template <class T>
+hipError_t collide_t(const Dev& d, int parity, int bs, int cpt, const CTile* tab, int ntile, hipStream_t s) {
+  switch (bs * 4 + cpt) {
+    case 128 * 4 + 1: return collide_bs<T, 128, 1>(d, parity, tab, ntile, s);
+    case 128 * 4 + 2: return collide_bs<T, 128, 2>(d, parity, tab, ntile, s);
+    case 256 * 4 + 1: return collide_bs<T, 256, 1>(d, parity, tab, ntile, s);
+    case 256 * 4 + 2: return collide_bs<T, 256, 2>(d, parity, tab, ntile, s);
+    case 512 * 4 + 1: return collide_bs<T, 512, 1>(d, parity, tab, ntile, s);
+    case 512 * 4 + 2: return collide_bs<T, 512, 2>(d, parity, tab, ntile, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+}  // namespace
+
+hipError_t launch_collide(const Dev& d, int prec, int parity, int bs, int cpt, const CTile* tab, int ntile,
+                          hipStream_t s) {
+  if (ntile <= 0) return hipSuccess;
+#define F(T) return collide_t<T>(d, parity, bs, cpt, tab, ntile, s);
   LBM_DISPATCH(prec, F)
 #undef F
   return hipErrorInvalidValue;
@@ -831,12 +903,27 @@ hipError_t launch_band(const Dev& d, int prec, int parity, hipStream_t s) {
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_wall(const Dev& d, int prec, int parity, hipStream_t s) {
-  if (d.nwall <= 0 || d.max_tiles <= 0) return hipSuccess;
-  const dim3 grid((unsigned)d.max_tiles, d.nwall);
-  hipError_t e = prec == 0 ? launch(k_wall<double>, grid, dim3(WBLOCK), s, Dev(d), int(parity))
-                           : launch(k_wall<float>, grid, dim3(WBLOCK), s, Dev(d), int(parity));
-  if (e != hipSuccess) return e;
+namespace {
+template <class R>
+hipError_t wall_t(const Dev& d, int parity, int tj, const int32_t* walls, dim3 grid, hipStream_t s) {
+  switch (tj) {
+    case 8: return launch(k_wall<R, 8>, grid, dim3(WBLOCK), s, Dev(d), walls, int(parity));
+    case 16: return launch(k_wall<R, 16>, grid, dim3(WBLOCK), s, Dev(d), walls, int(parity));
+    case 32: return launch(k_wall<R, 32>, grid, dim3(WBLOCK), s, Dev(d), walls, int(parity));
+    default: return hipErrorInvalidValue;
+  }
+}
+}  // namespace
+
+hipError_t launch_wall(const Dev& d, int prec, int parity, int tj, const int32_t* walls, int nwall, int tiles,
+                       hipStream_t s) {
+  if (nwall <= 0 || tiles <= 0) return hipSuccess;
+  const dim3 grid((unsigned)tiles, (unsigned)nwall);
+  return prec == 0 ? wall_t<double>(d, parity, tj, walls, grid, s) : wall_t<float>(d, parity, tj, walls, grid, s);
+}
+
+hipError_t launch_membrane(const Dev& d, int parity, hipStream_t s) {
+  if (d.nwall <= 0 || d.max_np <= 0) return hipSuccess;
   const dim3 g2((unsigned)((d.max_np + WBLOCK - 1) / WBLOCK), d.nwall);
   return launch(k_membrane, g2, dim3(WBLOCK), s, Dev(d), int(parity));
 }

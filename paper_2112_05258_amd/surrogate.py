@@ -124,6 +124,11 @@ class Surrogate:
         self.sync()
         return y
 
+    def predict_into(self, x, y):
+        """Enqueue inference of device rows x (m <= max_batch) into device y
+        on the context's stream, without waiting."""
+        _chk(self.L, self.ctx, self.L.lbm_sur_predict(self.ctx, _ptr(x), x.shape[0], _ptr(y)))
+
     def sync(self):
         _chk(self.L, self.ctx, self.L.lbm_sur_sync(self.ctx))
 
