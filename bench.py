@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp16", action="store_true", help="skip the FP16-storage run")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the learned-surrogate leg")
+    ap.add_argument("--pattern-probe", action="store_true",
+                    help="only the HBM ceiling of the collide access pattern (19 SoA loads and stores per cell)")
     ap.add_argument("--surrogate-only", action="store_true",
                     help="only the learned-surrogate leg (for profiling its kernels)")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble run")
@@ -317,6 +319,15 @@ def main():
     args = parse()
     if args.copy_probe:
         copy_probe()
+        return
+    if args.pattern_probe:
+        import subprocess
+        exe = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2112_05258_amd", "probe_stream")
+        res = {}
+        for line in subprocess.run([exe], check=True, capture_output=True, text=True).stdout.splitlines():
+            f = line.split()
+            res[f"{f[0]} {f[1]}"] = {f[k]: float(f[k + 1]) for k in range(2, len(f), 2)}
+        print(json.dumps({"pattern_probe": res}), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "

@@ -27,6 +27,9 @@ FLAGS = [
 ]
 
 
+PROBE = os.path.join(HERE, "probe_stream")
+
+
 def build(verbose=False):
     srcs = [os.path.join(CSRC, s) for s in SOURCES]
     tmp = LIB + ".tmp"
@@ -35,6 +38,13 @@ def build(verbose=False):
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
+    # the benchmark's access-pattern probe (a standalone program)
+    pflags = [f for f in FLAGS if f not in ("-fPIC", "-shared", "-munsafe-fp-atomics")]
+    cmd = [HIPCC] + pflags + ["-o", PROBE + ".tmp", os.path.join(CSRC, "probe_stream.hip")]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(PROBE + ".tmp", PROBE)
     return LIB
 
 
