@@ -156,6 +156,101 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
       }
 }
 
+// Forward product C = A B^T with both operands k-contiguous (activations h and
+// weights W), the hot path of inference.  Block tile 128 x 256, each of the 4
+// waves 64 x 128 (2 x 4 MFMA tiles: 6 fragment reads from LDS per 8 MFMAs),
+// k-step 32.  The next k-step's tiles are fetched into registers while the
+// current one is multiplied out of LDS, and stored into the other half of a
+// double-buffered LDS after it: one barrier per k-step.
+constexpr int FBM = 128, FBN = 256;
+
+template <int EPI>
+__global__ __launch_bounds__(256, 2) void k_gemm_fwd(GemmArgs g) {
+  __shared__ __attribute__((aligned(16))) uint16_t As[2][FBM * LDK];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[2][FBN * LDK];
+  const int tid = (int)threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int m0 = (int)blockIdx.y * FBM, n0 = (int)blockIdx.x * FBN;
+  const int wm = (wv >> 1) * 64, wn = (wv & 1) * 128;
+  f32x16 acc[2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
+  // 16-byte chunks of 8 k: A tile 128 x 32 = 512 chunks (2 per lane), B tile
+  // 256 x 32 = 1024 chunks (4 per lane); out-of-range chunks are zero
+  uint4 ra[2], rb[4];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int c = tid + 256 * q, r = c >> 2, kc = (c & 3) * 8;
+      ra[q] = make_uint4(0, 0, 0, 0);
+      if (m0 + r < g.a_ext && k0 + kc + 8 <= g.K) ra[q] = *(const uint4*)(g.A + (int64_t)(m0 + r) * g.lda + k0 + kc);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int c = tid + 256 * q, r = c >> 2, kc = (c & 3) * 8;
+      rb[q] = make_uint4(0, 0, 0, 0);
+      if (n0 + r < g.b_ext && k0 + kc + 8 <= g.K) rb[q] = *(const uint4*)(g.B + (int64_t)(n0 + r) * g.ldb + k0 + kc);
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int c = tid + 256 * q;
+      *(uint4*)(As[buf] + (c >> 2) * LDK + (c & 3) * 8) = ra[q];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int c = tid + 256 * q;
+      *(uint4*)(Bs[buf] + (c >> 2) * LDK + (c & 3) * 8) = rb[q];
+    }
+  };
+  const int fr = lane & 31, fk = (lane >> 5) * 8;
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  const int nk = (g.K + BK - 1) / BK;
+  for (int s = 0; s < nk; ++s) {
+    const int cur = s & 1;
+    const bool more = s + 1 < nk;
+    if (more) gload((s + 1) * BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 16) {
+      bf16x8 a[2], b[4];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) a[t] = *(const bf16x8*)(As[cur] + (wm + t * 32 + fr) * LDK + kk + fk);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) b[t] = *(const bf16x8*)(Bs[cur] + (wn + t * 32 + fr) * LDK + kk + fk);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    if (more) sstore(cur ^ 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int m = m0 + wm + i * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
+        const int n = n0 + wn + j * 32 + (lane & 31);
+        if (m >= g.M || n >= g.N) continue;
+        const float s = acc[i][j][v] + g.bias[n];
+        const int64_t o = (int64_t)m * g.ldo + n;
+        if (EPI == EPI_FWD_GELU) {
+          if (g.zout) g.zout[o] = s;
+          g.outh[o] = f2bf(gelu(s));
+        } else {
+          g.outf[o] = g.mu ? g.mu[n] + g.sigma[n] * s : s;
+        }
+      }
+}
+
 // inputs: X0[r][j] = 2 (x - lo) / (hi - lo) - 1 for r < m and j < n_in; 0 for
 // the padding columns up to KPAD and the padding rows m <= r < mp
 // (rows picked by idx outside [0, nrows) read zeros and set *err)
@@ -373,10 +468,15 @@ lbm_status gemm(lbm_sur_ctx* c, const GemmArgs& a) {
   if (a.K % 8 || a.lda % 8 || a.ldb % 8 || !aligned16(a.A) || !aligned16(a.B) || (!AKC && a.a_ext % 8) ||
       (!BKC && a.b_ext % 8) || a.M <= 0 || a.N <= 0)
     return fail(c, LBM_E_INVAL, "matrix product shape or alignment not supported");
-  dim3 grid((a.N + BN - 1) / BN, (a.M + BM - 1) / BM);
   const bool t = c->timing && c->nev + 2 <= (int)c->ev.size();
   if (t) SURCHK(c, hipEventRecord(c->ev[c->nev], c->stream));
-  hipLaunchKernelGGL((k_gemm<AKC, BKC, EPI>), grid, dim3(256), 0, c->stream, a);
+  if constexpr (AKC && BKC && (EPI == EPI_FWD_GELU || EPI == EPI_FWD_OUT)) {
+    dim3 grid((a.N + FBN - 1) / FBN, (a.M + FBM - 1) / FBM);
+    hipLaunchKernelGGL((k_gemm_fwd<EPI>), grid, dim3(256), 0, c->stream, a);
+  } else {
+    dim3 grid((a.N + BN - 1) / BN, (a.M + BM - 1) / BM);
+    hipLaunchKernelGGL((k_gemm<AKC, BKC, EPI>), grid, dim3(256), 0, c->stream, a);
+  }
   SURCHK(c, hipGetLastError());
   if (t) {
     SURCHK(c, hipEventRecord(c->ev[c->nev + 1], c->stream));
