@@ -231,6 +231,18 @@ lbm_status lbm_kernel_time(lbm_ctx* ctx, int32_t kernel, int64_t* launches, doub
  * of launching kernels one by one (default on; turned off while timing). */
 lbm_status lbm_set_graph(lbm_ctx* ctx, int32_t on);
 
+/* With a wall registered, run the wall exchange (band moments,
+ * interpolation, force, spreading, membrane) on a second stream of the
+ * library's own while the main stream collides the cells outside the wall
+ * band; the band cells collide after the spread force is complete.  The
+ * cells' slot sets are disjoint, so results are identical either way.
+ * Default off: on the elastic-tube workloads the band-only collide pass
+ * (band cells in short runs spread over most 256-cell tiles) and the
+ * kernels' competition for the CUs cost more than the overlap saves.
+ * Timing and autotuning always run the kernels in sequence.
+ * Synchronises and drops the captured step graph. */
+lbm_status lbm_set_overlap(lbm_ctx* ctx, int32_t on);
+
 /* Launch shapes per size class.  The instances of a context are grouped by
  * cell count into size classes (quartiles from 8 instances on, else one
  * class); each class has its own collide-stream launch (workgroup size and

@@ -72,6 +72,7 @@ SYMBOLS = {
     "lbm_set_timing": (C.c_int, [C.c_void_p, C.c_int32]),
     "lbm_kernel_time": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
     "lbm_set_graph": (C.c_int, [C.c_void_p, C.c_int32]),
+    "lbm_set_overlap": (C.c_int, [C.c_void_p, C.c_int32]),
     "lbm_num_classes": (C.c_int32, [C.c_void_p]),
     "lbm_class_info": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int64),
                                  C.POINTER(C.c_int64)]),
@@ -274,6 +275,9 @@ class Solver:
 
     def set_graph(self, on):
         self._check(lib().lbm_set_graph(self.h, 1 if on else 0))
+
+    def set_overlap(self, on):
+        self._check(lib().lbm_set_overlap(self.h, 1 if on else 0))
 
     # ---- launch shapes per size class (autotuner) ----------------------
     def classes(self):

@@ -109,7 +109,7 @@ bool build_geometry(const lbm_config& c, Geometry& g, std::string& err) {
 }
 
 struct Layout {
-  size_t flags, inst, ctab, lay, red, red_part, bc, st, wave, v0, err, walls, cwalls, total;
+  size_t flags, inst, ctab, btab, lay, red, red_part, bc, st, wave, v0, err, walls, cwalls, total;
   int64_t NT;
   int ntile_max, nred, nlay, wave_cap;
   int64_t nv0;
@@ -154,6 +154,7 @@ void plan(const std::vector<Geometry>& G, int prec, int wave_cap, Layout& L, std
   L.flags = o; o = align256(o + L.NT);
   L.inst = o; o = align256(o + n * sizeof(InstDesc));
   L.ctab = o; o = align256(o + (size_t)std::max(L.ntile_max, 1) * sizeof(CTile));
+  L.btab = o; o = align256(o + (size_t)std::max(L.ntile_max, 1) * sizeof(CTile));
   L.lay = o; o = align256(o + (size_t)std::max(L.nlay, 1) * 4);
   L.red = o; o = align256(o + (size_t)L.nred * sizeof(RedTab));
   L.red_part = o; o = align256(o + (size_t)L.nred * 16);
@@ -214,6 +215,12 @@ struct lbm_ctx {
   std::vector<int32_t> walls;
   std::vector<SizeClass> cls;
   std::vector<LaunchGroup> cgroups, wgroups;
+  // overlap of the wall exchange with the bulk collide: a side stream, the
+  // band-cell tile table (256-cell tiles holding a band cell) and events
+  bool overlap = false;
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_wall = nullptr, ev_join = nullptr;
+  int nbtile = 0;
   // per-class kernel events while tuning: (class, kind 0 collide / 1 wall)
   bool tuning = false;
   std::vector<std::pair<std::pair<int, int>, EventPair>> tune_rec;
@@ -280,6 +287,31 @@ hipError_t enqueue_step(lbm_ctx* c, int parity, bool timed) {
   };
   const CTile* tab = (const CTile*)(c->work + c->L.ctab);
   const int32_t* cw = (const int32_t*)(c->work + c->L.cwalls);
+  if (c->dev.nwall > 0 && c->overlap && c->side && !timed && !c->tuning) {
+    // main stream: 0D reductions, then the collide of cells outside the
+    // wall band; side stream: band moments, wall exchange, membrane.  The
+    // band cells collide on the main stream once the wall force is spread.
+    hipStream_t s2 = c->side;
+    if ((e = hipEventRecord(c->ev_fork, c->stream)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(s2, c->ev_fork, 0)) != hipSuccess) return e;
+    if ((e = launch_band(c->dev, c->prec, parity, s2)) != hipSuccess) return e;
+    for (const LaunchGroup& G : c->wgroups)
+      if ((e = launch_wall(c->dev, c->prec, parity, G.tj, cw + G.off, G.count, G.wall_tiles, s2)) != hipSuccess)
+        return e;
+    if ((e = hipEventRecord(c->ev_wall, s2)) != hipSuccess) return e;
+    if ((e = launch_membrane(c->dev, parity, s2)) != hipSuccess) return e;
+    if ((e = hipEventRecord(c->ev_join, s2)) != hipSuccess) return e;
+    if ((e = launch_reduce(c->dev, c->prec, parity, c->L.nred, c->stream)) != hipSuccess) return e;
+    for (const LaunchGroup& G : c->cgroups)
+      if ((e = launch_collide(c->dev, c->prec, parity, G.bs, G.cpt, tab + G.off, G.count, COLLIDE_BULK,
+                              c->stream)) != hipSuccess)
+        return e;
+    if ((e = hipStreamWaitEvent(c->stream, c->ev_wall, 0)) != hipSuccess) return e;
+    if ((e = launch_collide(c->dev, c->prec, parity, 256, 1, (const CTile*)(c->work + c->L.btab), c->nbtile,
+                            COLLIDE_BAND, c->stream)) != hipSuccess)
+      return e;
+    return hipStreamWaitEvent(c->stream, c->ev_join, 0);
+  }
   pre(1);
   e = launch_reduce(c->dev, c->prec, parity, c->L.nred, c->stream);
   if (e != hipSuccess) return e;
@@ -305,7 +337,7 @@ hipError_t enqueue_step(lbm_ctx* c, int parity, bool timed) {
   for (const LaunchGroup& G : c->cgroups) {
     EventPair p;
     tpre(p);
-    e = launch_collide(c->dev, c->prec, parity, G.bs, G.cpt, tab + G.off, G.count, c->stream);
+    e = launch_collide(c->dev, c->prec, parity, G.bs, G.cpt, tab + G.off, G.count, COLLIDE_ALL, c->stream);
     if (e != hipSuccess) return e;
     tpost(p, G.cls, 0);
   }
@@ -390,6 +422,21 @@ lbm_status build_groups(lbm_ctx* c, bool per_class) {
     G.count = (int)(walls.size() - G.off);
     if (G.count > 0) c->wgroups.push_back(G);
   }
+  // tiles of 256 cells that hold a band cell, for the band-only collide pass
+  std::vector<CTile> btab;
+  for (int i = 0; i < c->n; ++i) {
+    if (!c->wall[i].on) continue;
+    int32_t last = -1;
+    for (int32_t cell : c->wall[i].band) {   // ascending
+      const int32_t t = cell / 256;
+      if (t != last) btab.push_back(CTile{i, t * 256});
+      last = t;
+    }
+  }
+  if ((int64_t)btab.size() > c->L.ntile_max) return fail(c, LBM_E_STATE, "band tile table overflow");
+  c->nbtile = (int)btab.size();
+  if (!btab.empty())
+    HIPCHK(c, hipMemcpy(c->work + c->L.btab, btab.data(), btab.size() * sizeof(CTile), hipMemcpyHostToDevice));
   if ((int64_t)tab.size() > c->L.ntile_max) return fail(c, LBM_E_STATE, "tile table overflow");
   if (!tab.empty())
     HIPCHK(c, hipMemcpy(c->work + c->L.ctab, tab.data(), tab.size() * sizeof(CTile), hipMemcpyHostToDevice));
@@ -631,6 +678,15 @@ lbm_status lbm_init(const lbm_config* cfgs, int32_t n, const lbm_buffers* buf, v
     return LBM_E_DEVICE;
   }
   make_classes(c);
+  if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_wall, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+    g_init_err = "side stream or event creation failed";
+    (void)hipStreamSynchronize(c->stream);
+    delete c;
+    return LBM_E_DEVICE;
+  }
   if (build_groups(c, false) != LBM_OK) {
     g_init_err = c->err;
     (void)hipStreamSynchronize(c->stream);
@@ -897,6 +953,7 @@ lbm_status lbm_fsi_exchange(lbm_ctx* c, int32_t k, const lbm_wall_desc* w, void*
   c->wall[k].on = true;
   c->wall[k].np = np;
   c->wall[k].nband = d.nband;
+  c->wall[k].band = band;
   c->walls.clear();
   int maxb = 0;
   int64_t maxp = 0;
@@ -1067,17 +1124,29 @@ lbm_status lbm_set_graph(lbm_ctx* c, int32_t on) {
   return LBM_OK;
 }
 
+lbm_status lbm_set_overlap(lbm_ctx* c, int32_t on) {
+  if (!c) return LBM_E_INVAL;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  drop_graph(c);
+  c->overlap = on != 0;
+  return LBM_OK;
+}
+
 const char* lbm_last_error(const lbm_ctx* c) { return c ? c->err.c_str() : g_init_err.c_str(); }
 
 void lbm_destroy(lbm_ctx* c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
+  if (c->side) (void)hipStreamSynchronize(c->side);
   collect_times(c);
   for (auto& p : c->pool) {
     (void)hipEventDestroy(p.a);
     (void)hipEventDestroy(p.b);
   }
   drop_graph(c);
+  for (hipEvent_t e : {c->ev_fork, c->ev_wall, c->ev_join})
+    if (e) (void)hipEventDestroy(e);
+  if (c->side) (void)hipStreamDestroy(c->side);
   delete c;
 }
 

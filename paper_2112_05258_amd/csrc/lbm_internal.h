@@ -116,9 +116,11 @@ struct CTile {
 namespace lbm {
 hipError_t launch_reduce(const Dev& d, int prec, int parity, int nred, hipStream_t s);
 // collide-stream over a size class: ntile tiles of the table tab, workgroup
-// size bs (128, 256, 512) and cpt (1, 2) cells per lane
+// size bs (128, 256, 512) and cpt (1, 2) cells per lane; mode selects all
+// fluid cells, those outside the wall band, or the band cells only
+enum { COLLIDE_ALL = 0, COLLIDE_BULK = 1, COLLIDE_BAND = 2 };
 hipError_t launch_collide(const Dev& d, int prec, int parity, int bs, int cpt, const CTile* tab, int ntile,
-                          hipStream_t s);
+                          int mode, hipStream_t s);
 hipError_t launch_band(const Dev& d, int prec, int parity, hipStream_t s);
 // wall exchange over the walls of a size class, tiles of tj x (256 / tj)
 // points (tj = 8, 16, 32); tiles = tile count of the class's largest wall

@@ -328,8 +328,13 @@ __device__ __forceinline__ R deq_velocity(int i, R vx, R vy, R vz, R sx, R sy, R
 }
 
 // one lattice cell (local index of instance inst) of the collide-stream step
+// mode: COLLIDE_ALL, COLLIDE_BULK (cells outside the wall band) or
+// COLLIDE_BAND (band cells only).  The slots a cell writes in a step are
+// exactly the slots it reads, so the two partial passes touch disjoint
+// memory and the bulk pass may run while the wall exchange still reads the
+// band cells' populations.
 template <class S, bool ODD>
-__device__ __forceinline__ void collide_cell(const Dev& d, const int inst, const int64_t local) {
+__device__ __forceinline__ void collide_cell(const Dev& d, const int inst, const int64_t local, const int mode) {
   using R = typename Store<S>::R;
   using R4 = typename V4<R>::T;
   const InstDesc& I = d.inst[inst];
@@ -339,6 +344,7 @@ __device__ __forceinline__ void collide_cell(const Dev& d, const int inst, const
   const uint32_t c = (uint32_t)(I.cell0 + local);
   const uint8_t fl = d.flags[c];
   if ((fl & TYPE_MASK) != T_FLUID) return;
+  if (mode != COLLIDE_ALL && ((fl & F_BAND) != 0) != (mode == COLLIDE_BAND)) return;
   const int32_t sy = I.nx, sz = I.nx * I.ny;
   int32_t off[NQ];
 #pragma unroll
@@ -453,10 +459,10 @@ __device__ __forceinline__ void collide_cell(const Dev& d, const int inst, const
 // start + t + BS, ... so every load and store stays coalesced.  BS and CPT
 // are chosen per size class by the autotuner.
 template <class S, bool ODD, int BS, int CPT>
-__global__ __launch_bounds__(BS) void k_collide(Dev d, const CTile* __restrict__ tab) {
+__global__ __launch_bounds__(BS) void k_collide(Dev d, const CTile* __restrict__ tab, int mode) {
   const CTile t = tab[blockIdx.x];
 #pragma unroll
-  for (int q = 0; q < CPT; ++q) collide_cell<S, ODD>(d, t.inst, (int64_t)t.start + q * BS + (int)threadIdx.x);
+  for (int q = 0; q < CPT; ++q) collide_cell<S, ODD>(d, t.inst, (int64_t)t.start + q * BS + (int)threadIdx.x, mode);
 }
 
 // ---------------------------------------------------------------------------
@@ -865,28 +871,29 @@ hipError_t launch_reduce(const Dev& d, int prec, int parity, int nred, hipStream
 
 namespace {
 template <class T, int BS, int CPT>
-hipError_t collide_bs(const Dev& d, int parity, const CTile* tab, int ntile, hipStream_t s) {
-  return parity ? launch(k_collide<T, true, BS, CPT>, dim3(ntile), dim3(BS), s, Dev(d), tab)
-                : launch(k_collide<T, false, BS, CPT>, dim3(ntile), dim3(BS), s, Dev(d), tab);
+hipError_t collide_bs(const Dev& d, int parity, const CTile* tab, int ntile, int mode, hipStream_t s) {
+  return parity ? launch(k_collide<T, true, BS, CPT>, dim3(ntile), dim3(BS), s, Dev(d), tab, int(mode))
+                : launch(k_collide<T, false, BS, CPT>, dim3(ntile), dim3(BS), s, Dev(d), tab, int(mode));
 }
 template <class T>
-hipError_t collide_t(const Dev& d, int parity, int bs, int cpt, const CTile* tab, int ntile, hipStream_t s) {
+hipError_t collide_t(const Dev& d, int parity, int bs, int cpt, const CTile* tab, int ntile, int mode,
+                     hipStream_t s) {
   switch (bs * 4 + cpt) {
-    case 128 * 4 + 1: return collide_bs<T, 128, 1>(d, parity, tab, ntile, s);
-    case 128 * 4 + 2: return collide_bs<T, 128, 2>(d, parity, tab, ntile, s);
-    case 256 * 4 + 1: return collide_bs<T, 256, 1>(d, parity, tab, ntile, s);
-    case 256 * 4 + 2: return collide_bs<T, 256, 2>(d, parity, tab, ntile, s);
-    case 512 * 4 + 1: return collide_bs<T, 512, 1>(d, parity, tab, ntile, s);
-    case 512 * 4 + 2: return collide_bs<T, 512, 2>(d, parity, tab, ntile, s);
+    case 128 * 4 + 1: return collide_bs<T, 128, 1>(d, parity, tab, ntile, mode, s);
+    case 128 * 4 + 2: return collide_bs<T, 128, 2>(d, parity, tab, ntile, mode, s);
+    case 256 * 4 + 1: return collide_bs<T, 256, 1>(d, parity, tab, ntile, mode, s);
+    case 256 * 4 + 2: return collide_bs<T, 256, 2>(d, parity, tab, ntile, mode, s);
+    case 512 * 4 + 1: return collide_bs<T, 512, 1>(d, parity, tab, ntile, mode, s);
+    case 512 * 4 + 2: return collide_bs<T, 512, 2>(d, parity, tab, ntile, mode, s);
     default: return hipErrorInvalidValue;
   }
 }
 }  // namespace
 
 hipError_t launch_collide(const Dev& d, int prec, int parity, int bs, int cpt, const CTile* tab, int ntile,
-                          hipStream_t s) {
+                          int mode, hipStream_t s) {
   if (ntile <= 0) return hipSuccess;
-#define F(T) return collide_t<T>(d, parity, bs, cpt, tab, ntile, s);
+#define F(T) return collide_t<T>(d, parity, bs, cpt, tab, ntile, mode, s);
   LBM_DISPATCH(prec, F)
 #undef F
   return hipErrorInvalidValue;
