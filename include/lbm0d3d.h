@@ -135,8 +135,16 @@ lbm_status lbm_init(const lbm_config* cfgs, int32_t n, const lbm_buffers* buf, v
 
 /* Advance every instance by nsteps full steps (Algorithm 1): boundary
  * reductions and 0D update, IB force (if a wall is registered), fused
- * collide-stream.  Asynchronous.  Errors: LBM_E_INVAL (nsteps < 0). */
+ * collide-stream.  Asynchronous, except that with a wall registered it
+ * synchronises at every multiple of the band-check interval to test the
+ * wall's motion (and rebuilds the band when needed, see lbm_wall_desc).
+ * Errors: LBM_E_INVAL (nsteps < 0); LBM_E_BAND from a band rebuild. */
 lbm_status lbm_step(lbm_ctx* ctx, int64_t nsteps);
+
+/* Steps between wall-motion tests (default 32; 0 never tests, so the band
+ * stays where lbm_fsi_exchange built it).  The test is sound while no point
+ * moves a whole lattice unit between two tests. */
+lbm_status lbm_set_band_check(lbm_ctx* ctx, int32_t every);
 
 /* Set the 0D model of boundary b (0 inlet, 1 outlet, 2 exterior) of instance
  * inst: kind, params (see lbm_bc_kind), optional initial state.  Synchronises
@@ -159,8 +167,13 @@ lbm_status lbm_get_0d(lbm_ctx* ctx, int32_t inst, int32_t boundary, double* out)
  * directions (bending acts on X - X0), central difference in time with
  * areal mass `mass`.  X0_host: 3*n_points doubles (x,y,z per point), rest
  * = initial shape.  band_margin: extra cells kept around the wall
- * (default 2); a point whose stencil leaves the band raises LBM_E_BAND at
- * the next lbm_sync. */
+ * (default 2).  The band (the fluid cells the wall exchanges with) follows
+ * the wall: every band_check steps (lbm_set_band_check) lbm_step tests how
+ * far the points have moved since the band was built and rebuilds it around
+ * the current positions once that reaches band_margin - 1 lattice units.
+ * A point whose stencil still leaves the band raises LBM_E_BAND at the next
+ * lbm_sync; so does a rebuilt band that outgrows the buffer's reserve
+ * (twice the initial band plus 4096 cells) or reaches the box faces. */
 typedef struct {
   int32_t n_theta, n_z;
   const double* X0_host;

@@ -261,6 +261,22 @@ def small_fsi(nx=24, ny=24, nz=40, r=7.0, h=0.7, tau=0.6, seed=None):
     return c
 
 
+def inflating_tube():
+    """A soft elastic tube (r = 7, k = 0.002, areal mass 0.5) in a 30 x 30 x 40
+    box whose exterior is held 200 mmHg below the tube's pressure: the wall
+    moves outwards by almost three lattice units within 600 steps, past the
+    default band margin (the bulge next to the fixed end rings stays clear
+    of the box ends until then)."""
+    n, nz, r = 30, 40, 7.0
+    sc = scales(2500.0, 8000.0 * (r / 48.0) ** 2, 2.5e-6)
+    c = _elastic_tube(n, n, nz, r, 0.7, 0.002, 1e-3, sc, tau=0.6, mass=0.5)
+    p0 = c["p_init"]
+    c.update(name="inflating_tube_30x30x40", inlet=(BC_PRESSURE_CONST, [p0]), outlet=(BC_PRESSURE_CONST, [p0]),
+             exterior=(BC_PRESSURE_CONST, [p0 - 200 * sc["sigma_P"]]), steps=600)
+    c.pop("outlet_state")
+    return c
+
+
 def ensemble(n=256, seed=3):
     """Parameter draws of the batched ensemble (radius, length, LV, WK, wall):
     r ~ U[6, 16] lu and L ~ U[48, 160] lu (rounded), Emax ~ U[1.5, 3.0],

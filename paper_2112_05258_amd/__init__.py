@@ -73,6 +73,7 @@ SYMBOLS = {
     "lbm_kernel_time": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
     "lbm_set_graph": (C.c_int, [C.c_void_p, C.c_int32]),
     "lbm_set_overlap": (C.c_int, [C.c_void_p, C.c_int32]),
+    "lbm_set_band_check": (C.c_int, [C.c_void_p, C.c_int32]),
     "lbm_num_classes": (C.c_int32, [C.c_void_p]),
     "lbm_class_info": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int64),
                                  C.POINTER(C.c_int64)]),
@@ -278,6 +279,9 @@ class Solver:
 
     def set_overlap(self, on):
         self._check(lib().lbm_set_overlap(self.h, 1 if on else 0))
+
+    def set_band_check(self, every):
+        self._check(lib().lbm_set_band_check(self.h, int(every)))
 
     # ---- launch shapes per size class (autotuner) ----------------------
     def classes(self):

@@ -109,7 +109,7 @@ bool build_geometry(const lbm_config& c, Geometry& g, std::string& err) {
 }
 
 struct Layout {
-  size_t flags, inst, ctab, btab, lay, red, red_part, bc, st, wave, v0, err, walls, cwalls, total;
+  size_t flags, inst, ctab, btab, lay, red, red_part, bc, st, wave, v0, err, moved, walls, cwalls, total;
   int64_t NT;
   int ntile_max, nred, nlay, wave_cap;
   int64_t nv0;
@@ -163,6 +163,7 @@ void plan(const std::vector<Geometry>& G, int prec, int wave_cap, Layout& L, std
   L.wave = o; o = align256(o + n * (size_t)wave_cap * NREC * 8);
   L.v0 = o; o = align256(o + (size_t)L.nv0 * r4_size(prec));
   L.err = o; o = align256(o + 4);
+  L.moved = o; o = align256(o + 4);
   L.walls = o; o = align256(o + n * 4);
   L.cwalls = o; o = align256(o + n * 4);
   L.total = o;
@@ -177,7 +178,10 @@ struct Wall {
   bool on = false;
   int64_t np = 0;
   int nband = 0;
+  int margin = 2;
+  int64_t band_cap = 0;
   std::vector<int32_t> band;
+  std::vector<double> X0;      // rest positions, xyz per point (host copy)
 };
 
 // Instances of similar box volume share launch shapes, chosen by the
@@ -218,6 +222,7 @@ struct lbm_ctx {
   // overlap of the wall exchange with the bulk collide: a side stream, the
   // band-cell tile table (256-cell tiles holding a band cell) and events
   bool overlap = false;
+  int64_t band_check = 32;     // steps between wall-motion tests (0: never)
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_wall = nullptr, ev_join = nullptr;
   int nbtile = 0;
@@ -445,6 +450,63 @@ lbm_status build_groups(lbm_ctx* c, bool per_class) {
   return LBM_OK;
 }
 
+bool band_from_points(const Geometry& g, const double* X, int64_t np, int m, std::vector<int32_t>& band,
+                      std::string& err);
+
+// Rebuild the band of every wall around its current positions X0 + D^n
+// (D^n is in Xab[step & 1]) and restart the motion measure from there.
+lbm_status rebuild_bands(lbm_ctx* c) {
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  int maxb = 0;
+  for (int k = 0; k < c->n; ++k) {
+    Wall& W = c->wall[k];
+    if (!W.on) continue;
+    InstDesc& d = c->inst[k];
+    Geometry& g = c->geo[k];
+    const int64_t np = d.np;
+    std::vector<double> D4((size_t)np * 4), X((size_t)np * 3);
+    double* Dn = d.Xab[c->step & 1];
+    HIPCHK(c, hipMemcpy(D4.data(), Dn, (size_t)np * 32, hipMemcpyDeviceToHost));
+    for (int64_t p = 0; p < np; ++p)
+      for (int q = 0; q < 3; ++q) X[3 * p + q] = W.X0[3 * p + q] + D4[4 * p + q];
+    std::vector<int32_t> band;
+    std::string why;
+    if (!band_from_points(g, X.data(), np, W.margin, band, why)) return fail(c, LBM_E_BAND, "band rebuild: " + why);
+    if ((int64_t)band.size() > W.band_cap) return fail(c, LBM_E_BAND, "band rebuild: the band outgrew its capacity");
+    for (auto& t : g.flags) t &= (uint8_t)~F_BAND;
+    for (int32_t cell : band) g.flags[cell] |= F_BAND;
+    HIPCHK(c, hipMemcpy(c->work + c->L.flags + d.cell0, g.flags.data(), g.ncell, hipMemcpyHostToDevice));
+    if (!band.empty()) HIPCHK(c, hipMemcpy(d.band, band.data(), band.size() * 4, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(d.Dref, Dn, (size_t)np * 32, hipMemcpyDeviceToDevice));
+    d.nband = (int32_t)band.size();
+    HIPCHK(c, hipMemcpy(c->work + c->L.inst + k * sizeof(InstDesc), &d, sizeof d, hipMemcpyHostToDevice));
+    W.band.swap(band);
+    W.nband = d.nband;
+    maxb = std::max(maxb, W.nband);
+  }
+  HIPCHK(c, hipMemset(c->work + c->L.moved, 0, 4));
+  c->dev.max_band = maxb;
+  drop_graph(c);
+  return build_groups(c, false);
+}
+
+// Wall-motion test: once a point has moved m - 1 lattice units (m = band
+// margin) since its band was built, the band is rebuilt, so that no stencil
+// reaches past it as long as no point moves a whole unit between tests.
+lbm_status check_bands(lbm_ctx* c) {
+  int m = 1 << 30;
+  for (int k = 0; k < c->n; ++k)
+    if (c->wall[k].on) m = std::min(m, c->wall[k].margin);
+  if (m == (1 << 30)) return LBM_OK;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  uint32_t bits = 0;
+  HIPCHK(c, hipMemcpy(&bits, c->work + c->L.moved, 4, hipMemcpyDeviceToHost));
+  float moved;
+  std::memcpy(&moved, &bits, 4);
+  if (!(moved < (float)(m - 1))) return rebuild_bands(c);
+  return LBM_OK;
+}
+
 template <class T>
 lbm_status h2d(lbm_ctx* c, size_t off, const T* src, size_t count) {
   if (count == 0) return LBM_OK;
@@ -492,33 +554,59 @@ lbm_status read_pops(lbm_ctx* c, int k, std::vector<double>& out) {
   return LBM_OK;
 }
 
-bool wall_band(const lbm_ctx* c, int k, const lbm_wall_desc* w, std::vector<int32_t>& band, std::string& err) {
-  const Geometry& g = c->geo[k];
-  const int64_t np = (int64_t)w->n_theta * w->n_z;
-  const int m = w->band_margin > 0 ? w->band_margin : 2;
-  std::vector<uint8_t> mark(g.ncell, 0);
+// Band of a wall (fluid cells within margin m of the 4x4x4 stencils of the
+// points X, xyz per point): the stencil base cells b = floor(X) - 1 are
+// marked, then the marks are dilated by [b - m, b + 3 + m] along x, y and z
+// in turn (one running window per line).
+bool band_from_points(const Geometry& g, const double* X, int64_t np, int m, std::vector<int32_t>& band,
+                      std::string& err) {
+  std::vector<uint8_t> a(g.ncell, 0), t(g.ncell, 0);
+  const int n3[3] = {g.nx, g.ny, g.nz};
   for (int64_t p = 0; p < np; ++p) {
-    const double* X = w->X0_host + 3 * p;
     int b[3];
-    const int n3[3] = {g.nx, g.ny, g.nz};
-    for (int a = 0; a < 3; ++a) {
-      if (!std::isfinite(X[a])) { err = "non-finite wall point"; return false; }
-      b[a] = (int)std::floor(X[a]) - 1;
-      if (b[a] < 0 || b[a] + 3 > n3[a] - 1) { err = "wall stencil touches the box faces"; return false; }
+    for (int q = 0; q < 3; ++q) {
+      const double v = X[3 * p + q];
+      if (!std::isfinite(v)) { err = "non-finite wall point"; return false; }
+      b[q] = (int)std::floor(v) - 1;
+      if (b[q] < 0 || b[q] + 3 > n3[q] - 1) { err = "wall stencil touches the box faces"; return false; }
     }
-    for (int z = std::max(0, b[2] - m); z <= std::min(g.nz - 1, b[2] + 3 + m); ++z)
-      for (int y = std::max(0, b[1] - m); y <= std::min(g.ny - 1, b[1] + 3 + m); ++y)
-        for (int x = std::max(0, b[0] - m); x <= std::min(g.nx - 1, b[0] + 3 + m); ++x)
-          mark[x + (int64_t)g.nx * (y + (int64_t)g.ny * z)] = 1;
+    a[b[0] + (int64_t)g.nx * (b[1] + (int64_t)g.ny * b[2])] = 1;
+  }
+  const int64_t stride[3] = {1, g.nx, (int64_t)g.nx * g.ny};
+  for (int ax = 0; ax < 3; ++ax) {
+    const int n = n3[ax];
+    const int64_t s = stride[ax];
+    // lines along ax: every cell whose ax-coordinate is 0 starts one
+    for (int64_t c0 = 0; c0 < g.ncell; ++c0) {
+      if ((c0 / s) % n != 0) continue;
+      // cell i is covered by a base in [i - 3 - m, i + m]
+      int cnt = 0;
+      for (int i = -3 - m; i < n; ++i) {
+        const int add = i + m, drop = i - 4 - m;   // window [i - 3 - m, i + m]
+        if (add >= 0 && add < n) cnt += a[c0 + add * s];
+        if (drop >= 0 && drop < n) cnt -= a[c0 + drop * s];
+        if (i >= 0) t[c0 + i * s] = cnt > 0;
+      }
+    }
+    a.swap(t);
   }
   band.clear();
   for (int64_t cell = 0; cell < g.ncell; ++cell)
-    if (mark[cell] && (g.flags[cell] & TYPE_MASK) == T_FLUID) band.push_back((int32_t)cell);
+    if (a[cell] && (g.flags[cell] & TYPE_MASK) == T_FLUID) band.push_back((int32_t)cell);
   return true;
 }
 
+bool wall_band(const lbm_ctx* c, int k, const lbm_wall_desc* w, std::vector<int32_t>& band, std::string& err) {
+  const int m = w->band_margin > 0 ? w->band_margin : 2;
+  return band_from_points(c->geo[k], w->X0_host, (int64_t)w->n_theta * w->n_z, m, band, err);
+}
+
+// band list capacity reserved in the wall buffer (the band grows when the
+// wall dilates and the band is rebuilt)
+int64_t band_capacity(int64_t nband) { return 2 * nband + 4096; }
+
 struct FsiLayout {
-  size_t u4, b4, X0, Xa, Xb, slip, Vf, Fp, band, total;
+  size_t u4, b4, X0, Xa, Xb, slip, Vf, Fp, band, Dref, total;
 };
 FsiLayout fsi_plan(int64_t ncell, int64_t np, int64_t nband, int prec) {
   FsiLayout f;
@@ -532,7 +620,8 @@ FsiLayout fsi_plan(int64_t ncell, int64_t np, int64_t nband, int prec) {
   f.slip = o; o = align256(o + np * 32);
   f.Vf = o; o = align256(o + np * r4);
   f.Fp = o; o = align256(o + np * 32);
-  f.band = o; o = align256(o + std::max<int64_t>(nband, 1) * 4);
+  f.band = o; o = align256(o + band_capacity(nband) * 4);
+  f.Dref = o; o = align256(o + np * 32);
   f.total = o;
   return f;
 }
@@ -636,6 +725,7 @@ lbm_status lbm_init(const lbm_config* cfgs, int32_t n, const lbm_buffers* buf, v
   d.wave_cap = c->L.wave_cap;
   d.v0 = c->work + c->L.v0;
   d.err = (uint32_t*)(c->work + c->L.err);
+  d.moved = (uint32_t*)(c->work + c->L.moved);
   d.walls = (const int32_t*)(c->work + c->L.walls);
   d.nwall = 0;
 
@@ -665,6 +755,7 @@ lbm_status lbm_init(const lbm_config* cfgs, int32_t n, const lbm_buffers* buf, v
   if (e == hipSuccess) { e = up(c->L.bc, bc.data(), bc.size() * sizeof(BcDev)); what = "0D state upload"; }
   if (e == hipSuccess) { e = up(c->L.st, st.data(), st.size() * sizeof(InstState)); what = "step state upload"; }
   if (e == hipSuccess) { e = hipMemset(c->work + c->L.err, 0, 4); what = "error flag clear"; }
+  if (e == hipSuccess) { e = hipMemset(c->work + c->L.moved, 0, 4); what = "wall motion clear"; }
   if (e == hipSuccess) { e = hipMemset(c->work + c->L.v0, 0, (size_t)c->L.nv0 * r4_size(c->prec)); what = "snapshot clear"; }
   if (e == hipSuccess) { e = hipMemset(c->work + c->L.wave, 0, (size_t)n * c->L.wave_cap * NREC * 8); what = "waveform clear"; }
   for (int k = 0; k < n && e == hipSuccess; ++k) {
@@ -697,9 +788,29 @@ lbm_status lbm_init(const lbm_config* cfgs, int32_t n, const lbm_buffers* buf, v
   return LBM_OK;
 }
 
+static lbm_status run_steps(lbm_ctx* c, int64_t nsteps);
+
 lbm_status lbm_step(lbm_ctx* c, int64_t nsteps) {
   if (!c) return LBM_E_INVAL;
   if (nsteps < 0) return fail(c, LBM_E_INVAL, "nsteps < 0");
+  if (c->dev.nwall == 0 || c->band_check <= 0) return run_steps(c, nsteps);
+  // with walls: run up to each multiple of band_check, then test the motion
+  int64_t left = nsteps;
+  while (left > 0) {
+    const int64_t to_check = c->band_check - (c->step % c->band_check);
+    const int64_t k = std::min(left, to_check);
+    lbm_status s = run_steps(c, k);
+    if (s != LBM_OK) return s;
+    left -= k;
+    if (c->step % c->band_check == 0) {
+      s = check_bands(c);
+      if (s != LBM_OK) return s;
+    }
+  }
+  return LBM_OK;
+}
+
+static lbm_status run_steps(lbm_ctx* c, int64_t nsteps) {
   int64_t left = nsteps;
   const bool graph = c->use_graph && !c->timing && !c->tuning;
   if (graph && left >= 2) {
@@ -940,6 +1051,7 @@ lbm_status lbm_fsi_exchange(lbm_ctx* c, int32_t k, const lbm_wall_desc* w, void*
   d.Vf = F + f.Vf;
   d.Fp = F + f.Fp;
   d.band = (int32_t*)(F + f.band);
+  d.Dref = (double*)(F + f.Dref);
   d.ds_th = w->ds_theta; d.ds_z = w->ds_z; d.area = w->area;
   d.ks = w->k_stretch; d.ei = w->ei_bend; d.mass = w->mass; d.alpha = w->alpha; d.beta = w->beta;
   std::vector<double> X4((size_t)np * 4, 0.0);
@@ -954,6 +1066,9 @@ lbm_status lbm_fsi_exchange(lbm_ctx* c, int32_t k, const lbm_wall_desc* w, void*
   c->wall[k].np = np;
   c->wall[k].nband = d.nband;
   c->wall[k].band = band;
+  c->wall[k].margin = w->band_margin > 0 ? w->band_margin : 2;
+  c->wall[k].band_cap = band_capacity((int64_t)band.size());
+  c->wall[k].X0.assign(w->X0_host, w->X0_host + 3 * np);
   c->walls.clear();
   int maxb = 0;
   int64_t maxp = 0;
@@ -1121,6 +1236,12 @@ lbm_status lbm_kernel_time(lbm_ctx* c, int32_t kernel, int64_t* launches, double
 lbm_status lbm_set_graph(lbm_ctx* c, int32_t on) {
   if (!c) return LBM_E_INVAL;
   c->use_graph = on != 0;
+  return LBM_OK;
+}
+
+lbm_status lbm_set_band_check(lbm_ctx* c, int32_t every) {
+  if (!c || every < 0) return LBM_E_INVAL;
+  c->band_check = every;
   return LBM_OK;
 }
 

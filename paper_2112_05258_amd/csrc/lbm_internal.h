@@ -70,6 +70,7 @@ struct InstDesc {
   void* Vf;                // R4 per point (last step, for read-back)
   void* Fp;                // double4 per point: penalty force on the fluid (last step)
   int32_t* band;           // local cell ids of the band
+  double* Dref;            // double4 per point: displacement when the band was built
   double ds_th, ds_z, area, ks, ei, mass, alpha, beta;
 };
 
@@ -100,6 +101,7 @@ struct Dev {
   int32_t nwall;
   void* v0;                        // R4 per snapshot entry
   uint32_t* err;
+  uint32_t* moved;                 // max wall motion since the band was built (float bits)
   const int32_t* walls;            // instance ids with a wall
   int32_t max_band, max_np;
 };

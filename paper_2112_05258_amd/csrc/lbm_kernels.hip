@@ -549,6 +549,7 @@ __global__ __launch_bounds__(WBLOCK) void k_wall(Dev d, const int32_t* __restric
   __shared__ uint8_t sfl[BOXCAP];
   __shared__ int smin[3], smax[3];
   __shared__ int semax;
+  __shared__ uint32_t smove;
   const int inst = walls[blockIdx.y];
   const InstDesc& I = d.inst[inst];
   const int nth = I.nth, nzl = I.nzl;
@@ -581,7 +582,15 @@ __global__ __launch_bounds__(WBLOCK) void k_wall(Dev d, const int32_t* __restric
     smin[threadIdx.x] = 0x7fffffff;
     smax[threadIdx.x] = -0x7fffffff;
   }
+  if (threadIdx.x == 0) smove = 0u;
   __syncthreads();
+  // motion since the band was built (max norm; positive floats order as
+  // their bit patterns): the host rebuilds the band when it nears the margin
+  if (valid) {
+    const double3 Dr = ld3(I.Dref, p);
+    const float mv = (float)fmax(fabs(D.x - Dr.x), fmax(fabs(D.y - Dr.y), fabs(D.z - Dr.z)));
+    atomicMax(&smove, __float_as_uint(mv));
+  }
   const int bx0 = valid ? (int)floor(px) - 1 : 0, by0 = valid ? (int)floor(py) - 1 : 0,
             bz0 = valid ? (int)floor(pz) - 1 : 0;
   R wx[4], wy[4], wz[4];
@@ -596,6 +605,7 @@ __global__ __launch_bounds__(WBLOCK) void k_wall(Dev d, const int32_t* __restric
     atomicMax(&smax[0], bx0); atomicMax(&smax[1], by0); atomicMax(&smax[2], bz0);
   }
   __syncthreads();
+  if (threadIdx.x == 0 && smove != 0u) atomicMax(d.moved, smove);
   // every valid point has its stencil base in [-2, n], so the extents are
   // small and positive; a tile without a valid point has smin > smax
   const int ox = smin[0], oy = smin[1], oz = smin[2];

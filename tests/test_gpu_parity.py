@@ -142,6 +142,27 @@ def test_small_elastic_tube(oracle_mod, amd, precision, tol):
     assert e_x <= tol * 10 and e_f <= tol * 10
 
 
+def test_band_follows_a_moving_wall(oracle_mod, amd):
+    """The wall moves 2.9 lu outwards: with the band fixed where it was
+    built the stencils leave it (LBM_E_BAND); with the periodic motion test
+    the band is rebuilt around the wall and the run matches the oracle
+    (which interpolates over every fluid cell) to the FP64 bar."""
+    c = L.inflating_tube()
+    s = amd.solver_from_config(c, precision=amd.FP64)
+    s.set_band_check(0)
+    s.step(c["steps"])
+    with pytest.raises(amd.LbmError) as e:
+        s.sync()
+    assert e.value.code == -6
+    s.close()
+    o, s = _run_pair(oracle_mod, amd, c, c["steps"], amd.FP64)
+    _compare(o, s, c["flags"], 1e-12, wave_cols=(1, 2, 3, 4))
+    Do, _ = o.displacement()
+    e_x = rel_l2(s.read_wall()["X"] - c["mesh"]["X0"], Do)
+    print({"wall_X": f"{e_x:.2e}", "max_D": f"{np.abs(Do).max():.2f}"}, flush=True)
+    assert np.abs(Do).max() > 2.5 and e_x <= 1e-11
+
+
 def test_graph_replay_matches_eager(amd):
     c = L.cfg0()
     out = []
