@@ -138,7 +138,8 @@ lbm_status lbm_init(const lbm_config* cfgs, int32_t n, const lbm_buffers* buf, v
  * collide-stream.  Asynchronous, except that with a wall registered it
  * synchronises at every multiple of the band-check interval to test the
  * wall's motion (and rebuilds the band when needed, see lbm_wall_desc).
- * Errors: LBM_E_INVAL (nsteps < 0); LBM_E_BAND from a band rebuild. */
+ * Errors: LBM_E_INVAL (nsteps < 0); LBM_E_BAND or LBM_E_UNSTABLE from a
+ * band rebuild. */
 lbm_status lbm_step(lbm_ctx* ctx, int64_t nsteps);
 
 /* Steps between wall-motion tests (default 32; 0 never tests, so the band
@@ -173,7 +174,8 @@ lbm_status lbm_get_0d(lbm_ctx* ctx, int32_t inst, int32_t boundary, double* out)
  * the current positions once that reaches band_margin - 1 lattice units.
  * A point whose stencil still leaves the band raises LBM_E_BAND at the next
  * lbm_sync; so does a rebuilt band that outgrows the buffer's reserve
- * (twice the initial band plus 4096 cells) or reaches the box faces. */
+ * (twice the initial band plus 4096 cells).  Stencil cells outside the box
+ * take no part; a non-finite point stops the rebuild with LBM_E_UNSTABLE. */
 typedef struct {
   int32_t n_theta, n_z;
   const double* X0_host;
@@ -277,10 +279,11 @@ lbm_status lbm_get_launch(lbm_ctx* ctx, int32_t cls, lbm_launch* out);
  * and drops the captured step graph. */
 lbm_status lbm_set_launch(lbm_ctx* ctx, int32_t cls, const lbm_launch* launch);
 
-/* Autotuner: times every collide shape (6) and then every wall tile (3, if
- * walls are registered) over trial_steps steps each (rounded up to even,
- * after 2 untimed steps), per class with HIP events, and keeps each class's
- * fastest.  The trial steps are ordinary steps of the method: the state
+/* Autotuner: times the current shapes and every collide shape (6), then
+ * the current and every wall tile (3, if walls are registered), over
+ * trial_steps steps each (rounded up to even, after 2 untimed steps), per
+ * class with HIP events; a class changes shape only for a candidate at
+ * least 2 % faster than its current one.  The trial steps are ordinary steps of the method: the state
  * advances by *advanced steps (may be NULL).  Call after the 0D couplings
  * and walls are set. */
 lbm_status lbm_autotune(lbm_ctx* ctx, int32_t trial_steps, int64_t* advanced);

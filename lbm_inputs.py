@@ -215,21 +215,24 @@ def _elastic_tube(nx, ny, nz, r, h, k, ei, sc, tau, Emax=2.0, Emin=0.06, HR=75.0
     )
 
 
-def cfg1(h=0.5):
+def cfg1(h=0.5, tau=0.6, sigma_P=5e-7):
     """Elastic tube r = 48 in 128x128x512 (8.4 M cells), FP32, spring k 0.05,
     bending 1e-3, Peskin 4-point kernel, LV-elastance inlet (Emax 2.0, Emin
     0.06 mmHg/ml, HR 75) and Windkessel outlet (Z 0.05, C 1.5, R 1.0), one
-    cardiac cycle = 20 000 steps."""
-    sc = scales(25000.0, 8000.0, 2.5e-6)
-    c = _elastic_tube(128, 128, 512, 48.0, h, 0.05, 1e-3, sc, tau=0.52)
+    cardiac cycle = 20 000 steps.  tau and the pressure scale are free: at
+    tau = 0.52 the explicit penalty coupling grows a wall mode from rounding
+    and blows up within 2 000 steps; tau = 0.6 with sigma_P = 5e-7 lu/mmHg
+    runs the whole beat (peak wall motion ~4 lu)."""
+    sc = scales(25000.0, 8000.0, sigma_P)
+    c = _elastic_tube(128, 128, 512, 48.0, h, 0.05, 1e-3, sc, tau=tau)
     c.update(name="cfg1_fsi_tube_128x128x512", steps=20000)
     return c
 
 
 def cfg2():
-    """cfg1 geometry at 64x64x256 (r = 24) for the 16-bit storage study."""
-    sc = scales(25000.0, 1000.0, 2.5e-6)
-    c = _elastic_tube(64, 64, 256, 24.0, 0.5, 0.05, 1e-3, sc, tau=0.52)
+    """cfg1 geometry at 64x64x256 (r = 24)."""
+    sc = scales(25000.0, 8000.0 * (24.0 / 48.0) ** 2, 5e-7)
+    c = _elastic_tube(64, 64, 256, 24.0, 0.5, 0.05, 1e-3, sc, tau=0.6)
     c.update(name="cfg2_fsi_tube_64x64x256", steps=60000)
     return c
 
@@ -297,13 +300,13 @@ def ensemble(n=256, seed=3):
     return out
 
 
-def ensemble_config(p, h=0.5, tau=0.52):
+def ensemble_config(p, h=0.5, tau=0.6, sigma_P=5e-7):
     """Workload dict of one ensemble member: an elastic tube of radius r in a
     (2r + 8)^2 x (L + 2) box with the member's LV, Windkessel and wall.
     Volume scale sigma_V ~ r^2 keeps peak velocities near the large tube's."""
     r, L = p["r"], p["L"]
     n = 2 * r + 8
-    sc = scales(25000.0, 8000.0 * (r / 48.0) ** 2, 2.5e-6)
+    sc = scales(25000.0, 8000.0 * (r / 48.0) ** 2, sigma_P)
     c = _elastic_tube(n, n, L + 2, float(r), h, p["k"], 1e-3, sc, tau=tau, Emax=p["Emax"], Emin=p["Emin"],
                       HR=p["HR"], Z=p["Z"], C=p["C"], R=p["R"])
     c.update(name=f"ensemble_r{r}_L{L}")

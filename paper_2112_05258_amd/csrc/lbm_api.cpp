@@ -450,8 +450,8 @@ lbm_status build_groups(lbm_ctx* c, bool per_class) {
   return LBM_OK;
 }
 
-bool band_from_points(const Geometry& g, const double* X, int64_t np, int m, std::vector<int32_t>& band,
-                      std::string& err);
+int band_from_points(const Geometry& g, const double* X, int64_t np, int m, bool strict, std::vector<int32_t>& band,
+                     std::string& err);
 
 // Rebuild the band of every wall around its current positions X0 + D^n
 // (D^n is in Xab[step & 1]) and restart the motion measure from there.
@@ -471,7 +471,8 @@ lbm_status rebuild_bands(lbm_ctx* c) {
       for (int q = 0; q < 3; ++q) X[3 * p + q] = W.X0[3 * p + q] + D4[4 * p + q];
     std::vector<int32_t> band;
     std::string why;
-    if (!band_from_points(g, X.data(), np, W.margin, band, why)) return fail(c, LBM_E_BAND, "band rebuild: " + why);
+    if (band_from_points(g, X.data(), np, W.margin, false, band, why) != 1)
+      return fail(c, LBM_E_UNSTABLE, "band rebuild: " + why);
     if ((int64_t)band.size() > W.band_cap) return fail(c, LBM_E_BAND, "band rebuild: the band outgrew its capacity");
     for (auto& t : g.flags) t &= (uint8_t)~F_BAND;
     for (int32_t cell : band) g.flags[cell] |= F_BAND;
@@ -558,17 +559,24 @@ lbm_status read_pops(lbm_ctx* c, int k, std::vector<double>& out) {
 // points X, xyz per point): the stencil base cells b = floor(X) - 1 are
 // marked, then the marks are dilated by [b - m, b + 3 + m] along x, y and z
 // in turn (one running window per line).
-bool band_from_points(const Geometry& g, const double* X, int64_t np, int m, std::vector<int32_t>& band,
-                      std::string& err) {
+// strict: every stencil must lie inside the box (registration); otherwise a
+// base outside the box is clamped to it (a rebuilt band; stencil cells
+// outside the box take no part in the exchange).  Returns 1 on success, 0
+// for a stencil outside the box (strict) and -1 for a non-finite point.
+int band_from_points(const Geometry& g, const double* X, int64_t np, int m, bool strict, std::vector<int32_t>& band,
+                     std::string& err) {
   std::vector<uint8_t> a(g.ncell, 0), t(g.ncell, 0);
   const int n3[3] = {g.nx, g.ny, g.nz};
   for (int64_t p = 0; p < np; ++p) {
     int b[3];
     for (int q = 0; q < 3; ++q) {
       const double v = X[3 * p + q];
-      if (!std::isfinite(v)) { err = "non-finite wall point"; return false; }
+      if (!std::isfinite(v) || std::fabs(v) > 1e9) { err = "non-finite wall point"; return -1; }
       b[q] = (int)std::floor(v) - 1;
-      if (b[q] < 0 || b[q] + 3 > n3[q] - 1) { err = "wall stencil touches the box faces"; return false; }
+      if (b[q] < 0 || b[q] + 3 > n3[q] - 1) {
+        if (strict) { err = "wall stencil touches the box faces"; return 0; }
+        b[q] = std::min(std::max(b[q], 0), n3[q] - 1);
+      }
     }
     a[b[0] + (int64_t)g.nx * (b[1] + (int64_t)g.ny * b[2])] = 1;
   }
@@ -593,12 +601,12 @@ bool band_from_points(const Geometry& g, const double* X, int64_t np, int m, std
   band.clear();
   for (int64_t cell = 0; cell < g.ncell; ++cell)
     if (a[cell] && (g.flags[cell] & TYPE_MASK) == T_FLUID) band.push_back((int32_t)cell);
-  return true;
+  return 1;
 }
 
 bool wall_band(const lbm_ctx* c, int k, const lbm_wall_desc* w, std::vector<int32_t>& band, std::string& err) {
   const int m = w->band_margin > 0 ? w->band_margin : 2;
-  return band_from_points(c->geo[k], w->X0_host, (int64_t)w->n_theta * w->n_z, m, band, err);
+  return band_from_points(c->geo[k], w->X0_host, (int64_t)w->n_theta * w->n_z, m, true, band, err) == 1;
 }
 
 // band list capacity reserved in the wall buffer (the band grows when the
@@ -905,11 +913,12 @@ lbm_status lbm_autotune(lbm_ctx* c, int32_t trial_steps, int64_t* advanced) {
   // time every candidate over trial_steps ordinary steps (after two
   // untimed ones), per class and kernel; phase 0 tunes the collide shape,
   // phase 1 the wall tile with the chosen collide shape
-  auto trial = [&](const lbm_launch& cand, int kind, std::vector<double>& ms) -> lbm_status {
+  // cand == nullptr: every class on its own current shape
+  auto trial = [&](const lbm_launch* cand, int kind, std::vector<double>& ms) -> lbm_status {
     for (int q = 0; q < nc; ++q) {
       lbm_launch l = best[q];
-      if (kind == 0) { l.block = cand.block; l.cells_per_lane = cand.cells_per_lane; }
-      else l.wall_tile_theta = cand.wall_tile_theta;
+      if (cand && kind == 0) { l.block = cand->block; l.cells_per_lane = cand->cells_per_lane; }
+      if (cand && kind == 1) l.wall_tile_theta = cand->wall_tile_theta;
       apply_launch(c, q, l);
     }
     lbm_status s = build_groups(c, true);   // one launch per class, timed apart
@@ -938,31 +947,38 @@ lbm_status lbm_autotune(lbm_ctx* c, int32_t trial_steps, int64_t* advanced) {
     c->tune_rec.clear();
     return LBM_OK;
   };
-  const int shapes[6][2] = {{128, 1}, {128, 2}, {256, 1}, {256, 2}, {512, 1}, {512, 2}};
-  std::vector<double> bms(nc, 1e300), ms;
+  // A class keeps its current shape unless a candidate is at least 2 %
+  // faster (run-to-run timing noise is about 1 %): the current shapes are
+  // timed first in each phase.
+  const double gain = 0.98;
+  std::vector<double> bms, ms;
   std::vector<lbm_launch> pick = best;
+  lbm_status st = trial(nullptr, 0, bms);
+  if (st != LBM_OK) return st;
+  const int shapes[6][2] = {{128, 1}, {128, 2}, {256, 1}, {256, 2}, {512, 1}, {512, 2}};
   for (auto& sh : shapes) {
     lbm_launch cand = best[0];
     cand.block = sh[0];
     cand.cells_per_lane = sh[1];
-    lbm_status s = trial(cand, 0, ms);
-    if (s != LBM_OK) return s;
+    st = trial(&cand, 0, ms);
+    if (st != LBM_OK) return st;
     for (int q = 0; q < nc; ++q)
-      if (ms[q] < bms[q]) { bms[q] = ms[q]; pick[q].block = sh[0]; pick[q].cells_per_lane = sh[1]; }
+      if (ms[q] < bms[q] * gain) { bms[q] = ms[q]; pick[q].block = sh[0]; pick[q].cells_per_lane = sh[1]; }
   }
   for (int q = 0; q < nc; ++q) { best[q].block = pick[q].block; best[q].cells_per_lane = pick[q].cells_per_lane; }
   if (c->dev.nwall > 0) {
     std::vector<bool> has_wall(nc, false);
     for (int q = 0; q < nc; ++q)
       for (int32_t i : c->cls[q].inst) has_wall[q] = has_wall[q] || c->wall[i].on;
-    std::fill(bms.begin(), bms.end(), 1e300);
+    st = trial(nullptr, 1, bms);
+    if (st != LBM_OK) return st;
     for (int tj : {8, 16, 32}) {
       lbm_launch cand = best[0];
       cand.wall_tile_theta = tj;
-      lbm_status s = trial(cand, 1, ms);
-      if (s != LBM_OK) return s;
+      st = trial(&cand, 1, ms);
+      if (st != LBM_OK) return st;
       for (int q = 0; q < nc; ++q)
-        if (has_wall[q] && ms[q] < bms[q]) { bms[q] = ms[q]; pick[q].wall_tile_theta = tj; }
+        if (has_wall[q] && ms[q] < bms[q] * gain) { bms[q] = ms[q]; pick[q].wall_tile_theta = tj; }
     }
     for (int q = 0; q < nc; ++q) best[q].wall_tile_theta = pick[q].wall_tile_theta;
   }

@@ -79,7 +79,7 @@ def test_autotune_steps_are_ordinary_and_cache_round_trips(amd, tmp_path):
     cache = str(tmp_path / "launch.json")
     s = amd.solver_from_configs(cfgs, precision=amd.FP64)
     adv = s.autotune(trial_steps=4, cache=cache)
-    assert adv == 6 * (4 + 2)                  # no walls: collide shapes only
+    assert adv == 7 * (4 + 2)                  # no walls: current + 6 collide shapes
     assert s.t == adv
     ref = amd.solver_from_configs(cfgs, precision=amd.FP64)
     ref.step(adv)
@@ -101,7 +101,7 @@ def test_autotune_with_walls_and_bad_shapes(amd):
         p["L"] = min(p["L"], 40)
     s = amd.solver_from_configs([L.ensemble_config(p) for p in ps], precision=amd.FP32)
     adv = s.autotune(trial_steps=2)
-    assert adv == (6 + 3) * (2 + 2)
+    assert adv == (7 + 4) * (2 + 2)           # current + 6 shapes, current + 3 tiles
     for c in s.classes():
         assert c["block"] in (128, 256, 512) and c["cells_per_lane"] in (1, 2)
         assert c["wall_tile_theta"] in (8, 16, 32)

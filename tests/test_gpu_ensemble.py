@@ -84,9 +84,9 @@ def test_ensemble_member_matches_oracle(oracle_mod, amd):
         p["L"] = min(p["L"], 36)
     cfgs = [L.ensemble_config(p) for p in ps]
     # members start in equilibrium with the valve shut; drive them with an
-    # inlet pressure 10 mmHg above P0 so that there is flow to compare
+    # inlet pressure 50 mmHg above P0 so that there is flow to compare
     for c in cfgs:
-        c["inlet"] = (L.BC_PRESSURE_CONST, [c["p_init"] + 10 * 2.5e-6])
+        c["inlet"] = (L.BC_PRESSURE_CONST, [c["p_init"] + 50 * c["scales"]["sigma_P"]])
     b = amd.solver_from_configs(cfgs, precision=amd.FP64)
     b.step(60)
     b.sync()
