@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--no-surrogate", action="store_true", help="skip the learned-surrogate leg")
     ap.add_argument("--pattern-probe", action="store_true",
                     help="only the HBM ceiling of the collide access pattern (19 SoA loads and stores per cell)")
+    ap.add_argument("--full-beat", action="store_true",
+                    help="only cfg1 over one whole cardiac cycle in FP32 and FP16 storage")
     ap.add_argument("--surrogate-only", action="store_true",
                     help="only the learned-surrogate leg (for profiling its kernels)")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble run")
@@ -214,6 +216,44 @@ def run_surrogate(n_check=64, reps=20, batch=65536):
                          "avg_launch_us": round(gms / max(n, 1) * 1e3, 2)}}
 
 
+def full_beat():
+    """cfg1 for one whole cardiac cycle (20 000 steps) in FP32 and FP16
+    storage: stability, the pressure waveform, valve events, the wall's
+    motion (the band is rebuilt as it moves) and the FP16 run against FP32."""
+    import numpy as np
+    import torch
+    import lbm_inputs as L
+    import paper_2112_05258_amd as amd
+    c = L.cfg1()
+    sP = c["scales"]["sigma_P"]
+    out, waves = {"workload": c["name"], "steps": c["steps"]}, {}
+    for name, prec in (("fp32", amd.FP32), ("fp16s", amd.FP16S)):
+        s = amd.solver_from_config(c, precision=prec, wave_cap=c["steps"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        dmax = 0.0
+        while s.t < c["steps"]:
+            s.step(2000)
+            s.sync()
+            dmax = max(dmax, float(np.abs(s.read_wall()["X"] - c["mesh"]["X0"]).max()))
+            print(f"# {name} step {s.t}", file=sys.stderr, flush=True)
+        el = time.perf_counter() - t0
+        w = s.waveforms()
+        s.close()
+        waves[name] = w
+        out[name] = {"s": round(el, 2), "inlet_P_mmHg": [round(float(w[:, 2].min() / sP), 1),
+                                                         round(float(w[:, 2].max() / sP), 1)],
+                     "valve_openings": int((np.diff(w[:, 11]) == 1).sum()),
+                     "valve_closures": int((np.diff(w[:, 11]) == -1).sum()),
+                     "max_wall_motion_lu": round(dmax, 2), "finite": bool(np.isfinite(w[:, 1:5]).all())}
+    a, r = waves["fp16s"], waves["fp32"]
+    out["fp16s_vs_fp32"] = {
+        "peak_pressure_rel_err": float(f"{abs(a[:, 2].max() - r[:, 2].max()) / r[:, 2].max():.3e}"),
+        "pressure_pulse_rel_l2": float(f"{np.linalg.norm(a[:, 2] - r[:, 2]) / np.linalg.norm(r[:, 2] - c['p_init']):.3e}"),
+        "inlet_flux_rel_l2": float(f"{np.linalg.norm(a[:, 1] - r[:, 1]) / np.linalg.norm(r[:, 1]):.3e}")}
+    return out
+
+
 def _band_cells(cfg):
     """Band cells of the wall (same rule as the library: stencil + 2-cell margin, fluid only)."""
     import numpy as np
@@ -343,6 +383,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.surrogate_only:
         print(json.dumps({"surrogate": run_surrogate()}), flush=True)
+        return
+    if args.full_beat:
+        print(json.dumps({"full_beat": full_beat()}), flush=True)
         return
     cfg, desc = workload(args.workload)
     t_setup = time.perf_counter()
