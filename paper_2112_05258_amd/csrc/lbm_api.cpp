@@ -705,6 +705,7 @@ lbm_status lbm_init(const lbm_config* cfgs, int32_t n, const lbm_buffers* buf, v
   }
   for (int k = 0; k < n; ++k) {
     c->inst[k].tau = cfgs[k].tau;
+    c->inst[k].omega = 1.0 / cfgs[k].tau;
     c->inst[k].dref = 3.0 * cfgs[k].p_ref;
   }
   if (buf->pop_bytes < (size_t)NQ * c->L.NT * elem_size(c->prec) || buf->work_bytes < c->L.total) {

@@ -58,6 +58,7 @@ struct InstDesc {
   int64_t cell0, ncell;
   int64_t v0_off;          // first entry of this instance's inlet snapshot (nx*ny)
   double tau;
+  double omega;            // 1 / tau
   double dref;             // 3 p_ref: stored populations are g - w_i dref
   // wall (has_wall = 0: none)
   int32_t has_wall, nth, nzl, nband;

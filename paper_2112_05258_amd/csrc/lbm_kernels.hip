@@ -327,36 +327,94 @@ __device__ __forceinline__ R deq_velocity(int i, R vx, R vy, R vz, R sx, R sy, R
   return wgt<R>(i) * (R(3) * (es - eu) + R(4.5) * (es * es - eu * eu) - R(1.5) * (ss - uu));
 }
 
-// one lattice cell (local index of instance inst) of the collide-stream step
-// mode: COLLIDE_ALL, COLLIDE_BULK (cells outside the wall band) or
-// COLLIDE_BAND (band cells only).  The slots a cell writes in a step are
-// exactly the slots it reads, so the two partial passes touch disjoint
-// memory and the bulk pass may run while the wall exchange still reads the
-// band cells' populations.
-template <class S, bool ODD>
-__device__ __forceinline__ void collide_cell(const Dev& d, const int inst, const int64_t local, const int mode) {
+// s += e x for a lattice component e in {-1, 0, 1}, known at compile time
+// once the direction loops are unrolled.  The first nonzero term initialises
+// s, so neither a product with 0 nor a 0 + x is left in the code (IEEE rules
+// keep the compiler from dropping them itself).
+template <class R>
+__device__ __forceinline__ void eacc(R& s, bool& first, int e, R x) {
+  if (e == 0) return;
+  const R t = e > 0 ? x : -x;
+  s = first ? t : s + t;
+  first = false;
+}
+
+// e_i . (x, y, z) over the nonzero components of e_i (0 for the rest vector)
+template <class R>
+__device__ __forceinline__ R edot(int i, R x, R y, R z) {
+  R s = R(0);
+  bool first = true;
+  eacc(s, first, EX[i], x);
+  eacc(s, first, EY[i], y);
+  eacc(s, first, EZ[i], z);
+  return s;
+}
+
+// Moments of one cell (Eqs. rho, v): dl = sum g - dref (= delta - 3 p_ref),
+// j = sum e g, the velocity v = j + b / 2 of the forced scheme, and the
+// parts of the equilibrium shared by all directions.
+template <class R> struct Mom {
+  R dl, jx, jy, jz, vx, vy, vz, bx, by, bz, t0, vb;
+};
+template <class R, bool BAND>
+__device__ __forceinline__ Mom<R> moments(const R g[NQ], R bx, R by, R bz) {
+  Mom<R> m;
+  m.dl = g[0];
+  m.jx = m.jy = m.jz = R(0);
+  bool fx = true, fy = true, fz = true;
+#pragma unroll
+  for (int i = 1; i < NQ; ++i) {
+    m.dl += g[i];
+    eacc(m.jx, fx, EX[i], g[i]);
+    eacc(m.jy, fy, EY[i], g[i]);
+    eacc(m.jz, fz, EZ[i], g[i]);
+  }
+  m.bx = bx; m.by = by; m.bz = bz;
+  m.vx = BAND ? m.jx + R(0.5) * bx : m.jx;
+  m.vy = BAND ? m.jy + R(0.5) * by : m.jy;
+  m.vz = BAND ? m.jz + R(0.5) * bz : m.jz;
+  m.t0 = m.dl - R(1.5) * (m.vx * m.vx + m.vy * m.vy + m.vz * m.vz);
+  m.vb = m.vx * bx + m.vy * by + m.vz * bz;
+  return m;
+}
+
+// Post-collision value of direction i (Eqs. fi, feq, f):
+// g* = (1 - 1/tau) g + (1/tau) g_eq, g_eq = w (dl + 3 eu + 4.5 eu^2 - 1.5 uu),
+// plus the forcing term w (1 - 1/(2 tau)) (3 (e - v).b + 9 (e.v)(e.b)) on
+// band cells (zero where b = 0).
+template <class R, bool BAND>
+__device__ __forceinline__ R relax(int i, const Mom<R>& m, R g, R om) {
+  const R eu = edot<R>(i, m.vx, m.vy, m.vz);
+  const R r = i == 0 ? m.t0 : eu * (R(3) + R(4.5) * eu) + m.t0;
+  R v = (R(1) - om) * g + (om * wgt<R>(i)) * r;
+  if (BAND) {
+    const R eb = edot<R>(i, m.bx, m.by, m.bz);
+    v += ((R(1) - R(0.5) * om) * wgt<R>(i)) * (R(3) * (eb - m.vb) + R(9) * eu * eb);
+  }
+  return v;
+}
+
+// One lattice cell (global index c, local index local of instance inst) of
+// the collide-stream step.  NEAR: the wave holds a cell next to a solid or a
+// 0D-coupled ghost (per-direction source and target types are looked up);
+// BAND: the wave holds a cell of the wall's band (the IB force enters, zero
+// at the wave's other cells).  The plain body has neither.
+template <class S, bool ODD, bool NEAR, bool BAND>
+__device__ __forceinline__ void collide_body(const Dev& d, const int inst, const InstDesc& I, const int64_t local,
+                                             const uint32_t c, const uint8_t fl) {
   using R = typename Store<S>::R;
   using R4 = typename V4<R>::T;
-  const InstDesc& I = d.inst[inst];
-  if (local >= I.ncell) return;
-  // global cell index fits 32 bits (NT < 2^31); per-direction arrays are
-  // addressed as uniform base + 32-bit lane offset
-  const uint32_t c = (uint32_t)(I.cell0 + local);
-  const uint8_t fl = d.flags[c];
-  if ((fl & TYPE_MASK) != T_FLUID) return;
-  if (mode != COLLIDE_ALL && ((fl & F_BAND) != 0) != (mode == COLLIDE_BAND)) return;
   const int32_t sy = I.nx, sz = I.nx * I.ny;
   int32_t off[NQ];
 #pragma unroll
   for (int i = 0; i < NQ; ++i) off[i] = EX[i] + EY[i] * sy + EZ[i] * sz;
   S* __restrict__ A = (S*)d.pop;
   const int64_t NT = d.NT;
-  const bool near = fl & F_NEAR;
 
   // source cell types (only cells next to walls or ghosts look)
   // (3 bits per direction in one 64-bit word: two registers, not 19)
   uint64_t ntb = 0;
-  if (near) {
+  if (NEAR && (fl & F_NEAR)) {
 #pragma unroll
     for (int i = 1; i < NQ; ++i) ntb |= (uint64_t)(d.flags[c - off[i]] & TYPE_MASK) << (3 * i);
   }
@@ -370,69 +428,51 @@ __device__ __forceinline__ void collide_cell(const Dev& d, const int inst, const
   for (int i = 0; i < NQ; ++i) {
     if (!ODD) {
       g[i] = BufIO<S>::ld(rs(i), c * ES, d.inv_scale);
-    } else if (nt(i) == T_SOLID) {
+    } else if (NEAR && nt(i) == T_SOLID) {
       g[i] = BufIO<S>::ld(rs(i), c * ES, d.inv_scale);
     } else {
       g[i] = BufIO<S>::ld(rs(OPP[i]), (uint32_t)(c - off[i]) * ES, d.inv_scale);
     }
   }
-
-  // moments (Eqs. rho, v): dl = sum g - dref (= delta - 3 p_ref), j = sum e g
-  R dl = 0, jx = 0, jy = 0, jz = 0;
-#pragma unroll
-  for (int i = 0; i < NQ; ++i) {
-    dl += g[i];
-    jx += EX[i] * g[i];
-    jy += EY[i] * g[i];
-    jz += EZ[i] * g[i];
-  }
   R bx = 0, by = 0, bz = 0;
-  const bool band = fl & F_BAND;
-  if (band) {
+  if (BAND && (fl & F_BAND)) {
     const R4 b = ((const R4*)I.b4)[local];
     bx = b.x; by = b.y; bz = b.z;
   }
-  const R vx = jx + R(0.5) * bx, vy = jy + R(0.5) * by, vz = jz + R(0.5) * bz;
-  const R uu = vx * vx + vy * vy + vz * vz;
-  const R om = R(1) / R(I.tau);
-  const R cf = R(1) - R(0.5) * om;
-  const R vb = vx * bx + vy * by + vz * bz;
+  const Mom<R> m = moments<R, BAND>(g, bx, by, bz);
+  const R om = R(I.omega);
 
-  // collision (Eqs. fi, feq, f) and streaming, direction by direction.
-  // At a cell next to a 0D-coupled ghost x = c - e_i, the ghost hands c the
-  // value g*_i(c) + g_eq(P*, v*) - g_eq(P(c), v(c)) (Eq. Non-equilibrium3,
+  // collision and streaming, direction by direction.  At a cell next to a
+  // 0D-coupled ghost x = c - e_i, the ghost hands c the value
+  // g*_i(c) + g_eq(P*, v*) - g_eq(P(c), v(c)) (Eq. Non-equilibrium3,
   // x_f = c); it is formed right after g*_i, so that the post-collision
   // values need not stay live (the two stores go to different slots).
   R4 v0 = {0, 0, 0, 0};
   bool have_v0 = false;
 #pragma unroll
   for (int i = 0; i < NQ; ++i) {
-    const R eu = EX[i] * vx + EY[i] * vy + EZ[i] * vz;
-    const R geq = wgt<R>(i) * (dl + R(3) * eu + R(4.5) * eu * eu - R(1.5) * uu);
-    R v = g[i] - om * (g[i] - geq);
-    if (band) {
-      const R eb = EX[i] * bx + EY[i] * by + EZ[i] * bz;
-      v += cf * wgt<R>(i) * (R(3) * (eb - vb) + R(9) * eu * eb);
-    }
+    const R v = relax<R, BAND>(i, m, g[i], om);
     if (!ODD) {
       BufIO<S>::st(rs(OPP[i]), c * ES, v, d.scale);
+    } else if (!NEAR) {
+      BufIO<S>::st(rs(i), (uint32_t)(c + off[i]) * ES, v, d.scale);
     } else {
       const uint32_t td = nt(OPP[i]);  // type of c + e_i
       if (td == T_FLUID) BufIO<S>::st(rs(i), (uint32_t)(c + off[i]) * ES, v, d.scale);
       else if (td == T_SOLID) BufIO<S>::st(rs(OPP[i]), c * ES, v, d.scale);
     }
-    if (i > 0 && nt(i) >= T_INLET) {
+    if (NEAR && i > 0 && nt(i) >= T_INLET) {
       const BcDev& B = d.bc[3 * inst + (nt(i) - T_INLET)];
       R out;
       if (B.vmode == 0) {
-        out = v + wgt<R>(i) * (R(B.dstar - I.dref) - dl);
+        out = v + wgt<R>(i) * (R(B.dstar - I.dref) - m.dl);
       } else {
         R sx, s_y, s_z;
         if (B.vkind == VK_SNAPSHOT) {
           if (!have_v0) {
             R4* vp = (R4*)d.v0 + I.v0_off + (local % sz);
             if (B.snap) {
-              v0 = R4{jx, jy, jz, R(0)};
+              v0 = R4{m.jx, m.jy, m.jz, R(0)};
               *vp = v0;
             } else {
               v0 = *vp;
@@ -442,16 +482,41 @@ __device__ __forceinline__ void collide_cell(const Dev& d, const int inst, const
           const R Sf = R(B.S);
           sx = v0.x * Sf; s_y = v0.y * Sf; s_z = v0.z * Sf;
         } else if (B.vkind == VK_CORRECT) {
-          sx = vx; s_y = vy; s_z = vz + R(B.vz);
+          sx = m.vx; s_y = m.vy; s_z = m.vz + R(B.vz);
         } else {
           sx = 0; s_y = 0; s_z = R(B.vz);
         }
-        out = v + deq_velocity<R>(i, vx, vy, vz, sx, s_y, s_z);
+        out = v + deq_velocity<R>(i, m.vx, m.vy, m.vz, sx, s_y, s_z);
       }
       if (!ODD) BufIO<S>::st(rs(OPP[i]), (uint32_t)(c - off[i]) * ES, out, d.scale);
       else BufIO<S>::st(rs(i), c * ES, out, d.scale);
     }
   }
+}
+
+// one lattice cell (local index of instance inst) of the collide-stream step
+// mode: COLLIDE_ALL, COLLIDE_BULK (cells outside the wall band) or
+// COLLIDE_BAND (band cells only).  The slots a cell writes in a step are
+// exactly the slots it reads, so the two partial passes touch disjoint
+// memory and the bulk pass may run while the wall exchange still reads the
+// band cells' populations.  The body is chosen per wave (a vote over its
+// active lanes), so the choice never splits a wave.
+template <class S, bool ODD>
+__device__ __forceinline__ void collide_cell(const Dev& d, const int inst, const int64_t local, const int mode) {
+  const InstDesc& I = d.inst[inst];
+  if (local >= I.ncell) return;
+  // global cell index fits 32 bits (NT < 2^31); per-direction arrays are
+  // addressed as uniform base + 32-bit lane offset
+  const uint32_t c = (uint32_t)(I.cell0 + local);
+  const uint8_t fl = d.flags[c];
+  if ((fl & TYPE_MASK) != T_FLUID) return;
+  if (mode != COLLIDE_ALL && ((fl & F_BAND) != 0) != (mode == COLLIDE_BAND)) return;
+  if (__any(fl & F_NEAR))
+    collide_body<S, ODD, true, true>(d, inst, I, local, c, fl);
+  else if (__any(fl & F_BAND))
+    collide_body<S, ODD, false, true>(d, inst, I, local, c, fl);
+  else
+    collide_body<S, ODD, false, false>(d, inst, I, local, c, fl);
 }
 
 // One workgroup of BS lanes per tile of BS * CPT consecutive cells of one
@@ -468,6 +533,9 @@ __global__ __launch_bounds__(BS) void k_collide(Dev d, const CTile* __restrict__
 // ---------------------------------------------------------------------------
 // k_band: unforced velocity of band cells, force cleared
 // ---------------------------------------------------------------------------
+// The 18 moving directions only (e_0 = 0); all loads are independent of each
+// other, so a wave keeps all of them in flight (band cells form short runs
+// along x, and the kernel is bound by the partly used cache lines).
 template <class S, bool ODD>
 __global__ __launch_bounds__(WBLOCK) void k_band(Dev d) {
   using R = typename Store<S>::R;
@@ -478,13 +546,32 @@ __global__ __launch_bounds__(WBLOCK) void k_band(Dev d) {
   if (k >= I.nband) return;
   const int64_t lc = I.band[k];
   const int64_t c = I.cell0 + lc;
-  int64_t off[NQ];
-  dir_offsets(I.nx, (int64_t)I.nx * I.ny, off);
+  const int64_t NT = d.NT;
+  const S* __restrict__ A = (const S*)d.pop;
+  const float inv = d.inv_scale;
   R g[NQ];
-  load_cell<S, ODD>((const S*)d.pop, d.NT, d.flags, c, d.flags[c] & F_NEAR, off, d.inv_scale, g);
+  if (!ODD) {
+#pragma unroll
+    for (int i = 1; i < NQ; ++i) g[i] = Store<S>::ld(A + i * NT + c, inv);
+  } else {
+    // odd step: g_i = A[opp i][c - e_i], or the cell's own A[i][c] where
+    // c - e_i is SOLID (only cells flagged next to a wall look)
+    int64_t off[NQ];
+    dir_offsets(I.nx, (int64_t)I.nx * I.ny, off);
+    uint32_t solid = 0u;
+    if (d.flags[c] & F_NEAR) {
+#pragma unroll
+      for (int i = 1; i < NQ; ++i) solid |= (uint32_t)((d.flags[c - off[i]] & TYPE_MASK) == T_SOLID) << i;
+    }
+#pragma unroll
+    for (int i = 1; i < NQ; ++i) {
+      const int64_t e = ((solid >> i) & 1u) ? i * NT + c : OPP[i] * NT + c - off[i];
+      g[i] = Store<S>::ld(A + e, inv);
+    }
+  }
   R jx = 0, jy = 0, jz = 0;
 #pragma unroll
-  for (int i = 0; i < NQ; ++i) {
+  for (int i = 1; i < NQ; ++i) {
     jx += EX[i] * g[i];
     jy += EY[i] * g[i];
     jz += EZ[i] * g[i];
@@ -498,10 +585,12 @@ __global__ __launch_bounds__(WBLOCK) void k_band(Dev d) {
 // ---------------------------------------------------------------------------
 template <class R>
 __device__ __forceinline__ R phi4(R r) {
+  // both branches evaluated (their square roots clamped where unused) and
+  // the result selected, so the 12 weights of a point take no branch
   r = fabs(r);
-  if (r <= R(1)) return (R(3) - R(2) * r + sqrt(R(1) + R(4) * r - R(4) * r * r)) * R(0.125);
-  if (r < R(2)) return (R(5) - R(2) * r - sqrt(R(-7) + R(12) * r - R(4) * r * r)) * R(0.125);
-  return R(0);
+  const R a = (R(3) - R(2) * r + sqrt(fmax(R(1) + R(4) * r - R(4) * r * r, R(0)))) * R(0.125);
+  const R b = (R(5) - R(2) * r - sqrt(fmax(R(-7) + R(12) * r - R(4) * r * r, R(0)))) * R(0.125);
+  return r <= R(1) ? a : (r < R(2) ? b : R(0));
 }
 
 __device__ __forceinline__ double3 ld3(const double* p, int64_t k) {
@@ -539,15 +628,24 @@ template <> struct FixOf<double> {
 // global atomics (instead of 64 x 3 global atomics per point).
 // The tile shape TJ x TK (TJ * TK = 256) is chosen per size class by the
 // autotuner: wide in theta (32 x 8), square (16 x 16) or long in z (8 x 32).
+// In the staged path the 4 x 4 x 4 stencil loops are unrolled and free of
+// branches: each staged cell holds (u, m) with u = 0 outside the band and
+// m = 1 at a fluid cell outside the band, so one 16-byte LDS read per
+// stencil cell serves both the interpolation and the band check; tile-wide
+// extents and maxima are reduced within each wave first, so only one lane
+// per wave touches the shared LDS word.
 template <class R, int TJ>
 __global__ __launch_bounds__(WBLOCK) void k_wall(Dev d, const int32_t* __restrict__ walls, int parity) {
   constexpr int TK = (WBLOCK / 64) * 64 / TJ;
   using R4 = typename V4<R>::T;
-  // box cells; a 16 x 16 tile at 0.5 lu spans <= ~1000 (LDS stays < 64 KB)
-  constexpr int BOXCAP = sizeof(R) == 8 ? 1024 : 2048;
-  __shared__ R sbox[3 * BOXCAP];
+  using Fix = typename FixOf<R>::T;
+  // box cells: at 0.5 lu spacing a 16 x 16 or 8 x 32 tile spans <= ~1000,
+  // a 32 x 8 tile <= ~1600 (a larger box takes the unstaged path)
+  constexpr int BOXCAP = sizeof(R) == 8 ? 1024 : (TJ == 32 ? 2048 : 1280);
+  static_assert(3 * sizeof(Fix) <= sizeof(R4), "the spread accumulators reuse the staging box");
+  __shared__ R4 sbox[BOXCAP];
   __shared__ uint8_t sfl[BOXCAP];
-  __shared__ int smin[3], smax[3];
+  __shared__ int sext[6];   // min x, y, z; max x, y, z of the stencil bases
   __shared__ int semax;
   __shared__ uint32_t smove;
   const int inst = walls[blockIdx.y];
@@ -578,21 +676,36 @@ __global__ __launch_bounds__(WBLOCK) void k_wall(Dev d, const int32_t* __restric
   if (point && !inside) atomicOr(d.err, ERR_BAND);
   const bool valid = point && inside;
 
-  if (threadIdx.x < 3) {
-    smin[threadIdx.x] = 0x7fffffff;
-    smax[threadIdx.x] = -0x7fffffff;
+  if (threadIdx.x < 6) sext[threadIdx.x] = threadIdx.x < 3 ? 0x7fffffff : -0x7fffffff;
+  if (threadIdx.x == 0) {
+    smove = 0u;
+    semax = -100000;
   }
-  if (threadIdx.x == 0) smove = 0u;
   __syncthreads();
   // motion since the band was built (max norm; positive floats order as
   // their bit patterns): the host rebuilds the band when it nears the margin
+  uint32_t mv = 0u;
   if (valid) {
     const double3 Dr = ld3(I.Dref, p);
-    const float mv = (float)fmax(fabs(D.x - Dr.x), fmax(fabs(D.y - Dr.y), fabs(D.z - Dr.z)));
-    atomicMax(&smove, __float_as_uint(mv));
+    mv = __float_as_uint((float)fmax(fabs(D.x - Dr.x), fmax(fabs(D.y - Dr.y), fabs(D.z - Dr.z))));
   }
   const int bx0 = valid ? (int)floor(px) - 1 : 0, by0 = valid ? (int)floor(py) - 1 : 0,
             bz0 = valid ? (int)floor(pz) - 1 : 0;
+  {   // wave reductions over the active (here: all) lanes, one atomic per wave
+    const int lo[3] = {__ockl_wfred_min_i32(valid ? bx0 : 0x7fffffff), __ockl_wfred_min_i32(valid ? by0 : 0x7fffffff),
+                       __ockl_wfred_min_i32(valid ? bz0 : 0x7fffffff)};
+    const int hi[3] = {__ockl_wfred_max_i32(valid ? bx0 : -0x7fffffff), __ockl_wfred_max_i32(valid ? by0 : -0x7fffffff),
+                       __ockl_wfred_max_i32(valid ? bz0 : -0x7fffffff)};
+    mv = __ockl_wfred_max_u32(mv);
+    if (ln == 0) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        atomicMin(&sext[a], lo[a]);
+        atomicMax(&sext[3 + a], hi[a]);
+      }
+      atomicMax(&smove, mv);
+    }
+  }
   R wx[4], wy[4], wz[4];
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
@@ -600,26 +713,31 @@ __global__ __launch_bounds__(WBLOCK) void k_wall(Dev d, const int32_t* __restric
     wy[a] = phi4<R>((R)(((double)(by0 + a) - X0.y) - D.y));
     wz[a] = phi4<R>((R)(((double)(bz0 + a) - X0.z) - D.z));
   }
-  if (valid) {
-    atomicMin(&smin[0], bx0); atomicMin(&smin[1], by0); atomicMin(&smin[2], bz0);
-    atomicMax(&smax[0], bx0); atomicMax(&smax[1], by0); atomicMax(&smax[2], bz0);
-  }
   __syncthreads();
   if (threadIdx.x == 0 && smove != 0u) atomicMax(d.moved, smove);
   // every valid point has its stencil base in [-2, n], so the extents are
-  // small and positive; a tile without a valid point has smin > smax
-  const int ox = smin[0], oy = smin[1], oz = smin[2];
-  const bool any = smin[0] <= smax[0];
-  const int ex = any ? smax[0] - ox + 4 : 0, ey = any ? smax[1] - oy + 4 : 0, ez = any ? smax[2] - oz + 4 : 0;
+  // small and positive; a tile without a valid point has min > max
+  const int ox = sext[0], oy = sext[1], oz = sext[2];
+  const bool any = sext[0] <= sext[3];
+  const int ex = any ? sext[3] - ox + 4 : 0, ey = any ? sext[4] - oy + 4 : 0, ez = any ? sext[5] - oz + 4 : 0;
   const int64_t vol = (int64_t)ex * ey * ez;
   const bool staged = any && vol <= BOXCAP;   // uniform over the block
+  const int exy = ex * ey;
+  // box index q -> cell by float division: exact, as (q + 0.5) / n sits at
+  // least 0.5 / n from an integer and q < 2^21 keeps the rounding far below
+  const float rex = 1.0f / (float)max(ex, 1), rexy = 1.0f / (float)max(exy, 1);
   const R4* U = (const R4*)I.u4;
   auto box_cell = [&](int q, int& x, int& y, int& z) {
-    x = ox + q % ex;
-    y = oy + (q / ex) % ey;
-    z = oz + q / (ex * ey);
+    const int zq = (int)(((float)q + 0.5f) * rexy);
+    const int r = q - zq * exy;
+    const int yq = (int)(((float)r + 0.5f) * rex);
+    x = ox + (r - yq * ex);
+    y = oy + yq;
+    z = oz + zq;
   };
   auto in_box = [&](int x, int y, int z) { return x >= 0 && y >= 0 && z >= 0 && x < I.nx && y < I.ny && z < I.nz; };
+  // first box index of a point's stencil
+  const int q0 = valid && staged ? (bx0 - ox) + ex * ((by0 - oy) + ey * (bz0 - oz)) : 0;
 
   // ---- interpolation of the unforced velocity over the 4x4x4 stencil ----
   if (staged) {
@@ -631,44 +749,58 @@ __global__ __launch_bounds__(WBLOCK) void k_wall(Dev d, const int32_t* __restric
       if (in_box(x, y, z)) {
         const int64_t lc = x + (int64_t)I.nx * (y + (int64_t)I.ny * z);
         f = d.flags[I.cell0 + lc];
-        u = U[lc];  // only read where (f is FLUID and BAND)
+        if ((f & TYPE_MASK) == T_FLUID) {
+          if (f & F_BAND) {
+            const R4 v = U[lc];   // written for band cells only
+            u = R4{v.x, v.y, v.z, R(0)};
+          } else {
+            u.w = R(1);
+          }
+        }
       }
       sfl[q] = f;
-      sbox[3 * q] = u.x; sbox[3 * q + 1] = u.y; sbox[3 * q + 2] = u.z;
+      sbox[q] = u;
     }
     __syncthreads();
   }
   R Vx = 0, Vy = 0, Vz = 0;
   bool outside = false;
-  if (valid) {
+  if (valid && staged) {
+    R o = 0;   // > 0 iff a stencil weight != 0 falls on fluid outside the band
+#pragma unroll
+    for (int cz = 0; cz < 4; ++cz)
+#pragma unroll
+      for (int cy = 0; cy < 4; ++cy) {
+        const R wyz = wy[cy] * wz[cz];
+        const R4* row = sbox + q0 + ex * cy + exy * cz;
+#pragma unroll
+        for (int cx = 0; cx < 4; ++cx) {
+          const R4 u = row[cx];
+          const R w = wx[cx] * wyz;
+          Vx += u.x * w;
+          Vy += u.y * w;
+          Vz += u.z * w;
+          o = fmax(o, u.w * fabs(w));
+        }
+      }
+    outside = o > R(0);
+  } else if (valid) {
     for (int cz = 0; cz < 4; ++cz)
       for (int cy = 0; cy < 4; ++cy) {
         const R wyz = wy[cy] * wz[cz];
         for (int cx = 0; cx < 4; ++cx) {
           const int x = bx0 + cx, y = by0 + cy, z = bz0 + cz;
-          uint8_t f;
-          R ux, uy, uz;
-          if (staged) {
-            const int q = (x - ox) + ex * ((y - oy) + ey * (z - oz));
-            f = sfl[q];
-            ux = sbox[3 * q]; uy = sbox[3 * q + 1]; uz = sbox[3 * q + 2];
-          } else {
-            if (!in_box(x, y, z)) continue;
-            const int64_t lc = x + (int64_t)I.nx * (y + (int64_t)I.ny * z);
-            f = d.flags[I.cell0 + lc];
-            ux = uy = uz = 0;
-            if ((f & TYPE_MASK) == T_FLUID && (f & F_BAND)) {
-              const R4 u = U[lc];
-              ux = u.x; uy = u.y; uz = u.z;
-            }
-          }
+          if (!in_box(x, y, z)) continue;
+          const int64_t lc = x + (int64_t)I.nx * (y + (int64_t)I.ny * z);
+          const uint8_t f = d.flags[I.cell0 + lc];
           if ((f & TYPE_MASK) != T_FLUID) continue;
           const R w = wx[cx] * wyz;
           if (!(f & F_BAND)) {
             if (w != R(0)) outside = true;
             continue;
           }
-          Vx += ux * w; Vy += uy * w; Vz += uz * w;
+          const R4 u = U[lc];
+          Vx += u.x * w; Vy += u.y * w; Vz += u.z * w;
         }
       }
   }
@@ -700,30 +832,34 @@ __global__ __launch_bounds__(WBLOCK) void k_wall(Dev d, const int32_t* __restric
   // scale is a power of two per tile, 2^(M - e) with e the exponent of the
   // tile's largest |F area| and M the significand width of R (headroom of
   // 2^7 resp. 2^10 for the sums).
-  using Fix = typename FixOf<R>::T;
   if (staged) {
-    if (threadIdx.x == 0) semax = -100000;
     __syncthreads();  // everyone is done reading the staged velocity
     Fix* acc = (Fix*)sbox;
-    for (int q = threadIdx.x; q < 3 * (int)vol; q += WBLOCK) acc[q] = 0;
+    for (int q = threadIdx.x; q < (int)vol; q += WBLOCK) sbox[q] = R4{0, 0, 0, 0};
+    int em = -100000;
     if (valid) {
       const R m = fmax(fabs(fx), fmax(fabs(fy), fabs(fz)));
-      if (m > R(0)) atomicMax(&semax, (int)ilogb(m));
+      if (m > R(0)) em = (int)ilogb(m);
     }
+    em = __ockl_wfred_max_i32(em);
+    if (ln == 0 && em > -100000) atomicMax(&semax, em);
     __syncthreads();
     const int e = semax < -1000 ? 0 : semax;
     const R S = ldexp(R(1), FixOf<R>::M - e), invS = ldexp(R(1), e - FixOf<R>::M);
     if (valid) {
       const R sx = fx * S, sy = fy * S, sz = fz * S;
+#pragma unroll
       for (int cz = 0; cz < 4; ++cz)
+#pragma unroll
         for (int cy = 0; cy < 4; ++cy) {
           const R wyz = wy[cy] * wz[cz];
-          const int q0 = (bx0 - ox) + ex * ((by0 + cy - oy) + ey * (bz0 + cz - oz));
+          Fix* row = acc + 3 * (q0 + ex * cy + exy * cz);
+#pragma unroll
           for (int cx = 0; cx < 4; ++cx) {
             const R w = wx[cx] * wyz;
-            FixOf<R>::add(&acc[3 * (q0 + cx)], sx * w);
-            FixOf<R>::add(&acc[3 * (q0 + cx) + 1], sy * w);
-            FixOf<R>::add(&acc[3 * (q0 + cx) + 2], sz * w);
+            FixOf<R>::add(row + 3 * cx, sx * w);
+            FixOf<R>::add(row + 3 * cx + 1, sy * w);
+            FixOf<R>::add(row + 3 * cx + 2, sz * w);
           }
         }
     }
