@@ -94,11 +94,15 @@ lbm_status lbm_sur_train_step(lbm_sur_ctx* c, const float* x, const float* t, in
 
 /* Inference: y (device, m x n_out FP32, physical units) for m <= max_batch
  * rows of x (physical parameters; no check of the box here: callers route
- * points outside it to the solver). */
+ * points outside it to the solver).  With width 512 and 512 outputs the
+ * whole network runs as one kernel (activations stay on chip; the first
+ * call after a weight change also rebuilds a fragment-ordered weight copy
+ * in the context's memory); other shapes run one product per layer. */
 lbm_status lbm_sur_predict(lbm_sur_ctx* c, const float* x, int32_t m, float* y);
 
 /* Per-kernel time accumulation with HIP events on the context's stream
- * (matrix products only): on/off, then (launches, total ms). */
+ * (matrix products and the fused inference kernel only): on/off, then
+ * (launches, total ms, their FLOP count). */
 lbm_status lbm_sur_set_timing(lbm_sur_ctx* c, int32_t on);
 lbm_status lbm_sur_gemm_time(lbm_sur_ctx* c, int64_t* launches, double* ms, double* flops);
 

@@ -13,6 +13,9 @@
 //   k_loss                 squared error, its gradient in BF16, loss sum
 //   k_colsum               bias gradients
 //   k_adam / k_cast        Adam step; BF16 (K-padded) copy of the weights
+//   k_frag / k_mlp_fwd     inference of the whole network in one kernel for
+//                          width 512 and 512 outputs: weights in MFMA fragment
+//                          order, activations kept in LDS between layers
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -43,11 +46,26 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
   return (uint16_t)(u >> 16);
 }
 
-__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+// Phi(z) = (1 + erf(z / sqrt 2)) / 2, the standard normal CDF, with erf from
+// Abramowitz & Stegun 7.1.26 (|error| <= 1.5e-7): for x >= 0,
+// 1 - erf(x) = t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) exp(-x^2),
+// t = 1 / (1 + p x).  The z < 0 side takes that tail directly (no
+// cancellation).  About a dozen instructions, against erff's several dozen:
+// the GELU epilogues of the forward products are VALU work next to MFMA.
+__device__ __forceinline__ float phi_cdf(float z) {
+  const float x = fabsf(z) * 0.70710678118654752f;
+  const float t = __builtin_amdgcn_rcpf(1.0f + 0.3275911f * x);
+  const float poly =
+      t * (0.254829592f + t * (-0.284496736f + t * (1.421413741f + t * (-1.453152027f + t * 1.061405429f))));
+  const float q = poly * __expf(-x * x);   // 1 - erf(x)
+  return z >= 0.0f ? 1.0f - 0.5f * q : 0.5f * q;
+}
+
+__device__ __forceinline__ float gelu(float z) { return z * phi_cdf(z); }
 
 // d/dz [z Phi(z)] = Phi(z) + z phi(z)
 __device__ __forceinline__ float gelu_grad(float z) {
-  return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * expf(-0.5f * z * z);
+  return phi_cdf(z) + z * 0.39894228040143268f * __expf(-0.5f * z * z);
 }
 
 struct GemmArgs {
@@ -157,7 +175,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
 }
 
 // Forward product C = A B^T with both operands k-contiguous (activations h and
-// weights W), the hot path of inference.  Block tile 128 x 256, each of the 4
+// weights W): training's forward pass, and inference for other shapes.  Block tile 128 x 256, each of the 4
 // waves 64 x 128 (2 x 4 MFMA tiles: 6 fragment reads from LDS per 8 MFMAs),
 // k-step 32.  The next k-step's tiles are fetched into registers while the
 // current one is multiplied out of LDS, and stored into the other half of a
@@ -350,6 +368,153 @@ __global__ void k_adam(float* __restrict__ w, float* __restrict__ m1, float* __r
   to_bf16_copy(L, p, wn, wb);
 }
 
+
+// ---------------------------------------------------------------------------
+// Fused inference for width 512 and 512 outputs (the surrogate's shape)
+// ---------------------------------------------------------------------------
+// One 512-lane workgroup (8 waves) per 128 rows holds the rows' activations
+// in LDS (128 x 512 BF16, row pitch padded by 16 bytes) from the input
+// normalisation to the output layer, so hidden activations never travel to
+// HBM.  Wave w computes output columns 64 w .. 64 w + 63 of every layer
+// (4 x 2 MFMA tiles of 32 x 32): A fragments come from LDS, B fragments
+// (weights) stream from L2 in fragment order, two k-steps ahead of the
+// MFMAs that use them.  The GELU epilogue writes the layer's output over its
+// input in LDS between two barriers.
+constexpr int MR = 128, MWID = 512, APITCH = MWID + 8;
+
+// weights in MFMA fragment order: element ((nt K/16 + ks) 64 + lane) 8 + e of
+// layer l (N outputs, depth K = kp) is W[32 nt + lane % 32][16 ks + 8 (lane / 32) + e],
+// so the 64 lanes of a wave read one tile's k-step as 1 KB in a row
+__global__ void k_frag(const uint16_t* __restrict__ wb, LayerMap L, int64_t n, uint16_t* __restrict__ wf) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  int l = 0;
+  while (l + 1 < L.nl && p >= L.woff[l + 1]) ++l;
+  const int64_t q = p - L.woff[l];
+  const int K = L.kp[l], KS = K / 16;
+  const int e = (int)(q & 7), lane = (int)((q >> 3) & 63);
+  const int64_t t = q >> 9;
+  const int ks = (int)(t % KS), nt = (int)(t / KS);
+  wf[p] = wb[L.woff[l] + (int64_t)(nt * 32 + (lane & 31)) * K + ks * 16 + (lane >> 5) * 8 + e];
+}
+
+struct MlpArgs {
+  const float* x;       // m x nin inputs
+  int m, nin;
+  const float* lo;
+  const float* hi;
+  const uint16_t* wf;   // weights in fragment order (layout of wb)
+  const float* w;       // FP32 parameters (biases)
+  LayerMap L;
+  const float* mu;
+  const float* sigma;
+  float* y;             // m x 512 physical outputs
+};
+
+__global__ __launch_bounds__(512) void k_mlp_fwd(MlpArgs a) {
+  __shared__ __attribute__((aligned(16))) uint16_t act[MR * APITCH];
+  const int tid = (int)threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int r0 = (int)blockIdx.x * MR;
+  // inputs normalised as k_prep_x does; padding columns and rows are zero
+  for (int e = tid; e < MR * KPAD; e += 512) {
+    const int r = e / KPAD, j = e % KPAD;
+    float v = 0.0f;
+    if (j < a.nin && r0 + r < a.m)
+      v = 2.0f * (a.x[(int64_t)(r0 + r) * a.nin + j] - a.lo[j]) / (a.hi[j] - a.lo[j]) - 1.0f;
+    act[r * APITCH + j] = f2bf(v);
+  }
+  __syncthreads();
+  const int fr = lane & 31, fk = (lane >> 5) * 8;
+  f32x16 acc[4][2];
+  // acc = act (128 x K) W_l^T for this wave's two column tiles
+  auto layer = [&](int l) {
+    const int KS = a.L.kp[l] / 16;   // 2 for the first layer, 32 after
+    const bf16x8* W0 = (const bf16x8*)(a.wf + a.L.woff[l]) + (int64_t)(2 * wv) * KS * 64 + lane;
+    const bf16x8* W1 = W0 + (int64_t)KS * 64;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
+    // k-steps in pairs; the next pair's weight fragments are in flight while
+    // the current pair is multiplied (KS is even)
+    bf16x8 b0[2], b1[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      b0[q] = W0[q * 64];
+      b1[q] = W1[q * 64];
+    }
+    for (int c = 0; c < KS; c += 2) {
+      bf16x8 n0[2], n1[2];
+      const bool more = c + 2 < KS;
+      if (more) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          n0[q] = W0[(c + 2 + q) * 64];
+          n1[q] = W1[(c + 2 + q) * 64];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int k = (c + q) * 16 + fk;
+        bf16x8 af[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) af[i] = *(const bf16x8*)(act + (i * 32 + fr) * APITCH + k);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          acc[i][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[i], b0[q], acc[i][0], 0, 0, 0);
+          acc[i][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[i], b1[q], acc[i][1], 0, 0, 0);
+        }
+      }
+      if (more) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          b0[q] = n0[q];
+          b1[q] = n1[q];
+        }
+      }
+    }
+    __syncthreads();   // every wave has read this layer's input
+  };
+  auto bias_of = [&](int l) { return a.w + a.L.off[l] + (int64_t)a.L.out[l] * a.L.in[l]; };
+  // accumulator v of lane l: row 8 (v / 4) + 4 (l / 32) + v % 4 of its
+  // 32 x 32 tile, column l % 32
+  const int nl = a.L.nl;
+  for (int l = 0; l + 1 < nl; ++l) {
+    layer(l);
+    const float* bias = bias_of(l);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int col = (2 * wv + j) * 32 + fr;
+      const float bj = bias[col];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int row = i * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
+          // hardware round-to-nearest-even conversion (v_cvt_pk_bf16_f32)
+          act[row * APITCH + col] = __builtin_bit_cast(uint16_t, (__bf16)gelu(acc[i][j][v] + bj));
+        }
+    }
+    __syncthreads();
+  }
+  layer(nl - 1);
+  const float* bias = bias_of(nl - 1);
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int col = (2 * wv + j) * 32 + fr;
+    const float bj = bias[col], mj = a.mu[col], sj = a.sigma[col];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int row = i * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
+        if (r0 + row < a.m) a.y[(int64_t)(r0 + row) * MWID + col] = mj + sj * (acc[i][j][v] + bj);
+      }
+  }
+}
+
 }  // namespace sur
 
 using namespace sur;
@@ -366,7 +531,8 @@ struct lbm_sur_ctx {
   int64_t np, nwb;
   // device regions
   float *w, *m1, *m2, *g, *lo, *hi, *mu, *sigma, *Y, *Tn;
-  uint16_t *wb, *X0, *dz[2];
+  uint16_t *wb, *wf, *X0, *dz[2];
+  int64_t wgen, fgen;   // weight updates so far; the update wf was last built from
   uint16_t* H[8];
   float* Z[8];
   double* loss;
@@ -418,7 +584,7 @@ LayerMap layer_map(const lbm_sur_config& c, int64_t& np, int64_t& nwb) {
 }
 
 struct Plan {
-  size_t w, m1, m2, g, wb, lo, hi, mu, sigma, X0, H[8], Z[8], Y, Tn, dz[2], loss, errw, total;
+  size_t w, m1, m2, g, wb, wf, lo, hi, mu, sigma, X0, H[8], Z[8], Y, Tn, dz[2], loss, errw, total;
 };
 
 size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -437,6 +603,7 @@ Plan plan(const lbm_sur_config& c) {
   p.m2 = take(np * 4);
   p.g = take(np * 4);
   p.wb = take(nwb * 2);
+  p.wf = take(nwb * 2);
   p.lo = take(KPAD * 4);
   p.hi = take(KPAD * 4);
   p.mu = take((size_t)c.n_out * 4);
@@ -608,6 +775,31 @@ lbm_status read_loss(lbm_sur_ctx* c, double* loss) {
   SURCHK(c, hipMemcpy(loss, c->loss, 8, hipMemcpyDeviceToHost));
   return LBM_OK;
 }
+// the whole network in one kernel (k_mlp_fwd) when the hidden width and
+// the output count are 512
+bool fused_shape(const lbm_sur_config& C) { return C.width == MWID && C.n_out == MWID; }
+
+lbm_status predict_fused(lbm_sur_ctx* c, const float* x, int m, float* y) {
+  if (c->fgen != c->wgen) {   // weights changed: rebuild the fragment-order copy
+    hipLaunchKernelGGL(k_frag, dim3(blocks(c->nwb, 256)), dim3(256), 0, c->stream, c->wb, c->L, c->nwb, c->wf);
+    SURCHK(c, hipGetLastError());
+    c->fgen = c->wgen;
+  }
+  MlpArgs g;
+  g.x = x; g.m = m; g.nin = c->cfg.n_in; g.lo = c->lo; g.hi = c->hi;
+  g.wf = c->wf; g.w = c->w; g.L = c->L; g.mu = c->mu; g.sigma = c->sigma; g.y = y;
+  const bool t = c->timing && c->nev + 2 <= (int)c->ev.size();
+  if (t) SURCHK(c, hipEventRecord(c->ev[c->nev], c->stream));
+  hipLaunchKernelGGL(k_mlp_fwd, dim3(blocks(m, MR)), dim3(512), 0, c->stream, g);
+  SURCHK(c, hipGetLastError());
+  if (t) {
+    SURCHK(c, hipEventRecord(c->ev[c->nev + 1], c->stream));
+    c->nev += 2;
+    for (int l = 0; l < c->L.nl; ++l) c->flops += 2.0 * m * (double)c->L.out[l] * c->L.kp[l];
+  }
+  return LBM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -638,6 +830,9 @@ lbm_status lbm_sur_init(const lbm_sur_config* cfg, void* mem, size_t bytes, void
   char* b = (char*)mem;
   c->w = (float*)(b + p.w); c->m1 = (float*)(b + p.m1); c->m2 = (float*)(b + p.m2); c->g = (float*)(b + p.g);
   c->wb = (uint16_t*)(b + p.wb);
+  c->wf = (uint16_t*)(b + p.wf);
+  c->wgen = 0;
+  c->fgen = -1;
   c->lo = (float*)(b + p.lo); c->hi = (float*)(b + p.hi); c->mu = (float*)(b + p.mu); c->sigma = (float*)(b + p.sigma);
   c->X0 = (uint16_t*)(b + p.X0);
   for (int l = 0; l < cfg->n_hidden; ++l) {
@@ -678,6 +873,7 @@ lbm_status lbm_sur_set_params(lbm_sur_ctx* c, const double* theta, int64_t n) {
   SURCHK(c, hipGetLastError());
   SURCHK(c, hipStreamSynchronize(c->stream));
   c->step = 0;
+  c->wgen += 1;
   return LBM_OK;
 }
 
@@ -740,6 +936,7 @@ lbm_status lbm_sur_train_step(lbm_sur_ctx* c, const float* x, const float* t, in
   hipLaunchKernelGGL(k_adam, dim3(blocks(c->np, 256)), dim3(256), 0, c->stream, c->w, c->m1, c->m2, c->g, c->np,
                      (float)lr, (float)b1, (float)b2, (float)eps, bc1, bc2, c->L, c->wb);
   SURCHK(c, hipGetLastError());
+  c->wgen += 1;
   if (loss) TRY(read_loss(c, loss));
   return LBM_OK;
 }
@@ -747,6 +944,7 @@ lbm_status lbm_sur_train_step(lbm_sur_ctx* c, const float* x, const float* t, in
 lbm_status lbm_sur_predict(lbm_sur_ctx* c, const float* x, int32_t m, float* y) {
   if (!c || !y) return LBM_E_INVAL;
   TRY(check_batch(c, x, m, c->cfg.max_batch));
+  if (fused_shape(c->cfg)) return predict_fused(c, x, m, y);
   hipLaunchKernelGGL(k_prep_x, dim3(blocks((int64_t)m * KPAD, 256)), dim3(256), 0, c->stream, x, m, nullptr, m, m,
                      c->cfg.n_in, c->lo, c->hi, c->X0, c->errw);
   SURCHK(c, hipGetLastError());

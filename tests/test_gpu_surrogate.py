@@ -58,6 +58,35 @@ def test_forward_small_net_ragged_batch(sur):
     s.close()
 
 
+def test_fused_inference_full_size_ragged_batch_and_weight_updates(sur):
+    """The 7 -> 512 x 4 -> 512 network runs in one kernel (activations in
+    LDS, weights in fragment order): 300 rows (two full row blocks of 128
+    and a ragged one) against the FP64 network, before and after an Adam
+    step changes the weights (the fragment-order copy must follow)."""
+    rng = np.random.default_rng(21)
+    theta = L.mlp_init([7] + [512] * 4 + [512], seed=22)
+    lo, hi, mu, sigma = _scaling(512, rng)
+    s = sur.Surrogate(train_batch=64, max_batch=300)
+    s.set_params(theta)
+    s.set_scaling(lo, hi, mu, sigma)
+    X = L.surrogate_params(300, seed=23)
+    shapes = mlp.layer_shapes()
+    for step in range(2):
+        y = s.predict(X).cpu().numpy()
+        yo, _, _ = mlp.forward(s.params(), shapes, mlp.normalise_inputs(X, lo, hi))
+        e = _rel((y - mu) / sigma, yo)
+        tail = _rel((y[256:] - mu) / sigma, yo[256:])
+        print({"step": step, "forward_rel_l2": f"{e:.2e}", "ragged_block": f"{tail:.2e}"}, flush=True)
+        assert e <= 2e-2 and tail <= 2e-2
+        if step == 0:
+            T = mu + sigma * rng.normal(size=(64, 512))
+            xd, td = s._dev(X[:64]), s._dev(T)
+            s.stream.wait_stream(s.torch.cuda.current_stream(s.device))
+            s.train_step(xd, td, None, 1e-2)
+            assert np.abs(s.params() - theta).max() > 1e-3
+    s.close()
+
+
 def _full_case(seed, m):
     rng = np.random.default_rng(seed)
     theta = L.mlp_init([7] + [512] * 4 + [512], seed=seed)
