@@ -288,6 +288,23 @@ lbm_status lbm_set_launch(lbm_ctx* ctx, int32_t cls, const lbm_launch* launch);
  * and walls are set. */
 lbm_status lbm_autotune(lbm_ctx* ctx, int32_t trial_steps, int64_t* advanced);
 
+/* Checkpoint / resume.  lbm_save waits for the stream and writes to the
+ * file at path everything that determines later steps: populations, cell
+ * flags (band bits), the 0D boundary records, step counters, waveform rings,
+ * inlet snapshots, the error and motion words, and per wall its two
+ * displacement levels, slip integral, last interpolated velocity and force,
+ * displacement at the last band build and its band.  lbm_load restores such
+ * a file into a context built the same way (lbm_init with the same
+ * configurations, the same walls attached; 0D couplings are restored from
+ * the file), after which stepping continues bit for bit as the saved run
+ * would have.  Errors: LBM_E_INVAL (NULL, unopenable or unwritable path),
+ * LBM_E_STATE (not a checkpoint, truncated, or a context of another shape,
+ * precision, storage scale or waveform capacity; a saved band larger than
+ * the wall buffer holds), LBM_E_DEVICE.  A failed load may leave the context
+ * partly overwritten. */
+lbm_status lbm_save(lbm_ctx* ctx, const char* path);
+lbm_status lbm_load(lbm_ctx* ctx, const char* path);
+
 const char* lbm_last_error(const lbm_ctx* ctx);
 void lbm_destroy(lbm_ctx* ctx);
 

@@ -80,6 +80,8 @@ SYMBOLS = {
     "lbm_get_launch": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(Launch)]),
     "lbm_set_launch": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(Launch)]),
     "lbm_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64)]),
+    "lbm_save": (C.c_int, [C.c_void_p, C.c_char_p]),
+    "lbm_load": (C.c_int, [C.c_void_p, C.c_char_p]),
     "lbm_last_error": (C.c_char_p, [C.c_void_p]),
     "lbm_destroy": (None, [C.c_void_p]),
     "lbm_num_cells": (C.c_int64, [C.c_void_p, C.c_int32]),
@@ -201,6 +203,15 @@ class Solver:
 
     def sync(self):
         self._check(lib().lbm_sync(self.h))
+
+    def save(self, path):
+        """Checkpoint of the whole state to a file (lbm_save)."""
+        self._check(lib().lbm_save(self.h, os.fsencode(path)))
+
+    def load(self, path):
+        """Restore a checkpoint into this solver, built like the saved one
+        (lbm_load)."""
+        self._check(lib().lbm_load(self.h, os.fsencode(path)))
 
     def couple_0d(self, inst, boundary, kind, params, state=()):
         p = np.ascontiguousarray(params, dtype=np.float64)

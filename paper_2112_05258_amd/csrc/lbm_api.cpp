@@ -1270,6 +1270,175 @@ lbm_status lbm_set_overlap(lbm_ctx* c, int32_t on) {
   return LBM_OK;
 }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// checkpoint / resume
+// ---------------------------------------------------------------------------
+// File: a header (magic, version, context shape, step), one record per
+// instance (cells, wall points, band size), then the raw device state in a
+// fixed order: populations, cell flags (band bits), 0D boundary records,
+// per-instance step counters, waveform rings, inlet snapshots, error and
+// motion words, and per wall its displacements D^n / D^{n-1}, slip
+// integral, last interpolated velocity and force, displacement at the last
+// band build and the band cell list.  Band velocities and forces are not
+// saved: every step recomputes them before use.
+
+namespace {
+
+constexpr char CKPT_MAGIC[8] = {'L', 'B', 'M', '0', 'D', '3', 'D', 'C'};
+constexpr uint32_t CKPT_VERSION = 1;
+
+struct CkptHeader {
+  char magic[8];
+  uint32_t version;
+  int32_t n, prec, wave_cap;
+  int64_t NT, nv0, step;
+  float scale;
+  uint32_t pad;
+};
+
+struct CkptInst {
+  int64_t ncell, np;
+  int32_t has_wall, nband, margin, pad;
+};
+
+// the pieces of device state a checkpoint holds, in file order
+std::vector<std::pair<char*, size_t>> ckpt_pieces(lbm_ctx* c) {
+  std::vector<std::pair<char*, size_t>> v;
+  const size_t n = (size_t)c->n;
+  v.push_back({(char*)c->pop, (size_t)NQ * c->L.NT * elem_size(c->prec)});
+  v.push_back({c->work + c->L.flags, (size_t)c->L.NT});
+  v.push_back({c->work + c->L.bc, 3 * n * sizeof(BcDev)});
+  v.push_back({c->work + c->L.st, n * sizeof(InstState)});
+  v.push_back({c->work + c->L.wave, n * (size_t)c->L.wave_cap * NREC * 8});
+  v.push_back({c->work + c->L.v0, (size_t)c->L.nv0 * r4_size(c->prec)});
+  v.push_back({c->work + c->L.err, 4});
+  v.push_back({c->work + c->L.moved, 4});
+  for (int k = 0; k < c->n; ++k) {
+    if (!c->wall[k].on) continue;
+    const InstDesc& d = c->inst[k];
+    const size_t np = (size_t)d.np;
+    v.push_back({(char*)d.Xab[0], np * 32});
+    v.push_back({(char*)d.Xab[1], np * 32});
+    v.push_back({(char*)d.slip, np * 32});
+    v.push_back({(char*)d.Vf, np * r4_size(c->prec)});
+    v.push_back({(char*)d.Fp, np * 32});
+    v.push_back({(char*)d.Dref, np * 32});
+  }
+  return v;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_save(lbm_ctx* c, const char* path) {
+  if (!c || !path) return LBM_E_INVAL;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  FILE* f = std::fopen(path, "wb");
+  if (!f) return fail(c, LBM_E_INVAL, std::string("cannot open checkpoint file for writing: ") + path);
+  bool ok = true;
+  auto put = [&](const void* p, size_t b) { ok = ok && std::fwrite(p, 1, b, f) == b; };
+  CkptHeader h;
+  std::memset(&h, 0, sizeof h);
+  std::memcpy(h.magic, CKPT_MAGIC, 8);
+  h.version = CKPT_VERSION;
+  h.n = c->n; h.prec = c->prec; h.wave_cap = c->L.wave_cap;
+  h.NT = c->L.NT; h.nv0 = c->L.nv0; h.step = c->step; h.scale = c->scale;
+  put(&h, sizeof h);
+  for (int k = 0; k < c->n; ++k) {
+    CkptInst r;
+    std::memset(&r, 0, sizeof r);
+    r.ncell = c->geo[k].ncell;
+    r.has_wall = c->wall[k].on ? 1 : 0;
+    r.np = c->wall[k].on ? c->wall[k].np : 0;
+    r.nband = c->wall[k].on ? c->wall[k].nband : 0;
+    r.margin = c->wall[k].margin;
+    put(&r, sizeof r);
+  }
+  std::vector<char> buf;
+  for (const auto& pc : ckpt_pieces(c)) {
+    buf.resize(pc.second);
+    const hipError_t e = hipMemcpy(buf.data(), pc.first, pc.second, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+      std::fclose(f);
+      return fail(c, LBM_E_DEVICE, std::string("checkpoint read-back: ") + hipGetErrorString(e));
+    }
+    put(buf.data(), pc.second);
+  }
+  for (int k = 0; k < c->n; ++k)
+    if (c->wall[k].on) put(c->wall[k].band.data(), c->wall[k].band.size() * 4);
+  ok = (std::fclose(f) == 0) && ok;
+  if (!ok) return fail(c, LBM_E_INVAL, std::string("checkpoint write failed: ") + path);
+  return LBM_OK;
+}
+
+lbm_status lbm_load(lbm_ctx* c, const char* path) {
+  if (!c || !path) return LBM_E_INVAL;
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return fail(c, LBM_E_INVAL, std::string("cannot open checkpoint file: ") + path);
+  bool ok = true;
+  auto get = [&](void* p, size_t b) { ok = ok && std::fread(p, 1, b, f) == b; };
+  auto bad = [&](const char* m) {
+    std::fclose(f);
+    return fail(c, LBM_E_STATE, std::string("checkpoint does not fit this context: ") + m);
+  };
+  CkptHeader h;
+  get(&h, sizeof h);
+  if (!ok || std::memcmp(h.magic, CKPT_MAGIC, 8) != 0 || h.version != CKPT_VERSION) return bad("not a checkpoint");
+  if (h.n != c->n || h.prec != c->prec || h.wave_cap != c->L.wave_cap || h.NT != c->L.NT || h.nv0 != c->L.nv0 ||
+      h.scale != c->scale)
+    return bad("instances, precision, storage scale or waveform capacity differ");
+  std::vector<CkptInst> r((size_t)c->n);
+  for (int k = 0; k < c->n; ++k) {
+    get(&r[k], sizeof r[k]);
+    if (!ok) return bad("truncated");
+    const bool wall = c->wall[k].on;
+    if (r[k].ncell != c->geo[k].ncell || r[k].has_wall != (wall ? 1 : 0) || (wall && r[k].np != c->wall[k].np))
+      return bad("an instance's cells or wall differ");
+    if (wall && r[k].nband > c->wall[k].band_cap) return bad("a saved band exceeds the wall buffer's capacity");
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  drop_graph(c);
+  std::vector<char> buf;
+  for (const auto& pc : ckpt_pieces(c)) {
+    buf.resize(pc.second);
+    get(buf.data(), pc.second);
+    if (!ok) return bad("truncated");
+    const hipError_t e = hipMemcpy(pc.first, buf.data(), pc.second, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      std::fclose(f);
+      return fail(c, LBM_E_DEVICE, std::string("checkpoint upload: ") + hipGetErrorString(e));
+    }
+  }
+  // host copies: band bits of the flags, band lists, step
+  std::vector<uint8_t> fl((size_t)c->L.NT);
+  HIPCHK(c, hipMemcpy(fl.data(), c->work + c->L.flags, fl.size(), hipMemcpyDeviceToHost));
+  int maxb = 0;
+  for (int k = 0; k < c->n; ++k) {
+    Geometry& g = c->geo[k];
+    InstDesc& d = c->inst[k];
+    std::memcpy(g.flags.data(), fl.data() + d.cell0, (size_t)g.ncell);
+    if (!c->wall[k].on) continue;
+    Wall& W = c->wall[k];
+    std::vector<int32_t> band((size_t)r[k].nband);
+    get(band.data(), band.size() * 4);
+    if (!ok) return bad("truncated");
+    if (!band.empty()) HIPCHK(c, hipMemcpy(d.band, band.data(), band.size() * 4, hipMemcpyHostToDevice));
+    d.nband = r[k].nband;
+    HIPCHK(c, hipMemcpy(c->work + c->L.inst + k * sizeof(InstDesc), &d, sizeof d, hipMemcpyHostToDevice));
+    W.band.swap(band);
+    W.nband = d.nband;
+    W.margin = r[k].margin;
+    maxb = std::max(maxb, W.nband);
+  }
+  std::fclose(f);
+  c->dev.max_band = maxb;
+  c->step = h.step;
+  return build_groups(c, false);
+}
+
 const char* lbm_last_error(const lbm_ctx* c) { return c ? c->err.c_str() : g_init_err.c_str(); }
 
 void lbm_destroy(lbm_ctx* c) {
