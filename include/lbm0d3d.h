@@ -182,6 +182,14 @@ typedef struct {
   double ds_theta, ds_z, area;
   double k_stretch, ei_bend, mass, alpha, beta;
   int32_t band_margin;
+  int32_t kernel;   /* delta kernel: 0 Peskin 4-point (default), 1 cosine
+                       4-point (1 + cos(pi r / 2)) / 4 on |r| < 2 */
+  int32_t mode;     /* 0 built-in membrane (default); 1 external solid: the
+                       caller moves the points with lbm_set_wall, no membrane
+                       forces act (k_stretch, ei_bend, mass unused), and the
+                       library interpolates, forms the penalty force and
+                       spreads it; the force on the solid, -F, is read back
+                       with lbm_read_wall */
 } lbm_wall_desc;
 
 /* Device bytes the wall of one instance needs (Lagrangian state + dense
@@ -195,6 +203,16 @@ lbm_status lbm_fsi_query_sizes(lbm_ctx* ctx, int32_t inst, const lbm_wall_desc* 
  * the box faces). */
 lbm_status lbm_fsi_exchange(lbm_ctx* ctx, int32_t inst, const lbm_wall_desc* wall, void* fsi_buf,
                             size_t fsi_bytes);
+
+/* External solid (wall mode 1): positions X (host, 3*n_points doubles) of
+ * the points at the current step and their velocities V (lattice units per
+ * step).  Until the next call the points keep that velocity,
+ * X^{n+1} = 2 X^n - X^{n-1}.  Synchronises; rebuilds the band when the
+ * points have moved band_margin - 1 units or more since it was built.
+ * Errors: LBM_E_INVAL (NULL, no wall or a built-in membrane at inst),
+ * LBM_E_UNSTABLE (a non-finite or out-of-box point during a band rebuild),
+ * LBM_E_BAND (a rebuilt band larger than the buffer holds). */
+lbm_status lbm_set_wall(lbm_ctx* ctx, int32_t inst, const double* X, const double* V);
 
 /* Read the wall state: X, Xprev (positions at t_n, t_{n-1}), slip integral,
  * interpolated fluid velocity Vf and force on the fluid F of the last step;

@@ -74,6 +74,10 @@ def lib(extended=False):
         L.orc_elastance.argtypes = [dp, C.c_double, dp, dp]
         L.orc_phi4.restype = C.c_double
         L.orc_phi4.argtypes = [C.c_double]
+        L.orc_phicos.restype = C.c_double
+        L.orc_phicos.argtypes = [C.c_double]
+        L.orc_set_wall_options.argtypes = [vp, C.c_int, C.c_int]
+        L.orc_set_wall.argtypes = [vp, dp, dp]
         L.orc_lattice.argtypes = [ip, dp]
         L.orc_feq.argtypes = [C.c_double, dp, dp]
         L.orc_forcing.argtypes = [C.c_double, dp, dp, dp]
@@ -138,6 +142,10 @@ def elastance(par, t):
 
 def phi4(r):
     return lib().orc_phi4(float(r))
+
+
+def phicos(r):
+    return lib().orc_phicos(float(r))
 
 
 def filament_force(X, ds, Eh, EI):
@@ -221,6 +229,16 @@ class Oracle:
         self.L.orc_set_membrane(self.h, mesh["n_theta"], mesh["n_z"], xp, mesh["ds_theta"],
                                mesh["ds_z"], mesh["area"], k, ei, mass, alpha, beta)
 
+    def set_wall_options(self, kernel=0, external=False):
+        """Delta kernel (0 Peskin 4-point, 1 cosine) and external-solid mode."""
+        self.L.orc_set_wall_options(self.h, int(kernel), 1 if external else 0)
+
+    def set_wall(self, X, V):
+        """External-solid mode: positions at t_n and velocities (lu/step)."""
+        X, xp = _d(X)
+        V, vp = _d(V)
+        self.L.orc_set_wall(self.h, xp, vp)
+
     def lagrangian(self):
         out = [np.zeros((self.np, 3)) for _ in range(5)]
         ptrs = [o.ctypes.data_as(C.POINTER(C.c_double)) for o in out]
@@ -299,4 +317,5 @@ def from_config(cfg, pops=None, extended=False):
         o.set_rest(cfg["p_init"])
     if "mesh" in cfg:
         o.set_membrane(cfg["mesh"], cfg["k"], cfg["ei"], cfg["mass"], cfg["alpha"], cfg["beta"])
+        o.set_wall_options(cfg.get("kernel", 0), cfg.get("wall_mode", 0) == 1)
     return o

@@ -73,10 +73,12 @@ static const int EV[NQ][3] = {
     {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
 static real WT[NQ];
 static real CS2;  /* c_s^2 = 1/3 with dx/dt = 1 (Eq. tau) */
+static real PI;
 static const real RHO0 = 1;
 
 static void init_constants(void) {
   CS2 = (real)1 / 3;
+  PI = 4 * atan((real)1);
   for (int i = 0; i < NQ; ++i) {
     int n2 = EV[i][0] * EV[i][0] + EV[i][1] * EV[i][1] + EV[i][2] * EV[i][2];
     WT[i] = n2 == 0 ? (real)1 / 3 : (n2 == 1 ? (real)1 / 18 : (real)1 / 36);
@@ -147,6 +149,14 @@ static real phi4(real r) {
   return 0;
 }
 
+/* The 4-point cosine delta, (1 + cos(pi r / 2)) / 4 on |r| < 2: the variant
+ * kernel of the wall exchange (same support, partition of unity only). */
+static real phicos(real r) {
+  r = fabs(r);
+  if (r < 2) return (1 + cos(PI * r / 2)) / 4;
+  return 0;
+}
+
 double orc_smooth_S(double t, double t0, double Ls) {
   init_constants();
   return (double)smooth_S(t, t0, Ls);
@@ -159,6 +169,10 @@ void orc_elastance(const double* p, double t, double* E, double* dE) {
   *dE = (double)de;
 }
 double orc_phi4(double r) { return (double)phi4(r); }
+double orc_phicos(double r) {
+  init_constants();
+  return (double)phicos(r);
+}
 void orc_lattice(int* e, double* w) {
   init_constants();
   for (int i = 0; i < NQ; ++i) {
@@ -374,6 +388,8 @@ typedef struct {
   long np;
   real *X0, *Dn, *Dp, *slip, *Vf, *F;
   real ds_th, ds_z, area, ks, ei, mass, alpha, beta;
+  int kernel;              /* 0 Peskin 4-point, 1 cosine 4-point */
+  int external;            /* 1: the caller moves the points (no membrane forces) */
   /* waveforms */
   double* rec;
   long nrec, caprec;
@@ -461,6 +477,26 @@ int orc_set_membrane(void* ov, int nth, int nzl, const double* X0, double ds_th,
   return 0;
 }
 
+/* Wall options: delta kernel (0 Peskin 4-point, 1 cosine) and external-solid
+ * mode (1: the points are moved by the caller through orc_set_wall; between
+ * calls they keep their velocity, X^{n+1} = 2 X^n - X^{n-1}; no membrane
+ * forces act and the force on the solid is only reported). */
+void orc_set_wall_options(void* ov, int kernel, int external) {
+  orc_t* o = (orc_t*)ov;
+  o->kernel = kernel;
+  o->external = external;
+}
+
+/* Positions X (np*3) at t_n and velocities V (lattice units per step) of the
+ * points: D^n = X - X0, D^{n-1} = D^n - V. */
+void orc_set_wall(void* ov, const double* X, const double* V) {
+  orc_t* o = (orc_t*)ov;
+  for (long k = 0; k < 3 * o->np; ++k) {
+    o->Dn[k] = (real)X[k] - o->X0[k];
+    o->Dp[k] = o->Dn[k] - (real)V[k];
+  }
+}
+
 /* X, Xprev, slip integral, interpolated fluid velocity, force on the fluid:
  * each np*3 (any pointer may be NULL). */
 void orc_get_lagrangian(void* ov, double* X, double* Xp, double* slip, double* Vf, double* F) {
@@ -486,6 +522,8 @@ void orc_get_displacement(void* ov, double* Dn, double* Dp) {
 /* immersed-boundary transfer (Eqs. interpolation and EulForce)              */
 /* ------------------------------------------------------------------------ */
 
+static real delta(const orc_t* o, real r) { return o->kernel == 1 ? phicos(r) : phi4(r); }
+
 /* V(X) = sum over the 4x4x4 stencil of u(node) phi phi phi, FLUID nodes only,
  * for the point X = x0 + d; u is a dense [cell][3] field. */
 static void ib_interp_one(const orc_t* o, const real* x0, const real* d, const real* u, real V[3]) {
@@ -499,7 +537,7 @@ static void ib_interp_one(const orc_t* o, const real* x0, const real* d, const r
         if (x < 0 || y < 0 || z < 0 || x >= o->nx || y >= o->ny || z >= o->nz) continue;
         long id = cidx(o, x, y, z);
         if (o->type[id] != T_FLUID) continue;
-        real w = phi4((x - x0[0]) - d[0]) * phi4((y - x0[1]) - d[1]) * phi4((z - x0[2]) - d[2]);
+        real w = delta(o, (x - x0[0]) - d[0]) * delta(o, (y - x0[1]) - d[1]) * delta(o, (z - x0[2]) - d[2]);
         for (int k = 0; k < 3; ++k) V[k] += u[3 * id + k] * w;
       }
 }
@@ -515,7 +553,7 @@ static void ib_spread_one(const orc_t* o, const real* x0, const real* d, const r
         if (x < 0 || y < 0 || z < 0 || x >= o->nx || y >= o->ny || z >= o->nz) continue;
         long id = cidx(o, x, y, z);
         if (o->type[id] != T_FLUID) continue;
-        real w = phi4((x - x0[0]) - d[0]) * phi4((y - x0[1]) - d[1]) * phi4((z - x0[2]) - d[2]);
+        real w = delta(o, (x - x0[0]) - d[0]) * delta(o, (y - x0[1]) - d[1]) * delta(o, (z - x0[2]) - d[2]);
         for (int k = 0; k < 3; ++k) b[3 * id + k] += F[k] * area * w;
       }
 }
@@ -775,9 +813,9 @@ static void one_step(orc_t* o) {
       long k = p / o->nth;
       for (int a = 0; a < 3; ++a) {
         real dn = o->Dn[3 * p + a];
-        real dnew = (k == 0 || k == o->nzl - 1)
-                        ? dn
-                        : 2 * dn - o->Dp[3 * p + a] + (Fel[3 * p + a] - o->F[3 * p + a]) / o->mass;
+        real dnew = o->external                  ? 2 * dn - o->Dp[3 * p + a]
+                    : (k == 0 || k == o->nzl - 1) ? dn
+                    : 2 * dn - o->Dp[3 * p + a] + (Fel[3 * p + a] - o->F[3 * p + a]) / o->mass;
         o->Dp[3 * p + a] = dn;
         o->Dn[3 * p + a] = dnew;
       }

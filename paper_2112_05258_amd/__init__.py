@@ -44,7 +44,8 @@ class WallDesc(C.Structure):
     _fields_ = [("n_theta", C.c_int32), ("n_z", C.c_int32), ("X0_host", C.POINTER(C.c_double)),
                 ("ds_theta", C.c_double), ("ds_z", C.c_double), ("area", C.c_double),
                 ("k_stretch", C.c_double), ("ei_bend", C.c_double), ("mass", C.c_double),
-                ("alpha", C.c_double), ("beta", C.c_double), ("band_margin", C.c_int32)]
+                ("alpha", C.c_double), ("beta", C.c_double), ("band_margin", C.c_int32),
+                ("kernel", C.c_int32), ("mode", C.c_int32)]
 
 
 class Launch(C.Structure):
@@ -61,6 +62,7 @@ SYMBOLS = {
     "lbm_fsi_query_sizes": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(WallDesc), C.POINTER(C.c_size_t)]),
     "lbm_fsi_exchange": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(WallDesc), C.c_void_p, C.c_size_t]),
     "lbm_read_wall": (C.c_int, [C.c_void_p, C.c_int32] + [C.POINTER(C.c_double)] * 5),
+    "lbm_set_wall": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "lbm_write_populations": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_double)]),
     "lbm_set_rest": (C.c_int, [C.c_void_p, C.c_int32, C.c_double]),
     "lbm_read_populations": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_double)]),
@@ -225,19 +227,30 @@ class Solver:
         return dict(vmode=int(out[0]), pstar=out[1], S=out[2], Pv=out[3], Pw=out[4],
                     open=int(out[5]), Td=int(out[6]), vz=out[7])
 
-    def _wall_desc(self, mesh, k, ei, mass, alpha, beta, margin):
+    def _wall_desc(self, mesh, k, ei, mass, alpha, beta, margin, kernel=0, mode=0):
         X0 = np.ascontiguousarray(mesh["X0"], dtype=np.float64).reshape(-1)
         d = WallDesc(mesh["n_theta"], mesh["n_z"], _dp(X0), mesh["ds_theta"], mesh["ds_z"], mesh["area"],
-                     k, ei, mass, alpha, beta, margin)
+                     k, ei, mass, alpha, beta, margin, kernel, mode)
         return d, X0
 
-    def fsi_exchange(self, inst, mesh, k, ei, mass, alpha, beta, margin=2):
-        d, X0 = self._wall_desc(mesh, k, ei, mass, alpha, beta, margin)
+    def fsi_exchange(self, inst, mesh, k, ei, mass, alpha, beta, margin=2, kernel=0, mode=0):
+        """Attach the wall of instance inst: kernel 0 Peskin 4-point / 1
+        cosine; mode 0 built-in membrane / 1 external solid (set_wall)."""
+        d, X0 = self._wall_desc(mesh, k, ei, mass, alpha, beta, margin, kernel, mode)
         nb = C.c_size_t()
         self._check(lib().lbm_fsi_query_sizes(self.h, inst, C.byref(d), C.byref(nb)))
         buf = self.torch.empty(nb.value, dtype=self.torch.uint8, device=self.device)
         self._check(lib().lbm_fsi_exchange(self.h, inst, C.byref(d), C.c_void_p(buf.data_ptr()), nb.value))
         self.fsi[inst] = (buf, mesh["n_theta"] * mesh["n_z"])
+
+    def set_wall(self, X, V, inst=0):
+        """External solid: positions (n, 3) now and velocities (lu / step)."""
+        X = np.ascontiguousarray(X, dtype=np.float64).reshape(-1)
+        V = np.ascontiguousarray(V, dtype=np.float64).reshape(-1)
+        n = self.fsi[inst][1]
+        if X.size != 3 * n or V.size != 3 * n:
+            raise ValueError("set_wall needs (n_points, 3) positions and velocities")
+        self._check(lib().lbm_set_wall(self.h, inst, _dp(X), _dp(V)))
 
     def read_wall(self, inst=0):
         n = self.fsi[inst][1]
@@ -377,7 +390,8 @@ def solver_from_config(cfg, precision=FP32, pops=None, store_scale=0.0, wave_cap
     elif cfg.get("p_init", 0.0) != 0.0:
         s.set_rest(cfg["p_init"])
     if "mesh" in cfg:
-        s.fsi_exchange(0, cfg["mesh"], cfg["k"], cfg["ei"], cfg["mass"], cfg["alpha"], cfg["beta"])
+        s.fsi_exchange(0, cfg["mesh"], cfg["k"], cfg["ei"], cfg["mass"], cfg["alpha"], cfg["beta"],
+                       kernel=cfg.get("kernel", 0), mode=cfg.get("wall_mode", 0))
     return s
 
 
@@ -394,5 +408,6 @@ def solver_from_configs(cfgs, precision=FP32, store_scale=0.0, wave_cap=4096):
         if cfg.get("p_init", 0.0) != 0.0:
             s.set_rest(cfg["p_init"], inst=k)
         if "mesh" in cfg:
-            s.fsi_exchange(k, cfg["mesh"], cfg["k"], cfg["ei"], cfg["mass"], cfg["alpha"], cfg["beta"])
+            s.fsi_exchange(k, cfg["mesh"], cfg["k"], cfg["ei"], cfg["mass"], cfg["alpha"], cfg["beta"],
+                           kernel=cfg.get("kernel", 0), mode=cfg.get("wall_mode", 0))
     return s

@@ -641,6 +641,10 @@ bool valid_wall(const lbm_wall_desc* w, std::string& err) {
     err = "wall spacings, area and mass must be positive";
     return false;
   }
+  if (w->kernel < 0 || w->kernel > 1 || w->mode < 0 || w->mode > 1) {
+    err = "wall kernel and mode must be 0 or 1";
+    return false;
+  }
   return true;
 }
 
@@ -1071,6 +1075,8 @@ lbm_status lbm_fsi_exchange(lbm_ctx* c, int32_t k, const lbm_wall_desc* w, void*
   d.Dref = (double*)(F + f.Dref);
   d.ds_th = w->ds_theta; d.ds_z = w->ds_z; d.area = w->area;
   d.ks = w->k_stretch; d.ei = w->ei_bend; d.mass = w->mass; d.alpha = w->alpha; d.beta = w->beta;
+  d.kernel = w->kernel;
+  d.ext = w->mode;
   std::vector<double> X4((size_t)np * 4, 0.0);
   for (int64_t p = 0; p < np; ++p)
     for (int a = 0; a < 3; ++a) X4[4 * p + a] = w->X0_host[3 * p + a];
@@ -1100,6 +1106,32 @@ lbm_status lbm_fsi_exchange(lbm_ctx* c, int32_t k, const lbm_wall_desc* w, void*
   c->dev.max_band = maxb;
   c->dev.max_np = (int32_t)maxp;
   return build_groups(c, false);
+}
+
+lbm_status lbm_set_wall(lbm_ctx* c, int32_t k, const double* X, const double* V) {
+  if (!c || k < 0 || k >= c->n || !X || !V) return LBM_E_INVAL;
+  if (!c->wall[k].on || !c->inst[k].ext) return fail(c, LBM_E_INVAL, "no external-solid wall at this instance");
+  const InstDesc& d = c->inst[k];
+  Wall& W = c->wall[k];
+  const int64_t np = d.np;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  // D^n = X - X0 at the current parity, D^{n-1} = D^n - V
+  std::vector<double> Dn((size_t)np * 4, 0.0), Dm((size_t)np * 4, 0.0), Dr((size_t)np * 4);
+  HIPCHK(c, hipMemcpy(Dr.data(), d.Dref, (size_t)np * 32, hipMemcpyDeviceToHost));
+  double moved = 0.0;
+  for (int64_t p = 0; p < np; ++p)
+    for (int a = 0; a < 3; ++a) {
+      const double dn = X[3 * p + a] - W.X0[3 * p + a];
+      Dn[4 * p + a] = dn;
+      Dm[4 * p + a] = dn - V[3 * p + a];
+      const double m = std::fabs(dn - Dr[4 * p + a]);
+      moved = m > moved || !(m == m) ? m : moved;   // NaN propagates to the rebuild, which reports it
+    }
+  const int par = (int)(c->step & 1);
+  HIPCHK(c, hipMemcpy(d.Xab[par], Dn.data(), (size_t)np * 32, hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(d.Xab[par ^ 1], Dm.data(), (size_t)np * 32, hipMemcpyHostToDevice));
+  if (!(moved < (double)(W.margin - 1))) return rebuild_bands(c);
+  return LBM_OK;
 }
 
 lbm_status lbm_read_wall(lbm_ctx* c, int32_t k, double* X, double* Xp, double* slip, double* Vf, double* Fp) {

@@ -62,6 +62,8 @@ struct InstDesc {
   double dref;             // 3 p_ref: stored populations are g - w_i dref
   // wall (has_wall = 0: none)
   int32_t has_wall, nth, nzl, nband;
+  int32_t kernel;          // delta kernel: 0 Peskin 4-point, 1 cosine 4-point
+  int32_t ext;             // 1: external solid (points moved by the caller)
   int64_t np;
   void* u4;                // R4 per local cell: unforced velocity (band cells)
   void* b4;                // R4 per local cell: IB force density (band cells)

@@ -593,6 +593,14 @@ __device__ __forceinline__ R phi4(R r) {
   return r <= R(1) ? a : (r < R(2) ? b : R(0));
 }
 
+// the 4-point cosine delta (1 + cos(pi r / 2)) / 4 on |r| < 2 (variant kernel)
+template <class R>
+__device__ __forceinline__ R phicos(R r) {
+  r = fabs(r);
+  const R v = R(0.25) * (R(1) + cos(R(1.5707963267948966) * r));
+  return r < R(2) ? v : R(0);
+}
+
 __device__ __forceinline__ double3 ld3(const double* p, int64_t k) {
   const double4 v = ((const double4*)p)[k];
   return make_double3(v.x, v.y, v.z);
@@ -707,11 +715,14 @@ __global__ __launch_bounds__(WBLOCK) void k_wall(Dev d, const int32_t* __restric
     }
   }
   R wx[4], wy[4], wz[4];
+  const bool cosk = I.kernel == 1;   // uniform over the launch's instance
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
-    wx[a] = phi4<R>((R)(((double)(bx0 + a) - X0.x) - D.x));
-    wy[a] = phi4<R>((R)(((double)(by0 + a) - X0.y) - D.y));
-    wz[a] = phi4<R>((R)(((double)(bz0 + a) - X0.z) - D.z));
+    const R rx = (R)(((double)(bx0 + a) - X0.x) - D.x), ry = (R)(((double)(by0 + a) - X0.y) - D.y),
+            rz = (R)(((double)(bz0 + a) - X0.z) - D.z);
+    wx[a] = cosk ? phicos<R>(rx) : phi4<R>(rx);
+    wy[a] = cosk ? phicos<R>(ry) : phi4<R>(ry);
+    wz[a] = cosk ? phicos<R>(rz) : phi4<R>(rz);
   }
   __syncthreads();
   if (threadIdx.x == 0 && smove != 0u) atomicMax(d.moved, smove);
@@ -956,9 +967,14 @@ __global__ __launch_bounds__(WBLOCK) void k_membrane(Dev d, int parity) {
     f.z -= I.ei * (kp.z - 2.0 * kc.z + km.z) / dz2;
   }
 
-  // central difference in time; the wall receives -F
+  // central difference in time; the wall receives -F.  An external solid
+  // (moved by the caller) keeps its velocity between the caller's updates.
   double4 out;
-  if (interior) {
+  if (I.ext) {
+    out.x = 2.0 * D.x - Dm.x;
+    out.y = 2.0 * D.y - Dm.y;
+    out.z = 2.0 * D.z - Dm.z;
+  } else if (interior) {
     out.x = 2.0 * D.x - Dm.x + (f.x - Fx) / I.mass;
     out.y = 2.0 * D.y - Dm.y + (f.y - Fy) / I.mass;
     out.z = 2.0 * D.z - Dm.z + (f.z - Fz) / I.mass;

@@ -142,6 +142,59 @@ def test_small_elastic_tube(oracle_mod, amd, precision, tol):
     assert e_x <= tol * 10 and e_f <= tol * 10
 
 
+@pytest.mark.parametrize("precision,tol", [("FP64", 1e-12), ("FP32", 1e-5)])
+def test_cosine_kernel_small_elastic_tube(oracle_mod, amd, precision, tol):
+    """The variant delta kernel (1 + cos(pi r / 2)) / 4 in interpolation and
+    spreading: the small elastic tube against the oracle's kernel 1."""
+    c = L.small_fsi()
+    c["kernel"] = 1
+    o, s = _run_pair(oracle_mod, amd, c, 120, getattr(amd, precision))
+    _compare(o, s, c["flags"], tol)
+    Do, _ = o.displacement()
+    e_x = rel_l2(s.read_wall()["X"] - c["mesh"]["X0"], Do)
+    e_f = rel_l2(s.read_wall()["F"], o.lagrangian()["F"])
+    print({"wall_X": f"{e_x:.2e}", "wall_F": f"{e_f:.2e}"}, flush=True)
+    assert e_x <= tol * 10 and e_f <= tol * 10
+
+
+@pytest.mark.parametrize("precision,tol", [("FP64", 1e-12), ("FP32", 1e-5)])
+def test_external_solid_prescribed_motion(oracle_mod, amd, precision, tol):
+    """External-solid mode: the caller breathes the tube radially (amplitude
+    0.3 lu, period 60 steps), handing positions and velocities over every
+    third step (ballistic motion in between); the library interpolates,
+    forms the penalty force and spreads it.  Fields, waveforms, positions
+    and the force on the fluid against the oracle's external mode."""
+    c = L.small_fsi()
+    c["wall_mode"] = 1
+    o = oracle_mod.from_config(c, extended=(precision == "FP64"))
+    s = amd.solver_from_config(c, precision=getattr(amd, precision))
+    X0 = c["mesh"]["X0"]
+    rad = X0 - np.array([(c["nx"] - 1) / 2, (c["ny"] - 1) / 2, 0.0])
+    rad[:, 2] = 0.0
+    rad /= np.linalg.norm(rad, axis=1, keepdims=True)
+    w = 2 * np.pi / 60
+    for n in range(0, 90, 3):
+        X = X0 + 0.3 * np.sin(w * n) * rad
+        V = 0.3 * w * np.cos(w * n) * rad
+        o.set_wall(X, V)
+        s.set_wall(X, V)
+        o.step(3)
+        s.step(3)
+    s.sync()
+    _compare(o, s, c["flags"], tol)
+    lo, ls = o.lagrangian(), s.read_wall()
+    e_x = rel_l2(ls["X"] - X0, lo["X"] - X0)
+    e_f = rel_l2(ls["F"], lo["F"])
+    print({"wall_X": f"{e_x:.2e}", "wall_F": f"{e_f:.2e}"}, flush=True)
+    assert e_x <= tol and e_f <= tol * 10
+    with pytest.raises(amd.LbmError):   # a built-in membrane takes no positions
+        t = amd.solver_from_config(L.small_fsi(), precision=amd.FP32)
+        try:
+            t.set_wall(X, V)
+        finally:
+            t.close()
+
+
 def test_band_follows_a_moving_wall(oracle_mod, amd):
     """The wall moves 2.9 lu outwards: with the band fixed where it was
     built the stencils leave it (LBM_E_BAND); with the periodic motion test

@@ -222,6 +222,24 @@ def test_peskin_kernel_moments(oracle_mod):
     assert oracle_mod.phi4(0.0) == 0.5 and oracle_mod.phi4(2.0) == 0.0 and oracle_mod.phi4(2.5) == 0.0
 
 
+def test_cosine_kernel_values_and_moments(oracle_mod):
+    """The variant kernel (1 + cos(pi r / 2)) / 4: closed values, even,
+    support |r| < 2, partition of unity (four cosines a quarter period
+    apart sum to zero) and sum of squares 3/8 (cos^2 + sin^2 in pairs)."""
+    phi = oracle_mod.phicos
+    assert phi(0.0) == 0.5 and phi(2.0) == 0.0 and phi(-2.0) == 0.0 and phi(3.1) == 0.0
+    assert abs(phi(1.0) - 0.25) < 1e-16 and abs(phi(0.5) - (2 + math.sqrt(2)) / 8) < 1e-16
+    rng = np.random.default_rng(6)
+    for r in rng.random(50) * 4.0 - 2.0:
+        js = np.arange(-4, 5)
+        ph = np.array([phi(r - j) for j in js])
+        assert phi(r) == phi(-r)
+        assert abs(ph.sum() - 1.0) < 1e-15
+        assert abs((ph * ph).sum() - 3.0 / 8.0) < 1e-15
+    xs = np.linspace(0, 2, 41)
+    assert np.all(np.diff([phi(x) for x in xs]) < 0)
+
+
 def _box_oracle(oracle_mod, n=16):
     fl = np.zeros((n, n, n), np.uint8)
     return oracle_mod.Oracle(fl, 0.8), n
@@ -250,6 +268,58 @@ def test_ib_spread_adjoint_and_conservative(oracle_mod):
     V = o.ib_interp(X, u)
     assert abs((b * u).sum() - area * (F * V).sum()) < 1e-12
     assert np.abs(b.sum(0) - area * F.sum(0)).max() < 1e-13
+
+
+def test_ib_transfer_with_the_cosine_kernel(oracle_mod):
+    """Kernel 1 in the wall exchange: a unit spike interpolates to the
+    product of the kernel's values, constants interpolate exactly, and the
+    spreading stays the adjoint of the interpolation and conserves force;
+    a linear field is no longer reproduced (no first-moment condition),
+    which tells the variant apart from the default kernel."""
+    o, n = _box_oracle(oracle_mod)
+    o.set_wall_options(kernel=1)
+    X = L.random_points(30, [3, 3, 3], [12, 12, 12], seed=8)
+    node = np.floor(X[0]).astype(int)
+    u = np.zeros((n, n, n, 3))
+    u[node[2], node[1], node[0], 0] = 1.0
+    V = o.ib_interp(X[:1], u.reshape(-1, 3))
+    d = node - X[0]
+    assert abs(V[0, 0] - oracle_mod.phicos(d[0]) * oracle_mod.phicos(d[1]) * oracle_mod.phicos(d[2])) < 1e-15
+    c = np.array([0.3, -0.1, 0.2])
+    assert np.abs(o.ib_interp(X, np.tile(c, (n ** 3, 1))) - c).max() < 1e-14
+    rng = np.random.default_rng(9)
+    F = rng.standard_normal((30, 3))
+    u = rng.standard_normal((n ** 3, 3))
+    b = o.ib_spread(X, F, 0.4)
+    assert abs((b * u).sum() - 0.4 * (F * o.ib_interp(X, u)).sum()) < 1e-12
+    assert np.abs(b.sum(0) - 0.4 * F.sum(0)).max() < 1e-13
+    z, y, x = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    lin = np.stack([x, y, z], -1).astype(float).reshape(-1, 3) * 0.01
+    assert np.abs(o.ib_interp(X, lin) - X * 0.01).max() > 1e-5
+
+
+def test_external_solid_moves_ballistically_and_drags_the_fluid(oracle_mod):
+    """External-solid mode: between updates the points keep their velocity
+    (D after k steps = D + k V, with no membrane forces), and a wall
+    translating along +z pushes the fluid along +z (force on the fluid
+    parallel to the wall's velocity for alpha, beta < 0)."""
+    c = L.small_fsi()
+    c["wall_mode"] = 1
+    o = oracle_mod.from_config(c)
+    X0 = c["mesh"]["X0"]
+    V = np.zeros_like(X0)
+    V[:, 2] = 2e-3
+    X = X0 + 0.1 * V
+    o.set_wall(X, V)
+    k = 25
+    o.step(k)
+    Dn, Dp = o.displacement()
+    assert np.abs(Dn - (X - X0 + k * V)).max() < 1e-13
+    assert np.abs((Dn - Dp) - V).max() < 1e-13
+    p, u = o.fields()
+    fl = c["flags"] == L.FLUID
+    assert u[fl][:, 2].sum() > 0
+    assert o.lagrangian()["F"][:, 2].mean() > 0
 
 
 # ----------------------------------------------------------------------------
