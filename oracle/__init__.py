@@ -77,6 +77,7 @@ def lib(extended=False):
         L.orc_phicos.restype = C.c_double
         L.orc_phicos.argtypes = [C.c_double]
         L.orc_set_wall_options.argtypes = [vp, C.c_int, C.c_int]
+        L.orc_set_nee_variant.argtypes = [vp, C.c_int]
         L.orc_set_wall.argtypes = [vp, dp, dp]
         L.orc_lattice.argtypes = [ip, dp]
         L.orc_feq.argtypes = [C.c_double, dp, dp]
@@ -229,6 +230,10 @@ class Oracle:
         self.L.orc_set_membrane(self.h, mesh["n_theta"], mesh["n_z"], xp, mesh["ds_theta"],
                                mesh["ds_z"], mesh["area"], k, ei, mass, alpha, beta)
 
+    def set_nee_variant(self, v):
+        """0: x_f = x + e_i (literal, default); 1: the ghost's normal neighbour."""
+        self.L.orc_set_nee_variant(self.h, int(v))
+
     def set_wall_options(self, kernel=0, external=False):
         """Delta kernel (0 Peskin 4-point, 1 cosine) and external-solid mode."""
         self.L.orc_set_wall_options(self.h, int(kernel), 1 if external else 0)
@@ -305,6 +310,7 @@ def num_threads():
 def from_config(cfg, pops=None, extended=False):
     """Oracle set up from one of the lbm_inputs workload dicts."""
     o = Oracle(cfg["flags"], cfg["tau"], extended=extended)
+    o.set_nee_variant(cfg.get("nee_variant", 0))
     if "inlet" in cfg:
         o.set_bc(0, cfg["inlet"][0], cfg["inlet"][1], cfg.get("inlet_state", ()))
     if "outlet" in cfg:

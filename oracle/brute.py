@@ -156,6 +156,7 @@ class Brute:
         self.mesh = None
         self.n = 0
         self.records = []
+        self.nee_normal = False    # True: Eq. Non-equilibrium3 at the ghost's normal neighbour
 
     def set_pops(self, g):
         g = np.asarray(g).reshape(self.nz, self.ny, self.nx, 19)
@@ -213,6 +214,19 @@ class Brute:
         F[1:-1] -= m["ei"] * (kz[2:] - 2 * kz[1:-1] + kz[:-2]) / m["ds_z"] ** 2
         return F.reshape(-1, 3)
 
+    def _normal_neighbours(self):
+        """Flat index of the cell one step inwards from each cell along the
+        normal of the box face it lies on (z faces before x before y), -1
+        for cells on no face."""
+        z, y, x = np.meshgrid(np.arange(self.nz), np.arange(self.ny), np.arange(self.nx), indexing="ij")
+        dz = np.where(z == 0, 1, np.where(z == self.nz - 1, -1, 0))
+        onz = dz != 0
+        dx = np.where(onz, 0, np.where(x == 0, 1, np.where(x == self.nx - 1, -1, 0)))
+        onx = dx != 0
+        dy = np.where(onz | onx, 0, np.where(y == 0, 1, np.where(y == self.ny - 1, -1, 0)))
+        q = ((z + dz) * self.ny + (y + dy)) * self.nx + (x + dx)
+        return np.where((dx != 0) | (dy != 0) | (dz != 0), q, -1)
+
     # ------------------------------------------------------------------
     def step(self):
         t, tau, n = self.t, self.tau, self.n
@@ -258,31 +272,41 @@ class Brute:
         fs = np.where(fl[None], fs, 0.0)
 
         fn = np.zeros_like(f)
+        idx = np.arange(t.size).reshape(t.shape)
+        nn = self._normal_neighbours().ravel() if self.nee_normal else None
         for i in range(19):
             ex, ey, ez = E[i]
             pulled = np.roll(fs[i], shift=(ez, ey, ex), axis=(0, 1, 2))   # fs_i(x - e_i)
             src = np.roll(t, shift=(ez, ey, ex), axis=(0, 1, 2))
             val = np.where(src == FLUID, pulled, 0.0)
             val = np.where(src == SOLID, fs[OPP[i]], val)
+            # x_f: the receiving cell itself, or the ghost's normal neighbour
+            xf = idx
+            if nn is not None:
+                q = nn[np.roll(idx, shift=(ez, ey, ex), axis=(0, 1, 2))]
+                ok = (q >= 0) & (t.ravel()[np.maximum(q, 0)] == FLUID)
+                xf = np.where(ok, q, idx)
+            at = lambda a: a.ravel()[xf]                                   # noqa: E731
+            vf = v.reshape(-1, 3)[xf]
             for code, bc in ((INLET, self.bc[0]), (OUTLET, self.bc[1]), (EXTP, self.bc[2])):
                 sel = src == code
                 if not sel.any():
                     continue
                 if bc.mode == 0:
                     Pst = np.full(P.shape, CS2 + bc.pstar)
-                    vst = v
+                    vst = vf
                 else:
-                    Pst = P
+                    Pst = at(P)
                     if bc.kind == 3:
-                        vst = np.zeros_like(v)
-                        vst[1] = self.v0 * bc.S
+                        v0 = self.v0.reshape(-1, 3)[xf % (self.nx * self.ny)]
+                        vst = v0 * bc.S
                     elif bc.kind == 2:
-                        vst = v.copy()
+                        vst = vf.copy()
                         vst[..., 2] += bc.vc
                     else:
                         vst = np.zeros_like(v)
                         vst[..., 2] = bc.vc
-                nee = f_eq(Pst, vst)[i] + (1.0 - 1.0 / tau) * (f[i] - feq[i]) + Fi[i]
+                nee = f_eq(Pst, vst)[i] + (1.0 - 1.0 / tau) * (at(f[i]) - at(feq[i])) + at(Fi[i])
                 val = np.where(sel, nee, val)
             fn[i] = np.where(fl, val, 0.0)
         self.f = fn

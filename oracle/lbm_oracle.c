@@ -388,6 +388,7 @@ typedef struct {
   long np;
   real *X0, *Dn, *Dp, *slip, *Vf, *F;
   real ds_th, ds_z, area, ks, ei, mass, alpha, beta;
+  int nee_normal;          /* 1: NEE from the ghost's normal neighbour */
   int kernel;              /* 0 Peskin 4-point, 1 cosine 4-point */
   int external;            /* 1: the caller moves the points (no membrane forces) */
   /* waveforms */
@@ -399,6 +400,26 @@ typedef struct {
 static long cidx(const orc_t* o, int x, int y, int z) {
   return (long)x + (long)o->nx * ((long)y + (long)o->ny * z);
 }
+
+/* The neighbour of ghost cell s one cell inwards along the normal of the box
+ * face it lies on (z faces first, then x, then y): 0 for a cell on no face. */
+static int normal_neighbour(const orc_t* o, long s, long* q) {
+  const int x = (int)(s % o->nx), y = (int)((s / o->nx) % o->ny), z = (int)(s / ((long)o->nx * o->ny));
+  int dx = 0, dy = 0, dz = 0;
+  if (z == 0) dz = 1;
+  else if (z == o->nz - 1) dz = -1;
+  else if (x == 0) dx = 1;
+  else if (x == o->nx - 1) dx = -1;
+  else if (y == 0) dy = 1;
+  else if (y == o->ny - 1) dy = -1;
+  else return 0;
+  *q = cidx(o, x + dx, y + dy, z + dz);
+  return 1;
+}
+
+/* Non-equilibrium extrapolation variant: 0 literal x_f = x + e_i (default),
+ * 1 the ghost's normal neighbour (Guo, Zheng & Shi 2002). */
+void orc_set_nee_variant(void* ov, int v) { ((orc_t*)ov)->nee_normal = v == 1; }
 
 void* orc_create(int nx, int ny, int nz, double tau, const uint8_t* flags, int px, int py, int pz) {
   init_constants();
@@ -778,18 +799,26 @@ static void one_step(orc_t* o) {
       } else if (t == T_SOLID) {
         out = o->gs[c * NQ + opp(i)];
       } else {
-        /* Eq. Non-equilibrium3 with x_f = c: boundary equilibrium at (P*, v*)
-         * plus the relaxed non-equilibrium part and forcing of x_f. */
+        /* Eq. Non-equilibrium3: boundary equilibrium at (P*, v*) plus the
+         * relaxed non-equilibrium part and forcing of x_f; x_f = c (the
+         * literal x + e_i), or in the normal-neighbour variant the fluid
+         * cell next to the ghost along its plane's inward normal. */
+        long xf = c;
+        if (o->nee_normal) {
+          long q;
+          if (normal_neighbour(o, s, &q) && o->type[q] == T_FLUID) xf = q;
+        }
+        const int xfx = (int)(xf % nx), xfy = (int)((xf / nx) % ny);
         const orc_bc* bc = &o->bc[t == T_INLET ? 0 : (t == T_OUTLET ? 1 : 2)];
         real Dst, vst[3]; /* P* / c_s^2 - 1 and v* */
-        const real* vf = &o->v[3 * c];
+        const real* vf = &o->v[3 * xf];
         if (bc->vmode == 0) { /* pressure type: (P_0D, v(x_f)) */
           Dst = bc->pstar / CS2;
           for (int a = 0; a < 3; ++a) vst[a] = vf[a];
         } else { /* velocity type: (P(x_f), v_0D) */
-          Dst = o->D[c];
+          Dst = o->D[xf];
           if (bc->kind == K_LV) { /* Eq. vnew: v0(x_f, T_d) S(t_{n+1}) */
-            const real* w0 = &o->v0[3 * ((long)x + (long)nx * y)];
+            const real* w0 = &o->v0[3 * ((long)xfx + (long)nx * xfy)];
             for (int a = 0; a < 3; ++a) vst[a] = w0[a] * bc->S;
           } else if (bc->kind == K_WK3) {
             vst[0] = vf[0]; vst[1] = vf[1]; vst[2] = vf[2] + bc->vconst;
@@ -797,8 +826,8 @@ static void one_step(orc_t* o) {
             vst[0] = 0; vst[1] = 0; vst[2] = bc->vconst;
           }
         }
-        out = geq(i, Dst, vst) + (1 - 1 / tau) * (o->g[c * NQ + i] - geq(i, o->D[c], vf)) +
-              forcing(i, tau, vf, &o->b[3 * c]);
+        out = geq(i, Dst, vst) + (1 - 1 / tau) * (o->g[xf * NQ + i] - geq(i, o->D[xf], vf)) +
+              forcing(i, tau, vf, &o->b[3 * xf]);
       }
       o->gn[c * NQ + i] = out;
     }

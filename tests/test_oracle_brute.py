@@ -94,3 +94,43 @@ def test_immersed_membrane(oracle_mod):
     lo, lb = o.lagrangian(), b.mesh
     assert np.abs(lo["X"] - lb["X"]).max() < 1e-14
     assert np.abs(lo["slip"] - lb["slip"]).max() < 1e-14     # V_s = X - Xprev at |X| ~ 10
+
+
+def _normal(o, b):
+    o.set_nee_variant(1)
+    b.nee_normal = True
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_normal_neighbour_extrapolation(oracle_mod, seed):
+    """The normal-neighbour variant of Eq. Non-equilibrium3 (x_f one cell in
+    from the ghost along its plane's normal) with pressure- and
+    velocity-type boundaries on random geometry, where some ghosts have a
+    solid normal neighbour (the receiving cell stands in for it)."""
+    fl = L.random_flags(7, 6, 9, seed=seed)
+    bcs = [(L.BC_PRESSURE_CONST, [2e-4], ()),
+           (L.BC_WINDKESSEL3, [0.05, 50.0, 1.0, 1.0], [2e-4]),
+           (L.BC_VELOCITY_CONST, [-1e-3], ())]
+    o, b = _pair(oracle_mod, fl, 0.7 + 0.1 * seed, seed + 50, bcs)
+    _normal(o, b)
+    _compare(o, b, 6)
+
+
+def test_normal_neighbour_lv_valve_cycle(oracle_mod):
+    """LV inlet with the normal-neighbour variant: the snapshot and the
+    smoothed closure read the normal neighbour's record."""
+    fl = L.tube_flags(9, 9, 10, 4.0, 4.0, 3.2)
+    sc = L.scales(sigma_t=400.0, sigma_V=40.0, sigma_P=2.5e-5)
+    par = L.lv_params(2.0, 0.06, 75.0, 8.0, 0.01, sc)
+    bcs = [(L.BC_LV_ELASTANCE, par, ()),
+           (L.BC_WINDKESSEL3, L.wk_params(0.05, 1.5, 1.0, sc), [80 * 2.5e-5]),
+           (L.BC_PRESSURE_CONST, [0.0], ())]
+    o, b = _pair(oracle_mod, fl, 0.8, 31, bcs, amp=0.0)
+    _normal(o, b)
+    for _ in range(150):
+        o.step(1)
+        b.step()
+    w = o.waveforms()
+    assert w[:, 11].max() == 1.0 and w[-1, 11] == 0.0
+    assert np.abs(o.get_pops() - b.pops()).max() <= ATOL
+    assert np.abs(w[:, :5] - np.array(b.records)).max() <= ATOL * 100
