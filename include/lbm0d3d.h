@@ -105,6 +105,14 @@ typedef struct {
                             change of variables (f_eq is linear in P) that keeps
                             the stored values small where the pressure sits near
                             p_ref; every value handed in or out is still g = f - w */
+  int32_t nee_variant;   /* non-equilibrium extrapolation at 0D-coupled ghosts
+                            (Eq. Non-equilibrium3): 0 takes x_f as the fluid
+                            cell the ghost's population streams into (x_f = x
+                            + e_i, the paper's statement); 1 takes x_f as the
+                            ghost's neighbour along the inward normal of its box
+                            face where that cell is FLUID (Guo, Zheng & Shi
+                            2002), else as in 0.  Both agree on the populations
+                            along the face normal. */
 } lbm_config;
 
 typedef struct {

@@ -32,7 +32,8 @@ class LbmError(RuntimeError):
 class Config(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("tau", C.c_double),
                 ("precision", C.c_int32), ("store_scale", C.c_double),
-                ("flags", C.POINTER(C.c_uint8)), ("wave_cap", C.c_int32), ("p_ref", C.c_double)]
+                ("flags", C.POINTER(C.c_uint8)), ("wave_cap", C.c_int32), ("p_ref", C.c_double),
+                ("nee_variant", C.c_int32)]
 
 
 class Buffers(C.Structure):
@@ -163,7 +164,7 @@ class Solver:
         for k, b in enumerate(boxes):
             cfgs[k] = Config(b["nx"], b["ny"], b["nz"], float(b["tau"]), precision, float(store_scale),
                              self._flags[k].ctypes.data_as(C.POINTER(C.c_uint8)), wave_cap,
-                             float(b.get("p_ref", 0.0)))
+                             float(b.get("p_ref", 0.0)), int(b.get("nee_variant", 0)))
         self._cfgs = cfgs
         pb, wb = C.c_size_t(), C.c_size_t()
         self._check(lib().lbm_query_sizes(cfgs, self.n, C.byref(pb), C.byref(wb)), None)
@@ -380,7 +381,7 @@ def solver_from_config(cfg, precision=FP32, pops=None, store_scale=0.0, wave_cap
     """Solver for one workload dict (see lbm_inputs): box, 0D models, initial
     state and wall are passed through the C interface unchanged."""
     s = Solver(dict(nx=cfg["nx"], ny=cfg["ny"], nz=cfg["nz"], tau=cfg["tau"], flags=cfg["flags"],
-                    p_ref=cfg.get("p_ref", 0.0)),
+                    p_ref=cfg.get("p_ref", 0.0), nee_variant=cfg.get("nee_variant", 0)),
                precision=precision, store_scale=store_scale, wave_cap=wave_cap)
     for b, key in ((0, "inlet"), (1, "outlet"), (2, "exterior")):
         if key in cfg:
@@ -399,7 +400,7 @@ def solver_from_configs(cfgs, precision=FP32, store_scale=0.0, wave_cap=4096):
     """One batched context over several workload dicts (the ensemble): one
     launch per kernel per step advances every instance."""
     boxes = [dict(nx=c["nx"], ny=c["ny"], nz=c["nz"], tau=c["tau"], flags=c["flags"],
-                  p_ref=c.get("p_ref", 0.0)) for c in cfgs]
+                  p_ref=c.get("p_ref", 0.0), nee_variant=c.get("nee_variant", 0)) for c in cfgs]
     s = Solver(boxes, precision=precision, store_scale=store_scale, wave_cap=wave_cap)
     for k, cfg in enumerate(cfgs):
         for b, key in ((0, "inlet"), (1, "outlet"), (2, "exterior")):

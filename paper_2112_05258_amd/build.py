@@ -31,13 +31,28 @@ PROBE = os.path.join(HERE, "probe_stream")
 
 
 def build(verbose=False):
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
+    # one object per source, compiled side by side, then one link
+    inc = ["-I", os.path.join(HERE, "..", "include")]
+    cflags = [f for f in FLAGS if f != "-shared"]
+    objs, procs = [], []
+    for src in SOURCES:
+        obj = os.path.join(HERE, "_obj_" + os.path.splitext(src)[0] + ".o")
+        cmd = [HIPCC] + cflags + inc + ["-c", "-o", obj, os.path.join(CSRC, src)]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        objs.append(obj)
+        procs.append((cmd, subprocess.Popen(cmd)))
+    failed = [cmd for cmd, p in procs if p.wait() != 0]
+    if failed:
+        raise subprocess.CalledProcessError(1, failed[0])
     tmp = LIB + ".tmp"
-    cmd = [HIPCC] + FLAGS + ["-I", os.path.join(HERE, "..", "include"), "-o", tmp] + srcs
+    cmd = [HIPCC] + FLAGS + ["-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
+    for obj in objs:
+        os.remove(obj)
     # the benchmark's access-pattern probe (a standalone program)
     pflags = [f for f in FLAGS if f not in ("-fPIC", "-shared", "-munsafe-fp-atomics")]
     cmd = [HIPCC] + pflags + ["-o", PROBE + ".tmp", os.path.join(CSRC, "probe_stream.hip")]

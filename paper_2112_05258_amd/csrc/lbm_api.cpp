@@ -71,6 +71,7 @@ struct Geometry {
 bool build_geometry(const lbm_config& c, Geometry& g, std::string& err) {
   if (c.nx < 3 || c.ny < 3 || c.nz < 3) { err = "box dimensions must be >= 3"; return false; }
   if (!(c.tau > 0.5)) { err = "tau must be > 0.5"; return false; }
+  if (c.nee_variant != 0 && c.nee_variant != 1) { err = "nee_variant must be 0 or 1"; return false; }
   if (!c.flags) { err = "flags is NULL"; return false; }
   g.nx = c.nx; g.ny = c.ny; g.nz = c.nz;
   g.ncell = (int64_t)c.nx * c.ny * c.nz;
@@ -710,6 +711,7 @@ lbm_status lbm_init(const lbm_config* cfgs, int32_t n, const lbm_buffers* buf, v
   for (int k = 0; k < n; ++k) {
     c->inst[k].tau = cfgs[k].tau;
     c->inst[k].omega = 1.0 / cfgs[k].tau;
+    c->inst[k].nee = cfgs[k].nee_variant;
     c->inst[k].dref = 3.0 * cfgs[k].p_ref;
   }
   if (buf->pop_bytes < (size_t)NQ * c->L.NT * elem_size(c->prec) || buf->work_bytes < c->L.total) {
@@ -741,6 +743,7 @@ lbm_status lbm_init(const lbm_config* cfgs, int32_t n, const lbm_buffers* buf, v
   d.moved = (uint32_t*)(c->work + c->L.moved);
   d.walls = (const int32_t*)(c->work + c->L.walls);
   d.nwall = 0;
+  for (int k = 0; k < n; ++k) d.any_nee |= cfgs[k].nee_variant;
 
   std::vector<uint8_t> flags(c->L.NT);
   for (int k = 0; k < n; ++k)

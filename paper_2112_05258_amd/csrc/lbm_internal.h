@@ -64,6 +64,7 @@ struct InstDesc {
   int32_t has_wall, nth, nzl, nband;
   int32_t kernel;          // delta kernel: 0 Peskin 4-point, 1 cosine 4-point
   int32_t ext;             // 1: external solid (points moved by the caller)
+  int32_t nee;             // 1: normal-neighbour x_f in the extrapolation at ghosts
   int64_t np;
   void* u4;                // R4 per local cell: unforced velocity (band cells)
   void* b4;                // R4 per local cell: IB force density (band cells)
@@ -107,6 +108,8 @@ struct Dev {
   uint32_t* moved;                 // max wall motion since the band was built (float bits)
   const int32_t* walls;            // instance ids with a wall
   int32_t max_band, max_np;
+  int32_t any_nee;                 // some instance uses the normal-neighbour extrapolation
+  int32_t pad_;
 };
 
 // collide tile: BS * CPT consecutive local cells of one instance

@@ -31,6 +31,12 @@ __device__ constexpr int EY[NQ] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 
 __device__ constexpr int EZ[NQ] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
 __device__ constexpr int OPP[NQ] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
 
+// face direction along axis a (0 x, 1 y, 2 z) with sign sg, and the two face
+// directions an edge direction (i >= 7) is the sum of
+__device__ constexpr int face_dir(int a, int sg) { return 1 + 2 * a + (sg < 0 ? 1 : 0); }
+__device__ constexpr int edge_a(int i) { return EX[i] != 0 ? face_dir(0, EX[i]) : face_dir(1, EY[i]); }
+__device__ constexpr int edge_b(int i) { return EZ[i] != 0 ? face_dir(2, EZ[i]) : face_dir(1, EY[i]); }
+
 template <class R>
 __device__ __forceinline__ R wgt(int i) {
   return i == 0 ? R(1) / R(3) : (i < 7 ? R(1) / R(18) : R(1) / R(36));
@@ -399,7 +405,7 @@ __device__ __forceinline__ R relax(int i, const Mom<R>& m, R g, R om) {
 // 0D-coupled ghost (per-direction source and target types are looked up);
 // BAND: the wave holds a cell of the wall's band (the IB force enters, zero
 // at the wave's other cells).  The plain body has neither.
-template <class S, bool ODD, bool NEAR, bool BAND>
+template <class S, bool ODD, bool NEAR, bool BAND, bool NEE>
 __device__ __forceinline__ void collide_body(const Dev& d, const int inst, const InstDesc& I, const int64_t local,
                                              const uint32_t c, const uint8_t fl) {
   using R = typename Store<S>::R;
@@ -442,13 +448,46 @@ __device__ __forceinline__ void collide_body(const Dev& d, const int inst, const
   const Mom<R> m = moments<R, BAND>(g, bx, by, bz);
   const R om = R(I.omega);
 
-  // collision and streaming, direction by direction.  At a cell next to a
-  // 0D-coupled ghost x = c - e_i, the ghost hands c the value
-  // g*_i(c) + g_eq(P*, v*) - g_eq(P(c), v(c)) (Eq. Non-equilibrium3,
-  // x_f = c); it is formed right after g*_i, so that the post-collision
-  // values need not stay live (the two stores go to different slots).
+  // collision and streaming, direction by direction.  A 0D-coupled ghost
+  // x = c - e_i hands the fluid cell x + e_i the value
+  // g*_i(x_f) + g_eq(P*, v*) - g_eq(P(x_f), v(x_f)) (Eq. Non-equilibrium3).
+  // Literal reading: x_f = x + e_i, this cell.  Normal-neighbour reading
+  // (I.nee): x_f is the ghost's neighbour along the inward normal of its
+  // face.  Ghosts sit on the box faces and fluid cells inside, so the normal
+  // neighbour of the ghost c - e_i is c itself for a face direction, and for
+  // an edge direction e_i = e_a + e_b it is c - e_b or c - e_a, whichever is
+  // FLUID (at most one is: the other lies on the ghost's face); none being
+  // FLUID falls back to x_f = c.  That cell forms the value from its own
+  // moments and stores it into the receiver's slot (written by no one else
+  // in the step: the ghost neither reads nor writes), and the receiver skips
+  // it.  Each value is formed right after g*_i, so that the post-collision
+  // values need not stay live.
   R4 v0 = {0, 0, 0, 0};
   bool have_v0 = false;
+  auto ghost_value = [&](int i, uint32_t tg, R v) -> R {
+    const BcDev& B = d.bc[3 * inst + (tg - T_INLET)];
+    if (B.vmode == 0) return v + wgt<R>(i) * (R(B.dstar - I.dref) - m.dl);
+    R sx, s_y, s_z;
+    if (B.vkind == VK_SNAPSHOT) {
+      if (!have_v0) {
+        R4* vp = (R4*)d.v0 + I.v0_off + (local % sz);
+        if (B.snap) {
+          v0 = R4{m.jx, m.jy, m.jz, R(0)};
+          *vp = v0;
+        } else {
+          v0 = *vp;
+        }
+        have_v0 = true;
+      }
+      const R Sf = R(B.S);
+      sx = v0.x * Sf; s_y = v0.y * Sf; s_z = v0.z * Sf;
+    } else if (B.vkind == VK_CORRECT) {
+      sx = m.vx; s_y = m.vy; s_z = m.vz + R(B.vz);
+    } else {
+      sx = 0; s_y = 0; s_z = R(B.vz);
+    }
+    return v + deq_velocity<R>(i, m.vx, m.vy, m.vz, sx, s_y, s_z);
+  };
 #pragma unroll
   for (int i = 0; i < NQ; ++i) {
     const R v = relax<R, BAND>(i, m, g[i], om);
@@ -461,35 +500,27 @@ __device__ __forceinline__ void collide_body(const Dev& d, const int inst, const
       if (td == T_FLUID) BufIO<S>::st(rs(i), (uint32_t)(c + off[i]) * ES, v, d.scale);
       else if (td == T_SOLID) BufIO<S>::st(rs(OPP[i]), c * ES, v, d.scale);
     }
-    if (NEAR && i > 0 && nt(i) >= T_INLET) {
-      const BcDev& B = d.bc[3 * inst + (nt(i) - T_INLET)];
-      R out;
-      if (B.vmode == 0) {
-        out = v + wgt<R>(i) * (R(B.dstar - I.dref) - m.dl);
-      } else {
-        R sx, s_y, s_z;
-        if (B.vkind == VK_SNAPSHOT) {
-          if (!have_v0) {
-            R4* vp = (R4*)d.v0 + I.v0_off + (local % sz);
-            if (B.snap) {
-              v0 = R4{m.jx, m.jy, m.jz, R(0)};
-              *vp = v0;
-            } else {
-              v0 = *vp;
-            }
-            have_v0 = true;
-          }
-          const R Sf = R(B.S);
-          sx = v0.x * Sf; s_y = v0.y * Sf; s_z = v0.z * Sf;
-        } else if (B.vkind == VK_CORRECT) {
-          sx = m.vx; s_y = m.vy; s_z = m.vz + R(B.vz);
-        } else {
-          sx = 0; s_y = 0; s_z = R(B.vz);
-        }
-        out = v + deq_velocity<R>(i, m.vx, m.vy, m.vz, sx, s_y, s_z);
-      }
+    if (!NEAR || i == 0) continue;
+    const bool edge = i >= 7;
+    if (nt(i) >= T_INLET &&
+        !(NEE && edge && I.nee && (nt(edge_a(i)) == T_FLUID || nt(edge_b(i)) == T_FLUID))) {
+      const R out = ghost_value(i, nt(i), v);
       if (!ODD) BufIO<S>::st(rs(OPP[i]), (uint32_t)(c - off[i]) * ES, out, d.scale);
       else BufIO<S>::st(rs(i), c * ES, out, d.scale);
+    }
+    if (NEE && edge && I.nee) {
+      // this cell as the normal neighbour of the ghost c - e_k, handing
+      // direction i to the receiver c + e_t (e_i = e_k + e_t)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int k = h == 0 ? edge_a(i) : edge_b(i);
+        const int t = h == 0 ? edge_b(i) : edge_a(i);
+        if (nt(k) >= T_INLET && nt(OPP[t]) == T_FLUID) {
+          const R out = ghost_value(i, nt(k), v);
+          if (!ODD) BufIO<S>::st(rs(OPP[i]), (uint32_t)(c - off[k]) * ES, out, d.scale);
+          else BufIO<S>::st(rs(i), (uint32_t)(c + off[t]) * ES, out, d.scale);
+        }
+      }
     }
   }
 }
@@ -501,7 +532,7 @@ __device__ __forceinline__ void collide_body(const Dev& d, const int inst, const
 // memory and the bulk pass may run while the wall exchange still reads the
 // band cells' populations.  The body is chosen per wave (a vote over its
 // active lanes), so the choice never splits a wave.
-template <class S, bool ODD>
+template <class S, bool ODD, bool NEE>
 __device__ __forceinline__ void collide_cell(const Dev& d, const int inst, const int64_t local, const int mode) {
   const InstDesc& I = d.inst[inst];
   if (local >= I.ncell) return;
@@ -512,22 +543,24 @@ __device__ __forceinline__ void collide_cell(const Dev& d, const int inst, const
   if ((fl & TYPE_MASK) != T_FLUID) return;
   if (mode != COLLIDE_ALL && ((fl & F_BAND) != 0) != (mode == COLLIDE_BAND)) return;
   if (__any(fl & F_NEAR))
-    collide_body<S, ODD, true, true>(d, inst, I, local, c, fl);
+    collide_body<S, ODD, true, true, NEE>(d, inst, I, local, c, fl);
   else if (__any(fl & F_BAND))
-    collide_body<S, ODD, false, true>(d, inst, I, local, c, fl);
+    collide_body<S, ODD, false, true, NEE>(d, inst, I, local, c, fl);
   else
-    collide_body<S, ODD, false, false>(d, inst, I, local, c, fl);
+    collide_body<S, ODD, false, false, NEE>(d, inst, I, local, c, fl);
 }
 
 // One workgroup of BS lanes per tile of BS * CPT consecutive cells of one
 // instance (the tile table of a size class); lane t takes cells start + t,
 // start + t + BS, ... so every load and store stays coalesced.  BS and CPT
-// are chosen per size class by the autotuner.
-template <class S, bool ODD, int BS, int CPT>
+// are chosen per size class by the autotuner.  NEE: built with the
+// normal-neighbour extrapolation (a separate kernel, so that contexts without
+// it keep the smaller register budget).
+template <class S, bool ODD, int BS, int CPT, bool NEE>
 __global__ __launch_bounds__(BS) void k_collide(Dev d, const CTile* __restrict__ tab, int mode) {
   const CTile t = tab[blockIdx.x];
 #pragma unroll
-  for (int q = 0; q < CPT; ++q) collide_cell<S, ODD>(d, t.inst, (int64_t)t.start + q * BS + (int)threadIdx.x, mode);
+  for (int q = 0; q < CPT; ++q) collide_cell<S, ODD, NEE>(d, t.inst, (int64_t)t.start + q * BS + (int)threadIdx.x, mode);
 }
 
 // ---------------------------------------------------------------------------
@@ -1034,8 +1067,12 @@ hipError_t launch_reduce(const Dev& d, int prec, int parity, int nred, hipStream
 namespace {
 template <class T, int BS, int CPT>
 hipError_t collide_bs(const Dev& d, int parity, const CTile* tab, int ntile, int mode, hipStream_t s) {
-  return parity ? launch(k_collide<T, true, BS, CPT>, dim3(ntile), dim3(BS), s, Dev(d), tab, int(mode))
-                : launch(k_collide<T, false, BS, CPT>, dim3(ntile), dim3(BS), s, Dev(d), tab, int(mode));
+  const dim3 g(ntile), b(BS);
+  if (d.any_nee)
+    return parity ? launch(k_collide<T, true, BS, CPT, true>, g, b, s, Dev(d), tab, int(mode))
+                  : launch(k_collide<T, false, BS, CPT, true>, g, b, s, Dev(d), tab, int(mode));
+  return parity ? launch(k_collide<T, true, BS, CPT, false>, g, b, s, Dev(d), tab, int(mode))
+                : launch(k_collide<T, false, BS, CPT, false>, g, b, s, Dev(d), tab, int(mode));
 }
 template <class T>
 hipError_t collide_t(const Dev& d, int parity, int bs, int cpt, const CTile* tab, int ntile, int mode,

@@ -66,3 +66,7 @@ def test_size_query_and_argument_checks_on_cpu():
     cfg.tau = 0.8
     cfg.flags = inl.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
     assert amd.lib().lbm_query_sizes(ctypes.byref(cfg), 1, ctypes.byref(pb), ctypes.byref(wb)) == -1
+    cfg.flags = fl.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+    for v, want in ((1, 0), (2, -1), (-1, -1)):  # extrapolation variant: 0 or 1 only
+        cfg.nee_variant = v
+        assert amd.lib().lbm_query_sizes(ctypes.byref(cfg), 1, ctypes.byref(pb), ctypes.byref(wb)) == want, v
