@@ -243,7 +243,7 @@ __device__ void zerod_update(BcDev& b, int64_t n, double Qp, double Pbar) {
 template <class S, bool ODD>
 __global__ __launch_bounds__(RBLOCK) void k_reduce(Dev d) {
   using R = typename Store<S>::R;
-  __shared__ double sq[RBLOCK], sp[RBLOCK];
+  __shared__ double sq[RBLOCK], sp[RBLOCK], sq1[RBLOCK], sp1[RBLOCK];
   __shared__ int last;
   const RedTab t = d.red[blockIdx.x];
   const InstDesc& I = d.inst[t.inst];
@@ -285,16 +285,36 @@ __global__ __launch_bounds__(RBLOCK) void k_reduce(Dev d) {
     last = (done == (uint32_t)(I.nred - 1));
   }
   __syncthreads();
-  if (!last || threadIdx.x != 0) return;
+  if (!last) return;
 
-  // ---- last block of this instance: finish the sums in a fixed order ----
+  // ---- last block of this instance: finish the sums in a fixed order (a
+  // strided pass per lane, then the tree), all lanes loading partials at once
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   InstState* st = d.st + t.inst;
-  double Q[2] = {0.0, 0.0}, P[2] = {0.0, 0.0};
-  for (int b = I.red0; b < I.red0 + I.nred; ++b) {
-    const RedTab tb = d.red[b];
-    Q[tb.plane] += __hip_atomic_load(&d.red_part[2 * b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    P[tb.plane] += __hip_atomic_load(&d.red_part[2 * b + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  double q0 = 0.0, q1 = 0.0, p0 = 0.0, p1 = 0.0;
+  for (int b = I.red0 + (int)threadIdx.x; b < I.red0 + I.nred; b += RBLOCK) {
+    const double vq = __hip_atomic_load(&d.red_part[2 * b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const double vp = __hip_atomic_load(&d.red_part[2 * b + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (d.red[b].plane == 0) {
+      q0 += vq; p0 += vp;
+    } else {
+      q1 += vq; p1 += vp;
+    }
   }
+  sq[threadIdx.x] = q0; sp[threadIdx.x] = p0;
+  sq1[threadIdx.x] = q1; sp1[threadIdx.x] = p1;
+  __syncthreads();
+  for (int w = RBLOCK / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      sq[threadIdx.x] += sq[threadIdx.x + w];
+      sp[threadIdx.x] += sp[threadIdx.x + w];
+      sq1[threadIdx.x] += sq1[threadIdx.x + w];
+      sp1[threadIdx.x] += sp1[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  double Q[2] = {sq[0], sq1[0]}, P[2] = {sp[0], sp1[0]};
   for (int pl = 0; pl < 2; ++pl) P[pl] = I.lay_n[pl] ? P[pl] / (double)I.lay_n[pl] : 0.0;
   if (!isfinite(Q[0]) || !isfinite(Q[1]) || !isfinite(P[0]) || !isfinite(P[1]))
     atomicOr(d.err, ERR_NONFINITE);
