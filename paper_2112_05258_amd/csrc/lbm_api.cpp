@@ -64,10 +64,12 @@ struct Geometry {
   int nx, ny, nz;
   int64_t ncell;
   std::vector<uint8_t> flags;        // with F_NEAR (and F_BAND) bits
+  std::vector<uint64_t> nbr;         // NEAR cells: the 18 neighbour types, 3 bits each
   std::vector<int32_t> lay[2];
 };
 
-// Checks the cell types and derives NEAR bits and boundary-layer lists.
+// Checks the cell types and derives the NEAR bits, the neighbour-type words
+// of NEAR cells and the boundary-layer lists.
 bool build_geometry(const lbm_config& c, Geometry& g, std::string& err) {
   if (c.nx < 3 || c.ny < 3 || c.nz < 3) { err = "box dimensions must be >= 3"; return false; }
   if (!(c.tau > 0.5)) { err = "tau must be > 0.5"; return false; }
@@ -89,13 +91,19 @@ bool build_geometry(const lbm_config& c, Geometry& g, std::string& err) {
         if (t == T_OUTLET && z != g.nz - 1) { err = "OUTLET cell off the plane z = nz-1"; return false; }
         if (t == T_EXTP && !face) { err = "EXTP cell inside the box"; return false; }
       }
+  g.nbr.assign(g.ncell, 0);
   for (int z = 1; z < g.nz - 1; ++z)
     for (int y = 1; y < g.ny - 1; ++y)
       for (int x = 1; x < g.nx - 1; ++x) {
         uint8_t& t = at(x, y, z);
         if (t != T_FLUID) continue;
-        for (int i = 1; i < NQ; ++i)
-          if (at(x + EXh[i], y + EYh[i], z + EZh[i]) != T_FLUID) { t |= F_NEAR; break; }
+        uint64_t w = 0;
+        for (int i = 1; i < NQ; ++i)   // source of direction i: c - e_i (type bits only)
+          w |= (uint64_t)(at(x - EXh[i], y - EYh[i], z - EZh[i]) & TYPE_MASK) << (3 * i);
+        if (w != 0) {
+          t |= F_NEAR;
+          g.nbr[x + (int64_t)g.nx * (y + (int64_t)g.ny * z)] = w;
+        }
       }
   for (int pl = 0; pl < 2; ++pl) {
     g.lay[pl].clear();
@@ -110,7 +118,7 @@ bool build_geometry(const lbm_config& c, Geometry& g, std::string& err) {
 }
 
 struct Layout {
-  size_t flags, inst, ctab, btab, lay, red, red_part, bc, st, wave, v0, err, moved, walls, cwalls, total;
+  size_t flags, nbr, inst, ctab, btab, lay, red, red_part, bc, st, wave, v0, err, moved, walls, cwalls, total;
   int64_t NT;
   int ntile_max, nred, nlay, wave_cap;
   int64_t nv0;
@@ -153,6 +161,7 @@ void plan(const std::vector<Geometry>& G, int prec, int wave_cap, Layout& L, std
   const size_t n = G.size();
   size_t o = 0;
   L.flags = o; o = align256(o + L.NT);
+  L.nbr = o; o = align256(o + (size_t)L.NT * 8);
   L.inst = o; o = align256(o + n * sizeof(InstDesc));
   L.ctab = o; o = align256(o + (size_t)std::max(L.ntile_max, 1) * sizeof(CTile));
   L.btab = o; o = align256(o + (size_t)std::max(L.ntile_max, 1) * sizeof(CTile));
@@ -547,8 +556,8 @@ lbm_status read_pops(lbm_ctx* c, int k, std::vector<double>& out) {
       if (!odd) {
         v = val(i, cell);
       } else {
-        const int64_t src = cell - (EXh[i] + EYh[i] * sy + EZh[i] * sz);
-        v = (i != 0 && (g.flags[src] & TYPE_MASK) == T_SOLID) ? val(i, cell) : val(OPPh[i], src);
+        // streamed, bounced-back or extrapolated: all at A[opp i][c - e_i]
+        v = val(OPPh[i], cell - (EXh[i] + EYh[i] * sy + EZh[i] * sz));
       }
       out[(size_t)cell * NQ + i] = v + W[i] * d.dref;
     }
@@ -730,6 +739,7 @@ lbm_status lbm_init(const lbm_config* cfgs, int32_t n, const lbm_buffers* buf, v
   d.scale = c->scale;
   d.inv_scale = 1.0f / c->scale;
   d.flags = (const uint8_t*)(c->work + c->L.flags);
+  d.nbr = (const uint64_t*)(c->work + c->L.nbr);
   d.inst = (const InstDesc*)(c->work + c->L.inst);
   d.lay = (const int32_t*)(c->work + c->L.lay);
   d.red = (const RedTab*)(c->work + c->L.red);
@@ -765,6 +775,11 @@ lbm_status lbm_init(const lbm_config* cfgs, int32_t n, const lbm_buffers* buf, v
   hipError_t e = hipStreamSynchronize(c->stream);
   const char* what = "hipStreamSynchronize";
   if (e == hipSuccess) { e = up(c->L.flags, flags.data(), flags.size()); what = "flags upload"; }
+  for (int k = 0; k < n && e == hipSuccess; ++k) {
+    e = up(c->L.nbr + (size_t)c->inst[k].cell0 * 8, c->geo[k].nbr.data(), (size_t)c->geo[k].ncell * 8);
+    what = "neighbour-type upload";
+    std::vector<uint64_t>().swap(c->geo[k].nbr);   // device copy only from here on
+  }
   if (e == hipSuccess) { e = up(c->L.inst, c->inst.data(), c->inst.size() * sizeof(InstDesc)); what = "instance upload"; }
   if (e == hipSuccess) { e = up(c->L.lay, lay.data(), lay.size() * 4); what = "layer upload"; }
   if (e == hipSuccess) { e = up(c->L.red, red.data(), red.size() * sizeof(RedTab)); what = "reduction table upload"; }
@@ -1322,7 +1337,7 @@ lbm_status lbm_set_overlap(lbm_ctx* c, int32_t on) {
 namespace {
 
 constexpr char CKPT_MAGIC[8] = {'L', 'B', 'M', '0', 'D', '3', 'D', 'C'};
-constexpr uint32_t CKPT_VERSION = 1;
+constexpr uint32_t CKPT_VERSION = 2;
 
 struct CkptHeader {
   char magic[8];

@@ -120,21 +120,15 @@ __device__ __forceinline__ void dir_offsets(int64_t sy, int64_t sz, int64_t off[
 }
 
 // Populations of cell c at the current step (parity = step & 1), AA layout:
-// even: g_i = A[i][c]; odd: g_i = A[opp i][c - e_i], or A[i][c] when c - e_i
-// is SOLID (the bounce-back slot written by c itself).
+// even: g_i = A[i][c]; odd: g_i = A[opp i][c - e_i].  Halfway bounce-back
+// needs no case here: a population streamed toward a SOLID cell is stored
+// where the next step's plain load finds it (see collide_body).
 template <class S, bool ODD>
-__device__ __forceinline__ void load_cell(const S* __restrict__ A, int64_t NT, const uint8_t* __restrict__ flags,
-                                          int64_t c, bool near, const int64_t off[NQ], float inv,
-                                          typename Store<S>::R g[NQ]) {
+__device__ __forceinline__ void load_cell(const S* __restrict__ A, int64_t NT, int64_t c, const int64_t off[NQ],
+                                          float inv, typename Store<S>::R g[NQ]) {
 #pragma unroll
-  for (int i = 0; i < NQ; ++i) {
-    if (!ODD) {
-      g[i] = Store<S>::ld(A + i * NT + c, inv);
-    } else {
-      const bool bb = near && i != 0 && ((flags[c - off[i]] & TYPE_MASK) == T_SOLID);
-      g[i] = bb ? Store<S>::ld(A + i * NT + c, inv) : Store<S>::ld(A + OPP[i] * NT + c - off[i], inv);
-    }
-  }
+  for (int i = 0; i < NQ; ++i)
+    g[i] = ODD ? Store<S>::ld(A + OPP[i] * NT + c - off[i], inv) : Store<S>::ld(A + i * NT + c, inv);
 }
 
 // ---------------------------------------------------------------------------
@@ -254,9 +248,8 @@ __global__ __launch_bounds__(RBLOCK) void k_reduce(Dev d) {
   double q = 0.0, ps = 0.0;
   for (int k = threadIdx.x; k < t.count; k += RBLOCK) {
     const int64_t c = I.cell0 + d.lay[I.lay_off[t.plane] + t.start + k];
-    const bool near = d.flags[c] & F_NEAR;
     R g[NQ];
-    load_cell<S, ODD>(A, d.NT, d.flags, c, near, off, d.inv_scale, g);
+    load_cell<S, ODD>(A, d.NT, c, off, d.inv_scale, g);
     double s = I.dref, jz = 0.0;
 #pragma unroll
     for (int i = 0; i < NQ; ++i) {
@@ -421,8 +414,9 @@ __device__ __forceinline__ R relax(int i, const Mom<R>& m, R g, R om) {
 }
 
 // One lattice cell (global index c, local index local of instance inst) of
-// the collide-stream step.  NEAR: the wave holds a cell next to a solid or a
-// 0D-coupled ghost (per-direction source and target types are looked up);
+// the collide-stream step.  NEAR: the wave holds a cell next to a 0D-coupled
+// ghost, or (odd step) next to a solid (per-direction source and target
+// types are looked up);
 // BAND: the wave holds a cell of the wall's band (the IB force enters, zero
 // at the wave's other cells).  The plain body has neither.
 template <class S, bool ODD, bool NEAR, bool BAND, bool NEE>
@@ -437,12 +431,19 @@ __device__ __forceinline__ void collide_body(const Dev& d, const int inst, const
   S* __restrict__ A = (S*)d.pop;
   const int64_t NT = d.NT;
 
-  // source cell types (only cells next to walls or ghosts look)
-  // (3 bits per direction in one 64-bit word: two registers, not 19)
+  // source cell types (only cells next to walls or ghosts look), 3 bits per
+  // direction in one 64-bit word.  16-bit storage: the precomputed word, one
+  // load instead of 18 (its wave-level instruction count is what the 16-bit
+  // collide pays for); FP32 / FP64: from the flags, whose lines the wave
+  // reads anyway (the word's extra lines cost the bandwidth-bound step more)
   uint64_t ntb = 0;
   if (NEAR && (fl & F_NEAR)) {
+    if constexpr (sizeof(S) == 2) {
+      ntb = d.nbr[c];
+    } else {
 #pragma unroll
-    for (int i = 1; i < NQ; ++i) ntb |= (uint64_t)(d.flags[c - off[i]] & TYPE_MASK) << (3 * i);
+      for (int i = 1; i < NQ; ++i) ntb |= (uint64_t)(d.flags[c - off[i]] & TYPE_MASK) << (3 * i);
+    }
   }
   auto nt = [&](int i) -> uint32_t { return (uint32_t)(ntb >> (3 * i)) & 7u; };
 
@@ -452,13 +453,8 @@ __device__ __forceinline__ void collide_body(const Dev& d, const int inst, const
   R g[NQ];
 #pragma unroll
   for (int i = 0; i < NQ; ++i) {
-    if (!ODD) {
-      g[i] = BufIO<S>::ld(rs(i), c * ES, d.inv_scale);
-    } else if (NEAR && nt(i) == T_SOLID) {
-      g[i] = BufIO<S>::ld(rs(i), c * ES, d.inv_scale);
-    } else {
-      g[i] = BufIO<S>::ld(rs(OPP[i]), (uint32_t)(c - off[i]) * ES, d.inv_scale);
-    }
+    if (!ODD) g[i] = BufIO<S>::ld(rs(i), c * ES, d.inv_scale);
+    else g[i] = BufIO<S>::ld(rs(OPP[i]), (uint32_t)(c - off[i]) * ES, d.inv_scale);
   }
   R bx = 0, by = 0, bz = 0;
   if (BAND && (fl & F_BAND)) {
@@ -511,14 +507,17 @@ __device__ __forceinline__ void collide_body(const Dev& d, const int inst, const
 #pragma unroll
   for (int i = 0; i < NQ; ++i) {
     const R v = relax<R, BAND>(i, m, g[i], om);
-    if (!ODD) {
-      BufIO<S>::st(rs(OPP[i]), c * ES, v, d.scale);
-    } else if (!NEAR) {
-      BufIO<S>::st(rs(i), (uint32_t)(c + off[i]) * ES, v, d.scale);
-    } else {
-      const uint32_t td = nt(OPP[i]);  // type of c + e_i
-      if (td == T_FLUID) BufIO<S>::st(rs(i), (uint32_t)(c + off[i]) * ES, v, d.scale);
-      else if (td == T_SOLID) BufIO<S>::st(rs(OPP[i]), c * ES, v, d.scale);
+    if (!ODD) BufIO<S>::st(rs(OPP[i]), c * ES, v, d.scale);
+    else BufIO<S>::st(rs(i), (uint32_t)(c + off[i]) * ES, v, d.scale);
+    // halfway bounce-back: g*_i toward a SOLID cell x = c + e_i returns to c
+    // as direction opp i.  It goes to the slot the next step's plain load of
+    // that direction reads: x's A[i][x] after an even step, the own A[opp i][c]
+    // after an odd one (slots no other cell touches).  The plain store above
+    // then lands in a slot nobody reads (the solid's, or the own slot whose
+    // reader would be the solid).
+    if (NEAR && i > 0 && nt(OPP[i]) == T_SOLID) {
+      if (!ODD) BufIO<S>::st(rs(i), (uint32_t)(c + off[i]) * ES, v, d.scale);
+      else BufIO<S>::st(rs(OPP[i]), c * ES, v, d.scale);
     }
     if (!NEAR || i == 0) continue;
     const bool edge = i >= 7;
@@ -547,10 +546,11 @@ __device__ __forceinline__ void collide_body(const Dev& d, const int inst, const
 
 // one lattice cell (local index of instance inst) of the collide-stream step
 // mode: COLLIDE_ALL, COLLIDE_BULK (cells outside the wall band) or
-// COLLIDE_BAND (band cells only).  The slots a cell writes in a step are
-// exactly the slots it reads, so the two partial passes touch disjoint
-// memory and the bulk pass may run while the wall exchange still reads the
-// band cells' populations.  The body is chosen per wave (a vote over its
+// COLLIDE_BAND (band cells only).  A cell writes the slots it reads, and
+// next to a wall or ghost also slots that no fluid cell reads in the step
+// (a solid's or ghost's slot, or an own slot whose reader is a solid), so
+// the two partial passes touch disjoint memory and the bulk pass may run
+// while the wall exchange still reads the band cells' populations.  The body is chosen per wave (a vote over its
 // active lanes), so the choice never splits a wave.
 template <class S, bool ODD, bool NEE>
 __device__ __forceinline__ void collide_cell(const Dev& d, const int inst, const int64_t local, const int mode) {
@@ -607,20 +607,11 @@ __global__ __launch_bounds__(WBLOCK) void k_band(Dev d) {
 #pragma unroll
     for (int i = 1; i < NQ; ++i) g[i] = Store<S>::ld(A + i * NT + c, inv);
   } else {
-    // odd step: g_i = A[opp i][c - e_i], or the cell's own A[i][c] where
-    // c - e_i is SOLID (only cells flagged next to a wall look)
+    // odd step: g_i = A[opp i][c - e_i] (bounce-back values included)
     int64_t off[NQ];
     dir_offsets(I.nx, (int64_t)I.nx * I.ny, off);
-    uint32_t solid = 0u;
-    if (d.flags[c] & F_NEAR) {
 #pragma unroll
-      for (int i = 1; i < NQ; ++i) solid |= (uint32_t)((d.flags[c - off[i]] & TYPE_MASK) == T_SOLID) << i;
-    }
-#pragma unroll
-    for (int i = 1; i < NQ; ++i) {
-      const int64_t e = ((solid >> i) & 1u) ? i * NT + c : OPP[i] * NT + c - off[i];
-      g[i] = Store<S>::ld(A + e, inv);
-    }
+    for (int i = 1; i < NQ; ++i) g[i] = Store<S>::ld(A + OPP[i] * NT + c - off[i], inv);
   }
   R jx = 0, jy = 0, jz = 0;
 #pragma unroll
