@@ -161,7 +161,8 @@ void plan(const std::vector<Geometry>& G, int prec, int wave_cap, Layout& L, std
   const size_t n = G.size();
   size_t o = 0;
   L.flags = o; o = align256(o + L.NT);
-  L.nbr = o; o = align256(o + (size_t)L.NT * 8);
+  // neighbour-type words: read by the 16-bit collide only
+  L.nbr = o; o = align256(o + (elem_size(prec) == 2 ? (size_t)L.NT * 8 : 0));
   L.inst = o; o = align256(o + n * sizeof(InstDesc));
   L.ctab = o; o = align256(o + (size_t)std::max(L.ntile_max, 1) * sizeof(CTile));
   L.btab = o; o = align256(o + (size_t)std::max(L.ntile_max, 1) * sizeof(CTile));
@@ -177,7 +178,6 @@ void plan(const std::vector<Geometry>& G, int prec, int wave_cap, Layout& L, std
   L.walls = o; o = align256(o + n * 4);
   L.cwalls = o; o = align256(o + n * 4);
   L.total = o;
-  (void)prec;
 }
 
 struct EventPair {
@@ -776,9 +776,11 @@ lbm_status lbm_init(const lbm_config* cfgs, int32_t n, const lbm_buffers* buf, v
   const char* what = "hipStreamSynchronize";
   if (e == hipSuccess) { e = up(c->L.flags, flags.data(), flags.size()); what = "flags upload"; }
   for (int k = 0; k < n && e == hipSuccess; ++k) {
-    e = up(c->L.nbr + (size_t)c->inst[k].cell0 * 8, c->geo[k].nbr.data(), (size_t)c->geo[k].ncell * 8);
-    what = "neighbour-type upload";
-    std::vector<uint64_t>().swap(c->geo[k].nbr);   // device copy only from here on
+    if (elem_size(c->prec) == 2) {
+      e = up(c->L.nbr + (size_t)c->inst[k].cell0 * 8, c->geo[k].nbr.data(), (size_t)c->geo[k].ncell * 8);
+      what = "neighbour-type upload";
+    }
+    std::vector<uint64_t>().swap(c->geo[k].nbr);   // the device copy (if any) from here on
   }
   if (e == hipSuccess) { e = up(c->L.inst, c->inst.data(), c->inst.size() * sizeof(InstDesc)); what = "instance upload"; }
   if (e == hipSuccess) { e = up(c->L.lay, lay.data(), lay.size() * 4); what = "layer upload"; }

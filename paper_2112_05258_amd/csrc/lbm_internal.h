@@ -94,7 +94,8 @@ struct Dev {
   int64_t NT;
   float scale, inv_scale;          // 16-bit storage scale
   const uint8_t* flags;
-  const uint64_t* nbr;             // per NEAR cell: type of c - e_i in bits 3i..3i+2 (i = 1..18)
+  const uint64_t* nbr;             // per NEAR cell: type of c - e_i in bits 3i..3i+2 (i = 1..18);
+                                   // 16-bit storage only
   const InstDesc* inst;
   const int32_t* lay;              // layer cell lists (local cell ids)
   const RedTab* red;
