@@ -327,15 +327,26 @@ hipError_t enqueue_step(lbm_ctx* c, int parity, bool timed) {
       return e;
     return hipStreamWaitEvent(c->stream, c->ev_join, 0);
   }
-  pre(1);
-  e = launch_reduce(c->dev, c->prec, parity, c->L.nred, c->stream);
-  if (e != hipSuccess) return e;
-  post(1);
-  if (c->dev.nwall > 0) {
-    pre(2);
-    e = launch_band(c->dev, c->prec, parity, c->stream);
+  // With a wall, untimed steps run the 0D reductions and the band moments as
+  // one launch (the reductions hide behind the band's memory traffic);
+  // timed and tuning steps keep them apart, so that each has its own time.
+  const bool fused = c->dev.nwall > 0 && !timed && !c->tuning;
+  if (fused) {
+    e = launch_reduce_band(c->dev, c->prec, parity, c->L.nred, c->stream);
     if (e != hipSuccess) return e;
-    post(2);
+  } else {
+    pre(1);
+    e = launch_reduce(c->dev, c->prec, parity, c->L.nred, c->stream);
+    if (e != hipSuccess) return e;
+    post(1);
+  }
+  if (c->dev.nwall > 0) {
+    if (!fused) {
+      pre(2);
+      e = launch_band(c->dev, c->prec, parity, c->stream);
+      if (e != hipSuccess) return e;
+      post(2);
+    }
     pre(3);
     for (const LaunchGroup& G : c->wgroups) {
       EventPair p;

@@ -132,6 +132,8 @@ enum { COLLIDE_ALL = 0, COLLIDE_BULK = 1, COLLIDE_BAND = 2 };
 hipError_t launch_collide(const Dev& d, int prec, int parity, int bs, int cpt, const CTile* tab, int ntile,
                           int mode, hipStream_t s);
 hipError_t launch_band(const Dev& d, int prec, int parity, hipStream_t s);
+// the boundary reductions and the band moments in one launch
+hipError_t launch_reduce_band(const Dev& d, int prec, int parity, int nred, hipStream_t s);
 // wall exchange over the walls of a size class, tiles of tj x (256 / tj)
 // points (tj = 8, 16, 32); tiles = tile count of the class's largest wall
 hipError_t launch_wall(const Dev& d, int prec, int parity, int tj, const int32_t* walls, int nwall, int tiles,

@@ -235,11 +235,11 @@ __device__ void zerod_update(BcDev& b, int64_t n, double Qp, double Pbar) {
 // k_reduce: layer flux / pressure, then (last block) the 0D update
 // ---------------------------------------------------------------------------
 template <class S, bool ODD>
-__global__ __launch_bounds__(RBLOCK) void k_reduce(Dev d) {
+__device__ __forceinline__ void reduce_block(const Dev& d, const int blk) {
   using R = typename Store<S>::R;
   __shared__ double sq[RBLOCK], sp[RBLOCK], sq1[RBLOCK], sp1[RBLOCK];
   __shared__ int last;
-  const RedTab t = d.red[blockIdx.x];
+  const RedTab t = d.red[blk];
   const InstDesc& I = d.inst[t.inst];
   const int64_t sy = I.nx, sz = (int64_t)I.nx * I.ny;
   int64_t off[NQ];
@@ -270,8 +270,8 @@ __global__ __launch_bounds__(RBLOCK) void k_reduce(Dev d) {
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    d.red_part[2 * blockIdx.x] = sq[0];
-    d.red_part[2 * blockIdx.x + 1] = sp[0];
+    d.red_part[2 * blk] = sq[0];
+    d.red_part[2 * blk + 1] = sp[0];
     InstState* st = d.st + t.inst;
     const uint32_t done =
         __hip_atomic_fetch_add(&st->counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
@@ -330,6 +330,11 @@ __global__ __launch_bounds__(RBLOCK) void k_reduce(Dev d) {
   r[11] = bc[0].kind == BC_LV ? (double)bc[0].open : 0.0;
   st->step = n + 1;
   __hip_atomic_store(&st->counter, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <class S, bool ODD>
+__global__ __launch_bounds__(RBLOCK) void k_reduce(Dev d) {
+  reduce_block<S, ODD>(d, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -590,12 +595,12 @@ __global__ __launch_bounds__(BS) void k_collide(Dev d, const CTile* __restrict__
 // other, so a wave keeps all of them in flight (band cells form short runs
 // along x, and the kernel is bound by the partly used cache lines).
 template <class S, bool ODD>
-__global__ __launch_bounds__(WBLOCK) void k_band(Dev d) {
+__device__ __forceinline__ void band_block(const Dev& d, const int wall, const int bx) {
   using R = typename Store<S>::R;
   using R4 = typename V4<R>::T;
-  const int inst = d.walls[blockIdx.y];
+  const int inst = d.walls[wall];
   const InstDesc& I = d.inst[inst];
-  const int k = blockIdx.x * WBLOCK + threadIdx.x;
+  const int k = bx * WBLOCK + threadIdx.x;
   if (k >= I.nband) return;
   const int64_t lc = I.band[k];
   const int64_t c = I.cell0 + lc;
@@ -622,6 +627,26 @@ __global__ __launch_bounds__(WBLOCK) void k_band(Dev d) {
   }
   ((R4*)I.u4)[lc] = R4{jx, jy, jz, R(0)};
   ((R4*)I.b4)[lc] = R4{0, 0, 0, 0};
+}
+
+template <class S, bool ODD>
+__global__ __launch_bounds__(WBLOCK) void k_band(Dev d) {
+  band_block<S, ODD>(d, blockIdx.y, blockIdx.x);
+}
+
+// The boundary reductions and the band moments in one launch: the first
+// nred workgroups reduce (few, latency-bound), the others take nbx band
+// workgroups per wall.  The two read populations only and write disjoint
+// state, so the reductions run in the shadow of the band's memory traffic.
+template <class S, bool ODD>
+__global__ __launch_bounds__(WBLOCK) void k_reduce_band(Dev d, int nred, int nbx) {
+  static_assert(RBLOCK == WBLOCK, "one workgroup size for both parts");
+  const int b = (int)blockIdx.x;
+  if (b < nred) {
+    reduce_block<S, ODD>(d, b);
+  } else {
+    band_block<S, ODD>(d, (b - nred) / nbx, (b - nred) % nbx);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1104,6 +1129,19 @@ hipError_t launch_collide(const Dev& d, int prec, int parity, int bs, int cpt, c
                           int mode, hipStream_t s) {
   if (ntile <= 0) return hipSuccess;
 #define F(T) return collide_t<T>(d, parity, bs, cpt, tab, ntile, mode, s);
+  LBM_DISPATCH(prec, F)
+#undef F
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_reduce_band(const Dev& d, int prec, int parity, int nred, hipStream_t s) {
+  const int nbx = d.nwall > 0 ? (d.max_band + WBLOCK - 1) / WBLOCK : 0;
+  const int64_t nb = (int64_t)nred + (int64_t)nbx * d.nwall;
+  if (nb <= 0) return hipSuccess;
+  if (nb > 0x7fffffff) return hipErrorInvalidValue;
+#define F(T)                                                                                          \
+  return parity ? launch(k_reduce_band<T, true>, dim3((unsigned)nb), dim3(WBLOCK), s, Dev(d), nred, nbx) \
+                : launch(k_reduce_band<T, false>, dim3((unsigned)nb), dim3(WBLOCK), s, Dev(d), nred, nbx);
   LBM_DISPATCH(prec, F)
 #undef F
   return hipErrorInvalidValue;
