@@ -1124,18 +1124,20 @@ lbm_status lbm_fsi_exchange(lbm_ctx* c, int32_t k, const lbm_wall_desc* w, void*
   c->wall[k].band_cap = band_capacity((int64_t)band.size());
   c->wall[k].X0.assign(w->X0_host, w->X0_host + 3 * np);
   c->walls.clear();
-  int maxb = 0;
+  int maxb = 0, maxmt = 0;
   int64_t maxp = 0;
   for (int q = 0; q < c->n; ++q)
     if (c->wall[q].on) {
       c->walls.push_back(q);
       maxb = std::max(maxb, c->wall[q].nband);
       maxp = std::max(maxp, c->wall[q].np);
+      maxmt = std::max(maxmt, membrane_tiles(c->inst[q].nth, c->inst[q].nzl));
     }
   HIPCHK(c, hipMemcpy(c->work + c->L.walls, c->walls.data(), c->walls.size() * 4, hipMemcpyHostToDevice));
   c->dev.nwall = (int32_t)c->walls.size();
   c->dev.max_band = maxb;
   c->dev.max_np = (int32_t)maxp;
+  c->dev.max_mtile = maxmt;
   return build_groups(c, false);
 }
 

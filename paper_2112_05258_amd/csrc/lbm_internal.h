@@ -111,8 +111,12 @@ struct Dev {
   const int32_t* walls;            // instance ids with a wall
   int32_t max_band, max_np;
   int32_t any_nee;                 // some instance uses the normal-neighbour extrapolation
-  int32_t pad_;
+  int32_t max_mtile;               // largest membrane tile count of a wall (membrane_tiles)
 };
+
+// membrane step tiles: MEM_TJ x MEM_TK points (theta x z) per workgroup
+constexpr int MEM_TJ = 64, MEM_TK = WBLOCK / MEM_TJ;
+inline int membrane_tiles(int nth, int nzl) { return ((nth + MEM_TJ - 1) / MEM_TJ) * ((nzl + MEM_TK - 1) / MEM_TK); }
 
 // collide tile: BS * CPT consecutive local cells of one instance
 struct CTile {

@@ -978,35 +978,55 @@ __global__ __launch_bounds__(WBLOCK) void k_wall(Dev d, const int32_t* __restric
 
 // k_membrane: membrane forces (Eqs. tension and bending along theta and z)
 // and the wall's central-difference step, one lane per point, after k_wall
-// has produced this step's penalty force.
+// has produced this step's penalty force.  A workgroup takes a tile of
+// MJ x MK points (theta x z) and stages X0 and D of the tile and its 2-point
+// halo (periodic in theta) in LDS once, instead of each lane reading its ~30
+// neighbour values from L2.
+constexpr int MJ = MEM_TJ, MK = MEM_TK, MH = 2;
+constexpr int MLJ = MJ + 2 * MH, MLK = MK + 2 * MH;
 __global__ __launch_bounds__(WBLOCK) void k_membrane(Dev d, int parity) {
   const int inst = d.walls[blockIdx.y];
   const InstDesc& I = d.inst[inst];
-  const int64_t p = (int64_t)blockIdx.x * WBLOCK + threadIdx.x;
-  if (p >= I.np) return;
   const int nth = I.nth, nzl = I.nzl;
-  const int j = (int)(p % nth), k = (int)(p / nth);
+  const int ntj = (nth + MJ - 1) / MJ;
+  if ((int)blockIdx.x >= ntj * ((nzl + MK - 1) / MK)) return;  // whole block leaves
+  const int j0 = ((int)blockIdx.x % ntj) * MJ, k0 = ((int)blockIdx.x / ntj) * MK;
+  __shared__ double3 sx0[MLK][MLJ], sd[MLK][MLJ];
   const double* Dc = I.Xab[parity];
   double* Dn = I.Xab[parity ^ 1];
-  const double3 D = ld3(Dc, p), Dm = ld3(Dn, p);
+  for (int q = (int)threadIdx.x; q < MLJ * MLK; q += WBLOCK) {
+    const int hj = q % MLJ, hk = q / MLJ;
+    const int kk = k0 - MH + hk;
+    if (kk < 0 || kk >= nzl) continue;   // rows past the ends are never read
+    const int jj = ((j0 - MH + hj) % nth + nth) % nth;
+    const int64_t pp = jj + (int64_t)nth * kk;
+    sx0[hk][hj] = ld3(I.X0, pp);
+    sd[hk][hj] = ld3(Dc, pp);
+  }
+  __syncthreads();
+  const int tj = (int)threadIdx.x % MJ, tk = (int)threadIdx.x / MJ;
+  const int j = j0 + tj, k = k0 + tk;
+  if (j >= nth || k >= nzl) return;
+  const int64_t p = j + (int64_t)nth * k;
+  // staged values at theta offset dj, z offset dk from this point
+  auto DD = [&](int dj, int dk) -> double3 { return sd[tk + MH + dk][tj + MH + dj]; };
+  auto XX = [&](int dj, int dk) -> double3 { return sx0[tk + MH + dk][tj + MH + dj]; };
+  const double3 D = DD(0, 0), Dm = ld3(Dn, p);
   const double4 Fw = ((const double4*)I.Fp)[p];
   const double Fx = Fw.x, Fy = Fw.y, Fz = Fw.z;
-  // membrane forces (Eqs. tension and bending along theta and z)
-  auto P = [&](int jj, int kk) -> int64_t { return (int64_t)((jj % nth + nth) % nth) + (int64_t)nth * kk; };
-  // edge vector X_b - X_a = (X0_b - X0_a) + (D_b - D_a)
-  auto edge = [&](int64_t a, int64_t b) -> double3 {
-    const double3 xa = ld3(I.X0, a), xb = ld3(I.X0, b), da = ld3(Dc, a), db = ld3(Dc, b);
+  // edge vector X_b - X_a = (X0_b - X0_a) + (D_b - D_a), a and b as offsets
+  auto edge = [&](int ja, int ka, int jb, int kb) -> double3 {
+    const double3 xa = XX(ja, ka), xb = XX(jb, kb), da = DD(ja, ka), db = DD(jb, kb);
     return make_double3((xb.x - xa.x) + (db.x - da.x), (xb.y - xa.y) + (db.y - da.y),
                         (xb.z - xa.z) + (db.z - da.z));
   };
   const double dt2 = I.ds_th * I.ds_th, dz2 = I.ds_z * I.ds_z;
   double3 f = make_double3(0.0, 0.0, 0.0);
   {
-    const double3 tp = tension(edge(p, P(j + 1, k)), I.ds_th, I.ks);
-    const double3 tm = tension(edge(P(j - 1, k), p), I.ds_th, I.ks);
+    const double3 tp = tension(edge(0, 0, 1, 0), I.ds_th, I.ks);
+    const double3 tm = tension(edge(-1, 0, 0, 0), I.ds_th, I.ks);
     f.x += (tp.x - tm.x) / I.ds_th; f.y += (tp.y - tm.y) / I.ds_th; f.z += (tp.z - tm.z) / I.ds_th;
-    const double3 y2m = ld3(Dc, P(j - 2, k)), y1m = ld3(Dc, P(j - 1, k)), y0 = D, y1p = ld3(Dc, P(j + 1, k)),
-                  y2p = ld3(Dc, P(j + 2, k));
+    const double3 y2m = DD(-2, 0), y1m = DD(-1, 0), y0 = D, y1p = DD(1, 0), y2p = DD(2, 0);
     // curvature at j-1, j, j+1, then its second difference
     const double kmx = (y0.x - 2.0 * y1m.x + y2m.x) / dt2, kcx = (y1p.x - 2.0 * y0.x + y1m.x) / dt2,
                  kpx = (y2p.x - 2.0 * y1p.x + y0.x) / dt2;
@@ -1020,13 +1040,13 @@ __global__ __launch_bounds__(WBLOCK) void k_membrane(Dev d, int parity) {
   }
   const bool interior = k > 0 && k < nzl - 1;
   if (interior) {
-    const double3 tp = tension(edge(p, P(j, k + 1)), I.ds_z, I.ks);
-    const double3 tm = tension(edge(P(j, k - 1), p), I.ds_z, I.ks);
+    const double3 tp = tension(edge(0, 0, 0, 1), I.ds_z, I.ks);
+    const double3 tm = tension(edge(0, -1, 0, 0), I.ds_z, I.ks);
     f.x += (tp.x - tm.x) / I.ds_z; f.y += (tp.y - tm.y) / I.ds_z; f.z += (tp.z - tm.z) / I.ds_z;
     // curvature along z, zero on the end rings (simply supported)
     auto kap = [&](int kk) -> double3 {
       if (kk <= 0 || kk >= nzl - 1) return make_double3(0.0, 0.0, 0.0);
-      const double3 a = ld3(Dc, P(j, kk - 1)), b = ld3(Dc, P(j, kk)), c = ld3(Dc, P(j, kk + 1));
+      const double3 a = DD(0, kk - 1 - k), b = DD(0, kk - k), c = DD(0, kk + 1 - k);
       return make_double3((c.x - 2.0 * b.x + a.x) / dz2, (c.y - 2.0 * b.y + a.y) / dz2,
                           (c.z - 2.0 * b.z + a.z) / dz2);
     };
@@ -1178,8 +1198,8 @@ hipError_t launch_wall(const Dev& d, int prec, int parity, int tj, const int32_t
 }
 
 hipError_t launch_membrane(const Dev& d, int parity, hipStream_t s) {
-  if (d.nwall <= 0 || d.max_np <= 0) return hipSuccess;
-  const dim3 g2((unsigned)((d.max_np + WBLOCK - 1) / WBLOCK), d.nwall);
+  if (d.nwall <= 0 || d.max_np <= 0 || d.max_mtile <= 0) return hipSuccess;
+  const dim3 g2((unsigned)d.max_mtile, d.nwall);
   return launch(k_membrane, g2, dim3(WBLOCK), s, Dev(d), int(parity));
 }
 
