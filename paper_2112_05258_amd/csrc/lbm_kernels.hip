@@ -41,8 +41,10 @@ __device__ constexpr int edge_b(int i) { return EZ[i] != 0 ? face_dir(2, EZ[i]) 
 // and each XCD has its own L2.  This maps workgroup b of nb to a tile index
 // such that the workgroups of one XCD take consecutive tiles, so that
 // neighbouring tiles, which share halo lines, share an L2.  A bijection of
-// [0, nb).  Used by the membrane step (27.7 against 32.5 us on cfg1); the
-// collide (one stream through memory) and k_wall measured slower with it.
+// [0, nb).  Used by the band moments (cfg1 FP32 136 -> 123 us, FP16 80 ->
+// 64 us: neighbouring band chunks share the lines of their rows' runs) and
+// the membrane step (32.5 -> 27.7 us: halo rows); the collide (one stream
+// through memory) and k_wall measured slower with it.
 __device__ __forceinline__ int xcd_tile(int b, int nb) {
   const int q = nb >> 3, r = nb & 7, x = b & 7;
   return x * q + (x < r ? x : r) + (b >> 3);
@@ -642,7 +644,7 @@ __device__ __forceinline__ void band_block(const Dev& d, const int wall, const i
 
 template <class S, bool ODD>
 __global__ __launch_bounds__(WBLOCK) void k_band(Dev d) {
-  band_block<S, ODD>(d, blockIdx.y, blockIdx.x);
+  band_block<S, ODD>(d, blockIdx.y, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // The boundary reductions and the band moments in one launch: the first
@@ -656,7 +658,8 @@ __global__ __launch_bounds__(WBLOCK) void k_reduce_band(Dev d, int nred, int nbx
   if (b < nred) {
     reduce_block<S, ODD>(d, b);
   } else {
-    band_block<S, ODD>(d, (b - nred) / nbx, (b - nred) % nbx);
+    const int nbb = (int)gridDim.x - nred, bb = xcd_tile(b - nred, nbb);
+    band_block<S, ODD>(d, bb / nbx, bb % nbx);
   }
 }
 
