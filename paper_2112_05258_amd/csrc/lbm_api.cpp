@@ -520,6 +520,7 @@ lbm_status check_bands(lbm_ctx* c) {
   for (int k = 0; k < c->n; ++k)
     if (c->wall[k].on) m = std::min(m, c->wall[k].margin);
   if (m == (1 << 30)) return LBM_OK;
+  HIPCHK(c, launch_motion(c->dev, (int)(c->step & 1), c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   uint32_t bits = 0;
   HIPCHK(c, hipMemcpy(&bits, c->work + c->L.moved, 4, hipMemcpyDeviceToHost));

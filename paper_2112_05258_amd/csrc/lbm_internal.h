@@ -142,6 +142,9 @@ hipError_t launch_reduce_band(const Dev& d, int prec, int parity, int nred, hipS
 // points (tj = 8, 16, 32); tiles = tile count of the class's largest wall
 hipError_t launch_wall(const Dev& d, int prec, int parity, int tj, const int32_t* walls, int nwall, int tiles,
                        hipStream_t s);
+// wall motion since the band was built, into the moved word (parity: the
+// current displacement's half of the ping-pong pair)
+hipError_t launch_motion(const Dev& d, int parity, hipStream_t s);
 hipError_t launch_membrane(const Dev& d, int parity, hipStream_t s);
 hipError_t launch_fill_rest(const Dev& d, int prec, int64_t cell0, int64_t ncell, double dshift, hipStream_t s);
 }  // namespace lbm

@@ -738,7 +738,6 @@ __global__ __launch_bounds__(WBLOCK) void k_wall(Dev d, const int32_t* __restric
   __shared__ uint8_t sfl[BOXCAP];
   __shared__ int sext[6];   // min x, y, z; max x, y, z of the stencil bases
   __shared__ int semax;
-  __shared__ uint32_t smove;
   const int inst = walls[blockIdx.y];
   const InstDesc& I = d.inst[inst];
   const int nth = I.nth, nzl = I.nzl;
@@ -769,18 +768,8 @@ __global__ __launch_bounds__(WBLOCK) void k_wall(Dev d, const int32_t* __restric
   const bool valid = point && inside;
 
   if (threadIdx.x < 6) sext[threadIdx.x] = threadIdx.x < 3 ? 0x7fffffff : -0x7fffffff;
-  if (threadIdx.x == 0) {
-    smove = 0u;
-    semax = -100000;
-  }
+  if (threadIdx.x == 0) semax = -100000;
   __syncthreads();
-  // motion since the band was built (max norm; positive floats order as
-  // their bit patterns): the host rebuilds the band when it nears the margin
-  uint32_t mv = 0u;
-  if (valid) {
-    const double3 Dr = ld3(I.Dref, p);
-    mv = __float_as_uint((float)fmax(fabs(D.x - Dr.x), fmax(fabs(D.y - Dr.y), fabs(D.z - Dr.z))));
-  }
   const int bx0 = valid ? (int)floor(px) - 1 : 0, by0 = valid ? (int)floor(py) - 1 : 0,
             bz0 = valid ? (int)floor(pz) - 1 : 0;
   {   // wave reductions over the active (here: all) lanes, one atomic per wave
@@ -788,14 +777,12 @@ __global__ __launch_bounds__(WBLOCK) void k_wall(Dev d, const int32_t* __restric
                        __ockl_wfred_min_i32(valid ? bz0 : 0x7fffffff)};
     const int hi[3] = {__ockl_wfred_max_i32(valid ? bx0 : -0x7fffffff), __ockl_wfred_max_i32(valid ? by0 : -0x7fffffff),
                        __ockl_wfred_max_i32(valid ? bz0 : -0x7fffffff)};
-    mv = __ockl_wfred_max_u32(mv);
     if (ln == 0) {
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         atomicMin(&sext[a], lo[a]);
         atomicMax(&sext[3 + a], hi[a]);
       }
-      atomicMax(&smove, mv);
     }
   }
   R wx[4], wy[4], wz[4];
@@ -809,7 +796,6 @@ __global__ __launch_bounds__(WBLOCK) void k_wall(Dev d, const int32_t* __restric
     wz[a] = cosk ? phicos<R>(rz) : phi4<R>(rz);
   }
   __syncthreads();
-  if (threadIdx.x == 0 && smove != 0u) atomicMax(d.moved, smove);
   // every valid point has its stencil base in [-2, n], so the extents are
   // small and positive; a tile without a valid point has min > max
   const int ox = sext[0], oy = sext[1], oz = sext[2];
@@ -989,6 +975,23 @@ __global__ __launch_bounds__(WBLOCK) void k_wall(Dev d, const int32_t* __restric
         }
       }
   }
+}
+
+// k_motion: largest displacement of a wall point since its band was built
+// (max norm; positive floats order as their bit patterns) into the moved
+// word, launched right before the host's wall-motion test rather than in
+// every step.  D is the current displacement (Xab of the step parity).
+__global__ __launch_bounds__(WBLOCK) void k_motion(Dev d, int parity) {
+  const InstDesc& I = d.inst[d.walls[blockIdx.y]];
+  if ((int64_t)blockIdx.x * WBLOCK >= I.np) return;  // whole block leaves
+  const int64_t p = (int64_t)blockIdx.x * WBLOCK + threadIdx.x;
+  uint32_t mv = 0u;
+  if (p < I.np) {
+    const double3 D = ld3(I.Xab[parity], p), Dr = ld3(I.Dref, p);
+    mv = __float_as_uint((float)fmax(fabs(D.x - Dr.x), fmax(fabs(D.y - Dr.y), fabs(D.z - Dr.z))));
+  }
+  mv = __ockl_wfred_max_u32(mv);   // all lanes of the wave are active here
+  if ((threadIdx.x & 63) == 0 && mv != 0u) atomicMax(d.moved, mv);
 }
 
 // k_membrane: membrane forces (Eqs. tension and bending along theta and z)
@@ -1211,6 +1214,12 @@ hipError_t launch_wall(const Dev& d, int prec, int parity, int tj, const int32_t
   if (nwall <= 0 || tiles <= 0) return hipSuccess;
   const dim3 grid((unsigned)tiles, (unsigned)nwall);
   return prec == 0 ? wall_t<double>(d, parity, tj, walls, grid, s) : wall_t<float>(d, parity, tj, walls, grid, s);
+}
+
+hipError_t launch_motion(const Dev& d, int parity, hipStream_t s) {
+  if (d.nwall <= 0 || d.max_np <= 0) return hipSuccess;
+  const dim3 g((unsigned)((d.max_np + WBLOCK - 1) / WBLOCK), d.nwall);
+  return launch(k_motion, g, dim3(WBLOCK), s, Dev(d), int(parity));
 }
 
 hipError_t launch_membrane(const Dev& d, int parity, hipStream_t s) {
