@@ -613,7 +613,11 @@ __device__ __forceinline__ void band_block(const Dev& d, const int wall, const i
   using R4 = typename V4<R>::T;
   const int inst = d.walls[wall];
   const InstDesc& I = d.inst[inst];
-  const int k = bx * WBLOCK + threadIdx.x;
+  // chunk bx of this wall's band, in XCD-aware order over the wall's own
+  // chunks (its workgroups are consecutive, so they go to the XCDs in turn)
+  const int nb = (I.nband + WBLOCK - 1) / WBLOCK;
+  if (bx >= nb) return;
+  const int k = xcd_tile(bx, nb) * WBLOCK + threadIdx.x;
   if (k >= I.nband) return;
   const int64_t lc = I.band[k];
   const int64_t c = I.cell0 + lc;
@@ -644,7 +648,7 @@ __device__ __forceinline__ void band_block(const Dev& d, const int wall, const i
 
 template <class S, bool ODD>
 __global__ __launch_bounds__(WBLOCK) void k_band(Dev d) {
-  band_block<S, ODD>(d, blockIdx.y, xcd_tile(blockIdx.x, gridDim.x));
+  band_block<S, ODD>(d, blockIdx.y, blockIdx.x);
 }
 
 // The boundary reductions and the band moments in one launch: the first
@@ -658,8 +662,7 @@ __global__ __launch_bounds__(WBLOCK) void k_reduce_band(Dev d, int nred, int nbx
   if (b < nred) {
     reduce_block<S, ODD>(d, b);
   } else {
-    const int nbb = (int)gridDim.x - nred, bb = xcd_tile(b - nred, nbb);
-    band_block<S, ODD>(d, bb / nbx, bb % nbx);
+    band_block<S, ODD>(d, (b - nred) / nbx, (b - nred) % nbx);
   }
 }
 
