@@ -1010,8 +1010,10 @@ __global__ __launch_bounds__(WBLOCK) void k_membrane(Dev d, int parity) {
   const InstDesc& I = d.inst[inst];
   const int nth = I.nth, nzl = I.nzl;
   const int ntj = (nth + MJ - 1) / MJ;
-  const int bx = xcd_tile(blockIdx.x, gridDim.x);
-  if (bx >= ntj * ((nzl + MK - 1) / MK)) return;  // whole block leaves
+  // this wall's tiles in XCD-aware order over its own tile count
+  const int ntile = ntj * ((nzl + MK - 1) / MK);
+  if ((int)blockIdx.x >= ntile) return;  // whole block leaves
+  const int bx = xcd_tile(blockIdx.x, ntile);
   const int j0 = (bx % ntj) * MJ, k0 = (bx / ntj) * MK;
   __shared__ double3 sx0[MLK][MLJ], sd[MLK][MLJ];
   const double* Dc = I.Xab[parity];
