@@ -246,10 +246,13 @@ lbm_status lbm_read_populations(lbm_ctx* ctx, int32_t inst, double* g_host);
  * Synchronises. */
 lbm_status lbm_read_fields(lbm_ctx* ctx, int32_t inst, double* p_host, double* u_host);
 
-/* Per-step boundary waveforms of instance inst, 12 doubles per step:
+/* Per-step boundary waveforms of instance inst, 14 doubles per step:
  * [n, Q_in, p_in, Q_out, p_out, in_mode, in_value, out_mode, out_value, Pv,
- *  Pw_out, valve] (value = p* in pressure mode, S for the LV and the axial v*
- * or correction otherwise).  Writes the last min(cap, steps, wave_cap)
+ *  Pw_out, valve, Q_mid, p_mid] (value = p* in pressure mode, S for the LV
+ * and the axial v* or correction otherwise; Q_mid, p_mid: flux and mean
+ * gauge pressure, as for the boundary layers, on the mid-length plane
+ * z = nz/2 over the columns of the inlet's lumen, i.e. the FLUID cells of
+ * that plane above an INLET ghost; recorded only, coupled to nothing).  Writes the last min(cap, steps, wave_cap)
  * records, oldest first, and sets *n to that count.  Synchronises. */
 lbm_status lbm_read_waveforms(lbm_ctx* ctx, int32_t inst, double* out, int64_t cap, int64_t* n);
 

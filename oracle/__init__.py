@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lbm_oracle.c")
 _LIBS = {False: os.path.join(_HERE, "liblbm_oracle.so"),       # real = double
          True: os.path.join(_HERE, "liblbm_oracle_ext.so")}    # real = long double
-NREC = 12
+NREC = 14
 Q = 19
 
 

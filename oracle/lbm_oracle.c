@@ -62,7 +62,7 @@ typedef double real;
 #endif
 
 #define NQ 19
-#define NREC 12
+#define NREC 14
 
 /* D3Q19 velocities: rest, 6 faces, 12 edges (weights 1/3, 1/18, 1/36). */
 static const int EV[NQ][3] = {
@@ -731,6 +731,23 @@ static void one_step(orc_t* o) {
     Pm[side] = cnt ? ps / cnt : 0;
     o->bc[side].area = (real)cnt;
   }
+  /* the same sums on the mid-length plane z = nz/2, over the columns of the
+   * inlet's lumen (cells above an INLET ghost): recorded, not coupled */
+  real Qmid = 0, Pmid = 0;
+  {
+    const int zm = nz / 2;
+    long cnt = 0;
+    real ps = 0;
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x < nx; ++x) {
+        long c = cidx(o, x, y, zm);
+        if (o->type[c] != T_FLUID || o->type[cidx(o, x, y, 0)] != T_INLET) continue;
+        Qmid += o->j[3 * c + 2] / (1 + o->D[c]);
+        ps += CS2 * o->D[c];
+        cnt++;
+      }
+    Pmid = cnt ? ps / cnt : 0;
+  }
 
   /* 3. 0D models to t_{n+1} */
   bc_update(&o->bc[0], n, Qp[0], Pm[0]);
@@ -862,6 +879,7 @@ static void one_step(orc_t* o) {
   r[9] = (double)(o->bc[0].kind == K_LV ? o->bc[0].Pv : 0);
   r[10] = (double)(o->bc[1].kind == K_WK3 ? o->bc[1].Pw : 0);
   r[11] = o->bc[0].kind == K_LV ? (double)o->bc[0].open : 0.0;
+  r[12] = (double)Qmid; r[13] = (double)Pmid;
   record(o, r);
   o->step++;
 }

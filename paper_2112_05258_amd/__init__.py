@@ -15,7 +15,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbm0d3d.so")
 NQ = 19
-NREC = 12
+NREC = 14
 FP64, FP32, FP16S, BF16S = 0, 1, 2, 3
 KERNEL_COLLIDE, KERNEL_REDUCE, KERNEL_BAND, KERNEL_WALL = 0, 1, 2, 3
 

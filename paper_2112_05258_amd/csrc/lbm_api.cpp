@@ -65,7 +65,7 @@ struct Geometry {
   int64_t ncell;
   std::vector<uint8_t> flags;        // with F_NEAR (and F_BAND) bits
   std::vector<uint64_t> nbr;         // NEAR cells: the 18 neighbour types, 3 bits each
-  std::vector<int32_t> lay[2];
+  std::vector<int32_t> lay[3];   // boundary layers: inlet, outlet, mid-length
 };
 
 // Checks the cell types and derives the NEAR bits, the neighbour-type words
@@ -114,6 +114,13 @@ bool build_geometry(const lbm_config& c, Geometry& g, std::string& err) {
         if ((at(x, y, zl) & TYPE_MASK) == T_FLUID && at(x, y, zg) == gt)
           g.lay[pl].push_back(x + g.nx * (y + g.ny * zl));
   }
+  // mid-length plane z = nz/2, over the columns of the inlet's lumen (cells
+  // above an INLET ghost): its flux and pressure are recorded, not coupled
+  g.lay[2].clear();
+  for (int y = 0; y < g.ny; ++y)
+    for (int x = 0; x < g.nx; ++x)
+      if ((at(x, y, g.nz / 2) & TYPE_MASK) == T_FLUID && (at(x, y, 0) & TYPE_MASK) == T_INLET)
+        g.lay[2].push_back(x + g.nx * (y + g.ny * (g.nz / 2)));
   return true;
 }
 
@@ -138,7 +145,7 @@ void plan(const std::vector<Geometry>& G, int prec, int wave_cap, Layout& L, std
     d.v0_off = L.nv0;
     d.red0 = L.nred;
     int nr = 0;
-    for (int pl = 0; pl < 2; ++pl) {
+    for (int pl = 0; pl < 3; ++pl) {
       d.lay_off[pl] = L.nlay;
       d.lay_n[pl] = (int32_t)g.lay[pl].size();
       if (lay) lay->insert(lay->end(), g.lay[pl].begin(), g.lay[pl].end());
@@ -1353,7 +1360,7 @@ lbm_status lbm_set_overlap(lbm_ctx* c, int32_t on) {
 namespace {
 
 constexpr char CKPT_MAGIC[8] = {'L', 'B', 'M', '0', 'D', '3', 'D', 'C'};
-constexpr uint32_t CKPT_VERSION = 2;
+constexpr uint32_t CKPT_VERSION = 3;
 
 struct CkptHeader {
   char magic[8];

@@ -14,7 +14,7 @@
 namespace lbm {
 
 constexpr int NQ = 19;
-constexpr int NREC = 12;          // doubles per waveform record
+constexpr int NREC = 14;          // doubles per waveform record
 constexpr int MIN_TILE = 128;     // smallest collide tile (workgroup 128, 1 cell per lane)
 constexpr int RBLOCK = 256;       // boundary-reduction workgroup
 constexpr int RCHUNK = 256;       // layer cells per reduction workgroup (one per lane)
@@ -54,7 +54,7 @@ struct BcDev {
 struct InstDesc {
   int32_t nx, ny, nz;
   int32_t red0, nred;      // reduction blocks
-  int32_t lay_off[2], lay_n[2];   // inlet / outlet layer lists in the lay array
+  int32_t lay_off[3], lay_n[3];   // inlet / outlet / mid-length layer lists in the lay array
   int64_t cell0, ncell;
   int64_t v0_off;          // first entry of this instance's inlet snapshot (nx*ny)
   double tau;

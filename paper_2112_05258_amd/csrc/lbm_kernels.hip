@@ -250,7 +250,7 @@ __device__ void zerod_update(BcDev& b, int64_t n, double Qp, double Pbar) {
 template <class S, bool ODD>
 __device__ __forceinline__ void reduce_block(const Dev& d, const int blk) {
   using R = typename Store<S>::R;
-  __shared__ double sq[RBLOCK], sp[RBLOCK], sq1[RBLOCK], sp1[RBLOCK];
+  __shared__ double sq[RBLOCK], sp[RBLOCK], sq1[RBLOCK], sp1[RBLOCK], sq2[RBLOCK], sp2[RBLOCK];
   __shared__ int last;
   const RedTab t = d.red[blk];
   const InstDesc& I = d.inst[t.inst];
@@ -297,18 +297,22 @@ __device__ __forceinline__ void reduce_block(const Dev& d, const int blk) {
   // strided pass per lane, then the tree), all lanes loading partials at once
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   InstState* st = d.st + t.inst;
-  double q0 = 0.0, q1 = 0.0, p0 = 0.0, p1 = 0.0;
+  double q0 = 0.0, q1 = 0.0, q2 = 0.0, p0 = 0.0, p1 = 0.0, p2 = 0.0;
   for (int b = I.red0 + (int)threadIdx.x; b < I.red0 + I.nred; b += RBLOCK) {
     const double vq = __hip_atomic_load(&d.red_part[2 * b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const double vp = __hip_atomic_load(&d.red_part[2 * b + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (d.red[b].plane == 0) {
+    const int pl = d.red[b].plane;
+    if (pl == 0) {
       q0 += vq; p0 += vp;
-    } else {
+    } else if (pl == 1) {
       q1 += vq; p1 += vp;
+    } else {
+      q2 += vq; p2 += vp;
     }
   }
   sq[threadIdx.x] = q0; sp[threadIdx.x] = p0;
   sq1[threadIdx.x] = q1; sp1[threadIdx.x] = p1;
+  sq2[threadIdx.x] = q2; sp2[threadIdx.x] = p2;
   __syncthreads();
   for (int w = RBLOCK / 2; w > 0; w >>= 1) {
     if (threadIdx.x < w) {
@@ -316,12 +320,15 @@ __device__ __forceinline__ void reduce_block(const Dev& d, const int blk) {
       sp[threadIdx.x] += sp[threadIdx.x + w];
       sq1[threadIdx.x] += sq1[threadIdx.x + w];
       sp1[threadIdx.x] += sp1[threadIdx.x + w];
+      sq2[threadIdx.x] += sq2[threadIdx.x + w];
+      sp2[threadIdx.x] += sp2[threadIdx.x + w];
     }
     __syncthreads();
   }
   if (threadIdx.x != 0) return;
-  double Q[2] = {sq[0], sq1[0]}, P[2] = {sp[0], sp1[0]};
-  for (int pl = 0; pl < 2; ++pl) P[pl] = I.lay_n[pl] ? P[pl] / (double)I.lay_n[pl] : 0.0;
+  // planes: inlet, outlet (coupled to the 0D models), mid-length (recorded)
+  double Q[3] = {sq[0], sq1[0], sq2[0]}, P[3] = {sp[0], sp1[0], sp2[0]};
+  for (int pl = 0; pl < 3; ++pl) P[pl] = I.lay_n[pl] ? P[pl] / (double)I.lay_n[pl] : 0.0;
   if (!isfinite(Q[0]) || !isfinite(Q[1]) || !isfinite(P[0]) || !isfinite(P[1]))
     atomicOr(d.err, ERR_NONFINITE);
   const int64_t n = st->step;
@@ -341,6 +348,7 @@ __device__ __forceinline__ void reduce_block(const Dev& d, const int blk) {
   r[9] = bc[0].kind == BC_LV ? bc[0].Pv : 0.0;
   r[10] = bc[1].kind == BC_WK3 ? bc[1].Pw : 0.0;
   r[11] = bc[0].kind == BC_LV ? (double)bc[0].open : 0.0;
+  r[12] = Q[2]; r[13] = P[2];
   st->step = n + 1;
   __hip_atomic_store(&st->counter, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }

@@ -38,7 +38,7 @@ def _run_pair(oracle_mod, amd, cfg, steps, precision, pops=None, **kw):
     return o, s
 
 
-def _compare(o, s, fl, tol, wave_cols=(1, 2, 3, 4, 9, 10), check_pops=True):
+def _compare(o, s, fl, tol, wave_cols=(1, 2, 3, 4, 9, 10, 12, 13), check_pops=True):
     po, uo = o.fields()
     ps, us = s.fields()
     fluid = fl == L.FLUID
@@ -48,10 +48,11 @@ def _compare(o, s, fl, tol, wave_cols=(1, 2, 3, 4, 9, 10), check_pops=True):
     ws = s.waveforms()
     assert ws.shape == wo.shape, (ws.shape, wo.shape)
     errs = {"u": e_u, "p": e_p}
-    # waveforms: error over the norm of their family (fluxes Q_in, Q_out;
-    # pressures p_in, p_out, Pv, Pw), so that a boundary whose flux is ~0
+    # waveforms: error over the norm of their family (fluxes Q_in, Q_out,
+    # Q_mid; pressures p_in, p_out, Pv, Pw, p_mid), so that a boundary whose flux is ~0
     # (closed valve) is not judged by its rounding noise alone
-    fam = {1: (1, 3), 3: (1, 3), 2: (2, 4, 9, 10), 4: (2, 4, 9, 10), 9: (2, 4, 9, 10), 10: (2, 4, 9, 10)}
+    fam = {c: (1, 3, 12) for c in (1, 3, 12)}
+    fam.update({c: (2, 4, 9, 10, 13) for c in (2, 4, 9, 10, 13)})
     for c in wave_cols:
         den = max(np.linalg.norm(wo[:, k]) for k in fam[c])
         if den > 0:

@@ -169,11 +169,19 @@ def test_small_tube_steady_windkessel(oracle_mod):
     assert abs(Pout / (Qout * (Rp + Rd)) - 1.0) < 5e-3      # flux-correction offset ~0.3 %
     # history is settled: last 500 steps vary by < 1e-4
     assert np.abs(w[-500:, 3] - Qout).max() < 1e-4 * Qout
+    Qmid, Pmid = w[-1, 12:14]
+    # the steady flux is the same through every cross-section (mid-length
+    # plane z = 32 of 64 recorded beside the boundary layers)
+    assert abs(Qmid - Qin) < 1e-4 * Qin
     p, u = o.fields()
     fl = c["flags"]
     lum = fl[32] == L.FLUID
     pz = np.array([p[z][lum].mean() for z in range(16, 49)])
-    slope = np.polyfit(np.arange(16, 49), pz, 1)[0]
+    slope, icpt = np.polyfit(np.arange(16, 49), pz, 1)
+    # the recorded mid-length pressure lies on the developed tube's linear
+    # pressure profile at z = 32, to a tenth of one cell's pressure drop (a
+    # neighbouring plane would be a whole drop off)
+    assert abs(Pmid - (icpt + 32 * slope)) < 0.1 * abs(slope)
     nu = (c["tau"] - 0.5) / 3.0
     y, x = np.meshgrid(np.arange(24), np.arange(24), indexing="ij")
     r2 = (x - 11.5) ** 2 + (y - 11.5) ** 2
