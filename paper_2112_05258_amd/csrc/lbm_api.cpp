@@ -212,6 +212,7 @@ struct SizeClass {
 // with their slice of the packed tile table or wall list.
 struct LaunchGroup {
   int bs = 256, cpt = 1, tj = 16;
+  bool bigbox = false;         // wall tiles staged by the large-box kernel
   int cls = -1;                // the class timed by this launch while tuning
   size_t off = 0;              // first tile / wall entry
   int count = 0;               // tiles / walls
@@ -318,7 +319,7 @@ hipError_t enqueue_step(lbm_ctx* c, int parity, bool timed) {
     if ((e = hipStreamWaitEvent(s2, c->ev_fork, 0)) != hipSuccess) return e;
     if ((e = launch_band(c->dev, c->prec, parity, s2)) != hipSuccess) return e;
     for (const LaunchGroup& G : c->wgroups)
-      if ((e = launch_wall(c->dev, c->prec, parity, G.tj, cw + G.off, G.count, G.wall_tiles, s2)) != hipSuccess)
+      if ((e = launch_wall(c->dev, c->prec, parity, G.tj, G.bigbox, cw + G.off, G.count, G.wall_tiles, s2)) != hipSuccess)
         return e;
     if ((e = hipEventRecord(c->ev_wall, s2)) != hipSuccess) return e;
     if ((e = launch_membrane(c->dev, parity, s2)) != hipSuccess) return e;
@@ -358,7 +359,7 @@ hipError_t enqueue_step(lbm_ctx* c, int parity, bool timed) {
     for (const LaunchGroup& G : c->wgroups) {
       EventPair p;
       tpre(p);
-      e = launch_wall(c->dev, c->prec, parity, G.tj, cw + G.off, G.count, G.wall_tiles, c->stream);
+      e = launch_wall(c->dev, c->prec, parity, G.tj, G.bigbox, cw + G.off, G.count, G.wall_tiles, c->stream);
       if (e != hipSuccess) return e;
       tpost(p, G.cls, 1);
     }
@@ -411,6 +412,34 @@ void make_classes(lbm_ctx* c) {
 // (workgroup, cells per lane) and one wall launch per distinct tile width,
 // or one of each per class (per_class, for timing them apart).  Packs and
 // uploads the tile table and the wall list.
+// Whether wall i's tiles of tj x 256/tj points need the large-box wall
+// kernel: more than 1 in 10 of their stencil boxes at the rest shape exceed
+// 90 % of the standard staging capacity (coarse meshes; the margin leaves
+// room for the wall's motion).
+bool wall_needs_bigbox(const lbm_ctx* c, int i, int tj) {
+  const InstDesc& d = c->inst[i];
+  const std::vector<double>& X = c->wall[i].X0;
+  const int tk = 256 / tj, nth = d.nth, nzl = d.nzl;
+  const int64_t cap = wall_boxcap(c->prec == 0 ? 8 : 4, tj) * 9 / 10;
+  int64_t over = 0, total = 0;
+  for (int k0 = 0; k0 < nzl; k0 += tk)
+    for (int j0 = 0; j0 < nth; j0 += tj) {
+      int lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
+      for (int k = k0; k < std::min(k0 + tk, nzl); ++k)
+        for (int j = j0; j < std::min(j0 + tj, nth); ++j)
+          for (int a = 0; a < 3; ++a) {
+            const int b = (int)std::floor(X[3 * (j + (size_t)nth * k) + a]) - 1;
+            lo[a] = std::min(lo[a], b);
+            hi[a] = std::max(hi[a], b);
+          }
+      int64_t vol = 1;
+      for (int a = 0; a < 3; ++a) vol *= (int64_t)(hi[a] - lo[a] + 4);
+      over += vol > cap;
+      ++total;
+    }
+  return over * 10 > total;
+}
+
 lbm_status build_groups(lbm_ctx* c, bool per_class) {
   const int nc = (int)c->cls.size();
   std::vector<CTile> tab;
@@ -450,6 +479,7 @@ lbm_status build_groups(lbm_ctx* c, bool per_class) {
           walls.push_back(i);
           const InstDesc& d = c->inst[i];
           G.wall_tiles = std::max(G.wall_tiles, ((d.nth + G.tj - 1) / G.tj) * ((d.nzl + tk - 1) / tk));
+          G.bigbox = G.bigbox || wall_needs_bigbox(c, i, G.tj);
         }
     }
     G.count = (int)(walls.size() - G.off);

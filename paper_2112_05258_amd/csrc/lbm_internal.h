@@ -140,8 +140,12 @@ hipError_t launch_band(const Dev& d, int prec, int parity, hipStream_t s);
 hipError_t launch_reduce_band(const Dev& d, int prec, int parity, int nred, hipStream_t s);
 // wall exchange over the walls of a size class, tiles of tj x (256 / tj)
 // points (tj = 8, 16, 32); tiles = tile count of the class's largest wall
-hipError_t launch_wall(const Dev& d, int prec, int parity, int tj, const int32_t* walls, int nwall, int tiles,
-                       hipStream_t s);
+// LDS staging capacity of a wall tile's stencil box (cells), standard and
+// large-box kernels; element size 8 (FP64) or 4 (FP32 velocities)
+constexpr int wall_boxcap(int elem, int tj) { return elem == 8 ? 1024 : (tj == 32 ? 2048 : 1280); }
+constexpr int wall_boxcap_big(int elem) { return elem == 8 ? 2560 : 4096; }
+hipError_t launch_wall(const Dev& d, int prec, int parity, int tj, bool big, const int32_t* walls, int nwall,
+                       int tiles, hipStream_t s);
 // wall motion since the band was built, into the moved word (parity: the
 // current displacement's half of the ping-pong pair)
 hipError_t launch_motion(const Dev& d, int parity, hipStream_t s);

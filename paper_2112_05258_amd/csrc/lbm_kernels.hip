@@ -736,14 +736,15 @@ template <> struct FixOf<double> {
 // stencil cell serves both the interpolation and the band check; tile-wide
 // extents and maxima are reduced within each wave first, so only one lane
 // per wave touches the shared LDS word.
-template <class R, int TJ>
+template <class R, int TJ, bool BIG>
 __global__ __launch_bounds__(WBLOCK) void k_wall(Dev d, const int32_t* __restrict__ walls, int parity) {
   constexpr int TK = (WBLOCK / 64) * 64 / TJ;
   using R4 = typename V4<R>::T;
   using Fix = typename FixOf<R>::T;
   // box cells: at 0.5 lu spacing a 16 x 16 or 8 x 32 tile spans <= ~1000,
-  // a 32 x 8 tile <= ~1600 (a larger box takes the unstaged path)
-  constexpr int BOXCAP = sizeof(R) == 8 ? 1024 : (TJ == 32 ? 2048 : 1280);
+  // a 32 x 8 tile <= ~1600; BIG (coarser meshes, ~0.9 lu: up to ~3300 for
+  // 16 x 16) trades occupancy for staging; a larger box takes the unstaged path
+  constexpr int BOXCAP = BIG ? wall_boxcap_big(sizeof(R)) : wall_boxcap(sizeof(R), TJ);
   static_assert(3 * sizeof(Fix) <= sizeof(R4), "the spread accumulators reuse the staging box");
   __shared__ R4 sbox[BOXCAP];
   __shared__ uint8_t sfl[BOXCAP];
@@ -1212,21 +1213,26 @@ hipError_t launch_band(const Dev& d, int prec, int parity, hipStream_t s) {
 
 namespace {
 template <class R>
-hipError_t wall_t(const Dev& d, int parity, int tj, const int32_t* walls, dim3 grid, hipStream_t s) {
-  switch (tj) {
-    case 8: return launch(k_wall<R, 8>, grid, dim3(WBLOCK), s, Dev(d), walls, int(parity));
-    case 16: return launch(k_wall<R, 16>, grid, dim3(WBLOCK), s, Dev(d), walls, int(parity));
-    case 32: return launch(k_wall<R, 32>, grid, dim3(WBLOCK), s, Dev(d), walls, int(parity));
+hipError_t wall_t(const Dev& d, int parity, int tj, bool big, const int32_t* walls, dim3 grid, hipStream_t s) {
+  const dim3 b(WBLOCK);
+  switch (tj * 2 + (big ? 1 : 0)) {
+    case 16: return launch(k_wall<R, 8, false>, grid, b, s, Dev(d), walls, int(parity));
+    case 17: return launch(k_wall<R, 8, true>, grid, b, s, Dev(d), walls, int(parity));
+    case 32: return launch(k_wall<R, 16, false>, grid, b, s, Dev(d), walls, int(parity));
+    case 33: return launch(k_wall<R, 16, true>, grid, b, s, Dev(d), walls, int(parity));
+    case 64: return launch(k_wall<R, 32, false>, grid, b, s, Dev(d), walls, int(parity));
+    case 65: return launch(k_wall<R, 32, true>, grid, b, s, Dev(d), walls, int(parity));
     default: return hipErrorInvalidValue;
   }
 }
 }  // namespace
 
-hipError_t launch_wall(const Dev& d, int prec, int parity, int tj, const int32_t* walls, int nwall, int tiles,
-                       hipStream_t s) {
+hipError_t launch_wall(const Dev& d, int prec, int parity, int tj, bool big, const int32_t* walls, int nwall,
+                       int tiles, hipStream_t s) {
   if (nwall <= 0 || tiles <= 0) return hipSuccess;
   const dim3 grid((unsigned)tiles, (unsigned)nwall);
-  return prec == 0 ? wall_t<double>(d, parity, tj, walls, grid, s) : wall_t<float>(d, parity, tj, walls, grid, s);
+  return prec == 0 ? wall_t<double>(d, parity, tj, big, walls, grid, s)
+                   : wall_t<float>(d, parity, tj, big, walls, grid, s);
 }
 
 hipError_t launch_motion(const Dev& d, int parity, hipStream_t s) {

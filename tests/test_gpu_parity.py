@@ -196,6 +196,30 @@ def test_external_solid_prescribed_motion(oracle_mod, amd, precision, tol):
             t.close()
 
 
+@pytest.mark.parametrize("h,tj", [(0.7, 16), (0.7, 32), (1.4, 16)])
+def test_wall_staging_paths(oracle_mod, amd, h, tj):
+    """The wall exchange's three ways of handling a tile's stencil box, each
+    against the oracle (the library picks the kernel from the rest shape; the
+    box sizes below follow from the mesh).  h = 0.7, 16 x 16 tiles: boxes of
+    600-1694 cells, the large-box kernel stages them all; h = 0.7, 32 x 8:
+    1188-1782 cells, the standard kernel stages them all; h = 1.4, 16 x 16:
+    3060-4950 cells, the large-box kernel stages those up to 4096 and the
+    rest take the unstaged path (stencils read and spread in global memory)."""
+    c = L.small_fsi(h=h)
+    o = oracle_mod.from_config(c, extended=True)
+    s = amd.solver_from_config(c, precision=amd.FP64)
+    s.set_launch(0, 256, 1, tj)
+    o.step(60)
+    s.step(60)
+    s.sync()
+    _compare(o, s, c["flags"], 1e-12)
+    Do, _ = o.displacement()
+    X = s.read_wall()["X"]
+    e_x = rel_l2(X - c["mesh"]["X0"], Do)
+    floor = np.finfo(float).eps * np.linalg.norm(X) / np.linalg.norm(Do)
+    assert e_x <= 1e-11 + floor, (e_x, floor)
+
+
 def test_band_follows_a_moving_wall(oracle_mod, amd):
     """The wall moves 2.9 lu outwards: with the band fixed where it was
     built the stencils leave it (LBM_E_BAND); with the periodic motion test
