@@ -199,6 +199,7 @@ struct Wall {
   int64_t band_cap = 0;
   std::vector<int32_t> band;
   std::vector<double> X0;      // rest positions, xyz per point (host copy)
+  std::vector<double> Xband;   // positions the band was last built around (host copy)
 };
 
 // Instances of similar box volume share launch shapes, chosen by the
@@ -413,15 +414,18 @@ void make_classes(lbm_ctx* c) {
 // or one of each per class (per_class, for timing them apart).  Packs and
 // uploads the tile table and the wall list.
 // Whether wall i's tiles of tj x 256/tj points need the large-box wall
-// kernel: more than 1 in 10 of their stencil boxes at the rest shape exceed
-// 90 % of the standard staging capacity (coarse meshes; the margin leaves
-// room for the wall's motion).
+// kernel: some stencil box, at the positions the band was last built
+// around, exceeds 90 % of the standard staging capacity (coarse meshes, or
+// a wall whose motion has stretched its tiles; the margin leaves room for
+// the motion until the next band build).  One tile on the unstaged path
+// (stencils read and spread in global memory) sets the whole launch's
+// duration, so a single one is enough to switch.
 bool wall_needs_bigbox(const lbm_ctx* c, int i, int tj) {
   const InstDesc& d = c->inst[i];
-  const std::vector<double>& X = c->wall[i].X0;
+  const std::vector<double>& X = c->wall[i].Xband;
   const int tk = 256 / tj, nth = d.nth, nzl = d.nzl;
   const int64_t cap = wall_boxcap(c->prec == 0 ? 8 : 4, tj) * 9 / 10;
-  int64_t over = 0, total = 0;
+  int64_t over = 0;
   for (int k0 = 0; k0 < nzl; k0 += tk)
     for (int j0 = 0; j0 < nth; j0 += tj) {
       int lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
@@ -435,9 +439,8 @@ bool wall_needs_bigbox(const lbm_ctx* c, int i, int tj) {
       int64_t vol = 1;
       for (int a = 0; a < 3; ++a) vol *= (int64_t)(hi[a] - lo[a] + 4);
       over += vol > cap;
-      ++total;
     }
-  return over * 10 > total;
+  return over > 0;
 }
 
 lbm_status build_groups(lbm_ctx* c, bool per_class) {
@@ -541,6 +544,7 @@ lbm_status rebuild_bands(lbm_ctx* c) {
     HIPCHK(c, hipMemcpy(c->work + c->L.inst + k * sizeof(InstDesc), &d, sizeof d, hipMemcpyHostToDevice));
     W.band.swap(band);
     W.nband = d.nband;
+    W.Xband.swap(X);
     maxb = std::max(maxb, W.nband);
   }
   HIPCHK(c, hipMemset(c->work + c->L.moved, 0, 4));
@@ -1161,6 +1165,7 @@ lbm_status lbm_fsi_exchange(lbm_ctx* c, int32_t k, const lbm_wall_desc* w, void*
   c->wall[k].margin = w->band_margin > 0 ? w->band_margin : 2;
   c->wall[k].band_cap = band_capacity((int64_t)band.size());
   c->wall[k].X0.assign(w->X0_host, w->X0_host + 3 * np);
+  c->wall[k].Xband = c->wall[k].X0;
   c->walls.clear();
   int maxb = 0, maxmt = 0;
   int64_t maxp = 0;
@@ -1534,6 +1539,12 @@ lbm_status lbm_load(lbm_ctx* c, const char* path) {
     W.band.swap(band);
     W.nband = d.nband;
     W.margin = r[k].margin;
+    // positions the restored band was built around: X0 + Dref
+    std::vector<double> Dr((size_t)d.np * 4);
+    HIPCHK(c, hipMemcpy(Dr.data(), d.Dref, (size_t)d.np * 32, hipMemcpyDeviceToHost));
+    W.Xband.resize((size_t)d.np * 3);
+    for (int64_t p = 0; p < d.np; ++p)
+      for (int a = 0; a < 3; ++a) W.Xband[3 * p + a] = W.X0[3 * p + a] + Dr[4 * p + a];
     maxb = std::max(maxb, W.nband);
   }
   std::fclose(f);
