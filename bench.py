@@ -377,7 +377,8 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the method's multi-GPU sharding is described in DESIGN.md)", file=sys.stderr)
+              "(the library runs on one GPU; how the method would shard is a design note, not code)",
+              file=sys.stderr)
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
