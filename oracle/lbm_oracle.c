@@ -547,9 +547,22 @@ static real delta(const orc_t* o, real r) { return o->kernel == 1 ? phicos(r) : 
 
 /* V(X) = sum over the 4x4x4 stencil of u(node) phi phi phi, FLUID nodes only,
  * for the point X = x0 + d; u is a dense [cell][3] field. */
+/* The stencil of the point X = x0 + d: the 4 x 4 x 4 nodes from
+ * base = floor(X) - 1, and the kernel's value along each axis at each of its
+ * 4 node offsets (phi(x - X) per axis; a node's weight is their product). */
+static void ib_stencil(const orc_t* o, const real* x0, const real* d, int base[3], real phi[3][4]) {
+  for (int a = 0; a < 3; ++a) {
+    base[a] = (int)floor(x0[a] + d[a]) - 1;
+    for (int m = 0; m < 4; ++m) phi[a][m] = delta(o, ((base[a] + m) - x0[a]) - d[a]);
+  }
+}
+
+/* V(X) = sum over the 4x4x4 stencil of u(node) phi phi phi, FLUID nodes only,
+ * for the point X = x0 + d; u is a dense [cell][3] field. */
 static void ib_interp_one(const orc_t* o, const real* x0, const real* d, const real* u, real V[3]) {
   int base[3];
-  for (int a = 0; a < 3; ++a) base[a] = (int)floor(x0[a] + d[a]) - 1;
+  real phi[3][4];
+  ib_stencil(o, x0, d, base, phi);
   V[0] = V[1] = V[2] = 0;
   for (int c = 0; c < 4; ++c)
     for (int bb = 0; bb < 4; ++bb)
@@ -558,25 +571,53 @@ static void ib_interp_one(const orc_t* o, const real* x0, const real* d, const r
         if (x < 0 || y < 0 || z < 0 || x >= o->nx || y >= o->ny || z >= o->nz) continue;
         long id = cidx(o, x, y, z);
         if (o->type[id] != T_FLUID) continue;
-        real w = delta(o, (x - x0[0]) - d[0]) * delta(o, (y - x0[1]) - d[1]) * delta(o, (z - x0[2]) - d[2]);
+        real w = phi[0][a] * phi[1][bb] * phi[2][c];
         for (int k = 0; k < 3; ++k) V[k] += u[3 * id + k] * w;
       }
 }
 
-/* b(node) += F area phi phi phi, FLUID nodes only, points in order. */
-static void ib_spread_one(const orc_t* o, const real* x0, const real* d, const real F[3], real area, real* b) {
+/* b(node) += F area phi phi phi, FLUID nodes only, for the nodes of the
+ * stencil with zlo <= z < zhi. */
+static void ib_spread_one(const orc_t* o, const real* x0, const real* d, const real F[3], real area, real* b,
+                          int zlo, int zhi) {
   int base[3];
-  for (int a = 0; a < 3; ++a) base[a] = (int)floor(x0[a] + d[a]) - 1;
+  real phi[3][4];
+  ib_stencil(o, x0, d, base, phi);
   for (int c = 0; c < 4; ++c)
     for (int bb = 0; bb < 4; ++bb)
       for (int a = 0; a < 4; ++a) {
         int x = base[0] + a, y = base[1] + bb, z = base[2] + c;
-        if (x < 0 || y < 0 || z < 0 || x >= o->nx || y >= o->ny || z >= o->nz) continue;
+        if (x < 0 || y < 0 || z < zlo || x >= o->nx || y >= o->ny || z >= zhi) continue;
         long id = cidx(o, x, y, z);
         if (o->type[id] != T_FLUID) continue;
-        real w = delta(o, (x - x0[0]) - d[0]) * delta(o, (y - x0[1]) - d[1]) * delta(o, (z - x0[2]) - d[2]);
+        real w = phi[0][a] * phi[1][bb] * phi[2][c];
         for (int k = 0; k < 3; ++k) b[3 * id + k] += F[k] * area * w;
       }
+}
+
+/* b = sum over all points, in index order, of their spread force.  Each
+ * thread owns a range of z planes and adds only into its own cells while it
+ * walks every point in order, so each cell receives its terms in the same
+ * order whatever the thread count. */
+static void ib_spread_all(const orc_t* o, long np, const real* X0, const real* Dn, const real* F, real area,
+                          real* b) {
+#pragma omp parallel
+  {
+    int nt = 1, t = 0;
+#ifdef _OPENMP
+    nt = omp_get_num_threads();
+    t = omp_get_thread_num();
+#endif
+    const int zlo = (int)((long)o->nz * t / nt), zhi = (int)((long)o->nz * (t + 1) / nt);
+    for (long p = 0; p < np; ++p) {
+      const real* x0 = &X0[3 * p];
+      const real* d = Dn ? &Dn[3 * p] : NULL;
+      const int zb = (int)floor(x0[2] + (d ? d[2] : 0)) - 1;
+      if (zb + 3 < zlo || zb >= zhi) continue;
+      const real zero[3] = {0, 0, 0};
+      ib_spread_one(o, x0, d ? d : zero, &F[3 * p], area, b, zlo, zhi);
+    }
+  }
 }
 
 void orc_ib_interp(void* ov, long np, const double* X, const double* u, double* V) {
@@ -593,13 +634,12 @@ void orc_ib_interp(void* ov, long np, const double* X, const double* u, double* 
 void orc_ib_spread(void* ov, long np, const double* X, const double* F, double area, double* b) {
   orc_t* o = (orc_t*)ov;
   real* bb = (real*)calloc((size_t)3 * o->ncell, sizeof(real));
-  for (long p = 0; p < np; ++p) {
-    real x0[3] = {X[3 * p], X[3 * p + 1], X[3 * p + 2]}, d[3] = {0, 0, 0};
-    real f[3] = {F[3 * p], F[3 * p + 1], F[3 * p + 2]};
-    ib_spread_one(o, x0, d, f, area, bb);
-  }
+  real* xx = (real*)malloc(sizeof(real) * 3 * np + 1);
+  real* ff = (real*)malloc(sizeof(real) * 3 * np + 1);
+  for (long k = 0; k < 3 * np; ++k) { xx[k] = X[k]; ff[k] = F[k]; }
+  ib_spread_all(o, np, xx, NULL, ff, area, bb);
   for (long k = 0; k < 3 * o->ncell; ++k) b[k] = (double)bb[k];
-  free(bb);
+  free(bb); free(xx); free(ff);
 }
 
 /* Membrane force per unit area on every point (Eq. structure restricted to the
@@ -612,6 +652,7 @@ static void membrane_force(const orc_t* o, const real* D, real* Fel) {
   real* kt = (real*)calloc((size_t)3 * o->np, sizeof(real));
   real* kz = (real*)calloc((size_t)3 * o->np, sizeof(real));
   real dt2 = o->ds_th * o->ds_th, dz2 = o->ds_z * o->ds_z;
+#pragma omp parallel for schedule(static)
   for (int k = 0; k < nzl; ++k)
     for (int jj = 0; jj < nth; ++jj) {
       long p = jj + (long)nth * k;
@@ -625,6 +666,7 @@ static void membrane_force(const orc_t* o, const real* D, real* Fel) {
   /* edge vector from point a to point b: (X0_b - X0_a) + (D_b - D_a) */
 #define EDGE(a, b, out)                                                          \
   for (int q = 0; q < 3; ++q) out[q] = (X0[3 * (b) + q] - X0[3 * (a) + q]) + (D[3 * (b) + q] - D[3 * (a) + q]);
+#pragma omp parallel for schedule(static)
   for (int k = 0; k < nzl; ++k)
     for (int jj = 0; jj < nth; ++jj) {
       long p = jj + (long)nth * k;
@@ -766,6 +808,7 @@ static void one_step(orc_t* o) {
   memset(o->b, 0, sizeof(real) * 3 * o->ncell);
   if (o->np > 0) {
     real* u = (real*)malloc(sizeof(real) * 3 * o->ncell);
+#pragma omp parallel for schedule(static)
     for (long c = 0; c < 3 * o->ncell; ++c) u[c] = o->j[c] / RHO0;
 #pragma omp parallel for schedule(static)
     for (long p = 0; p < o->np; ++p) {
@@ -777,8 +820,7 @@ static void one_step(orc_t* o) {
         o->F[3 * p + a] = o->alpha * o->slip[3 * p + a] + o->beta * d; /* on the fluid */
       }
     }
-    for (long p = 0; p < o->np; ++p)
-      ib_spread_one(o, &o->X0[3 * p], &o->Dn[3 * p], &o->F[3 * p], o->area, o->b);
+    ib_spread_all(o, o->np, o->X0, o->Dn, o->F, o->area, o->b);
     free(u);
   }
   if (o->body[0] != 0 || o->body[1] != 0 || o->body[2] != 0) {
@@ -855,6 +897,7 @@ static void one_step(orc_t* o) {
   if (o->np > 0) {
     real* Fel = (real*)malloc(sizeof(real) * 3 * o->np);
     membrane_force(o, o->Dn, Fel);
+#pragma omp parallel for schedule(static)
     for (long p = 0; p < o->np; ++p) {
       long k = p / o->nth;
       for (int a = 0; a < 3; ++a) {
