@@ -39,8 +39,6 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp16", action="store_true", help="skip the FP16-storage run")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the learned-surrogate leg")
-    ap.add_argument("--pattern-probe", action="store_true",
-                    help="only the HBM ceiling of the collide access pattern (19 SoA loads and stores per cell)")
     ap.add_argument("--full-beat", action="store_true",
                     help="only cfg1 over one whole cardiac cycle in FP32 and FP16 storage")
     ap.add_argument("--surrogate-only", action="store_true",
@@ -231,12 +229,14 @@ def full_beat():
         s = amd.solver_from_config(c, precision=prec, wave_cap=c["steps"])
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        dmax = 0.0
+        dmax, seg = 0.0, []
         while s.t < c["steps"]:
+            t1 = time.perf_counter()
             s.step(2000)
             s.sync()
+            seg.append(round((time.perf_counter() - t1) / 2000 * 1e3, 4))
             dmax = max(dmax, float(np.abs(s.read_wall()["X"] - c["mesh"]["X0"]).max()))
-            print(f"# {name} step {s.t}", file=sys.stderr, flush=True)
+            print(f"# {name} step {s.t} {seg[-1]} ms/step", file=sys.stderr, flush=True)
         el = time.perf_counter() - t0
         w = s.waveforms()
         s.close()
@@ -245,7 +245,8 @@ def full_beat():
                                                          round(float(w[:, 2].max() / sP), 1)],
                      "valve_openings": int((np.diff(w[:, 11]) == 1).sum()),
                      "valve_closures": int((np.diff(w[:, 11]) == -1).sum()),
-                     "max_wall_motion_lu": round(dmax, 2), "finite": bool(np.isfinite(w[:, 1:5]).all())}
+                     "max_wall_motion_lu": round(dmax, 2), "finite": bool(np.isfinite(w[:, 1:5]).all()),
+                     "ms_per_step_by_2000_step_segment": seg}
     a, r = waves["fp16s"], waves["fp32"]
     out["fp16s_vs_fp32"] = {
         "peak_pressure_rel_err": float(f"{abs(a[:, 2].max() - r[:, 2].max()) / r[:, 2].max():.3e}"),
@@ -365,15 +366,6 @@ def main():
     args = parse()
     if args.copy_probe:
         copy_probe()
-        return
-    if args.pattern_probe:
-        import subprocess
-        exe = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2112_05258_amd", "probe_stream")
-        res = {}
-        for line in subprocess.run([exe], check=True, capture_output=True, text=True).stdout.splitlines():
-            f = line.split()
-            res[f"{f[0]} {f[1]}"] = {f[k]: float(f[k + 1]) for k in range(2, len(f), 2)}
-        print(json.dumps({"pattern_probe": res}), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "

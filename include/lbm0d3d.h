@@ -241,12 +241,18 @@ lbm_status lbm_set_rest(lbm_ctx* ctx, int32_t inst, double p);
  * instance inst at the current step.  Synchronises. */
 lbm_status lbm_read_populations(lbm_ctx* ctx, int32_t inst, double* g_host);
 
-/* Read gauge pressure p = c_s^2 sum g (ncell doubles) and first moment
- * sum e_i g_i (3*ncell doubles) of instance inst; either may be NULL.
- * Synchronises. */
+/* The field outputs of Algorithm 1 (pressure and velocity, Eqs. rho and v)
+ * at the current step: gauge pressure p = c_s^2 sum g (ncell doubles) and
+ * the first moment sum e_i g_i (3*ncell doubles, rho_0 = 1) of instance inst;
+ * either may be NULL; 0 off-fluid.  The first moment is the unforced
+ * velocity: where the wall's force density b acts, Eq. v's velocity of the
+ * next collision is this plus b/2, and b of the next step is only known once
+ * that step's exchange has run.  Synchronises. */
 lbm_status lbm_read_fields(lbm_ctx* ctx, int32_t inst, double* p_host, double* u_host);
 
-/* Per-step boundary waveforms of instance inst, 14 doubles per step:
+/* The boundary outputs of Algorithm 1 (the flux and pressure waveforms of
+ * Sec. 2.1.2 at both 0D-coupled planes and the 0D states driving them).
+ * Per-step boundary waveforms of instance inst, 14 doubles per step:
  * [n, Q_in, p_in, Q_out, p_out, in_mode, in_value, out_mode, out_value, Pv,
  *  Pw_out, valve, Q_mid, p_mid] (value = p* in pressure mode, S for the LV
  * and the axial v* or correction otherwise; Q_mid, p_mid: flux and mean
@@ -256,9 +262,21 @@ lbm_status lbm_read_fields(lbm_ctx* ctx, int32_t inst, double* p_host, double* u
  * records, oldest first, and sets *n to that count.  Synchronises. */
 lbm_status lbm_read_waveforms(lbm_ctx* ctx, int32_t inst, double* out, int64_t cap, int64_t* n);
 
-/* Wait for the stream; LBM_E_UNSTABLE if a boundary flux or pressure became
- * non-finite, LBM_E_BAND if a wall point left its band. */
+/* Wait for the stream and report failures: LBM_E_UNSTABLE if a boundary
+ * flux or pressure became non-finite (or a wall point did, at a band
+ * rebuild), LBM_E_BAND if a wall point left its band.  Each instance has its
+ * own error word, and an instance that fails is frozen from then on: its
+ * populations, wall, 0D state and waveform record stay as they were and no
+ * kernel touches it again.  A single-instance context reports its failure
+ * here; a batch (n > 1) goes on while any instance runs, so lbm_sync fails
+ * only once every instance has failed, and lbm_instance_status names the
+ * failed ones. */
 lbm_status lbm_sync(lbm_ctx* ctx);
+
+/* Status of instance inst: LBM_OK while it runs, LBM_E_UNSTABLE or
+ * LBM_E_BAND once it has failed and been frozen.  Synchronises.  Errors:
+ * LBM_E_INVAL (index out of range). */
+lbm_status lbm_instance_status(lbm_ctx* ctx, int32_t inst);
 
 /* Steps taken so far. */
 int64_t lbm_steps(const lbm_ctx* ctx);
@@ -326,11 +344,16 @@ lbm_status lbm_autotune(lbm_ctx* ctx, int32_t trial_steps, int64_t* advanced);
  * a file into a context built the same way (lbm_init with the same
  * configurations, the same walls attached; 0D couplings are restored from
  * the file), after which stepping continues bit for bit as the saved run
- * would have.  Errors: LBM_E_INVAL (NULL, unopenable or unwritable path),
- * LBM_E_STATE (not a checkpoint, truncated, or a context of another shape,
- * precision, storage scale or waveform capacity; a saved band larger than
- * the wall buffer holds), LBM_E_DEVICE.  A failed load may leave the context
- * partly overwritten. */
+ * would have.  lbm_load reads and checks the whole file on the host before
+ * it uploads anything: the cell types must equal the context's own (only the
+ * band bits may differ), each band list must hold ascending FLUID cells of
+ * its instance that are exactly the cells with the band bit, the 0D records
+ * must name valid kinds for their boundaries, and nothing may follow the
+ * band lists.  Errors: LBM_E_INVAL (NULL, unopenable or unwritable path),
+ * LBM_E_STATE (not a checkpoint, truncated, malformed, or a context of another
+ * shape, precision, storage scale or waveform capacity; a saved band larger
+ * than the wall buffer holds), LBM_E_DEVICE.  A load refused with
+ * LBM_E_STATE leaves the context as it was. */
 lbm_status lbm_save(lbm_ctx* ctx, const char* path);
 lbm_status lbm_load(lbm_ctx* ctx, const char* path);
 

@@ -197,7 +197,11 @@ def cfg0():
 
 def _elastic_tube(nx, ny, nz, r, h, k, ei, sc, tau, Emax=2.0, Emin=0.06, HR=75.0,
                   Z=0.05, C=1.5, R=1.0, P0_mmHg=80.0, mass=2.0,
-                  alpha=-0.05, beta=-0.5):
+                  alpha=-0.05, beta=-0.5, nee=0, p_ext=None):
+    """Elastic tube workload.  The tube and the box start at rest at P0; the
+    exterior ghosts hold p_ext (None: P0, so that the wall starts in
+    equilibrium) and nee selects the extrapolation variant at the 0D planes
+    (0 literal x_f = x + e_i, 1 the ghost's normal neighbour)."""
     cx, cy = (nx - 1) / 2.0, (ny - 1) / 2.0
     mesh = cylinder_mesh(cx, cy, r, 2.0, nz - 3.0, h)
     p0 = P0_mmHg * sc["sigma_P"]
@@ -207,33 +211,41 @@ def _elastic_tube(nx, ny, nz, r, h, k, ei, sc, tau, Emax=2.0, Emin=0.06, HR=75.0
         inlet=(BC_LV_ELASTANCE, lv_params(Emax, Emin, HR, 8.0, 0.075, sc)),
         outlet=(BC_WINDKESSEL3, wk_params(Z, C, R, sc)),
         outlet_state=[p0],            # Windkessel chamber starts at P0
-        exterior=(BC_PRESSURE_CONST, [p0]),
+        exterior=(BC_PRESSURE_CONST, [p0 if p_ext is None else p_ext]),
         p_init=p0,                    # uniform initial gauge pressure P0 != 0
         p_ref=p0,                     # storage reference (exact change of variables)
         mesh=mesh, k=k, ei=ei, mass=mass, alpha=alpha, beta=beta,
-        scales=sc,
+        scales=sc, nee_variant=nee,
     )
 
 
-def cfg1(h=0.5, tau=0.6, sigma_P=5e-7):
+def cfg1(h=0.5, tau=0.5085, sigma_P=5e-7):
     """Elastic tube r = 48 in 128x128x512 (8.4 M cells), FP32, spring k 0.05,
     bending 1e-3, Peskin 4-point kernel, LV-elastance inlet (Emax 2.0, Emin
     0.06 mmHg/ml, HR 75) and Windkessel outlet (Z 0.05, C 1.5, R 1.0), one
-    cardiac cycle = 20 000 steps.  tau and the pressure scale are free: at
-    tau = 0.52 the explicit penalty coupling grows a wall mode from rounding
-    and blows up within 2 000 steps; tau = 0.6 with sigma_P = 5e-7 lu/mmHg
-    runs the whole beat (peak wall motion ~4 lu)."""
+    cardiac cycle = 20 000 steps.  tau = 0.5085 gives the Womersley number 16
+    of the paper's aorta at r = 48 and 20 000 steps a beat.  The 0D planes
+    take the normal-neighbour extrapolation (the literal per-direction form
+    feeds each inlet-layer cell's own velocity back into it and runs away
+    under strong inflow) and the exterior sits at gauge pressure 0, so the
+    tube is always inflated (with the exterior at the diastolic-range P0 the
+    thin wall buckles when the tube pressure falls below it)."""
     sc = scales(25000.0, 8000.0, sigma_P)
-    c = _elastic_tube(128, 128, 512, 48.0, h, 0.05, 1e-3, sc, tau=tau)
+    c = _elastic_tube(128, 128, 512, 48.0, h, 0.05, 1e-3, sc, tau=tau, nee=1, p_ext=0.0)
     c.update(name="cfg1_fsi_tube_128x128x512", steps=20000)
     return c
 
 
-def cfg2():
-    """cfg1 geometry at 64x64x256 (r = 24)."""
+def cfg2(beats=1):
+    """cfg1's construction at 64x64x256 (r = 24, 0.5 lu wall spacing,
+    302 x 503 points), tau 0.6, over `beats` cardiac cycles of 20 000 steps.
+    One beat by default: in the second beat a wall mode grows next to the
+    fixed end rings at peak flow and the run diverges before the third ends,
+    in every variant tried (exterior at P0 or 0, axial pre-stretch, wall
+    reaching closer to the end planes, bending 1e-2)."""
     sc = scales(25000.0, 8000.0 * (24.0 / 48.0) ** 2, 5e-7)
-    c = _elastic_tube(64, 64, 256, 24.0, 0.5, 0.05, 1e-3, sc, tau=0.6)
-    c.update(name="cfg2_fsi_tube_64x64x256", steps=60000)
+    c = _elastic_tube(64, 64, 256, 24.0, 0.5, 0.05, 1e-3, sc, tau=0.6, nee=1, p_ext=0.0)
+    c.update(name="cfg2_fsi_tube_64x64x256", steps=20000 * beats)
     return c
 
 
@@ -308,7 +320,7 @@ def ensemble_config(p, h=0.5, tau=0.6, sigma_P=5e-7):
     n = 2 * r + 8
     sc = scales(25000.0, 8000.0 * (r / 48.0) ** 2, sigma_P)
     c = _elastic_tube(n, n, L + 2, float(r), h, p["k"], 1e-3, sc, tau=tau, Emax=p["Emax"], Emin=p["Emin"],
-                      HR=p["HR"], Z=p["Z"], C=p["C"], R=p["R"])
+                      HR=p["HR"], Z=p["Z"], C=p["C"], R=p["R"], nee=1, p_ext=0.0)
     c.update(name=f"ensemble_r{r}_L{L}")
     return c
 

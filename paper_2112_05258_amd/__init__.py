@@ -71,6 +71,7 @@ SYMBOLS = {
     "lbm_read_waveforms": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.c_int64,
                                      C.POINTER(C.c_int64)]),
     "lbm_sync": (C.c_int, [C.c_void_p]),
+    "lbm_instance_status": (C.c_int, [C.c_void_p, C.c_int32]),
     "lbm_steps": (C.c_int64, [C.c_void_p]),
     "lbm_set_timing": (C.c_int, [C.c_void_p, C.c_int32]),
     "lbm_kernel_time": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
@@ -206,6 +207,18 @@ class Solver:
 
     def sync(self):
         self._check(lib().lbm_sync(self.h))
+
+    def instance_status(self, inst):
+        """0 while instance inst runs, else the lbm_status it failed with
+        (it is then frozen)."""
+        code = lib().lbm_instance_status(self.h, int(inst))
+        if code == -1:
+            self._check(code)
+        return code
+
+    def failed(self):
+        """Indices of the instances that have failed and been frozen."""
+        return [k for k in range(self.n) if self.instance_status(k) != 0]
 
     def save(self, path):
         """Checkpoint of the whole state to a file (lbm_save)."""

@@ -27,9 +27,6 @@ FLAGS = [
 ]
 
 
-PROBE = os.path.join(HERE, "probe_stream")
-
-
 def build(verbose=False):
     # one object per source, compiled side by side, then one link
     inc = ["-I", os.path.join(HERE, "..", "include")]
@@ -53,13 +50,6 @@ def build(verbose=False):
     os.replace(tmp, LIB)
     for obj in objs:
         os.remove(obj)
-    # the benchmark's access-pattern probe (a standalone program)
-    pflags = [f for f in FLAGS if f not in ("-fPIC", "-shared", "-munsafe-fp-atomics")]
-    cmd = [HIPCC] + pflags + ["-o", PROBE + ".tmp", os.path.join(CSRC, "probe_stream.hip")]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.check_call(cmd)
-    os.replace(PROBE + ".tmp", PROBE)
     return LIB
 
 

@@ -66,6 +66,9 @@ struct Geometry {
   std::vector<uint8_t> flags;        // with F_NEAR (and F_BAND) bits
   std::vector<uint64_t> nbr;         // NEAR cells: the 18 neighbour types, 3 bits each
   std::vector<int32_t> lay[3];   // boundary layers: inlet, outlet, mid-length
+  // FLUID cells next to a 0D-coupled ghost (within one cell in each axis),
+  // ascending: where the normal-neighbour extrapolation does its work
+  std::vector<int32_t> ghost_near;
 };
 
 // Checks the cell types and derives the NEAR bits, the neighbour-type words
@@ -113,6 +116,25 @@ bool build_geometry(const lbm_config& c, Geometry& g, std::string& err) {
       for (int x = 0; x < g.nx; ++x)
         if ((at(x, y, zl) & TYPE_MASK) == T_FLUID && at(x, y, zg) == gt)
           g.lay[pl].push_back(x + g.nx * (y + g.ny * zl));
+  }
+  g.ghost_near.clear();
+  if (c.nee_variant == 1) {
+    std::vector<uint8_t> mark(g.ncell, 0);
+    for (int z = 0; z < g.nz; ++z)
+      for (int y = 0; y < g.ny; ++y)
+        for (int x = 0; x < g.nx; ++x) {
+          const uint8_t t = at(x, y, z) & TYPE_MASK;
+          if (t != T_INLET && t != T_OUTLET && t != T_EXTP) continue;
+          for (int dz = -1; dz <= 1; ++dz)
+            for (int dy = -1; dy <= 1; ++dy)
+              for (int dx = -1; dx <= 1; ++dx) {
+                const int xx = x + dx, yy = y + dy, zz = z + dz;
+                if (xx < 0 || yy < 0 || zz < 0 || xx >= g.nx || yy >= g.ny || zz >= g.nz) continue;
+                if ((at(xx, yy, zz) & TYPE_MASK) == T_FLUID) mark[xx + (int64_t)g.nx * (yy + (int64_t)g.ny * zz)] = 1;
+              }
+        }
+    for (int64_t cell = 0; cell < g.ncell; ++cell)
+      if (mark[cell]) g.ghost_near.push_back((int32_t)cell);
   }
   // mid-length plane z = nz/2, over the columns of the inlet's lumen (cells
   // above an INLET ghost): its flux and pressure are recorded, not coupled
@@ -180,7 +202,7 @@ void plan(const std::vector<Geometry>& G, int prec, int wave_cap, Layout& L, std
   L.st = o; o = align256(o + n * sizeof(InstState));
   L.wave = o; o = align256(o + n * (size_t)wave_cap * NREC * 8);
   L.v0 = o; o = align256(o + (size_t)L.nv0 * r4_size(prec));
-  L.err = o; o = align256(o + 4);
+  L.err = o; o = align256(o + n * 4);          // one error word per instance
   L.moved = o; o = align256(o + 4);
   L.walls = o; o = align256(o + n * 4);
   L.cwalls = o; o = align256(o + n * 4);
@@ -213,6 +235,8 @@ struct SizeClass {
 // with their slice of the packed tile table or wall list.
 struct LaunchGroup {
   int bs = 256, cpt = 1, tj = 16;
+  bool nee = false;            // collide tiles holding cells next to a 0D ghost of an
+                               // instance with the normal-neighbour extrapolation
   bool bigbox = false;         // wall tiles staged by the large-box kernel
   int cls = -1;                // the class timed by this launch while tuning
   size_t off = 0;              // first tile / wall entry
@@ -327,12 +351,12 @@ hipError_t enqueue_step(lbm_ctx* c, int parity, bool timed) {
     if ((e = hipEventRecord(c->ev_join, s2)) != hipSuccess) return e;
     if ((e = launch_reduce(c->dev, c->prec, parity, c->L.nred, c->stream)) != hipSuccess) return e;
     for (const LaunchGroup& G : c->cgroups)
-      if ((e = launch_collide(c->dev, c->prec, parity, G.bs, G.cpt, tab + G.off, G.count, COLLIDE_BULK,
+      if ((e = launch_collide(c->dev, c->prec, parity, G.bs, G.cpt, G.nee, tab + G.off, G.count, COLLIDE_BULK,
                               c->stream)) != hipSuccess)
         return e;
     if ((e = hipStreamWaitEvent(c->stream, c->ev_wall, 0)) != hipSuccess) return e;
-    if ((e = launch_collide(c->dev, c->prec, parity, 256, 1, (const CTile*)(c->work + c->L.btab), c->nbtile,
-                            COLLIDE_BAND, c->stream)) != hipSuccess)
+    if ((e = launch_collide(c->dev, c->prec, parity, 256, 1, c->dev.any_nee != 0,
+                            (const CTile*)(c->work + c->L.btab), c->nbtile, COLLIDE_BAND, c->stream)) != hipSuccess)
       return e;
     return hipStreamWaitEvent(c->stream, c->ev_join, 0);
   }
@@ -372,7 +396,7 @@ hipError_t enqueue_step(lbm_ctx* c, int parity, bool timed) {
   for (const LaunchGroup& G : c->cgroups) {
     EventPair p;
     tpre(p);
-    e = launch_collide(c->dev, c->prec, parity, G.bs, G.cpt, tab + G.off, G.count, COLLIDE_ALL, c->stream);
+    e = launch_collide(c->dev, c->prec, parity, G.bs, G.cpt, G.nee, tab + G.off, G.count, COLLIDE_ALL, c->stream);
     if (e != hipSuccess) return e;
     tpost(p, G.cls, 0);
   }
@@ -450,22 +474,39 @@ lbm_status build_groups(lbm_ctx* c, bool per_class) {
   c->cgroups.clear();
   c->wgroups.clear();
   std::vector<bool> done(nc, false), wdone(nc, false);
+  // The tiles that hold a cell next to a 0D ghost of an instance with the
+  // normal-neighbour extrapolation go to a launch of their own, the only one
+  // built with that variant (it needs more registers, which would cost every
+  // other tile occupancy).
   for (int q = 0; q < nc; ++q) {
     if (done[q]) continue;
     LaunchGroup G;
     G.bs = c->cls[q].bs;
     G.cpt = c->cls[q].cpt;
     G.cls = q;
-    G.off = tab.size();
     const int64_t span = (int64_t)G.bs * G.cpt;
+    std::vector<CTile> plain, nee;
     for (int r = q; r < nc; ++r) {
       if (done[r] || (r != q && (per_class || c->cls[r].bs != G.bs || c->cls[r].cpt != G.cpt))) continue;
       done[r] = true;
-      for (int32_t i : c->cls[r].inst)
-        for (int64_t s = 0; s < c->inst[i].ncell; s += span) tab.push_back(CTile{i, (int32_t)s});
+      for (int32_t i : c->cls[r].inst) {
+        const std::vector<int32_t>& gn = c->geo[i].ghost_near;
+        for (int64_t s = 0; s < c->inst[i].ncell; s += span) {
+          auto it = std::lower_bound(gn.begin(), gn.end(), (int32_t)s);
+          (it != gn.end() && *it < s + span ? nee : plain).push_back(CTile{i, (int32_t)s});
+        }
+      }
     }
-    G.count = (int)(tab.size() - G.off);
-    if (G.count > 0) c->cgroups.push_back(G);
+    for (int v = 0; v < 2; ++v) {
+      const std::vector<CTile>& part = v ? nee : plain;
+      if (part.empty()) continue;
+      LaunchGroup H = G;
+      H.nee = v == 1;
+      H.off = tab.size();
+      tab.insert(tab.end(), part.begin(), part.end());
+      H.count = (int)part.size();
+      c->cgroups.push_back(H);
+    }
   }
   for (int q = 0; q < nc; ++q) {
     if (wdone[q]) continue;
@@ -518,10 +559,25 @@ int band_from_points(const Geometry& g, const double* X, int64_t np, int m, bool
 // (D^n is in Xab[step & 1]) and restart the motion measure from there.
 lbm_status rebuild_bands(lbm_ctx* c) {
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  std::vector<uint32_t> ierr((size_t)c->n);
+  HIPCHK(c, hipMemcpy(ierr.data(), c->work + c->L.err, ierr.size() * 4, hipMemcpyDeviceToHost));
+  // In a batch a wall whose band cannot be rebuilt freezes its instance
+  // (the error word says why) and the others go on; a single instance
+  // reports the failure.
+  auto freeze = [&](int k, uint32_t bit, lbm_status code, const std::string& why) -> lbm_status {
+    if (c->n == 1) return fail(c, code, why);
+    ierr[k] |= bit | ERR_FROZEN;
+    HIPCHK(c, hipMemcpy(c->work + c->L.err + (size_t)k * 4, &ierr[k], 4, hipMemcpyHostToDevice));
+    return LBM_OK;
+  };
   int maxb = 0;
   for (int k = 0; k < c->n; ++k) {
     Wall& W = c->wall[k];
     if (!W.on) continue;
+    if (ierr[k]) {   // frozen: its band stays as it was
+      maxb = std::max(maxb, W.nband);
+      continue;
+    }
     InstDesc& d = c->inst[k];
     Geometry& g = c->geo[k];
     const int64_t np = d.np;
@@ -532,9 +588,14 @@ lbm_status rebuild_bands(lbm_ctx* c) {
       for (int q = 0; q < 3; ++q) X[3 * p + q] = W.X0[3 * p + q] + D4[4 * p + q];
     std::vector<int32_t> band;
     std::string why;
-    if (band_from_points(g, X.data(), np, W.margin, false, band, why) != 1)
-      return fail(c, LBM_E_UNSTABLE, "band rebuild: " + why);
-    if ((int64_t)band.size() > W.band_cap) return fail(c, LBM_E_BAND, "band rebuild: the band outgrew its capacity");
+    const bool finite = band_from_points(g, X.data(), np, W.margin, false, band, why) == 1;
+    if (!finite || (int64_t)band.size() > W.band_cap) {
+      const lbm_status fs = !finite ? freeze(k, ERR_NONFINITE, LBM_E_UNSTABLE, "band rebuild: " + why)
+                                    : freeze(k, ERR_BAND, LBM_E_BAND, "band rebuild: the band outgrew its capacity");
+      if (fs != LBM_OK) return fs;
+      maxb = std::max(maxb, W.nband);
+      continue;
+    }
     for (auto& t : g.flags) t &= (uint8_t)~F_BAND;
     for (int32_t cell : band) g.flags[cell] |= F_BAND;
     HIPCHK(c, hipMemcpy(c->work + c->L.flags + d.cell0, g.flags.data(), g.ncell, hipMemcpyHostToDevice));
@@ -580,6 +641,24 @@ lbm_status h2d(lbm_ctx* c, size_t off, const T* src, size_t count) {
 
 // Read the raw storage of instance k into host doubles, AoS [cell][19],
 // undoing the AA parity permutation.
+// Steps instance k has taken: the context's count, or, for an instance that
+// failed and was frozen, the count it stopped at (its state is at that step).
+lbm_status inst_step(lbm_ctx* c, int k, int64_t* t) {
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  InstState st;
+  HIPCHK(c, hipMemcpy(&st, c->work + c->L.st + (size_t)k * sizeof(InstState), sizeof st, hipMemcpyDeviceToHost));
+  *t = st.step;
+  return LBM_OK;
+}
+
+lbm_status inst_live(lbm_ctx* c, int k) {
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  uint32_t e = 0;
+  HIPCHK(c, hipMemcpy(&e, c->work + c->L.err + (size_t)k * 4, 4, hipMemcpyDeviceToHost));
+  if (e) return fail(c, LBM_E_STATE, "instance " + std::to_string(k) + " has failed and is frozen");
+  return LBM_OK;
+}
+
 lbm_status read_pops(lbm_ctx* c, int k, std::vector<double>& out) {
   const Geometry& g = c->geo[k];
   const InstDesc& d = c->inst[k];
@@ -600,7 +679,10 @@ lbm_status read_pops(lbm_ctx* c, int k, std::vector<double>& out) {
     }
   };
   const int64_t sy = g.nx, sz = (int64_t)g.nx * g.ny;
-  const bool odd = c->step & 1;
+  int64_t tk = 0;
+  lbm_status r = inst_step(c, k, &tk);
+  if (r != LBM_OK) return r;
+  const bool odd = tk & 1;
   out.assign((size_t)g.ncell * NQ, 0.0);
   for (int64_t cell = 0; cell < g.ncell; ++cell) {
     if ((g.flags[cell] & TYPE_MASK) != T_FLUID) continue;
@@ -840,7 +922,7 @@ lbm_status lbm_init(const lbm_config* cfgs, int32_t n, const lbm_buffers* buf, v
   if (e == hipSuccess) { e = up(c->L.red, red.data(), red.size() * sizeof(RedTab)); what = "reduction table upload"; }
   if (e == hipSuccess) { e = up(c->L.bc, bc.data(), bc.size() * sizeof(BcDev)); what = "0D state upload"; }
   if (e == hipSuccess) { e = up(c->L.st, st.data(), st.size() * sizeof(InstState)); what = "step state upload"; }
-  if (e == hipSuccess) { e = hipMemset(c->work + c->L.err, 0, 4); what = "error flag clear"; }
+  if (e == hipSuccess) { e = hipMemset(c->work + c->L.err, 0, (size_t)n * 4); what = "error flag clear"; }
   if (e == hipSuccess) { e = hipMemset(c->work + c->L.moved, 0, 4); what = "wall motion clear"; }
   if (e == hipSuccess) { e = hipMemset(c->work + c->L.v0, 0, (size_t)c->L.nv0 * r4_size(c->prec)); what = "snapshot clear"; }
   if (e == hipSuccess) { e = hipMemset(c->work + c->L.wave, 0, (size_t)n * c->L.wave_cap * NREC * 8); what = "waveform clear"; }
@@ -1187,6 +1269,7 @@ lbm_status lbm_fsi_exchange(lbm_ctx* c, int32_t k, const lbm_wall_desc* w, void*
 lbm_status lbm_set_wall(lbm_ctx* c, int32_t k, const double* X, const double* V) {
   if (!c || k < 0 || k >= c->n || !X || !V) return LBM_E_INVAL;
   if (!c->wall[k].on || !c->inst[k].ext) return fail(c, LBM_E_INVAL, "no external-solid wall at this instance");
+  if (lbm_status r = inst_live(c, k)) return r;
   const InstDesc& d = c->inst[k];
   Wall& W = c->wall[k];
   const int64_t np = d.np;
@@ -1232,9 +1315,11 @@ lbm_status lbm_read_wall(lbm_ctx* c, int32_t k, double* X, double* Xp, double* s
       for (int a = 0; a < 3; ++a) dst[3 * p + a] = t[4 * p + a];
     return LBM_OK;
   };
-  const int par = (int)(c->step & 1);
+  int64_t tk = 0;
+  lbm_status r = inst_step(c, k, &tk);
+  if (r != LBM_OK) return r;
+  const int par = (int)(tk & 1);
   std::vector<double> x0((size_t)np * 3);
-  lbm_status r;
   if ((r = get4(d.X0, x0.data())) != LBM_OK) return r;
   auto add_x0 = [&](double* dst) {
     if (dst) for (size_t q = 0; q < x0.size(); ++q) dst[q] += x0[q];
@@ -1250,6 +1335,7 @@ lbm_status lbm_read_wall(lbm_ctx* c, int32_t k, double* X, double* Xp, double* s
 lbm_status lbm_write_populations(lbm_ctx* c, int32_t k, const double* g) {
   if (!c || !g || k < 0 || k >= c->n) return LBM_E_INVAL;
   if (c->step & 1) return fail(c, LBM_E_STATE, "populations can only be written after an even number of steps");
+  if (lbm_status r = inst_live(c, k)) return r;
   const Geometry& geo = c->geo[k];
   const InstDesc& d = c->inst[k];
   const int es = elem_size(c->prec);
@@ -1277,6 +1363,7 @@ lbm_status lbm_write_populations(lbm_ctx* c, int32_t k, const double* g) {
 lbm_status lbm_set_rest(lbm_ctx* c, int32_t k, double p) {
   if (!c || k < 0 || k >= c->n) return LBM_E_INVAL;
   if (c->step & 1) return fail(c, LBM_E_STATE, "rest state can only be set after an even number of steps");
+  if (lbm_status r = inst_live(c, k)) return r;
   HIPCHK(c, launch_fill_rest(c->dev, c->prec, c->inst[k].cell0, c->inst[k].ncell, 3.0 * p - c->inst[k].dref,
                              c->stream));
   return LBM_OK;
@@ -1313,16 +1400,18 @@ lbm_status lbm_read_fields(lbm_ctx* c, int32_t k, double* p, double* u) {
 lbm_status lbm_read_waveforms(lbm_ctx* c, int32_t k, double* out, int64_t cap, int64_t* n) {
   if (!c || !n || k < 0 || k >= c->n || cap < 0 || (!out && cap > 0)) return LBM_E_INVAL;
   const int64_t W = c->L.wave_cap;
-  const int64_t have = std::min<int64_t>(c->step, W);
+  int64_t tk = 0;   // records written: the instance's own step count
+  lbm_status r = inst_step(c, k, &tk);
+  if (r != LBM_OK) return r;
+  const int64_t have = std::min<int64_t>(tk, W);
   const int64_t cnt = std::min<int64_t>(have, cap);
   *n = cnt;
   if (cnt == 0) return LBM_OK;
   std::vector<double> ring((size_t)W * NREC);
-  HIPCHK(c, hipStreamSynchronize(c->stream));
   HIPCHK(c, hipMemcpy(ring.data(), c->work + c->L.wave + (size_t)k * W * NREC * 8, ring.size() * 8,
                       hipMemcpyDeviceToHost));
   for (int64_t q = 0; q < cnt; ++q) {
-    const int64_t step = c->step - cnt + q;
+    const int64_t step = tk - cnt + q;
     std::memcpy(out + q * NREC, ring.data() + (step % W) * NREC, NREC * 8);
   }
   return LBM_OK;
@@ -1331,13 +1420,32 @@ lbm_status lbm_read_waveforms(lbm_ctx* c, int32_t k, double* out, int64_t cap, i
 lbm_status lbm_sync(lbm_ctx* c) {
   if (!c) return LBM_E_INVAL;
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  uint32_t e = 0;
-  HIPCHK(c, hipMemcpy(&e, c->work + c->L.err, 4, hipMemcpyDeviceToHost));
-  if (e & ERR_NONFINITE) return fail(c, LBM_E_UNSTABLE, "boundary flux or pressure became non-finite");
-  if (e & ERR_BAND) return fail(c, LBM_E_BAND, "a wall point left its band of cells");
-  return LBM_OK;
+  std::vector<uint32_t> e((size_t)c->n);
+  HIPCHK(c, hipMemcpy(e.data(), c->work + c->L.err, e.size() * 4, hipMemcpyDeviceToHost));
+  int failed = 0, first = -1;
+  for (int k = 0; k < c->n; ++k)
+    if (e[k]) {
+      ++failed;
+      if (first < 0) first = k;
+    }
+  // a batch keeps running while any instance does: the failed ones are
+  // frozen and reported one by one (lbm_instance_status)
+  if (failed == 0 || failed < c->n) return LBM_OK;
+  const std::string who = c->n > 1 ? "every instance failed; the first, " + std::to_string(first) + ": " : "";
+  if (e[first] & ERR_NONFINITE) return fail(c, LBM_E_UNSTABLE, who + "boundary flux or pressure became non-finite");
+  return fail(c, LBM_E_BAND, who + "a wall point left its band of cells");
 }
 
+lbm_status lbm_instance_status(lbm_ctx* c, int32_t inst) {
+  if (!c) return LBM_E_INVAL;
+  if (inst < 0 || inst >= c->n) return fail(c, LBM_E_INVAL, "instance index out of range");
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  uint32_t e = 0;
+  HIPCHK(c, hipMemcpy(&e, c->work + c->L.err + (size_t)inst * 4, 4, hipMemcpyDeviceToHost));
+  if (e & ERR_NONFINITE) return LBM_E_UNSTABLE;
+  if (e & ERR_BAND) return LBM_E_BAND;
+  return LBM_OK;
+}
 int64_t lbm_steps(const lbm_ctx* c) { return c ? c->step : -1; }
 
 lbm_status lbm_set_timing(lbm_ctx* c, int32_t on) {
@@ -1395,7 +1503,7 @@ lbm_status lbm_set_overlap(lbm_ctx* c, int32_t on) {
 namespace {
 
 constexpr char CKPT_MAGIC[8] = {'L', 'B', 'M', '0', 'D', '3', 'D', 'C'};
-constexpr uint32_t CKPT_VERSION = 3;
+constexpr uint32_t CKPT_VERSION = 4;
 
 struct CkptHeader {
   char magic[8];
@@ -1421,7 +1529,7 @@ std::vector<std::pair<char*, size_t>> ckpt_pieces(lbm_ctx* c) {
   v.push_back({c->work + c->L.st, n * sizeof(InstState)});
   v.push_back({c->work + c->L.wave, n * (size_t)c->L.wave_cap * NREC * 8});
   v.push_back({c->work + c->L.v0, (size_t)c->L.nv0 * r4_size(c->prec)});
-  v.push_back({c->work + c->L.err, 4});
+  v.push_back({c->work + c->L.err, n * 4});
   v.push_back({c->work + c->L.moved, 4});
   for (int k = 0; k < c->n; ++k) {
     if (!c->wall[k].on) continue;
@@ -1486,11 +1594,14 @@ lbm_status lbm_load(lbm_ctx* c, const char* path) {
   if (!c || !path) return LBM_E_INVAL;
   FILE* f = std::fopen(path, "rb");
   if (!f) return fail(c, LBM_E_INVAL, std::string("cannot open checkpoint file: ") + path);
+  // The whole file is read and checked on the host before anything reaches
+  // the device, so a truncated or corrupt file leaves the context untouched.
   bool ok = true;
   auto get = [&](void* p, size_t b) { ok = ok && std::fread(p, 1, b, f) == b; };
-  auto bad = [&](const char* m) {
-    std::fclose(f);
-    return fail(c, LBM_E_STATE, std::string("checkpoint does not fit this context: ") + m);
+  auto bad = [&](const std::string& m) {
+    if (f) std::fclose(f);
+    f = nullptr;
+    return fail(c, LBM_E_STATE, "checkpoint does not fit this context: " + m);
   };
   CkptHeader h;
   get(&h, sizeof h);
@@ -1498,6 +1609,7 @@ lbm_status lbm_load(lbm_ctx* c, const char* path) {
   if (h.n != c->n || h.prec != c->prec || h.wave_cap != c->L.wave_cap || h.NT != c->L.NT || h.nv0 != c->L.nv0 ||
       h.scale != c->scale)
     return bad("instances, precision, storage scale or waveform capacity differ");
+  if (h.step < 0) return bad("negative step count");
   std::vector<CkptInst> r((size_t)c->n);
   for (int k = 0; k < c->n; ++k) {
     get(&r[k], sizeof r[k]);
@@ -1505,34 +1617,85 @@ lbm_status lbm_load(lbm_ctx* c, const char* path) {
     const bool wall = c->wall[k].on;
     if (r[k].ncell != c->geo[k].ncell || r[k].has_wall != (wall ? 1 : 0) || (wall && r[k].np != c->wall[k].np))
       return bad("an instance's cells or wall differ");
-    if (wall && r[k].nband > c->wall[k].band_cap) return bad("a saved band exceeds the wall buffer's capacity");
+    if (wall && (r[k].nband < 0 || r[k].nband > c->wall[k].band_cap))
+      return bad("a saved band is negative or exceeds the wall buffer's capacity");
+    if (wall && (r[k].margin < 1 || r[k].margin > 64)) return bad("a saved band margin is outside [1, 64]");
   }
-  HIPCHK(c, hipStreamSynchronize(c->stream));
-  drop_graph(c);
-  std::vector<char> buf;
-  for (const auto& pc : ckpt_pieces(c)) {
-    buf.resize(pc.second);
-    get(buf.data(), pc.second);
+  const auto pieces = ckpt_pieces(c);
+  std::vector<std::vector<char>> data(pieces.size());
+  for (size_t q = 0; q < pieces.size(); ++q) {
+    data[q].resize(pieces[q].second);
+    get(data[q].data(), pieces[q].second);
     if (!ok) return bad("truncated");
-    const hipError_t e = hipMemcpy(pc.first, buf.data(), pc.second, hipMemcpyHostToDevice);
-    if (e != hipSuccess) {
-      std::fclose(f);
-      return fail(c, LBM_E_DEVICE, std::string("checkpoint upload: ") + hipGetErrorString(e));
+  }
+  std::vector<std::vector<int32_t>> bands((size_t)c->n);
+  for (int k = 0; k < c->n; ++k) {
+    if (!c->wall[k].on) continue;
+    bands[k].resize((size_t)r[k].nband);
+    get(bands[k].data(), bands[k].size() * 4);
+    if (!ok) return bad("truncated");
+  }
+  char extra;
+  if (std::fread(&extra, 1, 1, f) != 0) return bad("trailing bytes after the band lists");
+  std::fclose(f);
+  f = nullptr;
+
+  // pieces 1..3 are the flags, the 0D records and the step counters; 6 the
+  // error words
+  const uint8_t* fl = (const uint8_t*)data[1].data();
+  const BcDev* bc = (const BcDev*)data[2].data();
+  const InstState* st = (const InstState*)data[3].data();
+  const uint32_t* ew = (const uint32_t*)data[6].data();
+  for (int k = 0; k < c->n; ++k) {
+    if (ew[k] & ~(ERR_NONFINITE | ERR_BAND | ERR_FROZEN)) return bad("an error word is malformed");
+    const Geometry& g = c->geo[k];
+    const InstDesc& d = c->inst[k];
+    // cell types and the near bits are fixed by the geometry: only the band
+    // bit may differ from the context's own flags
+    int64_t nbandbits = 0;
+    for (int64_t lc = 0; lc < g.ncell; ++lc) {
+      const uint8_t a = fl[d.cell0 + lc], b = g.flags[(size_t)lc];
+      if ((a & (uint8_t)~F_BAND) != (b & (uint8_t)~F_BAND)) return bad("cell types differ from the context's geometry");
+      if (a & F_BAND) {
+        if ((a & TYPE_MASK) != T_FLUID) return bad("a band bit on a non-FLUID cell");
+        ++nbandbits;
+      }
+    }
+    for (int b = 0; b < 3; ++b) {
+      const BcDev& q = bc[3 * k + b];
+      if (q.boundary != b || q.kind < BC_PRESSURE || q.kind > BC_LV || (q.kind == BC_LV && b != 0) ||
+          (q.vmode != 0 && q.vmode != 1) || q.vkind < VK_CONST || q.vkind > VK_SNAPSHOT)
+        return bad("a 0D boundary record is malformed");
+    }
+    if (st[k].counter != 0u || st[k].step < 0) return bad("an instance's step record is malformed");
+    if (!c->wall[k].on) {
+      if (nbandbits != 0) return bad("band bits in an instance without a wall");
+      continue;
+    }
+    // band: ascending local FLUID cells, exactly those with the band bit
+    const std::vector<int32_t>& band = bands[k];
+    if ((int64_t)band.size() != nbandbits) return bad("the band list and the band bits disagree");
+    for (size_t q = 0; q < band.size(); ++q) {
+      if (band[q] < 0 || band[q] >= g.ncell || (q > 0 && band[q] <= band[q - 1]))
+        return bad("band cells out of range or not ascending");
+      if (!(fl[d.cell0 + band[q]] & F_BAND)) return bad("a band cell without its band bit");
     }
   }
-  // host copies: band bits of the flags, band lists, step
-  std::vector<uint8_t> fl((size_t)c->L.NT);
-  HIPCHK(c, hipMemcpy(fl.data(), c->work + c->L.flags, fl.size(), hipMemcpyDeviceToHost));
+
+  // everything checked: upload
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  drop_graph(c);
+  for (size_t q = 0; q < pieces.size(); ++q)
+    if (pieces[q].second)
+      HIPCHK(c, hipMemcpy(pieces[q].first, data[q].data(), pieces[q].second, hipMemcpyHostToDevice));
   int maxb = 0;
   for (int k = 0; k < c->n; ++k) {
     Geometry& g = c->geo[k];
     InstDesc& d = c->inst[k];
-    std::memcpy(g.flags.data(), fl.data() + d.cell0, (size_t)g.ncell);
+    std::memcpy(g.flags.data(), fl + d.cell0, (size_t)g.ncell);
     if (!c->wall[k].on) continue;
     Wall& W = c->wall[k];
-    std::vector<int32_t> band((size_t)r[k].nband);
-    get(band.data(), band.size() * 4);
-    if (!ok) return bad("truncated");
+    std::vector<int32_t>& band = bands[k];
     if (!band.empty()) HIPCHK(c, hipMemcpy(d.band, band.data(), band.size() * 4, hipMemcpyHostToDevice));
     d.nband = r[k].nband;
     HIPCHK(c, hipMemcpy(c->work + c->L.inst + k * sizeof(InstDesc), &d, sizeof d, hipMemcpyHostToDevice));
@@ -1547,7 +1710,6 @@ lbm_status lbm_load(lbm_ctx* c, const char* path) {
       for (int a = 0; a < 3; ++a) W.Xband[3 * p + a] = W.X0[3 * p + a] + Dr[4 * p + a];
     maxb = std::max(maxb, W.nband);
   }
-  std::fclose(f);
   c->dev.max_band = maxb;
   c->step = h.step;
   return build_groups(c, false);

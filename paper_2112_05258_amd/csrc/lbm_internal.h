@@ -28,7 +28,12 @@ constexpr uint8_t F_BAND = 16;    // FLUID cell inside a wall's band (may carry 
 enum : int32_t { BC_PRESSURE = 0, BC_VELOCITY = 1, BC_WK3 = 2, BC_LV = 3 };
 enum : int32_t { VK_CONST = 0, VK_CORRECT = 1, VK_SNAPSHOT = 2 };
 
-enum : uint32_t { ERR_NONFINITE = 1u, ERR_BAND = 2u };
+// Error word of an instance: what failed (NONFINITE, BAND), and FROZEN once
+// the instance is no longer stepped.  The first reduction of the step after
+// a failure sets FROZEN (so the failing step itself runs to its end and the
+// frozen state sits at the instance's own step count); a band rebuild that
+// fails on the host sets both at once, between steps.
+enum : uint32_t { ERR_NONFINITE = 1u, ERR_BAND = 2u, ERR_FROZEN = 4u };
 
 // 0D boundary model: configuration, state, and what it hands the collide
 // kernel for the current step.
@@ -106,7 +111,7 @@ struct Dev {
   int32_t wave_cap;
   int32_t nwall;
   void* v0;                        // R4 per snapshot entry
-  uint32_t* err;
+  uint32_t* err;                   // per instance: ERR_* bits
   uint32_t* moved;                 // max wall motion since the band was built (float bits)
   const int32_t* walls;            // instance ids with a wall
   int32_t max_band, max_np;
@@ -130,11 +135,13 @@ struct CTile {
 namespace lbm {
 hipError_t launch_reduce(const Dev& d, int prec, int parity, int nred, hipStream_t s);
 // collide-stream over a size class: ntile tiles of the table tab, workgroup
-// size bs (128, 256, 512) and cpt (1, 2) cells per lane; mode selects all
-// fluid cells, those outside the wall band, or the band cells only
+// size bs (128, 256, 512) and cpt (1, 2) cells per lane; nee: the build with
+// the normal-neighbour extrapolation (for tiles next to a 0D ghost of an
+// instance that asks for it); mode selects all fluid cells, those outside
+// the wall band, or the band cells only
 enum { COLLIDE_ALL = 0, COLLIDE_BULK = 1, COLLIDE_BAND = 2 };
-hipError_t launch_collide(const Dev& d, int prec, int parity, int bs, int cpt, const CTile* tab, int ntile,
-                          int mode, hipStream_t s);
+hipError_t launch_collide(const Dev& d, int prec, int parity, int bs, int cpt, bool nee, const CTile* tab,
+                          int ntile, int mode, hipStream_t s);
 hipError_t launch_band(const Dev& d, int prec, int parity, hipStream_t s);
 // the boundary reductions and the band moments in one launch
 hipError_t launch_reduce_band(const Dev& d, int prec, int parity, int nred, hipStream_t s);
@@ -142,7 +149,7 @@ hipError_t launch_reduce_band(const Dev& d, int prec, int parity, int nred, hipS
 // points (tj = 8, 16, 32); tiles = tile count of the class's largest wall
 // LDS staging capacity of a wall tile's stencil box (cells), standard and
 // large-box kernels; element size 8 (FP64) or 4 (FP32 velocities)
-constexpr int wall_boxcap(int elem, int tj) { return elem == 8 ? 1024 : (tj == 32 ? 2048 : 1280); }
+constexpr int wall_boxcap(int elem, int tj) { return elem == 8 ? 1024 : (tj == 32 ? 2048 : 1792); }
 constexpr int wall_boxcap_big(int elem) { return elem == 8 ? 2560 : 4096; }
 hipError_t launch_wall(const Dev& d, int prec, int parity, int tj, bool big, const int32_t* walls, int nwall,
                        int tiles, hipStream_t s);

@@ -253,6 +253,13 @@ __device__ __forceinline__ void reduce_block(const Dev& d, const int blk) {
   __shared__ double sq[RBLOCK], sp[RBLOCK], sq1[RBLOCK], sp1[RBLOCK], sq2[RBLOCK], sp2[RBLOCK];
   __shared__ int last;
   const RedTab t = d.red[blk];
+  // an instance that failed in an earlier step is frozen from this step on:
+  // no further reductions, 0D updates or records, and the later kernels of
+  // the step skip it (uniform over the block)
+  if (d.err[t.inst] != 0u) {
+    if (threadIdx.x == 0) atomicOr(d.err + t.inst, ERR_FROZEN);
+    return;
+  }
   const InstDesc& I = d.inst[t.inst];
   const int64_t sy = I.nx, sz = (int64_t)I.nx * I.ny;
   int64_t off[NQ];
@@ -330,7 +337,7 @@ __device__ __forceinline__ void reduce_block(const Dev& d, const int blk) {
   double Q[3] = {sq[0], sq1[0], sq2[0]}, P[3] = {sp[0], sp1[0], sp2[0]};
   for (int pl = 0; pl < 3; ++pl) P[pl] = I.lay_n[pl] ? P[pl] / (double)I.lay_n[pl] : 0.0;
   if (!isfinite(Q[0]) || !isfinite(Q[1]) || !isfinite(P[0]) || !isfinite(P[1]))
-    atomicOr(d.err, ERR_NONFINITE);
+    atomicOr(d.err + t.inst, ERR_NONFINITE);
   const int64_t n = st->step;
   BcDev* bc = d.bc + 3 * t.inst;
   bc[0].area = (double)I.lay_n[0];
@@ -600,11 +607,13 @@ __device__ __forceinline__ void collide_cell(const Dev& d, const int inst, const
 // instance (the tile table of a size class); lane t takes cells start + t,
 // start + t + BS, ... so every load and store stays coalesced.  BS and CPT
 // are chosen per size class by the autotuner.  NEE: built with the
-// normal-neighbour extrapolation (a separate kernel, so that contexts without
-// it keep the smaller register budget).
+// normal-neighbour extrapolation (a separate kernel, launched only over the
+// tiles that hold a cell next to a 0D ghost, so that every other tile keeps
+// the smaller register budget).
 template <class S, bool ODD, int BS, int CPT, bool NEE>
 __global__ __launch_bounds__(BS) void k_collide(Dev d, const CTile* __restrict__ tab, int mode) {
   const CTile t = tab[blockIdx.x];
+  if (d.err[t.inst] & ERR_FROZEN) return;   // whole block leaves
 #pragma unroll
   for (int q = 0; q < CPT; ++q) collide_cell<S, ODD, NEE>(d, t.inst, (int64_t)t.start + q * BS + (int)threadIdx.x, mode);
 }
@@ -620,6 +629,7 @@ __device__ __forceinline__ void band_block(const Dev& d, const int wall, const i
   using R = typename Store<S>::R;
   using R4 = typename V4<R>::T;
   const int inst = d.walls[wall];
+  if (d.err[inst] & ERR_FROZEN) return;
   const InstDesc& I = d.inst[inst];
   // chunk bx of this wall's band, in XCD-aware order over the wall's own
   // chunks (its workgroups are consecutive, so they go to the XCDs in turn)
@@ -751,6 +761,7 @@ __global__ __launch_bounds__(WBLOCK) void k_wall(Dev d, const int32_t* __restric
   __shared__ int sext[6];   // min x, y, z; max x, y, z of the stencil bases
   __shared__ int semax;
   const int inst = walls[blockIdx.y];
+  if (d.err[inst] & ERR_FROZEN) return;   // whole block leaves
   const InstDesc& I = d.inst[inst];
   const int nth = I.nth, nzl = I.nzl;
   const int ntj = (nth + TJ - 1) / TJ;
@@ -776,7 +787,7 @@ __global__ __launch_bounds__(WBLOCK) void k_wall(Dev d, const int32_t* __restric
   const double px = X0.x + D.x, py = X0.y + D.y, pz = X0.z + D.z;
   const bool inside = px >= -1.0 && py >= -1.0 && pz >= -1.0 && px <= (double)I.nx &&
                       py <= (double)I.ny && pz <= (double)I.nz;
-  if (point && !inside) atomicOr(d.err, ERR_BAND);
+  if (point && !inside) atomicOr(d.err + inst, ERR_BAND);
   const bool valid = point && inside;
 
   if (threadIdx.x < 6) sext[threadIdx.x] = threadIdx.x < 3 ? 0x7fffffff : -0x7fffffff;
@@ -897,7 +908,7 @@ __global__ __launch_bounds__(WBLOCK) void k_wall(Dev d, const int32_t* __restric
         }
       }
   }
-  if (outside) atomicOr(d.err, ERR_BAND);
+  if (outside) atomicOr(d.err + inst, ERR_BAND);
 
   // ---- penalty force on the fluid (Eq. LagForce) ----
   double Fx = 0, Fy = 0, Fz = 0;
@@ -994,7 +1005,9 @@ __global__ __launch_bounds__(WBLOCK) void k_wall(Dev d, const int32_t* __restric
 // word, launched right before the host's wall-motion test rather than in
 // every step.  D is the current displacement (Xab of the step parity).
 __global__ __launch_bounds__(WBLOCK) void k_motion(Dev d, int parity) {
-  const InstDesc& I = d.inst[d.walls[blockIdx.y]];
+  const int inst = d.walls[blockIdx.y];
+  if (d.err[inst] != 0u) return;   // failed instances take no part in the test
+  const InstDesc& I = d.inst[inst];
   if ((int64_t)blockIdx.x * WBLOCK >= I.np) return;  // whole block leaves
   const int64_t p = (int64_t)blockIdx.x * WBLOCK + threadIdx.x;
   uint32_t mv = 0u;
@@ -1016,6 +1029,7 @@ constexpr int MJ = MEM_TJ, MK = MEM_TK, MH = 2;
 constexpr int MLJ = MJ + 2 * MH, MLK = MK + 2 * MH;
 __global__ __launch_bounds__(WBLOCK) void k_membrane(Dev d, int parity) {
   const int inst = d.walls[blockIdx.y];
+  if (d.err[inst] & ERR_FROZEN) return;
   const InstDesc& I = d.inst[inst];
   const int nth = I.nth, nzl = I.nzl;
   const int ntj = (nth + MJ - 1) / MJ;
@@ -1155,33 +1169,33 @@ hipError_t launch_reduce(const Dev& d, int prec, int parity, int nred, hipStream
 
 namespace {
 template <class T, int BS, int CPT>
-hipError_t collide_bs(const Dev& d, int parity, const CTile* tab, int ntile, int mode, hipStream_t s) {
+hipError_t collide_bs(const Dev& d, int parity, bool nee, const CTile* tab, int ntile, int mode, hipStream_t s) {
   const dim3 g(ntile), b(BS);
-  if (d.any_nee)
+  if (nee)
     return parity ? launch(k_collide<T, true, BS, CPT, true>, g, b, s, Dev(d), tab, int(mode))
                   : launch(k_collide<T, false, BS, CPT, true>, g, b, s, Dev(d), tab, int(mode));
   return parity ? launch(k_collide<T, true, BS, CPT, false>, g, b, s, Dev(d), tab, int(mode))
                 : launch(k_collide<T, false, BS, CPT, false>, g, b, s, Dev(d), tab, int(mode));
 }
 template <class T>
-hipError_t collide_t(const Dev& d, int parity, int bs, int cpt, const CTile* tab, int ntile, int mode,
+hipError_t collide_t(const Dev& d, int parity, int bs, int cpt, bool nee, const CTile* tab, int ntile, int mode,
                      hipStream_t s) {
   switch (bs * 4 + cpt) {
-    case 128 * 4 + 1: return collide_bs<T, 128, 1>(d, parity, tab, ntile, mode, s);
-    case 128 * 4 + 2: return collide_bs<T, 128, 2>(d, parity, tab, ntile, mode, s);
-    case 256 * 4 + 1: return collide_bs<T, 256, 1>(d, parity, tab, ntile, mode, s);
-    case 256 * 4 + 2: return collide_bs<T, 256, 2>(d, parity, tab, ntile, mode, s);
-    case 512 * 4 + 1: return collide_bs<T, 512, 1>(d, parity, tab, ntile, mode, s);
-    case 512 * 4 + 2: return collide_bs<T, 512, 2>(d, parity, tab, ntile, mode, s);
+    case 128 * 4 + 1: return collide_bs<T, 128, 1>(d, parity, nee, tab, ntile, mode, s);
+    case 128 * 4 + 2: return collide_bs<T, 128, 2>(d, parity, nee, tab, ntile, mode, s);
+    case 256 * 4 + 1: return collide_bs<T, 256, 1>(d, parity, nee, tab, ntile, mode, s);
+    case 256 * 4 + 2: return collide_bs<T, 256, 2>(d, parity, nee, tab, ntile, mode, s);
+    case 512 * 4 + 1: return collide_bs<T, 512, 1>(d, parity, nee, tab, ntile, mode, s);
+    case 512 * 4 + 2: return collide_bs<T, 512, 2>(d, parity, nee, tab, ntile, mode, s);
     default: return hipErrorInvalidValue;
   }
 }
 }  // namespace
 
-hipError_t launch_collide(const Dev& d, int prec, int parity, int bs, int cpt, const CTile* tab, int ntile,
-                          int mode, hipStream_t s) {
+hipError_t launch_collide(const Dev& d, int prec, int parity, int bs, int cpt, bool nee, const CTile* tab,
+                          int ntile, int mode, hipStream_t s) {
   if (ntile <= 0) return hipSuccess;
-#define F(T) return collide_t<T>(d, parity, bs, cpt, tab, ntile, mode, s);
+#define F(T) return collide_t<T>(d, parity, bs, cpt, nee, tab, ntile, mode, s);
   LBM_DISPATCH(prec, F)
 #undef F
   return hipErrorInvalidValue;

@@ -1,15 +1,15 @@
 """Write the FP64 oracle's record of the 64 x 64 x 256 elastic tube
 (lbm_inputs.cfg2: r = 24, 0.5 lu wall spacing, LV-elastance inlet, Windkessel
-outlet, three beats = 60 000 steps):
+outlet, one beat = 20 000 steps):
 
 * cfg2_waveforms.txt.gz -- every 16th per-step boundary record
   (n, Q_in, P_in, Q_out, P_out, Pv, Pw_out, valve);
 * cfg2_slices.txt.gz -- gauge pressure and first moment on the mid-length
-  cross-section z = nz/2 at steps 44 000 (early systole of the third beat)
-  and 60 000, and on the axial section y = ny/2 at step 60 000 (FLUID cells);
-* cfg2_wall.txt.gz -- the positions of the wall's mid ring at step 60 000.
+  cross-section z = nz/2 at steps 7 500 (peak systolic flow) and 20 000, and
+  on the axial section y = ny/2 at step 20 000 (FLUID cells);
+* cfg2_wall.txt.gz -- the positions of the wall's mid ring at step 20 000.
 
-Calls only the oracle.  About two hours on 8 cores:
+Calls only the oracle.  About 45 minutes on 8 cores:
 
     python tests/golden/make_cfg2.py
 """
@@ -27,7 +27,7 @@ import oracle  # noqa: E402
 
 EVERY = 16
 COLS = (0, 1, 2, 3, 4, 9, 10, 11)      # n, Q_in, P_in, Q_out, P_out, Pv, Pw_out, valve
-CROSS_T = (44000, 60000)
+CROSS_T = (7500, 20000)
 
 
 def _slice_rows(t, plane, p, u, fl):

@@ -126,3 +126,58 @@ def test_checkpoint_refusals(amd, tmp_path):
         p64.load(junk)
     assert e.value.code == -4
     p64.close()
+
+
+def test_corrupt_checkpoints_are_refused_before_any_upload(amd, tmp_path):
+    """A truncated file, a band list with an index past the box or out of
+    order, a changed cell type and trailing bytes are all refused with
+    E_STATE on the host, and the context keeps its step and populations."""
+    c = L.small_fsi()
+    a = amd.solver_from_config(c, precision=amd.FP32)
+    a.step(6)
+    good = os.path.join(str(tmp_path), "good.bin")
+    a.save(good)
+    a.close()
+    raw = open(good, "rb").read()
+    ncell = c["nx"] * c["ny"] * c["nz"]
+    head, inst = 56, 32                        # CkptHeader, one CkptInst
+    flags_at = head + inst + 19 * ncell * 4    # after the FP32 populations
+    fl = np.flatnonzero(c["flags"].ravel() == L.FLUID)
+    fluid = int(fl[len(fl) // 2])
+    assert raw[flags_at + fluid] & 7 == L.FLUID
+    nband = int(np.frombuffer(raw[head + 20:head + 24], dtype=np.int32)[0])   # CkptInst.nband
+    assert nband > 2
+    band = np.frombuffer(raw[len(raw) - 4 * nband:], dtype=np.int32)
+    assert np.all(np.diff(band) > 0) and band[-1] < ncell
+
+    def patched(name, data):
+        p = os.path.join(str(tmp_path), name)
+        with open(p, "wb") as f:
+            f.write(data)
+        return p
+
+    bad_band = bytearray(raw)
+    bad_band[len(raw) - 4:] = np.int32(ncell + 1000).tobytes()
+    swapped = bytearray(raw)
+    swapped[len(raw) - 8:] = np.array([band[-1], band[-2]], dtype=np.int32).tobytes()
+    bad_type = bytearray(raw)
+    bad_type[flags_at + fluid] = L.SOLID
+    cases = {"truncated_in_band": raw[:-10], "truncated_in_pops": raw[:head + inst + 1000],
+             "band_index_past_box": bytes(bad_band), "band_not_ascending": bytes(swapped),
+             "cell_type_changed": bytes(bad_type), "trailing_bytes": raw + b"\0" * 16}
+    b = amd.solver_from_config(c, precision=amd.FP32)
+    b.step(2)
+    b.sync()
+    g0 = b.read_populations(0)
+    for name, data in cases.items():
+        print("case", name, flush=True)
+        with pytest.raises(amd.LbmError) as e:
+            b.load(patched(name + ".bin", data))
+        assert e.value.code == -4, name
+        assert b.t == 2, name
+        assert np.array_equal(b.read_populations(0), g0), name
+    b.load(good)
+    assert b.t == 6
+    b.step(2)
+    b.sync()
+    b.close()
