@@ -100,6 +100,32 @@ lbm_status lbm_sur_train_step(lbm_sur_ctx* c, const float* x, const float* t, in
  * in the context's memory); other shapes run one product per layer. */
 lbm_status lbm_sur_predict(lbm_sur_ctx* c, const float* x, int32_t m, float* y);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * fused inference as lbm_sur_predict, with no context.  The network
+ * (cfg->n_in <= 32, width 512, 1..7 hidden layers, 512 outputs;
+ * max_batch and train_batch are not used) is read from the caller's device
+ * arrays: theta (lbm_sur_num_params FP32 values in the parameter layout
+ * above), the input box lo, hi (n_in FP32 each) and the output scaling mu,
+ * sigma (n_out FP32 each); x (m x n_in) and y (m x 512) as for
+ * lbm_sur_predict, 0 <= m <= 2^22.  All pointers device, 4-byte aligned,
+ * owned by the caller; the work is enqueued on stream (NULL = default) and
+ * nothing is synchronised.  With the same FP32 values (parameters and
+ * scaling rounded to nearest from FP64, as lbm_sur_set_params and
+ * lbm_sur_set_scaling do) the output equals lbm_sur_predict's bit for bit.
+ * Scratch: the BF16 weights in fragment order go to a static device array
+ * of 2^21 values (4 MiB) that each GPU holds for the life of the process;
+ * every call rebuilds them from theta.  Calls on one GPU share that array,
+ * so calls that overlap on one GPU (different streams, or host threads)
+ * race.  Allocates nothing; its first call on a device looks up the array's
+ * address there.  Errors: LBM_E_INVAL (NULL or misaligned pointer, a shape
+ * the fused kernel does not take, m out of range), LBM_E_DEVICE (no
+ * device, a failed launch); lbm_sur_last_error(NULL) gives the message of
+ * this thread's last failed call. */
+lbm_status lbm_sur_predict_static(const lbm_sur_config* cfg, const float* theta, const float* lo, const float* hi,
+                                  const float* mu, const float* sigma, const float* x, int32_t m, float* y,
+                                  void* stream);
+
 /* Per-kernel time accumulation with HIP events on the context's stream
  * (matrix products and the fused inference kernel only): on/off, then
  * (launches, total ms, their FLOP count). */

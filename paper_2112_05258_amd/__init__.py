@@ -112,6 +112,8 @@ SUR_SYMBOLS = {
     "lbm_sur_train_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int32,
                                      C.c_double, C.c_double, C.c_double, C.c_double, C.POINTER(C.c_double)]),
     "lbm_sur_predict": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
+    "lbm_sur_predict_static": (C.c_int, [C.POINTER(SurConfig)] + [C.c_void_p] * 6 + [C.c_int32, C.c_void_p,
+                                                                                    C.c_void_p]),
     "lbm_sur_set_timing": (C.c_int, [C.c_void_p, C.c_int32]),
     "lbm_sur_gemm_time": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_double),
                                     C.POINTER(C.c_double)]),

@@ -21,6 +21,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -398,6 +399,31 @@ __global__ void k_frag(const uint16_t* __restrict__ wb, LayerMap L, int64_t n, u
   wf[p] = wb[L.woff[l] + (int64_t)(nt * 32 + (lane & 31)) * K + ks * 16 + (lane >> 5) * 8 + e];
 }
 
+// The same fragment-order copy straight from FP32 parameters (the
+// composition of the BF16 cast with rows padded to kp, and k_frag, element
+// for element): used by the allocation-free inference, whose fragments live
+// in a static device array rather than a context's memory.
+__global__ void k_frag_f32(const float* __restrict__ w, LayerMap L, int64_t n, uint16_t* __restrict__ wf) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  int l = 0;
+  while (l + 1 < L.nl && p >= L.woff[l + 1]) ++l;
+  const int64_t q = p - L.woff[l];
+  const int K = L.kp[l], KS = K / 16;
+  const int e = (int)(q & 7), lane = (int)((q >> 3) & 63);
+  const int64_t t = q >> 9;
+  const int ks = (int)(t % KS), nt = (int)(t / KS);
+  const int row = nt * 32 + (lane & 31), col = ks * 16 + (lane >> 5) * 8 + e;
+  wf[p] = col < L.in[l] ? f2bf(w[L.off[l] + (int64_t)row * L.in[l] + col]) : (uint16_t)0;
+}
+
+// Scratch of the allocation-free inference: the fragment-order BF16 weights
+// of one network (at most NOALLOC_WEIGHTS values: n_in <= 32, width 512,
+// up to 7 hidden layers, 512 outputs need 1 851 392).  One copy per GPU for
+// the life of the process; every call on a GPU shares it.
+constexpr int64_t NOALLOC_WEIGHTS = (int64_t)2 << 20;
+__device__ __align__(256) uint16_t scratch[NOALLOC_WEIGHTS];
+
 struct MlpArgs {
   const float* x;       // m x nin inputs
   int m, nin;
@@ -552,6 +578,12 @@ lbm_status fail(lbm_sur_ctx* c, lbm_status s, const std::string& m) {
   if (c) c->err = m;
   return s;
 }
+
+// allocation-free inference: the static fragment buffer's address per device
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+thread_local std::string g_static_err;   // last failure of a context-free call
 
 #define SURCHK(c, x)                                                               \
   do {                                                                             \
@@ -993,7 +1025,57 @@ lbm_status lbm_sur_sync(lbm_sur_ctx* c) {
   return LBM_OK;
 }
 
-const char* lbm_sur_last_error(const lbm_sur_ctx* c) { return c ? c->err.c_str() : "null context"; }
+const char* lbm_sur_last_error(const lbm_sur_ctx* c) {
+  return c ? c->err.c_str() : (g_static_err.empty() ? "null context" : g_static_err.c_str());
+}
+
+lbm_status lbm_sur_predict_static(const lbm_sur_config* cfg, const float* theta, const float* lo, const float* hi,
+                                  const float* mu, const float* sigma, const float* x, int32_t m, float* y,
+                                  void* stream) {
+  auto bad = [](lbm_status st, const char* msg) {
+    g_static_err = msg;
+    return st;
+  };
+  if (!cfg || !theta || !lo || !hi || !mu || !sigma || !x || !y) return bad(LBM_E_INVAL, "NULL argument");
+  for (const void* q : {(const void*)theta, (const void*)lo, (const void*)hi, (const void*)mu, (const void*)sigma,
+                        (const void*)x, (const void*)y})
+    if ((uintptr_t)q & 3) return bad(LBM_E_INVAL, "device arrays must be 4-byte aligned");
+  if (cfg->n_in < 1 || cfg->n_in > KPAD || cfg->width != MWID || cfg->n_out != MWID || cfg->n_hidden < 1 ||
+      cfg->n_hidden > 7)
+    return bad(LBM_E_INVAL, "allocation-free inference takes n_in <= 32, width 512, 1..7 hidden layers, 512 outputs");
+  if (m < 0 || m > (1 << 22)) return bad(LBM_E_INVAL, "row count outside [0, 2^22]");
+  int64_t np = 0, nwb = 0;
+  const LayerMap L = layer_map(*cfg, np, nwb);
+  if (nwb > NOALLOC_WEIGHTS) return bad(LBM_E_INVAL, "network larger than the static fragment buffer");
+  if (m == 0) return LBM_OK;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+    return bad(LBM_E_DEVICE, "no current device");
+  uint16_t* wf = nullptr;
+  {
+    // the array's device address on this GPU, looked up once per device
+    // (with that device current); host code never uses the symbol itself
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+      void* ptr = nullptr;
+      if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr)
+        return bad(LBM_E_DEVICE, "hipGetSymbolAddress of the static fragment buffer failed");
+      g_scratch_ptr[dev] = ptr;
+    }
+    wf = (uint16_t*)g_scratch_ptr[dev];
+  }
+  hipStream_t s = (hipStream_t)stream;
+  // every call rebuilds the fragments from the caller's parameters, so the
+  // buffer holds nothing that must start at zero
+  hipLaunchKernelGGL(k_frag_f32, dim3(blocks(nwb, 256)), dim3(256), 0, s, theta, L, nwb, wf);
+  if (hipGetLastError() != hipSuccess) return bad(LBM_E_DEVICE, "fragment kernel launch failed");
+  MlpArgs g;
+  g.x = x; g.m = m; g.nin = cfg->n_in; g.lo = lo; g.hi = hi;
+  g.wf = wf; g.w = theta; g.L = L; g.mu = mu; g.sigma = sigma; g.y = y;
+  hipLaunchKernelGGL(k_mlp_fwd, dim3(blocks(m, MR)), dim3(512), 0, s, g);
+  if (hipGetLastError() != hipSuccess) return bad(LBM_E_DEVICE, "inference kernel launch failed");
+  return LBM_OK;
+}
 
 lbm_status lbm_sur_destroy(lbm_sur_ctx* c) {
   if (!c) return LBM_E_INVAL;
