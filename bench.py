@@ -9,11 +9,15 @@ membrane update, fused collide-stream.  The same workload is then run with
 FP16 storage (FP32 collide) for the storage-precision comparison.
 
 Prints ONE JSON line.  `value` = fluid-cell updates per second (MLUPS) of the
-FP32 path over the timed steps, inputs resident in HBM.  `roofline` is the
-collide-stream kernel's algorithmic bytes per launch over its average
-duration (HIP events on the solver's stream, same timed region) against
-8 TB/s.  `cpu_baseline` is the FP64 CPU oracle on a bounded sample of the
-same workload.
+FP32 path over the timed steps, inputs resident in HBM.  The timed steps
+start PREP_STEPS steps into the cardiac cycle (valve open, wall inflating and
+moving, band rebuilds due), after the warmup; the same run also times the
+whole 20 000-step beat (`full_beat`).  `roofline` is the collide-stream
+kernel's algorithmic bytes per launch over its average duration (HIP events
+on the solver's stream, same timed region) against 8 TB/s.  `cpu_baseline`
+is the FP64 CPU oracle on a bounded sample of the same workload (all host
+threads and one), with its rates on the small rigid tube and the 64x64x256
+tube beside it.
 """
 from __future__ import annotations
 
@@ -27,6 +31,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+PREP_STEPS = 6000    # the timed window starts this far into the beat (valve open, wall moving)
 PMC_FILE = os.path.join(ROOT, "profiles", "collide_cfg1_fp32_pmc.txt")
 
 
@@ -41,10 +46,10 @@ def parse():
     ap.add_argument("--no-surrogate", action="store_true", help="skip the learned-surrogate leg")
     ap.add_argument("--full-beat", action="store_true",
                     help="only cfg1 over one whole cardiac cycle in FP32 and FP16 storage")
+    ap.add_argument("--no-full-beat", action="store_true", help="skip the whole-beat leg")
     ap.add_argument("--surrogate-only", action="store_true",
                     help="only the learned-surrogate leg (for profiling its kernels)")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble run")
-    ap.add_argument("--ensemble-steps", type=int, default=100)
     ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "fp16s", "bf16s"])
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device copy of 1 GiB (calibration of the HBM byte counters)")
@@ -97,7 +102,8 @@ def run_gpu(cfg, precision, steps, warmup):
     s = amd.solver_from_config(cfg, precision=prec)
     fl = cfg["flags"]
     nfluid = int((fl == L.FLUID).sum())
-    s.step(warmup)
+    prep = PREP_STEPS if "mesh" in cfg else 0
+    s.step(prep + warmup)
     s.sync()
     # throughput: the production path (HIP graph replays of an even+odd
     # step pair, no per-kernel events)
@@ -130,41 +136,46 @@ def run_gpu(cfg, precision, steps, warmup):
     finite = bool(np.isfinite(w[:, 1:5]).all())
     s.close()
     return dict(total_ms=total_ms, nfluid=nfluid, kt=kt, avg_collide_ms=avg_ms,
-                bytes_collide=bytes_collide, finite=finite, es=es)
+                bytes_collide=bytes_collide, finite=finite, es=es, first_step=prep + warmup)
 
 
-def precision_study_errors():
-    """Run the 16-bit storage study workload (three beats) in FP16S and BF16S
-    and compare with the FP64 oracle's stored record (tests/golden): the
-    pointwise inlet-pressure error over the pulse pressure, the error of each
-    beat's systolic peak, and the relative L2 of the inlet flux."""
+def storage_precision_errors():
+    """The 64x64x256 elastic tube (one beat, 20 000 steps) with FP16 and BF16
+    population storage against the FP64 oracle's stored record
+    (tests/golden/cfg2_*): error of the inlet pressure's systolic peak,
+    relative L2 of the inlet pressure pulse and flux waveforms and of the
+    velocity on the mid-length cross-section at peak flow."""
     import numpy as np
     import lbm_inputs as L
     import paper_2112_05258_amd as amd
     here = os.path.dirname(os.path.abspath(__file__))
-    wr = np.loadtxt(os.path.join(here, "tests", "golden", "precision_study_waveforms.txt"))
-    c = L.precision_study()
-    beat = c["steps"] // 3
+    wr = np.loadtxt(os.path.join(here, "tests", "golden", "cfg2_waveforms.txt.gz"))
+    sl = np.loadtxt(os.path.join(here, "tests", "golden", "cfg2_slices.txt.gz"))
+    slr = sl[(sl[:, 0] == 7500) & (sl[:, 1] == 0)]
+    c = L.cfg2()
+    zmid = c["nz"] // 2
+    m = c["flags"][zmid] == L.FLUID
     out = {"workload": c["name"], "steps": c["steps"]}
     for name, prec in (("fp16s", amd.FP16S), ("bf16s", amd.BF16S)):
         s = amd.solver_from_config(c, precision=prec, wave_cap=c["steps"])
-        s.step(c["steps"])
+        s.step(7500)
         s.sync()
-        w = s.waveforms()[7::8][:, (0, 1, 2, 3, 4, 9, 10, 11)]
+        u = s.fields()[1][zmid][m]
+        s.step(c["steps"] - s.t)
+        s.sync()
+        w = s.waveforms()[15::16][:, (0, 1, 2, 3, 4, 9, 10, 11)]
         s.close()
         P, Pr = w[:, 2], wr[:, 2]
-        peaks = []
-        for b in range(3):
-            m = (wr[:, 0] >= b * beat) & (wr[:, 0] < (b + 1) * beat)
-            peaks.append(abs(P[m].max() - Pr[m].max()) / Pr[m].max())
-        out[name] = {"pressure_max_err_over_pulse": float(f"{np.abs(P - Pr).max() / (Pr.max() - Pr.min()):.3e}"),
-                     "pressure_pulse_rel_l2": float(f"{np.linalg.norm(P - Pr) / np.linalg.norm(Pr - c['p_init']):.3e}"),
-                     "peak_pressure_rel_err": float(f"{max(peaks):.3e}"),
-                     "inlet_flux_rel_l2": float(f"{np.linalg.norm(w[:, 1] - wr[:, 1]) / np.linalg.norm(wr[:, 1]):.3e}")}
+        out[name] = {"peak_pressure_rel_err": float(f"{abs(P.max() - Pr.max()) / Pr.max():.3e}"),
+                     "pressure_pulse_rel_l2": float(f"{np.linalg.norm(P - Pr) / np.linalg.norm(Pr - Pr.min()):.3e}"),
+                     "inlet_flux_rel_l2": float(f"{np.linalg.norm(w[:, 1] - wr[:, 1]) / np.linalg.norm(wr[:, 1]):.3e}"),
+                     "velocity_rel_l2_peak_flow": float(f"{np.linalg.norm(u - slr[:, 5:8]) / np.linalg.norm(slr[:, 5:8]):.3e}"),
+                     "valve_closure_step": int(w[1:, 0][np.diff(w[:, 7]) == -1][0])
+                     if (np.diff(w[:, 7]) == -1).any() else None}
     return out
 
 
-def run_surrogate(n_check=64, reps=20, batch=65536):
+def run_surrogate(n_check=128, reps=20, batch=65536):
     """Trained surrogate: error against fresh solver runs on held-out
     parameter draws (the solver is the judge), inference throughput at the
     given batch, and the inference kernel's MFMA rate (HIP events on the
@@ -241,7 +252,9 @@ def full_beat():
         w = s.waveforms()
         s.close()
         waves[name] = w
-        out[name] = {"s": round(el, 2), "inlet_P_mmHg": [round(float(w[:, 2].min() / sP), 1),
+        nfl = int((c["flags"] == L.FLUID).sum())
+        out[name] = {"s": round(el, 2), "mlups": round(nfl * c["steps"] / el / 1e6, 1),
+                     "inlet_P_mmHg": [round(float(w[:, 2].min() / sP), 1),
                                                          round(float(w[:, 2].max() / sP), 1)],
                      "valve_openings": int((np.diff(w[:, 11]) == 1).sum()),
                      "valve_closures": int((np.diff(w[:, 11]) == -1).sum()),
@@ -273,10 +286,14 @@ def _band_cells(cfg):
     return int((mark & (cfg["flags"] == L.FLUID)).sum())
 
 
-def run_ensemble(steps, warmup, n=256, seed=3):
+def run_ensemble(n=256, seed=3):
     """The batched ensemble: n elastic tubes of random size and 0D / wall
-    parameters advanced together (one launch per kernel per step, HIP graph).
-    Returns aggregate MLUPS and cardiac-cycle waveforms per second."""
+    parameters advanced together (one launch per kernel per step, HIP graph),
+    with launch shapes from the autotuner, run until the member with the
+    longest cardiac cycle has completed its first.  Members that fail are
+    frozen (and listed) while the rest run on.  MLUPS over the whole run;
+    waveforms/s = cardiac cycles completed by the members that did not fail,
+    over the run's wall time."""
     import numpy as np
     import torch
     import lbm_inputs as L
@@ -287,59 +304,76 @@ def run_ensemble(steps, warmup, n=256, seed=3):
     s = amd.solver_from_configs(cfgs, precision=amd.FP32, wave_cap=64)
     t_setup = time.perf_counter() - t0
     nfluid = sum(int((c["flags"] == L.FLUID).sum()) for c in cfgs)
-    s.step(warmup)
-    s.sync()
-
-    def timed():
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(s.stream)
-        s.step(steps)
-        e1.record(s.stream)
-        e1.synchronize()
-        s.sync()
-        return e0.elapsed_time(e1)
-
-    ms_default = timed()
-    # launch shapes per size class (box-volume quartiles) from the autotuner
-    # (its trial steps are ordinary steps); the figure is the tuned run
+    beats = np.array([c["inlet"][1][2] for c in cfgs])
+    # launch shapes per size class (box-volume quartiles) from the autotuner;
+    # its trial steps are ordinary steps of the run
     t0 = time.perf_counter()
     tuned_steps = s.autotune(trial_steps=8)
     t_tune = time.perf_counter() - t0
-    ms = timed()
-    steps_per_s = steps / (ms * 1e-3)
-    # one waveform = one cardiac cycle of one tube (T_c steps)
-    wf = sum(steps_per_s / c["inlet"][1][2] for c in cfgs)
-    finite = all(bool(np.isfinite(s.waveforms(k, cap=2)[:, 1:5]).all()) for k in range(n))
+    total = int(np.ceil(beats.max()))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(total - s.t)
+    s.sync()
+    el = time.perf_counter() - t0
+    ran = total - tuned_steps
+    failed = s.failed()
+    live = np.ones(n, bool)
+    live[failed] = False
+    cycles = float(np.floor(total / beats)[live].sum())
+    finite = all(bool(np.isfinite(s.waveforms(k, cap=2)[:, 1:5]).all()) for k in range(n) if live[k])
     classes = s.classes()
     s.close()
     return {"instances": n, "cells": int(sum(c["nx"] * c["ny"] * c["nz"] for c in cfgs)), "fluid_cells": nfluid,
             "wall_points": int(sum(c["mesh"]["X0"].shape[0] for c in cfgs)),
-            "value": round(nfluid * steps / (ms * 1e-3) / 1e6, 1), "unit": "MLUPS",
-            "ms_per_step": round(ms / steps, 4), "waveforms_per_s": round(wf, 3),
-            "setup_s": round(t_setup, 1), "steps": steps, "finite": finite,
-            "default_launch_ms_per_step": round(ms_default / steps, 4),
+            "value": round(nfluid * ran / el / 1e6, 1), "unit": "MLUPS",
+            "ms_per_step": round(el / ran * 1e3, 4), "steps": total, "s": round(el, 2),
+            "waveforms_per_s": round(cycles / el, 3), "cycles_completed": int(cycles),
+            "failed_members": failed, "finite": finite, "setup_s": round(t_setup, 1),
             "autotune": {"steps": tuned_steps, "s": round(t_tune, 2),
                          "classes": [{k: c[k] for k in ("instances", "cells", "block", "cells_per_lane",
                                                         "wall_tile_theta")} for c in classes]}}
 
 
-def cpu_baseline(cfg, budget_s=20.0):
+def _oracle_rate(cfg, budget_s, max_steps):
+    """FP64 oracle MLUPS over a bounded number of steps (the first outside the clock)."""
     import oracle
-    o = oracle.from_config(cfg)
     import lbm_inputs as L
+    o = oracle.from_config(cfg)
     nfluid = int((cfg["flags"] == L.FLUID).sum())
-    o.step(1)                                # first step outside the clock
+    o.step(1)
     n, t0 = 0, time.perf_counter()
     while True:
         o.step(1)
         n += 1
         dt = time.perf_counter() - t0
-        if dt > budget_s or n >= 50:
+        if dt > budget_s or n >= max_steps:
             break
-    return dict(value=nfluid * n / dt / 1e6, unit="MLUPS", cores=oracle.num_threads(), kind="oracle",
-                sample=f"{n} steps of the full workload (FP64, {nfluid} fluid cells), {dt:.1f} s")
+    return nfluid * n / dt / 1e6, n, dt, nfluid
+
+
+def cpu_baseline(cfg, budget_s=20.0):
+    """The oracle as it stands on the host's cores: the benchmark workload on
+    every thread and on one, and the small rigid tube and the 64x64x256
+    tube on every thread."""
+    import ctypes
+    import oracle
+    import lbm_inputs as L
+    v, n, dt, nfluid = _oracle_rate(cfg, budget_s, 50)
+    out = dict(value=round(v, 2), unit="MLUPS", cores=oracle.num_threads(), kind="oracle",
+               sample=f"{n} steps of the full workload (FP64, {nfluid} fluid cells), {dt:.1f} s")
+    nt = oracle.num_threads()
+    gomp = ctypes.CDLL("libgomp.so.1")   # the OpenMP runtime the oracle runs on
+    gomp.omp_set_num_threads(1)
+    try:
+        v1, n1, dt1, _ = _oracle_rate(cfg, budget_s / 2, 8)
+    finally:
+        gomp.omp_set_num_threads(nt)
+    out["one_thread"] = {"value": round(v1, 3), "sample": f"{n1} steps, {dt1:.1f} s"}
+    for name, c in (("cfg0_rigid_tube_24x24x64", L.cfg0()), ("cfg2_fsi_tube_64x64x256", L.cfg2())):
+        vv, nn, dd, _ = _oracle_rate(c, budget_s / 4, 2000)
+        out[name] = {"value": round(vv, 2), "sample": f"{nn} steps, {dd:.1f} s"}
+    return out
 
 
 def traffic_from_profile(precision):
@@ -404,7 +438,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {desc}", "fluid_cells": r["nfluid"],
                    "precision": args.precision,
-                   "step": "reduce+0D, band, wall, collide-stream"},
+                   "step": "reduce+0D, band, wall, collide-stream",
+                   "window": f"steps {r['first_step']}..{r['first_step'] + args.steps} of the cycle"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic_from_profile(args.precision),
@@ -422,9 +457,11 @@ def main():
         out["fp16s"] = {"value": round(m16, 1), "unit": "MLUPS", "ratio_vs_fp32": round(m16 / mlups, 3),
                         "collide_ratio_vs_fp32": round(r["avg_collide_ms"] / r16["avg_collide_ms"], 3),
                         "collide_achieved_GBs": round(a16, 1), "collide_frac": round(a16 / HBM_PEAK_GBS, 4)}
-        out["fp16s"]["waveform_error_vs_fp64_oracle"] = precision_study_errors()
+        out["fp16s"]["waveform_error_vs_fp64_oracle"] = storage_precision_errors()
     if not args.no_ensemble and args.workload == "cfg1" and args.precision == "fp32":
-        out["ensemble"] = run_ensemble(args.ensemble_steps, 10)
+        out["ensemble"] = run_ensemble()
+    if not args.no_full_beat and args.workload == "cfg1" and args.precision == "fp32":
+        out["full_beat"] = full_beat()
     if not args.no_surrogate and args.workload == "cfg1" and args.precision == "fp32":
         out["surrogate"] = run_surrogate()
     if not args.no_cpu:

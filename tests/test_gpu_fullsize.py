@@ -1,7 +1,7 @@
 """Parity at the benchmark's full sizes, in the launch configuration bench.py
 times (HIP graph replays, default or autotuned launch shapes), on outputs the
-oracle computes directly: sampled cells, the boundary waveforms and sampled
-wall points after a few steps of cfg1 (8.4 M cells, 612 045 wall points),
+oracle computes directly: every fluid cell, the boundary waveforms and every
+wall point after a few steps of cfg1 (8.4 M cells, 612 045 wall points),
 members of the 256-tube ensemble, the 16-bit storage mode, and the
 surrogate's inference at batch 65 536.  The oracle runs on the host's cores
 (about a second per cfg1 step on 16 threads), so the runs are short; the
@@ -46,16 +46,15 @@ def cfg1_runs(oracle_mod, amd):
     return res
 
 
-def _sample(c, n=20000, seed=5):
-    idx = np.flatnonzero(c["flags"].ravel() == L.FLUID)
-    return np.random.default_rng(seed).choice(idx, n, replace=False)
+def _fluid(c):
+    return np.flatnonzero(c["flags"].ravel() == L.FLUID)
 
 
 def test_cfg1_fp32_full_size_matches_oracle(cfg1_runs):
     c = cfg1_runs["cfg"]
     (po, uo), wo, Do = cfg1_runs["oracle"]
     (ps, us), ws, Ds = cfg1_runs["fp32"]
-    k = _sample(c)
+    k = _fluid(c)
     e = {"u": _rel(us.reshape(-1, 3)[k], uo.reshape(-1, 3)[k]),
          "p": _rel(ps.ravel()[k], po.ravel()[k]),
          "Q": _rel(ws[:, (1, 3, 12)], wo[:, (1, 3, 12)]),
@@ -75,7 +74,7 @@ def test_cfg1_fp16s_full_size_within_storage_bound(cfg1_runs):
     c = cfg1_runs["cfg"]
     (po, uo), wo, Do = cfg1_runs["oracle"]
     (ps, us), ws, Ds = cfg1_runs["fp16s"]
-    k = _sample(c)
+    k = _fluid(c)
     e = {"u": _rel(us.reshape(-1, 3)[k], uo.reshape(-1, 3)[k]),
          "p": _rel(ps.ravel()[k], po.ravel()[k]),
          "wall": _rel(Ds, Do)}
@@ -106,7 +105,7 @@ def test_ensemble_members_full_size_match_oracle(oracle_mod, amd):
         e_w = _rel(s.read_wall(k)["X"] - cfgs[k]["mesh"]["X0"], o.displacement()[0])
         print({"member": k, "cells": int(sizes[k]), "u": f"{e_u:.2e}", "p": f"{e_p:.2e}", "wall": f"{e_w:.2e}"},
               flush=True)
-        assert e_u <= 1e-5 and e_p <= 1e-5 and e_w <= 1e-4
+        assert e_u <= 1e-5 and e_p <= 1e-5 and e_w <= 1e-5
     s.close()
 
 

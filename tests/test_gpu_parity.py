@@ -29,6 +29,13 @@ def amd():
     return amd
 
 
+def wall_bar(precision, tol, n):
+    """Bar of the wall's displacement and penalty force after n steps: FP64
+    sums the spread force's atomic-order rounding through the slip integral
+    and the displacement recursion, sqrt(n) * tol; FP32 meets tol itself."""
+    return tol * np.sqrt(n) if precision == "FP64" else tol
+
+
 def _run_pair(oracle_mod, amd, cfg, steps, precision, pops=None, **kw):
     o = oracle_mod.from_config(cfg, pops=pops, extended=(precision == amd.FP64))
     s = amd.solver_from_config(cfg, precision=precision, pops=pops, **kw)
@@ -130,7 +137,12 @@ def test_lv_inlet_valve_cycle(oracle_mod, amd, precision, tol):
 @pytest.mark.parametrize("precision,tol", [("FP64", 1e-12), ("FP32", 1e-5)])
 def test_small_elastic_tube(oracle_mod, amd, precision, tol):
     """Elastic tube (immersed membrane, LV inlet, Windkessel outlet, exterior
-    at P0): lattice fields, waveforms and wall positions."""
+    at P0): lattice fields, waveforms and wall positions.  Wall bar in FP64
+    (wall_bar): the order of the spread force's atomic additions varies, and
+    both the slip integral behind the penalty force F (a small difference
+    Vf - Vs) and the displacement recursion D^{n+1} = 2 D^n - D^{n-1} +
+    (f - F)/m sum that rounding over the n steps like a random walk, so the
+    bar is sqrt(n) times the fields' 1e-12; FP32 meets the plain bar."""
     c = L.small_fsi()
     o, s = _run_pair(oracle_mod, amd, c, 120, getattr(amd, precision))
     _compare(o, s, c["flags"], tol)
@@ -140,7 +152,7 @@ def test_small_elastic_tube(oracle_mod, amd, precision, tol):
     e_x = rel_l2(ls["X"] - X0, Do)
     e_f = rel_l2(ls["F"], lo["F"])
     print({"wall_X": f"{e_x:.2e}", "wall_F": f"{e_f:.2e}"}, flush=True)
-    assert e_x <= tol * 10 and e_f <= tol * 10
+    assert e_x <= wall_bar(precision, tol, 120) and e_f <= wall_bar(precision, tol, 120)
 
 
 @pytest.mark.parametrize("precision,tol", [("FP64", 1e-12), ("FP32", 1e-5)])
@@ -155,7 +167,7 @@ def test_cosine_kernel_small_elastic_tube(oracle_mod, amd, precision, tol):
     e_x = rel_l2(s.read_wall()["X"] - c["mesh"]["X0"], Do)
     e_f = rel_l2(s.read_wall()["F"], o.lagrangian()["F"])
     print({"wall_X": f"{e_x:.2e}", "wall_F": f"{e_f:.2e}"}, flush=True)
-    assert e_x <= tol * 10 and e_f <= tol * 10
+    assert e_x <= wall_bar(precision, tol, 120) and e_f <= wall_bar(precision, tol, 120)
 
 
 @pytest.mark.parametrize("precision,tol", [("FP64", 1e-12), ("FP32", 1e-5)])
@@ -187,7 +199,7 @@ def test_external_solid_prescribed_motion(oracle_mod, amd, precision, tol):
     e_x = rel_l2(ls["X"] - X0, lo["X"] - X0)
     e_f = rel_l2(ls["F"], lo["F"])
     print({"wall_X": f"{e_x:.2e}", "wall_F": f"{e_f:.2e}"}, flush=True)
-    assert e_x <= tol and e_f <= tol * 10
+    assert e_x <= tol and e_f <= tol   # the positions are the caller's
     with pytest.raises(amd.LbmError):   # a built-in membrane takes no positions
         t = amd.solver_from_config(L.small_fsi(), precision=amd.FP32)
         try:

@@ -85,7 +85,7 @@ def run_study(amd, precision):
 
 @pytest.mark.parametrize("precision,bars", [
     ("FP64", dict(pulse=1e-8, peak=1e-8, P=1e-8, Q=1e-8, u=1e-8)),
-    ("FP32", dict(pulse=1e-3, peak=1e-3, P=1e-3, Q=1e-3, u=1e-3)),
+    ("FP32", dict(pulse=1e-5, peak=1e-5, P=1e-5, Q=1e-5, u=1e-5)),
     ("FP16S", dict(pulse=3e-2, peak=1e-2, P=1e-2, Q=2e-2, u=2e-2)),
     ("BF16S", dict(pulse=2e-1, peak=5e-2, P=1e-1, Q=2e-1, u=2e-1)),
 ])
