@@ -147,21 +147,24 @@ bool build_geometry(const lbm_config& c, Geometry& g, std::string& err) {
 }
 
 struct Layout {
-  size_t flags, nbr, inst, ctab, btab, lay, red, red_part, bc, st, wave, v0, err, moved, walls, cwalls, total;
-  int64_t NT;
+  size_t flags, nbr, inst, ctab, btab, lay, red, red_part, bc, st, wave, v0, err, moved, walls, cwalls;
+  size_t bmark, btmp, bcnt, gate, total;
+  int64_t NT, nbcnt;
   int ntile_max, nred, nlay, wave_cap;
   int64_t nv0;
 };
 
 void plan(const std::vector<Geometry>& G, int prec, int wave_cap, Layout& L, std::vector<InstDesc>* inst,
           std::vector<int32_t>* lay, std::vector<RedTab>* red) {
-  L.NT = 0; L.ntile_max = 0; L.nred = 0; L.nlay = 0; L.nv0 = 0; L.wave_cap = wave_cap;
+  L.NT = 0; L.ntile_max = 0; L.nred = 0; L.nlay = 0; L.nv0 = 0; L.wave_cap = wave_cap; L.nbcnt = 0;
   for (size_t k = 0; k < G.size(); ++k) {
     const Geometry& g = G[k];
     InstDesc d;
     std::memset(&d, 0, sizeof d);
     d.nx = g.nx; d.ny = g.ny; d.nz = g.nz;
     d.cell0 = L.NT; d.ncell = g.ncell;
+    d.cblk0 = L.nbcnt;
+    L.nbcnt += (g.ncell + BCELLS - 1) / BCELLS;
     // collide tiles: at most one per MIN_TILE cells, whatever the launch shape
     L.ntile_max += (int)((g.ncell + MIN_TILE - 1) / MIN_TILE);
     d.v0_off = L.nv0;
@@ -206,6 +209,10 @@ void plan(const std::vector<Geometry>& G, int prec, int wave_cap, Layout& L, std
   L.moved = o; o = align256(o + 4);
   L.walls = o; o = align256(o + n * 4);
   L.cwalls = o; o = align256(o + n * 4);
+  L.bmark = o; o = align256(o + L.NT);
+  L.btmp = o; o = align256(o + L.NT);
+  L.bcnt = o; o = align256(o + (size_t)std::max<int64_t>(L.nbcnt, 1) * 4);
+  L.gate = o; o = align256(o + 4);
   L.total = o;
 }
 
@@ -260,6 +267,12 @@ struct lbm_ctx {
   std::string err;
   std::vector<Wall> wall;
   std::vector<int32_t> walls;
+  // band rebuilds on the device: the host copies of the bands (lists, sizes,
+  // band bits of the flags, positions they were built around) are out of
+  // date until refresh_bands reads them back
+  bool bands_stale = false;
+  int maxlines[3] = {0, 0, 0};   // most lines along x, y, z of a walled instance
+  int maxblk = 0;                // most blocks of BCELLS cells of a walled instance
   std::vector<SizeClass> cls;
   std::vector<LaunchGroup> cgroups, wgroups;
   // overlap of the wall exchange with the bulk collide: a side stream, the
@@ -467,7 +480,10 @@ bool wall_needs_bigbox(const lbm_ctx* c, int i, int tj) {
   return over > 0;
 }
 
+lbm_status refresh_bands(lbm_ctx* c);
+
 lbm_status build_groups(lbm_ctx* c, bool per_class) {
+  if (lbm_status r = refresh_bands(c)) return r;
   const int nc = (int)c->cls.size();
   std::vector<CTile> tab;
   std::vector<int32_t> walls;
@@ -555,9 +571,38 @@ lbm_status build_groups(lbm_ctx* c, bool per_class) {
 int band_from_points(const Geometry& g, const double* X, int64_t np, int m, bool strict, std::vector<int32_t>& band,
                      std::string& err);
 
+// Read the bands the device rebuilt back into the host copies (band lists,
+// sizes, band bits of the flags, positions they were built around).
+lbm_status refresh_bands(lbm_ctx* c) {
+  if (!c->bands_stale) return LBM_OK;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  std::vector<InstDesc> dd((size_t)c->n);
+  HIPCHK(c, hipMemcpy(dd.data(), c->work + c->L.inst, dd.size() * sizeof(InstDesc), hipMemcpyDeviceToHost));
+  std::vector<uint8_t> fl((size_t)c->L.NT);
+  HIPCHK(c, hipMemcpy(fl.data(), c->work + c->L.flags, fl.size(), hipMemcpyDeviceToHost));
+  for (int k = 0; k < c->n; ++k) {
+    Wall& W = c->wall[k];
+    if (!W.on) continue;
+    InstDesc& d = c->inst[k];
+    d.nband = dd[k].nband;
+    W.nband = d.nband;
+    W.band.resize((size_t)d.nband);
+    if (d.nband) HIPCHK(c, hipMemcpy(W.band.data(), d.band, (size_t)d.nband * 4, hipMemcpyDeviceToHost));
+    std::memcpy(c->geo[k].flags.data(), fl.data() + d.cell0, (size_t)d.ncell);
+    std::vector<double> Dr((size_t)d.np * 4);
+    HIPCHK(c, hipMemcpy(Dr.data(), d.Dref, (size_t)d.np * 32, hipMemcpyDeviceToHost));
+    W.Xband.resize((size_t)d.np * 3);
+    for (int64_t p = 0; p < d.np; ++p)
+      for (int a = 0; a < 3; ++a) W.Xband[3 * p + a] = W.X0[3 * p + a] + Dr[4 * p + a];
+  }
+  c->bands_stale = false;
+  return LBM_OK;
+}
+
 // Rebuild the band of every wall around its current positions X0 + D^n
 // (D^n is in Xab[step & 1]) and restart the motion measure from there.
 lbm_status rebuild_bands(lbm_ctx* c) {
+  if (lbm_status r = refresh_bands(c)) return r;
   HIPCHK(c, hipStreamSynchronize(c->stream));
   std::vector<uint32_t> ierr((size_t)c->n);
   HIPCHK(c, hipMemcpy(ierr.data(), c->work + c->L.err, ierr.size() * 4, hipMemcpyDeviceToHost));
@@ -609,7 +654,7 @@ lbm_status rebuild_bands(lbm_ctx* c) {
     maxb = std::max(maxb, W.nband);
   }
   HIPCHK(c, hipMemset(c->work + c->L.moved, 0, 4));
-  c->dev.max_band = maxb;
+  (void)maxb;
   drop_graph(c);
   return build_groups(c, false);
 }
@@ -617,11 +662,21 @@ lbm_status rebuild_bands(lbm_ctx* c) {
 // Wall-motion test: once a point has moved m - 1 lattice units (m = band
 // margin) since its band was built, the band is rebuilt, so that no stencil
 // reaches past it as long as no point moves a whole unit between tests.
+// The test and the rebuild run on the device without a host round trip (a
+// gate word decides); with the overlap of the wall exchange on (its
+// band-only collide pass needs the host's band lists) the host waits for the
+// motion word and rebuilds on the host.
 lbm_status check_bands(lbm_ctx* c) {
   int m = 1 << 30;
   for (int k = 0; k < c->n; ++k)
     if (c->wall[k].on) m = std::min(m, c->wall[k].margin);
   if (m == (1 << 30)) return LBM_OK;
+  if (!c->overlap) {
+    HIPCHK(c, launch_motion(c->dev, (int)(c->step & 1), c->stream));
+    HIPCHK(c, launch_band_rebuild(c->dev, (int)(c->step & 1), (float)(m - 1), c->maxlines, c->maxblk, c->stream));
+    c->bands_stale = true;
+    return LBM_OK;
+  }
   HIPCHK(c, launch_motion(c->dev, (int)(c->step & 1), c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   uint32_t bits = 0;
@@ -886,6 +941,10 @@ lbm_status lbm_init(const lbm_config* cfgs, int32_t n, const lbm_buffers* buf, v
   d.v0 = c->work + c->L.v0;
   d.err = (uint32_t*)(c->work + c->L.err);
   d.moved = (uint32_t*)(c->work + c->L.moved);
+  d.bmark = (uint8_t*)(c->work + c->L.bmark);
+  d.btmp = (uint8_t*)(c->work + c->L.btmp);
+  d.bcnt = (int32_t*)(c->work + c->L.bcnt);
+  d.gate = (uint32_t*)(c->work + c->L.gate);
   d.walls = (const int32_t*)(c->work + c->L.walls);
   d.nwall = 0;
   for (int k = 0; k < n; ++k) d.any_nee |= cfgs[k].nee_variant;
@@ -924,6 +983,10 @@ lbm_status lbm_init(const lbm_config* cfgs, int32_t n, const lbm_buffers* buf, v
   if (e == hipSuccess) { e = up(c->L.st, st.data(), st.size() * sizeof(InstState)); what = "step state upload"; }
   if (e == hipSuccess) { e = hipMemset(c->work + c->L.err, 0, (size_t)n * 4); what = "error flag clear"; }
   if (e == hipSuccess) { e = hipMemset(c->work + c->L.moved, 0, 4); what = "wall motion clear"; }
+  if (e == hipSuccess) {   // the device band rebuild keeps its marks zero between rebuilds
+    e = hipMemset(c->work + c->L.bmark, 0, (size_t)(c->L.btmp - c->L.bmark) + (size_t)c->L.NT);
+    what = "band marks clear";
+  }
   if (e == hipSuccess) { e = hipMemset(c->work + c->L.v0, 0, (size_t)c->L.nv0 * r4_size(c->prec)); what = "snapshot clear"; }
   if (e == hipSuccess) { e = hipMemset(c->work + c->L.wave, 0, (size_t)n * c->L.wave_cap * NREC * 8); what = "waveform clear"; }
   for (int k = 0; k < n && e == hipSuccess; ++k) {
@@ -1200,6 +1263,7 @@ lbm_status lbm_fsi_query_sizes(lbm_ctx* c, int32_t k, const lbm_wall_desc* w, si
 lbm_status lbm_fsi_exchange(lbm_ctx* c, int32_t k, const lbm_wall_desc* w, void* fsi, size_t fsi_bytes) {
   if (!c || k < 0 || k >= c->n || !fsi) return LBM_E_INVAL;
   if (!valid_wall(w, c->err)) return LBM_E_INVAL;
+  if (lbm_status r = refresh_bands(c)) return r;
   std::vector<int32_t> band;
   if (!wall_band(c, k, w, band, c->err)) return LBM_E_INVAL;
   Geometry& g = c->geo[k];
@@ -1232,6 +1296,8 @@ lbm_status lbm_fsi_exchange(lbm_ctx* c, int32_t k, const lbm_wall_desc* w, void*
   d.ks = w->k_stretch; d.ei = w->ei_bend; d.mass = w->mass; d.alpha = w->alpha; d.beta = w->beta;
   d.kernel = w->kernel;
   d.ext = w->mode;
+  d.band_margin = w->band_margin > 0 ? w->band_margin : 2;
+  d.band_cap = (int32_t)band_capacity((int64_t)band.size());
   std::vector<double> X4((size_t)np * 4, 0.0);
   for (int64_t p = 0; p < np; ++p)
     for (int a = 0; a < 3; ++a) X4[4 * p + a] = w->X0_host[3 * p + a];
@@ -1249,14 +1315,23 @@ lbm_status lbm_fsi_exchange(lbm_ctx* c, int32_t k, const lbm_wall_desc* w, void*
   c->wall[k].X0.assign(w->X0_host, w->X0_host + 3 * np);
   c->wall[k].Xband = c->wall[k].X0;
   c->walls.clear();
+  // launch grids sized for the largest band a wall may grow to (its list's
+  // capacity), so that bands rebuilt on the device need no new grid
   int maxb = 0, maxmt = 0;
   int64_t maxp = 0;
+  c->maxlines[0] = c->maxlines[1] = c->maxlines[2] = 0;
+  c->maxblk = 0;
   for (int q = 0; q < c->n; ++q)
     if (c->wall[q].on) {
+      const InstDesc& e = c->inst[q];
       c->walls.push_back(q);
-      maxb = std::max(maxb, c->wall[q].nband);
+      maxb = std::max(maxb, (int)c->wall[q].band_cap);
       maxp = std::max(maxp, c->wall[q].np);
-      maxmt = std::max(maxmt, membrane_tiles(c->inst[q].nth, c->inst[q].nzl));
+      maxmt = std::max(maxmt, membrane_tiles(e.nth, e.nzl));
+      c->maxlines[0] = std::max(c->maxlines[0], e.ny * e.nz);
+      c->maxlines[1] = std::max(c->maxlines[1], e.nx * e.nz);
+      c->maxlines[2] = std::max(c->maxlines[2], e.nx * e.ny);
+      c->maxblk = std::max(c->maxblk, (int)((e.ncell + BCELLS - 1) / BCELLS));
     }
   HIPCHK(c, hipMemcpy(c->work + c->L.walls, c->walls.data(), c->walls.size() * 4, hipMemcpyHostToDevice));
   c->dev.nwall = (int32_t)c->walls.size();
@@ -1483,7 +1558,9 @@ lbm_status lbm_set_overlap(lbm_ctx* c, int32_t on) {
   HIPCHK(c, hipStreamSynchronize(c->stream));
   drop_graph(c);
   c->overlap = on != 0;
-  return LBM_OK;
+  // the band-only collide pass reads the band tiles the host derives from
+  // the band lists: bring them up to date
+  return build_groups(c, false);
 }
 
 }  // extern "C"
@@ -1551,6 +1628,7 @@ extern "C" {
 
 lbm_status lbm_save(lbm_ctx* c, const char* path) {
   if (!c || !path) return LBM_E_INVAL;
+  if (lbm_status r = refresh_bands(c)) return r;
   HIPCHK(c, hipStreamSynchronize(c->stream));
   FILE* f = std::fopen(path, "wb");
   if (!f) return fail(c, LBM_E_INVAL, std::string("cannot open checkpoint file for writing: ") + path);
@@ -1698,6 +1776,7 @@ lbm_status lbm_load(lbm_ctx* c, const char* path) {
     std::vector<int32_t>& band = bands[k];
     if (!band.empty()) HIPCHK(c, hipMemcpy(d.band, band.data(), band.size() * 4, hipMemcpyHostToDevice));
     d.nband = r[k].nband;
+    d.band_margin = r[k].margin;
     HIPCHK(c, hipMemcpy(c->work + c->L.inst + k * sizeof(InstDesc), &d, sizeof d, hipMemcpyHostToDevice));
     W.band.swap(band);
     W.nband = d.nband;
@@ -1710,7 +1789,8 @@ lbm_status lbm_load(lbm_ctx* c, const char* path) {
       for (int a = 0; a < 3; ++a) W.Xband[3 * p + a] = W.X0[3 * p + a] + Dr[4 * p + a];
     maxb = std::max(maxb, W.nband);
   }
-  c->dev.max_band = maxb;
+  (void)maxb;
+  c->bands_stale = false;
   c->step = h.step;
   return build_groups(c, false);
 }

@@ -79,6 +79,9 @@ struct InstDesc {
   void* Vf;                // R4 per point (last step, for read-back)
   void* Fp;                // double4 per point: penalty force on the fluid (last step)
   int32_t* band;           // local cell ids of the band
+  int32_t band_margin;     // cells kept around the stencils (band rebuild)
+  int32_t band_cap;        // capacity of the band list
+  int64_t cblk0;           // first block count of this instance (band rebuild)
   double* Dref;            // double4 per point: displacement when the band was built
   double ds_th, ds_z, area, ks, ei, mass, alpha, beta;
 };
@@ -113,6 +116,12 @@ struct Dev {
   void* v0;                        // R4 per snapshot entry
   uint32_t* err;                   // per instance: ERR_* bits
   uint32_t* moved;                 // max wall motion since the band was built (float bits)
+  // band rebuild on the device: cell marks (two byte arrays over all cells),
+  // band cells per block of BCELLS cells, and the gate word (1: rebuild now)
+  uint8_t* bmark;
+  uint8_t* btmp;
+  int32_t* bcnt;
+  uint32_t* gate;
   const int32_t* walls;            // instance ids with a wall
   int32_t max_band, max_np;
   int32_t any_nee;                 // some instance uses the normal-neighbour extrapolation
@@ -153,6 +162,15 @@ constexpr int wall_boxcap(int elem, int tj) { return elem == 8 ? 1024 : (tj == 3
 constexpr int wall_boxcap_big(int elem) { return elem == 8 ? 2560 : 4096; }
 hipError_t launch_wall(const Dev& d, int prec, int parity, int tj, bool big, const int32_t* walls, int nwall,
                        int tiles, hipStream_t s);
+// Band rebuild on the device: the gate opens once the motion word reaches
+// thresh; then every wall's band is rebuilt around the current positions
+// (parity) by marking the stencil bases, dilating the marks along x, y and
+// z, setting the band bits of the flags and compacting the band list.
+// maxlines: most lines along x, y, z of a walled instance; maxblk: most
+// blocks of BCELLS cells of one.
+constexpr int BCELLS = 1024;
+hipError_t launch_band_rebuild(const Dev& d, int parity, float thresh, const int maxlines[3], int maxblk,
+                               hipStream_t s);
 // wall motion since the band was built, into the moved word (parity: the
 // current displacement's half of the ping-pong pair)
 hipError_t launch_motion(const Dev& d, int parity, hipStream_t s);

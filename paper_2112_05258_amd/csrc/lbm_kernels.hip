@@ -1019,6 +1019,178 @@ __global__ __launch_bounds__(WBLOCK) void k_motion(Dev d, int parity) {
   if ((threadIdx.x & 63) == 0 && mv != 0u) atomicMax(d.moved, mv);
 }
 
+// ---------------------------------------------------------------------------
+// Band rebuild on the device (launched at each band check, gated on the
+// motion word).  The band of a wall is the FLUID cells within the margin m of
+// the 4x4x4 stencils of its points: the stencil bases b = floor(X) - 1
+// (clamped into the box) are marked, the marks are dilated to
+// [b - m, b + 3 + m] along x, y and z in turn (one running window per
+// line), the band bits of the flags are set from the result and the band
+// list is compacted in ascending cell order.  Every kernel leaves at once
+// when the gate is shut.  Invariant: bmark is zero between rebuilds.
+// ---------------------------------------------------------------------------
+__global__ void k_band_gate(Dev d, float thresh) {
+  if (threadIdx.x != 0) return;
+  const float moved = __uint_as_float(*d.moved);
+  const uint32_t open = moved < thresh ? 0u : 1u;   // a NaN motion opens it as well
+  *d.gate = open;
+  if (open) *d.moved = 0u;
+}
+
+__global__ __launch_bounds__(WBLOCK) void k_band_seed(Dev d, int parity) {
+  if (*d.gate == 0u) return;
+  const int inst = d.walls[blockIdx.y];
+  if (d.err[inst] != 0u) return;   // failed instances get an empty band
+  const InstDesc& I = d.inst[inst];
+  const int64_t p = (int64_t)blockIdx.x * WBLOCK + threadIdx.x;
+  if (p >= I.np) return;
+  const double3 X0 = ld3(I.X0, p), D = ld3(I.Xab[parity], p);
+  ((double4*)I.Dref)[p] = double4{D.x, D.y, D.z, 0.0};
+  const double x = X0.x + D.x, y = X0.y + D.y, z = X0.z + D.z;
+  // a non-finite point (or one far outside the box) fails its instance; the
+  // comparisons are false for NaN
+  if (!(fabs(x) <= 1e9 && fabs(y) <= 1e9 && fabs(z) <= 1e9)) {
+    atomicOr(d.err + inst, ERR_NONFINITE | ERR_FROZEN);
+    return;
+  }
+  const int bx = min(max((int)floor(x) - 1, 0), I.nx - 1);
+  const int by = min(max((int)floor(y) - 1, 0), I.ny - 1);
+  const int bz = min(max((int)floor(z) - 1, 0), I.nz - 1);
+  d.bmark[I.cell0 + bx + (int64_t)I.nx * (by + (int64_t)I.ny * bz)] = 1;
+}
+
+// one lane per line along axis of one walled instance: out[i] = 1 when in
+// holds a mark in [i - 3 - m, i + m] on the line
+__global__ __launch_bounds__(WBLOCK) void k_band_dilate(Dev d, int axis, const uint8_t* __restrict__ in,
+                                                        uint8_t* __restrict__ out) {
+  if (*d.gate == 0u) return;
+  const InstDesc& I = d.inst[d.walls[blockIdx.y]];
+  const int64_t q = (int64_t)blockIdx.x * WBLOCK + threadIdx.x;
+  const int64_t sxy = (int64_t)I.nx * I.ny;
+  int n;
+  int64_t c0, st;
+  if (axis == 0) {          // lines (y, z)
+    if (q >= (int64_t)I.ny * I.nz) return;
+    n = I.nx; c0 = q * I.nx; st = 1;
+  } else if (axis == 1) {   // lines (x, z)
+    if (q >= (int64_t)I.nx * I.nz) return;
+    n = I.ny; c0 = q % I.nx + sxy * (q / I.nx); st = I.nx;
+  } else {                  // lines (x, y)
+    if (q >= sxy) return;
+    n = I.nz; c0 = q; st = sxy;
+  }
+  const int m = I.band_margin;
+  const int64_t base = I.cell0 + c0;
+  int cnt = 0;
+  for (int i = -3 - m; i < n; ++i) {
+    const int add = i + m, drop = i - 4 - m;
+    if (add >= 0 && add < n) cnt += in[base + add * st];
+    if (drop >= 0 && drop < n) cnt -= in[base + drop * st];
+    if (i >= 0) out[base + i * st] = cnt > 0 ? 1 : 0;
+  }
+}
+
+// sum over a 256-lane workgroup (every lane active)
+__device__ __forceinline__ int block_sum(int v, int* sh) {
+  v = __ockl_wfred_add_i32(v);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  const int t = sh[0] + sh[1] + sh[2] + sh[3];
+  __syncthreads();
+  return t;
+}
+
+// exclusive prefix over a 256-lane workgroup (every lane active)
+__device__ __forceinline__ int block_prefix(int v, int* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int off = 1; off < WBLOCK; off <<= 1) {
+    const int a = threadIdx.x >= (unsigned)off ? sh[threadIdx.x - off] : 0;
+    __syncthreads();
+    sh[threadIdx.x] += a;
+    __syncthreads();
+  }
+  const int r = sh[threadIdx.x] - v;
+  __syncthreads();
+  return r;
+}
+
+// band bits from the dilated marks (FLUID cells only), marks cleared, band
+// cells counted per block of BCELLS cells (4 consecutive cells per lane)
+__global__ __launch_bounds__(WBLOCK) void k_band_flags(Dev d) {
+  __shared__ int sh[4];
+  if (*d.gate == 0u) return;
+  const InstDesc& I = d.inst[d.walls[blockIdx.y]];
+  const int64_t b0 = (int64_t)blockIdx.x * BCELLS;
+  if (b0 >= I.ncell) return;   // whole block
+  uint8_t* fl = (uint8_t*)d.flags;
+  int cnt = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int64_t lc = b0 + 4 * threadIdx.x + q;
+    if (lc >= I.ncell) break;
+    const int64_t c = I.cell0 + lc;
+    const uint8_t f = fl[c];
+    const bool band = d.btmp[c] != 0 && (f & TYPE_MASK) == T_FLUID;
+    const uint8_t nf = band ? (uint8_t)(f | F_BAND) : (uint8_t)(f & ~F_BAND);
+    if (nf != f) fl[c] = nf;
+    d.bmark[c] = 0;
+    cnt += band ? 1 : 0;
+  }
+  cnt = block_sum(cnt, sh);
+  if (threadIdx.x == 0) d.bcnt[I.cblk0 + blockIdx.x] = cnt;
+}
+
+// exclusive scan of each wall's block counts (one workgroup per wall); the
+// total is the new band size, and a band past the list's capacity fails
+// the instance
+__global__ __launch_bounds__(WBLOCK) void k_band_scan(Dev d) {
+  __shared__ int sh[WBLOCK];
+  if (*d.gate == 0u) return;
+  const int inst = d.walls[blockIdx.x];
+  InstDesc& I = ((InstDesc*)d.inst)[inst];
+  const int nblk = (int)((I.ncell + BCELLS - 1) / BCELLS);
+  int32_t* cnt = d.bcnt + I.cblk0;
+  const int per = (nblk + WBLOCK - 1) / WBLOCK;
+  const int lo = min(nblk, (int)threadIdx.x * per), hi = min(nblk, lo + per);
+  int s = 0;
+  for (int b = lo; b < hi; ++b) s += cnt[b];
+  int run = block_prefix(s, sh);
+  for (int b = lo; b < hi; ++b) {
+    const int v = cnt[b];
+    cnt[b] = run;
+    run += v;
+  }
+  if (threadIdx.x == WBLOCK - 1) {
+    if (run > I.band_cap) atomicOr(d.err + inst, ERR_BAND | ERR_FROZEN);
+    else I.nband = run;
+  }
+}
+
+// the band list: cell ids in ascending order at the scanned block offsets
+__global__ __launch_bounds__(WBLOCK) void k_band_write(Dev d) {
+  __shared__ int sh[WBLOCK];
+  if (*d.gate == 0u) return;
+  const InstDesc& I = d.inst[d.walls[blockIdx.y]];
+  const int64_t b0 = (int64_t)blockIdx.x * BCELLS;
+  if (b0 >= I.ncell) return;   // whole block
+  bool in[4];
+  int cnt = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int64_t lc = b0 + 4 * threadIdx.x + q;
+    in[q] = lc < I.ncell && (d.flags[I.cell0 + lc] & F_BAND) != 0;
+    cnt += in[q] ? 1 : 0;
+  }
+  int off = d.bcnt[I.cblk0 + blockIdx.x] + block_prefix(cnt, sh);
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    if (in[q]) {
+      if (off < I.band_cap) I.band[off] = (int32_t)(b0 + 4 * threadIdx.x + q);
+      ++off;
+    }
+}
+
 // k_membrane: membrane forces (Eqs. tension and bending along theta and z)
 // and the wall's central-difference step, one lane per point, after k_wall
 // has produced this step's penalty force.  A workgroup takes a tile of
@@ -1253,6 +1425,24 @@ hipError_t launch_motion(const Dev& d, int parity, hipStream_t s) {
   if (d.nwall <= 0 || d.max_np <= 0) return hipSuccess;
   const dim3 g((unsigned)((d.max_np + WBLOCK - 1) / WBLOCK), d.nwall);
   return launch(k_motion, g, dim3(WBLOCK), s, Dev(d), int(parity));
+}
+hipError_t launch_band_rebuild(const Dev& d, int parity, float thresh, const int maxlines[3], int maxblk,
+                               hipStream_t s) {
+  if (d.nwall <= 0) return hipSuccess;
+  hipError_t e;
+  if ((e = launch(k_band_gate, dim3(1), dim3(64), s, Dev(d), thresh)) != hipSuccess) return e;
+  const dim3 gp((unsigned)((d.max_np + WBLOCK - 1) / WBLOCK), d.nwall);
+  if ((e = launch(k_band_seed, gp, dim3(WBLOCK), s, Dev(d), int(parity))) != hipSuccess) return e;
+  const uint8_t* src[3] = {d.bmark, d.btmp, d.bmark};
+  uint8_t* dst[3] = {d.btmp, d.bmark, d.btmp};   // x: marks -> tmp, y: tmp -> marks, z: marks -> tmp
+  for (int a = 0; a < 3; ++a) {
+    const dim3 gl((unsigned)((maxlines[a] + WBLOCK - 1) / WBLOCK), d.nwall);
+    if ((e = launch(k_band_dilate, gl, dim3(WBLOCK), s, Dev(d), int(a), src[a], dst[a])) != hipSuccess) return e;
+  }
+  const dim3 gb((unsigned)maxblk, d.nwall);
+  if ((e = launch(k_band_flags, gb, dim3(WBLOCK), s, Dev(d))) != hipSuccess) return e;
+  if ((e = launch(k_band_scan, dim3(d.nwall), dim3(WBLOCK), s, Dev(d))) != hipSuccess) return e;
+  return launch(k_band_write, gb, dim3(WBLOCK), s, Dev(d));
 }
 
 hipError_t launch_membrane(const Dev& d, int parity, hipStream_t s) {
