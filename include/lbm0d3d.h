@@ -17,9 +17,13 @@
  * - Pressures are gauge, p = P - c_s^2 (so sum f = 1 + 3p).
  * - Cell types (the flags array): FLUID 0, SOLID 1 (halfway bounce-back),
  *   INLET 2 (ghost of boundary 0, only on the plane z = 0), OUTLET 3 (ghost
- *   of boundary 1, only on z = nz-1), EXTP 4 (ghost of boundary 2, the
+ *   of an outlet, only on z = nz-1), EXTP 4 (ghost of boundary 2, the
  *   exterior, anywhere on the box faces).  Every cell on the box faces must
- *   be non-FLUID.
+ *   be non-FLUID.  Several outlets (Sec. 2.1.2: each outlet has its own 0D
+ *   model): an OUTLET ghost carries its outlet index k = 0..7 in bits 5-7 of
+ *   its byte (LBM_CELL_OUTLET | k << 5); every other byte is a plain type.
+ * - Boundaries (0D records of an instance): 0 inlet, 1 outlet 0, 2 exterior,
+ *   2 + k outlet k (k = 1..7).
  *
  * Memory and streams: the caller owns every device buffer (allocate with any
  * allocator, e.g. torch) and the HIP stream.  A context only borrows them;
@@ -155,10 +159,13 @@ lbm_status lbm_step(lbm_ctx* ctx, int64_t nsteps);
  * moves a whole lattice unit between two tests. */
 lbm_status lbm_set_band_check(lbm_ctx* ctx, int32_t every);
 
-/* Set the 0D model of boundary b (0 inlet, 1 outlet, 2 exterior) of instance
- * inst: kind, params (see lbm_bc_kind), optional initial state.  Synchronises
- * the stream.  Errors: LBM_E_INVAL (kind/boundary mismatch, too few params:
- * PRESSURE/VELOCITY need 1, WINDKESSEL3 3 or 4, LV 11). */
+/* Set the 0D model of boundary b (0 inlet, 1 outlet 0, 2 exterior, 2 + k
+ * outlet k) of instance inst: kind, params (see lbm_bc_kind), optional
+ * initial state.  Each outlet's model sees the flux and mean pressure of its
+ * own layer (the FLUID cells of z = nz-2 above its ghosts) and sets its own
+ * ghosts.  Synchronises the stream.  Errors: LBM_E_INVAL (kind/boundary
+ * mismatch: the LV only at the inlet, the exterior constant models only;
+ * too few params: PRESSURE/VELOCITY need 1, WINDKESSEL3 3 or 4, LV 11). */
 lbm_status lbm_couple_0d(lbm_ctx* ctx, int32_t inst, int32_t boundary, int32_t kind,
                          const double* params, int32_t nparams, const double* state, int32_t nstate);
 
@@ -261,6 +268,15 @@ lbm_status lbm_read_fields(lbm_ctx* ctx, int32_t inst, double* p_host, double* u
  * that plane above an INLET ghost; recorded only, coupled to nothing).  Writes the last min(cap, steps, wave_cap)
  * records, oldest first, and sets *n to that count.  Synchronises. */
 lbm_status lbm_read_waveforms(lbm_ctx* ctx, int32_t inst, double* out, int64_t cap, int64_t* n);
+
+/* Per-outlet waveforms of instance inst (Sec. 2.1.2, each outlet's flux and
+ * pressure and its Windkessel state): 24 doubles per step, for outlet
+ * k = 0..7 [Q_k, p_k, Pw_k] (flux through its layer in +z, mean gauge
+ * pressure of the layer, Windkessel pressure or 0 for another model; 0 for
+ * an outlet without cells).  Outlet 0 repeats columns 3, 4 and 10 of
+ * lbm_read_waveforms.  Writes the last min(cap, steps, wave_cap) records,
+ * oldest first, and sets *n to that count.  Synchronises. */
+lbm_status lbm_read_outlet_waveforms(lbm_ctx* ctx, int32_t inst, double* out, int64_t cap, int64_t* n);
 
 /* Wait for the stream and report failures: LBM_E_UNSTABLE if a boundary
  * flux or pressure became non-finite (or a wall point did, at a band

@@ -268,6 +268,33 @@ def precision_study(r=12.0):
     return c
 
 
+def outlet_flag(k):
+    """Cell-type byte of an OUTLET ghost of outlet k (index in bits 5-7)."""
+    return OUTLET | (k << 5)
+
+
+def branched_duct(nx=14, ny=10, nz=40, septum_from=None, Rd=(1.0, 2.0), Rp=0.05, C=50.0, tau=1.0,
+                  p_in=1e-3 / 3.0):
+    """Rigid rectangular duct with one inlet and two outlets: the lumen is the
+    box interior, a 2-cell SOLID septum (x = nx/2 - 1, nx/2) divides its last
+    part into two mirror-image branches, and the OUTLET ghosts of the left
+    branch are outlet 0, those of the right branch outlet 1.  Constant
+    inlet pressure; each outlet drives its own 3-element Windkessel (Rp, C,
+    Rd[k]; pressure in, outflow out, as for the small rigid tube)."""
+    f = tube_flags(nx, ny, nz, (nx - 1) / 2, (ny - 1) / 2, 1e9)   # the whole interior is lumen
+    z0 = nz // 2 if septum_from is None else septum_from
+    xs = (nx // 2 - 1, nx // 2)
+    f[z0:, 1:ny - 1, xs[0]:xs[1] + 1] = SOLID
+    out = f[nz - 1]
+    out[(out == OUTLET)] = outlet_flag(0)
+    right = np.zeros_like(out, dtype=bool)
+    right[:, xs[1] + 1:] = True
+    out[right & (out == outlet_flag(0))] = outlet_flag(1)
+    return dict(name=f"branched_duct_{nx}x{ny}x{nz}", nx=nx, ny=ny, nz=nz, tau=tau, flags=f,
+                inlet=(BC_PRESSURE_CONST, [p_in]), p_ref=p_in, p_init=p_in,
+                outlets=[(BC_WINDKESSEL3, [Rp, C, Rd[k], 1.0], [p_in]) for k in range(2)])
+
+
 def small_fsi(nx=24, ny=24, nz=40, r=7.0, h=0.7, tau=0.6, seed=None):
     """Small elastic tube with the cfg1 boundary models, for parity tests."""
     sc = scales(2500.0, 8000.0 * (r / 48.0) ** 2, 2.5e-6)

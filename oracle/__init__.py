@@ -20,6 +20,7 @@ _SRC = os.path.join(_HERE, "lbm_oracle.c")
 _LIBS = {False: os.path.join(_HERE, "liblbm_oracle.so"),       # real = double
          True: os.path.join(_HERE, "liblbm_oracle_ext.so")}    # real = long double
 NREC = 14
+NOUT = 8          # outlets per box (index in bits 5-7 of an OUTLET ghost's cell type)
 Q = 19
 
 
@@ -67,6 +68,8 @@ def lib(extended=False):
         L.orc_get_force.argtypes = [vp, dp]
         L.orc_get_waveforms.restype = C.c_long
         L.orc_get_waveforms.argtypes = [vp, dp, C.c_long]
+        L.orc_get_outlet_waveforms.restype = C.c_long
+        L.orc_get_outlet_waveforms.argtypes = [vp, dp, C.c_long]
         L.orc_get_step.restype = C.c_long
         L.orc_get_step.argtypes = [vp]
         L.orc_smooth_S.restype = C.c_double
@@ -302,6 +305,14 @@ class Oracle:
         self.L.orc_get_waveforms(self.h, out.ctypes.data_as(C.POINTER(C.c_double)), n)
         return out
 
+    def outlet_waveforms(self):
+        """(steps, NOUT, 3): flux, mean gauge pressure and Windkessel Pw of
+        each outlet per step."""
+        n = self.L.orc_get_outlet_waveforms(self.h, None, 0)
+        out = np.zeros((n, NOUT, 3))
+        self.L.orc_get_outlet_waveforms(self.h, out.ctypes.data_as(C.POINTER(C.c_double)), n)
+        return out
+
 
 def num_threads():
     return lib().orc_num_threads()
@@ -315,6 +326,8 @@ def from_config(cfg, pops=None, extended=False):
         o.set_bc(0, cfg["inlet"][0], cfg["inlet"][1], cfg.get("inlet_state", ()))
     if "outlet" in cfg:
         o.set_bc(1, cfg["outlet"][0], cfg["outlet"][1], cfg.get("outlet_state", ()))
+    for k, (kind, par, st) in enumerate(cfg.get("outlets", ())):   # outlet k: boundary 1 or 2 + k
+        o.set_bc(1 if k == 0 else 2 + k, kind, par, st)
     if "exterior" in cfg:
         o.set_bc(2, cfg["exterior"][0], cfg["exterior"][1])
     if pops is not None:

@@ -63,6 +63,13 @@ typedef double real;
 
 #define NQ 19
 #define NREC 14
+/* Outlets: the OUTLET ghosts of one instance may form up to NOUT separate
+ * outlets, each with its own 0D model (the paper's several outlets, each with
+ * a Windkessel, Sec. 2.1.2); the cell-type byte of an OUTLET ghost carries
+ * its outlet index k in bits 5-7.  Boundary records: 0 inlet, 1 outlet 0,
+ * 2 exterior, 2 + k outlet k >= 1. */
+#define NOUT 8
+#define NBC (3 + NOUT - 1)
 
 /* D3Q19 velocities: rest, 6 faces, 12 edges (weights 1/3, 1/18, 1/36). */
 static const int EV[NQ][3] = {
@@ -197,7 +204,7 @@ int orc_is_extended(void) { return sizeof(real) > sizeof(double); }
 /* ------------------------------------------------------------------------ */
 
 typedef struct {
-  int boundary; /* 0 inlet (z = 0), 1 outlet (z = nz-1), 2 exterior */
+  int boundary; /* 0 inlet (z = 0), 1 outlet 0 (z = nz-1), 2 exterior, 2 + k outlet k */
   int kind;
   real par[16];
   real area;      /* number of layer cells of the boundary (flux -> velocity) */
@@ -377,11 +384,12 @@ typedef struct {
   long ncell;
   real tau;
   int per[3];
-  uint8_t* type;
+  uint8_t* type;           /* cell type (low 3 bits of the cell-type byte) */
+  uint8_t* oid;            /* outlet index of an OUTLET ghost (bits 5-7) */
   real *g, *gs, *gn;       /* [cell][19] */
   real *D, *j, *v, *b;     /* moments delta = sum g, j = sum e g; v; force */
   real *v0;                /* inlet-layer snapshot, nx*ny*3 */
-  orc_bc bc[3];
+  orc_bc bc[NBC];
   real body[3], body_omega;
   /* membrane: rest shape X0 and displacements D = X - X0 */
   int nth, nzl;
@@ -391,8 +399,9 @@ typedef struct {
   int nee_normal;          /* 1: NEE from the ghost's normal neighbour */
   int kernel;              /* 0 Peskin 4-point, 1 cosine 4-point */
   int external;            /* 1: the caller moves the points (no membrane forces) */
-  /* waveforms */
+  /* waveforms; per outlet k: flux, mean gauge pressure, Windkessel Pw */
   double* rec;
+  double* orec;            /* [step][NOUT][3] */
   long nrec, caprec;
   long step;
 } orc_t;
@@ -428,7 +437,11 @@ void* orc_create(int nx, int ny, int nz, double tau, const uint8_t* flags, int p
   o->per[0] = px; o->per[1] = py; o->per[2] = pz;
   o->ncell = (long)nx * ny * nz;
   o->type = (uint8_t*)malloc(o->ncell);
-  memcpy(o->type, flags, o->ncell);
+  o->oid = (uint8_t*)malloc(o->ncell);
+  for (long c = 0; c < o->ncell; ++c) {
+    o->type[c] = flags[c] & 7;
+    o->oid[c] = o->type[c] == T_OUTLET ? flags[c] >> 5 : 0;
+  }
   o->g = (real*)calloc((size_t)o->ncell * NQ, sizeof(real));
   o->gs = (real*)calloc((size_t)o->ncell * NQ, sizeof(real));
   o->gn = (real*)calloc((size_t)o->ncell * NQ, sizeof(real));
@@ -438,23 +451,25 @@ void* orc_create(int nx, int ny, int nz, double tau, const uint8_t* flags, int p
   o->b = (real*)calloc((size_t)o->ncell * 3, sizeof(real));
   o->v0 = (real*)calloc((size_t)nx * ny * 3, sizeof(real));
   double zero = 0.0;
-  for (int k = 0; k < 3; ++k) bc_init(&o->bc[k], k, K_PRESSURE, &zero, 1, NULL, 0);
+  for (int k = 0; k < NBC; ++k) bc_init(&o->bc[k], k, K_PRESSURE, &zero, 1, NULL, 0);
   return o;
 }
 
 void orc_destroy(void* ov) {
   orc_t* o = (orc_t*)ov;
   if (!o) return;
-  free(o->type); free(o->g); free(o->gs); free(o->gn);
+  free(o->type); free(o->oid); free(o->g); free(o->gs); free(o->gn);
   free(o->D); free(o->j); free(o->v); free(o->b); free(o->v0);
   free(o->X0); free(o->Dn); free(o->Dp); free(o->slip); free(o->Vf); free(o->F);
-  free(o->rec);
+  free(o->rec); free(o->orec);
   free(o);
 }
 
+/* boundary: 0 inlet, 1 outlet 0, 2 exterior, 2 + k outlet k (k = 1..NOUT-1) */
 void orc_set_bc(void* ov, int boundary, int kind, const double* par, int npar,
                 const double* st, int nst) {
   orc_t* o = (orc_t*)ov;
+  if (boundary < 0 || boundary >= NBC) return;
   bc_init(&o->bc[boundary], boundary, kind, par, npar, st, nst);
 }
 
@@ -711,14 +726,19 @@ void orc_membrane_force(void* ov, const double* X, double* Fel) {
 /* one time step                                                             */
 /* ------------------------------------------------------------------------ */
 
-static void record(orc_t* o, const double* r) {
+static void record(orc_t* o, const double* r, const double* ro) {
   if (o->nrec == o->caprec) {
     o->caprec = o->caprec ? 2 * o->caprec : 1024;
     o->rec = (double*)realloc(o->rec, sizeof(double) * NREC * o->caprec);
+    o->orec = (double*)realloc(o->orec, sizeof(double) * 3 * NOUT * o->caprec);
   }
   memcpy(&o->rec[NREC * o->nrec], r, sizeof(double) * NREC);
+  memcpy(&o->orec[3 * NOUT * o->nrec], ro, sizeof(double) * 3 * NOUT);
   o->nrec++;
 }
+
+/* boundary record of the OUTLET ghost with outlet index k */
+static int outlet_bc(int k) { return k == 0 ? 1 : 2 + k; }
 
 static int src_cell(const orc_t* o, int x, int y, int z, int i, long* out) {
   int c[3] = {x - EV[i][0], y - EV[i][1], z - EV[i][2]};
@@ -753,9 +773,11 @@ static void one_step(orc_t* o) {
     o->j[3 * c] = jx; o->j[3 * c + 1] = jy; o->j[3 * c + 2] = jz;
   }
 
-  /* 2. flux and mean gauge pressure on the first fluid layer of each plane */
-  real Qp[2] = {0, 0}, Pm[2] = {0, 0};
-  for (int side = 0; side < 2; ++side) {
+  /* 2. flux and mean gauge pressure on the first fluid layer next to each
+   *    0D plane: the inlet (side 0) and each outlet k (side 1 + k: the cells
+   *    of z = nz-2 above an OUTLET ghost of index k) */
+  real Qp[1 + NOUT], Pm[1 + NOUT];
+  for (int side = 0; side < 1 + NOUT; ++side) {
     int zl = side == 0 ? 1 : nz - 2, zg = side == 0 ? 0 : nz - 1;
     int gt = side == 0 ? T_INLET : T_OUTLET;
     long cnt = 0;
@@ -763,15 +785,16 @@ static void one_step(orc_t* o) {
     for (int y = 0; y < ny; ++y)
       for (int x = 0; x < nx; ++x) {
         if (zl < 0 || zl >= nz) continue;
-        long c = cidx(o, x, y, zl);
-        if (o->type[c] != T_FLUID || o->type[cidx(o, x, y, zg)] != gt) continue;
+        long c = cidx(o, x, y, zl), gc = cidx(o, x, y, zg);
+        if (o->type[c] != T_FLUID || o->type[gc] != gt) continue;
+        if (side > 0 && o->oid[gc] != side - 1) continue;
         q += o->j[3 * c + 2] / (1 + o->D[c]); /* sum e f / sum f, dA = 1 */
         ps += CS2 * o->D[c];                    /* P - c_s^2 */
         cnt++;
       }
     Qp[side] = q;
     Pm[side] = cnt ? ps / cnt : 0;
-    o->bc[side].area = (real)cnt;
+    o->bc[side == 0 ? 0 : outlet_bc(side - 1)].area = (real)cnt;
   }
   /* the same sums on the mid-length plane z = nz/2, over the columns of the
    * inlet's lumen (cells above an INLET ghost): recorded, not coupled */
@@ -793,7 +816,7 @@ static void one_step(orc_t* o) {
 
   /* 3. 0D models to t_{n+1} */
   bc_update(&o->bc[0], n, Qp[0], Pm[0]);
-  bc_update(&o->bc[1], n, Qp[1], Pm[1]);
+  for (int k = 0; k < NOUT; ++k) bc_update(&o->bc[outlet_bc(k)], n, Qp[1 + k], Pm[1 + k]);
   bc_update(&o->bc[2], n, 0, 0);
   if (o->bc[0].snap) { /* v0(x_f) = v(x_f, T_d) on the inlet layer */
     for (int y = 0; y < ny; ++y)
@@ -868,7 +891,7 @@ static void one_step(orc_t* o) {
           if (normal_neighbour(o, s, &q) && o->type[q] == T_FLUID) xf = q;
         }
         const int xfx = (int)(xf % nx), xfy = (int)((xf / nx) % ny);
-        const orc_bc* bc = &o->bc[t == T_INLET ? 0 : (t == T_OUTLET ? 1 : 2)];
+        const orc_bc* bc = &o->bc[t == T_INLET ? 0 : (t == T_OUTLET ? outlet_bc(o->oid[s]) : 2)];
         real Dst, vst[3]; /* P* / c_s^2 - 1 and v* */
         const real* vf = &o->v[3 * xf];
         if (bc->vmode == 0) { /* pressure type: (P_0D, v(x_f)) */
@@ -923,7 +946,14 @@ static void one_step(orc_t* o) {
   r[10] = (double)(o->bc[1].kind == K_WK3 ? o->bc[1].Pw : 0);
   r[11] = o->bc[0].kind == K_LV ? (double)o->bc[0].open : 0.0;
   r[12] = (double)Qmid; r[13] = (double)Pmid;
-  record(o, r);
+  double ro[3 * NOUT];
+  for (int k = 0; k < NOUT; ++k) {
+    const orc_bc* b = &o->bc[outlet_bc(k)];
+    ro[3 * k] = (double)Qp[1 + k];
+    ro[3 * k + 1] = (double)Pm[1 + k];
+    ro[3 * k + 2] = b->kind == K_WK3 ? (double)b->Pw : 0.0;
+  }
+  record(o, r, ro);
   o->step++;
 }
 
@@ -959,6 +989,14 @@ long orc_get_waveforms(void* ov, double* out, long cap) {
   orc_t* o = (orc_t*)ov;
   long n = o->nrec < cap ? o->nrec : cap;
   if (out && n) memcpy(out, o->rec, sizeof(double) * NREC * n);
+  return o->nrec;
+}
+
+/* per step and outlet k = 0..NOUT-1: flux, mean gauge pressure, Pw */
+long orc_get_outlet_waveforms(void* ov, double* out, long cap) {
+  orc_t* o = (orc_t*)ov;
+  long n = o->nrec < cap ? o->nrec : cap;
+  if (out && n) memcpy(out, o->orec, sizeof(double) * 3 * NOUT * n);
   return o->nrec;
 }
 

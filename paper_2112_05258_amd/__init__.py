@@ -16,6 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbm0d3d.so")
 NQ = 19
 NREC = 14
+NOUT = 8          # outlets per instance (index in bits 5-7 of an OUTLET ghost's cell type)
 FP64, FP32, FP16S, BF16S = 0, 1, 2, 3
 KERNEL_COLLIDE, KERNEL_REDUCE, KERNEL_BAND, KERNEL_WALL = 0, 1, 2, 3
 
@@ -70,6 +71,8 @@ SYMBOLS = {
     "lbm_read_fields": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "lbm_read_waveforms": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.c_int64,
                                      C.POINTER(C.c_int64)]),
+    "lbm_read_outlet_waveforms": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.c_int64,
+                                            C.POINTER(C.c_int64)]),
     "lbm_sync": (C.c_int, [C.c_void_p]),
     "lbm_instance_status": (C.c_int, [C.c_void_p, C.c_int32]),
     "lbm_steps": (C.c_int64, [C.c_void_p]),
@@ -305,6 +308,15 @@ class Solver:
         self._check(lib().lbm_read_waveforms(self.h, inst, _dp(out), cap, C.byref(n)))
         return out[: n.value]
 
+    def outlet_waveforms(self, inst=0, cap=1 << 30):
+        """(steps, NOUT, 3): flux, mean gauge pressure and Windkessel Pw of
+        each outlet per step."""
+        cap = min(cap, self.t)
+        out = np.zeros((max(cap, 1), NOUT * 3))
+        n = C.c_int64()
+        self._check(lib().lbm_read_outlet_waveforms(self.h, inst, _dp(out), cap, C.byref(n)))
+        return out[: n.value].reshape(-1, NOUT, 3)
+
     def set_timing(self, on):
         self._check(lib().lbm_set_timing(self.h, 1 if on else 0))
 
@@ -392,22 +404,30 @@ class Solver:
         return adv.value
 
 
+def _couple_all(s, k, cfg):
+    """0D models of a workload dict: inlet, outlet (outlet 0), exterior, and
+    an optional list `outlets` of (kind, params, state) for outlets 0, 1, ..."""
+    for b, key in ((0, "inlet"), (1, "outlet"), (2, "exterior")):
+        if key in cfg:
+            s.couple_0d(k, b, cfg[key][0], cfg[key][1], cfg.get(key + "_state", ()))
+    for q, (kind, par, st) in enumerate(cfg.get("outlets", ())):
+        s.couple_0d(k, 1 if q == 0 else 2 + q, kind, par, st)
+
+
 def solver_from_config(cfg, precision=FP32, pops=None, store_scale=0.0, wave_cap=4096):
     """Solver for one workload dict (see lbm_inputs): box, 0D models, initial
     state and wall are passed through the C interface unchanged."""
     s = Solver(dict(nx=cfg["nx"], ny=cfg["ny"], nz=cfg["nz"], tau=cfg["tau"], flags=cfg["flags"],
                     p_ref=cfg.get("p_ref", 0.0), nee_variant=cfg.get("nee_variant", 0)),
                precision=precision, store_scale=store_scale, wave_cap=wave_cap)
-    for b, key in ((0, "inlet"), (1, "outlet"), (2, "exterior")):
-        if key in cfg:
-            s.couple_0d(0, b, cfg[key][0], cfg[key][1], cfg.get(key + "_state", ()))
+    _couple_all(s, 0, cfg)
     if pops is not None:
         s.write_populations(pops)
     elif cfg.get("p_init", 0.0) != 0.0:
         s.set_rest(cfg["p_init"])
     if "mesh" in cfg:
         s.fsi_exchange(0, cfg["mesh"], cfg["k"], cfg["ei"], cfg["mass"], cfg["alpha"], cfg["beta"],
-                       kernel=cfg.get("kernel", 0), mode=cfg.get("wall_mode", 0))
+                       margin=cfg.get("band_margin", 2), kernel=cfg.get("kernel", 0), mode=cfg.get("wall_mode", 0))
     return s
 
 
@@ -418,12 +438,11 @@ def solver_from_configs(cfgs, precision=FP32, store_scale=0.0, wave_cap=4096):
                   p_ref=c.get("p_ref", 0.0), nee_variant=c.get("nee_variant", 0)) for c in cfgs]
     s = Solver(boxes, precision=precision, store_scale=store_scale, wave_cap=wave_cap)
     for k, cfg in enumerate(cfgs):
-        for b, key in ((0, "inlet"), (1, "outlet"), (2, "exterior")):
-            if key in cfg:
-                s.couple_0d(k, b, cfg[key][0], cfg[key][1], cfg.get(key + "_state", ()))
+        _couple_all(s, k, cfg)
         if cfg.get("p_init", 0.0) != 0.0:
             s.set_rest(cfg["p_init"], inst=k)
         if "mesh" in cfg:
             s.fsi_exchange(k, cfg["mesh"], cfg["k"], cfg["ei"], cfg["mass"], cfg["alpha"], cfg["beta"],
-                           kernel=cfg.get("kernel", 0), mode=cfg.get("wall_mode", 0))
+                           margin=cfg.get("band_margin", 2), kernel=cfg.get("kernel", 0),
+                           mode=cfg.get("wall_mode", 0))
     return s

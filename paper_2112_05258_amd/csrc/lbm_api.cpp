@@ -65,7 +65,7 @@ struct Geometry {
   int64_t ncell;
   std::vector<uint8_t> flags;        // with F_NEAR (and F_BAND) bits
   std::vector<uint64_t> nbr;         // NEAR cells: the 18 neighbour types, 3 bits each
-  std::vector<int32_t> lay[3];   // boundary layers: inlet, outlet, mid-length
+  std::vector<int32_t> lay[NPL];   // boundary layers: inlet, outlet 0, mid-length, outlets 1..7
   // FLUID cells next to a 0D-coupled ghost (within one cell in each axis),
   // ascending: where the normal-neighbour extrapolation does its work
   std::vector<int32_t> ghost_near;
@@ -86,9 +86,10 @@ bool build_geometry(const lbm_config& c, Geometry& g, std::string& err) {
   for (int z = 0; z < g.nz; ++z)
     for (int y = 0; y < g.ny; ++y)
       for (int x = 0; x < g.nx; ++x) {
-        const uint8_t t = at(x, y, z);
+        const uint8_t raw = at(x, y, z), t = raw & TYPE_MASK;
         const bool face = x == 0 || y == 0 || z == 0 || x == g.nx - 1 || y == g.ny - 1 || z == g.nz - 1;
-        if (t > T_EXTP) { err = "cell type out of range"; return false; }
+        if (t > T_EXTP || (raw & (F_NEAR | F_BAND)) || (t != T_OUTLET && (raw >> OUT_SHIFT)))
+          { err = "cell type out of range (only OUTLET ghosts carry an outlet index in bits 5-7)"; return false; }
         if (face && t == T_FLUID) { err = "FLUID cell on the box boundary"; return false; }
         if (t == T_INLET && z != 0) { err = "INLET cell off the plane z = 0"; return false; }
         if (t == T_OUTLET && z != g.nz - 1) { err = "OUTLET cell off the plane z = nz-1"; return false; }
@@ -108,14 +109,20 @@ bool build_geometry(const lbm_config& c, Geometry& g, std::string& err) {
           g.nbr[x + (int64_t)g.nx * (y + (int64_t)g.ny * z)] = w;
         }
       }
-  for (int pl = 0; pl < 2; ++pl) {
-    g.lay[pl].clear();
-    const int zl = pl == 0 ? 1 : g.nz - 2, zg = pl == 0 ? 0 : g.nz - 1;
-    const uint8_t gt = pl == 0 ? T_INLET : T_OUTLET;
+  // inlet layer (plane 0) and the layer of each outlet k (plane
+  // outlet_slot(k)): FLUID cells of z = 1 / z = nz-2 next to the ghost plane
+  for (int pl = 0; pl < NPL; ++pl) g.lay[pl].clear();
+  for (int side = 0; side < 1 + NOUT; ++side) {
+    const int zl = side == 0 ? 1 : g.nz - 2, zg = side == 0 ? 0 : g.nz - 1;
+    const uint8_t gt = side == 0 ? T_INLET : T_OUTLET;
+    const int pl = side == 0 ? 0 : outlet_slot(side - 1);
     for (int y = 0; y < g.ny; ++y)
-      for (int x = 0; x < g.nx; ++x)
-        if ((at(x, y, zl) & TYPE_MASK) == T_FLUID && at(x, y, zg) == gt)
+      for (int x = 0; x < g.nx; ++x) {
+        const uint8_t gc = at(x, y, zg);
+        if ((at(x, y, zl) & TYPE_MASK) == T_FLUID && (gc & TYPE_MASK) == gt &&
+            (side == 0 || (gc >> OUT_SHIFT) == side - 1))
           g.lay[pl].push_back(x + g.nx * (y + g.ny * zl));
+      }
   }
   g.ghost_near.clear();
   if (c.nee_variant == 1) {
@@ -147,7 +154,7 @@ bool build_geometry(const lbm_config& c, Geometry& g, std::string& err) {
 }
 
 struct Layout {
-  size_t flags, nbr, inst, ctab, btab, lay, red, red_part, bc, st, wave, v0, err, moved, walls, cwalls;
+  size_t flags, nbr, inst, ctab, btab, lay, red, red_part, bc, st, wave, owave, v0, err, moved, walls, cwalls;
   size_t bmark, btmp, bcnt, gate, total;
   int64_t NT, nbcnt;
   int ntile_max, nred, nlay, wave_cap;
@@ -170,7 +177,7 @@ void plan(const std::vector<Geometry>& G, int prec, int wave_cap, Layout& L, std
     d.v0_off = L.nv0;
     d.red0 = L.nred;
     int nr = 0;
-    for (int pl = 0; pl < 3; ++pl) {
+    for (int pl = 0; pl < NPL; ++pl) {
       d.lay_off[pl] = L.nlay;
       d.lay_n[pl] = (int32_t)g.lay[pl].size();
       if (lay) lay->insert(lay->end(), g.lay[pl].begin(), g.lay[pl].end());
@@ -201,9 +208,10 @@ void plan(const std::vector<Geometry>& G, int prec, int wave_cap, Layout& L, std
   L.lay = o; o = align256(o + (size_t)std::max(L.nlay, 1) * 4);
   L.red = o; o = align256(o + (size_t)L.nred * sizeof(RedTab));
   L.red_part = o; o = align256(o + (size_t)L.nred * 16);
-  L.bc = o; o = align256(o + 3 * n * sizeof(BcDev));
+  L.bc = o; o = align256(o + NBC * n * sizeof(BcDev));
   L.st = o; o = align256(o + n * sizeof(InstState));
   L.wave = o; o = align256(o + n * (size_t)wave_cap * NREC * 8);
+  L.owave = o; o = align256(o + n * (size_t)wave_cap * NOREC * 8);
   L.v0 = o; o = align256(o + (size_t)L.nv0 * r4_size(prec));
   L.err = o; o = align256(o + n * 4);          // one error word per instance
   L.moved = o; o = align256(o + 4);
@@ -406,13 +414,34 @@ hipError_t enqueue_step(lbm_ctx* c, int parity, bool timed) {
     post(3);
   }
   pre(0);
+  // The few tiles next to a 0D ghost (the normal-neighbour build) run on the
+  // side stream beside the bulk launch: in the AA pattern every cell reads
+  // and writes only its own slots, so the two launches are independent, and
+  // the small one would otherwise add its own latency to the step.  Timed
+  // and tuning steps keep them in sequence.
+  const bool fork = !timed && !c->tuning && c->side != nullptr;
+  bool forked = false;
+  if (fork)
+    for (const LaunchGroup& G : c->cgroups) {
+      if (!G.nee) continue;
+      if (!forked) {
+        if ((e = hipEventRecord(c->ev_fork, c->stream)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(c->side, c->ev_fork, 0)) != hipSuccess) return e;
+        forked = true;
+      }
+      e = launch_collide(c->dev, c->prec, parity, G.bs, G.cpt, true, tab + G.off, G.count, COLLIDE_ALL, c->side);
+      if (e != hipSuccess) return e;
+    }
+  if (forked && (e = hipEventRecord(c->ev_join, c->side)) != hipSuccess) return e;
   for (const LaunchGroup& G : c->cgroups) {
+    if (fork && G.nee) continue;
     EventPair p;
     tpre(p);
     e = launch_collide(c->dev, c->prec, parity, G.bs, G.cpt, G.nee, tab + G.off, G.count, COLLIDE_ALL, c->stream);
     if (e != hipSuccess) return e;
     tpost(p, G.cls, 0);
   }
+  if (forked && (e = hipStreamWaitEvent(c->stream, c->ev_join, 0)) != hipSuccess) return e;
   post(0);
   return hipSuccess;
 }
@@ -940,6 +969,7 @@ lbm_status lbm_init(const lbm_config* cfgs, int32_t n, const lbm_buffers* buf, v
   d.wave_cap = c->L.wave_cap;
   d.v0 = c->work + c->L.v0;
   d.err = (uint32_t*)(c->work + c->L.err);
+  d.owave = (double*)(c->work + c->L.owave);
   d.moved = (uint32_t*)(c->work + c->L.moved);
   d.bmark = (uint8_t*)(c->work + c->L.bmark);
   d.btmp = (uint8_t*)(c->work + c->L.btmp);
@@ -952,11 +982,11 @@ lbm_status lbm_init(const lbm_config* cfgs, int32_t n, const lbm_buffers* buf, v
   std::vector<uint8_t> flags(c->L.NT);
   for (int k = 0; k < n; ++k)
     std::memcpy(flags.data() + c->inst[k].cell0, c->geo[k].flags.data(), c->geo[k].ncell);
-  std::vector<BcDev> bc(3 * n);
-  for (int k = 0; k < 3 * n; ++k) {
+  std::vector<BcDev> bc(NBC * n);
+  for (int k = 0; k < NBC * n; ++k) {
     std::memset(&bc[k], 0, sizeof(BcDev));
     bc[k].kind = BC_PRESSURE;
-    bc[k].boundary = k % 3;
+    bc[k].boundary = k % NBC;
     bc[k].Td = -1;
   }
   std::vector<InstState> st(n);
@@ -989,6 +1019,10 @@ lbm_status lbm_init(const lbm_config* cfgs, int32_t n, const lbm_buffers* buf, v
   }
   if (e == hipSuccess) { e = hipMemset(c->work + c->L.v0, 0, (size_t)c->L.nv0 * r4_size(c->prec)); what = "snapshot clear"; }
   if (e == hipSuccess) { e = hipMemset(c->work + c->L.wave, 0, (size_t)n * c->L.wave_cap * NREC * 8); what = "waveform clear"; }
+  if (e == hipSuccess) {
+    e = hipMemset(c->work + c->L.owave, 0, (size_t)n * c->L.wave_cap * NOREC * 8);
+    what = "outlet waveform clear";
+  }
   for (int k = 0; k < n && e == hipSuccess; ++k) {
     e = launch_fill_rest(d, c->prec, c->inst[k].cell0, c->inst[k].ncell, -c->inst[k].dref, c->stream);
     what = "rest-state fill launch";
@@ -1215,7 +1249,7 @@ lbm_status lbm_autotune(lbm_ctx* c, int32_t trial_steps, int64_t* advanced) {
 lbm_status lbm_couple_0d(lbm_ctx* c, int32_t inst, int32_t b, int32_t kind, const double* params, int32_t np,
                          const double* state, int32_t nst) {
   if (!c) return LBM_E_INVAL;
-  if (inst < 0 || inst >= c->n || b < 0 || b > 2) return fail(c, LBM_E_INVAL, "bad instance or boundary");
+  if (inst < 0 || inst >= c->n || b < 0 || b >= NBC) return fail(c, LBM_E_INVAL, "bad instance or boundary");
   if (!params && np > 0) return fail(c, LBM_E_INVAL, "params NULL");
   int need = kind == BC_PRESSURE || kind == BC_VELOCITY ? 1 : (kind == BC_WK3 ? 3 : (kind == BC_LV ? 11 : -1));
   if (need < 0) return fail(c, LBM_E_INVAL, "unknown 0D kind");
@@ -1235,16 +1269,16 @@ lbm_status lbm_couple_0d(lbm_ctx* c, int32_t inst, int32_t b, int32_t kind, cons
   if (kind == BC_WK3) B.Pw = (state && nst > 0) ? state[0] : 0.0;
   if (kind == BC_LV) B.Pv = (state && nst > 0) ? state[0] : params[4];
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  HIPCHK(c, hipMemcpy(c->work + c->L.bc + (3 * (size_t)inst + b) * sizeof(BcDev), &B, sizeof B,
+  HIPCHK(c, hipMemcpy(c->work + c->L.bc + (NBC * (size_t)inst + b) * sizeof(BcDev), &B, sizeof B,
                       hipMemcpyHostToDevice));
   return LBM_OK;
 }
 
 lbm_status lbm_get_0d(lbm_ctx* c, int32_t inst, int32_t b, double* out) {
-  if (!c || !out || inst < 0 || inst >= c->n || b < 0 || b > 2) return LBM_E_INVAL;
+  if (!c || !out || inst < 0 || inst >= c->n || b < 0 || b >= NBC) return LBM_E_INVAL;
   BcDev B;
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  HIPCHK(c, hipMemcpy(&B, c->work + c->L.bc + (3 * (size_t)inst + b) * sizeof(BcDev), sizeof B,
+  HIPCHK(c, hipMemcpy(&B, c->work + c->L.bc + (NBC * (size_t)inst + b) * sizeof(BcDev), sizeof B,
                       hipMemcpyDeviceToHost));
   out[0] = B.vmode; out[1] = B.pstar; out[2] = B.S; out[3] = B.Pv;
   out[4] = B.Pw; out[5] = B.open; out[6] = (double)B.Td; out[7] = B.vz;
@@ -1492,6 +1526,25 @@ lbm_status lbm_read_waveforms(lbm_ctx* c, int32_t k, double* out, int64_t cap, i
   return LBM_OK;
 }
 
+lbm_status lbm_read_outlet_waveforms(lbm_ctx* c, int32_t k, double* out, int64_t cap, int64_t* n) {
+  if (!c || !n || k < 0 || k >= c->n || cap < 0 || (!out && cap > 0)) return LBM_E_INVAL;
+  const int64_t W = c->L.wave_cap;
+  int64_t tk = 0;
+  lbm_status r = inst_step(c, k, &tk);
+  if (r != LBM_OK) return r;
+  const int64_t cnt = std::min<int64_t>(std::min<int64_t>(tk, W), cap);
+  *n = cnt;
+  if (cnt == 0) return LBM_OK;
+  std::vector<double> ring((size_t)W * NOREC);
+  HIPCHK(c, hipMemcpy(ring.data(), c->work + c->L.owave + (size_t)k * W * NOREC * 8, ring.size() * 8,
+                      hipMemcpyDeviceToHost));
+  for (int64_t q = 0; q < cnt; ++q) {
+    const int64_t step = tk - cnt + q;
+    std::memcpy(out + q * NOREC, ring.data() + (step % W) * NOREC, NOREC * 8);
+  }
+  return LBM_OK;
+}
+
 lbm_status lbm_sync(lbm_ctx* c) {
   if (!c) return LBM_E_INVAL;
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -1580,7 +1633,7 @@ lbm_status lbm_set_overlap(lbm_ctx* c, int32_t on) {
 namespace {
 
 constexpr char CKPT_MAGIC[8] = {'L', 'B', 'M', '0', 'D', '3', 'D', 'C'};
-constexpr uint32_t CKPT_VERSION = 4;
+constexpr uint32_t CKPT_VERSION = 5;
 
 struct CkptHeader {
   char magic[8];
@@ -1602,9 +1655,10 @@ std::vector<std::pair<char*, size_t>> ckpt_pieces(lbm_ctx* c) {
   const size_t n = (size_t)c->n;
   v.push_back({(char*)c->pop, (size_t)NQ * c->L.NT * elem_size(c->prec)});
   v.push_back({c->work + c->L.flags, (size_t)c->L.NT});
-  v.push_back({c->work + c->L.bc, 3 * n * sizeof(BcDev)});
+  v.push_back({c->work + c->L.bc, NBC * n * sizeof(BcDev)});
   v.push_back({c->work + c->L.st, n * sizeof(InstState)});
   v.push_back({c->work + c->L.wave, n * (size_t)c->L.wave_cap * NREC * 8});
+  v.push_back({c->work + c->L.owave, n * (size_t)c->L.wave_cap * NOREC * 8});
   v.push_back({c->work + c->L.v0, (size_t)c->L.nv0 * r4_size(c->prec)});
   v.push_back({c->work + c->L.err, n * 4});
   v.push_back({c->work + c->L.moved, 4});
@@ -1718,12 +1772,12 @@ lbm_status lbm_load(lbm_ctx* c, const char* path) {
   std::fclose(f);
   f = nullptr;
 
-  // pieces 1..3 are the flags, the 0D records and the step counters; 6 the
+  // pieces 1..3 are the flags, the 0D records and the step counters; 7 the
   // error words
   const uint8_t* fl = (const uint8_t*)data[1].data();
   const BcDev* bc = (const BcDev*)data[2].data();
   const InstState* st = (const InstState*)data[3].data();
-  const uint32_t* ew = (const uint32_t*)data[6].data();
+  const uint32_t* ew = (const uint32_t*)data[7].data();
   for (int k = 0; k < c->n; ++k) {
     if (ew[k] & ~(ERR_NONFINITE | ERR_BAND | ERR_FROZEN)) return bad("an error word is malformed");
     const Geometry& g = c->geo[k];
@@ -1739,8 +1793,8 @@ lbm_status lbm_load(lbm_ctx* c, const char* path) {
         ++nbandbits;
       }
     }
-    for (int b = 0; b < 3; ++b) {
-      const BcDev& q = bc[3 * k + b];
+    for (int b = 0; b < NBC; ++b) {
+      const BcDev& q = bc[NBC * k + b];
       if (q.boundary != b || q.kind < BC_PRESSURE || q.kind > BC_LV || (q.kind == BC_LV && b != 0) ||
           (q.vmode != 0 && q.vmode != 1) || q.vkind < VK_CONST || q.vkind > VK_SNAPSHOT)
         return bad("a 0D boundary record is malformed");

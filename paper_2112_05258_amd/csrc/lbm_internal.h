@@ -20,6 +20,18 @@ constexpr int RBLOCK = 256;       // boundary-reduction workgroup
 constexpr int RCHUNK = 256;       // layer cells per reduction workgroup (one per lane)
 constexpr int WBLOCK = 256;       // wall / band workgroups
 
+// Outlets: the OUTLET ghosts of an instance may form up to NOUT separate
+// outlets, each with its own 0D model; an OUTLET ghost's cell-type byte
+// carries its outlet index k in bits 5-7.  0D records per instance (NBC):
+// 0 inlet, 1 outlet 0, 2 exterior, 2 + k outlet k >= 1.  Boundary layers
+// per instance (NPL): 0 inlet, 1 outlet 0, 2 mid-length plane, 2 + k outlet k.
+constexpr int NOUT = 8;
+constexpr int NBC = 2 + NOUT;
+constexpr int NPL = 2 + NOUT;
+constexpr int OUT_SHIFT = 5;
+__host__ __device__ constexpr int outlet_slot(int k) { return k == 0 ? 1 : 2 + k; }
+constexpr int NOREC = 3 * NOUT;   // per-outlet record: flux, mean gauge pressure, Pw
+
 enum : uint8_t { T_FLUID = 0, T_SOLID = 1, T_INLET = 2, T_OUTLET = 3, T_EXTP = 4 };
 constexpr uint8_t TYPE_MASK = 7;
 constexpr uint8_t F_NEAR = 8;     // FLUID cell with at least one non-FLUID neighbour
@@ -59,7 +71,7 @@ struct BcDev {
 struct InstDesc {
   int32_t nx, ny, nz;
   int32_t red0, nred;      // reduction blocks
-  int32_t lay_off[3], lay_n[3];   // inlet / outlet / mid-length layer lists in the lay array
+  int32_t lay_off[NPL], lay_n[NPL];   // boundary-layer lists (planes as above) in the lay array
   int64_t cell0, ncell;
   int64_t v0_off;          // first entry of this instance's inlet snapshot (nx*ny)
   double tau;
@@ -108,9 +120,10 @@ struct Dev {
   const int32_t* lay;              // layer cell lists (local cell ids)
   const RedTab* red;
   double* red_part;                // 2 doubles per reduction block
-  BcDev* bc;                       // 3 per instance
+  BcDev* bc;                       // NBC per instance
   InstState* st;
   double* wave;                    // [inst][wave_cap][NREC]
+  double* owave;                   // [inst][wave_cap][NOREC]: per outlet Q, p, Pw
   int32_t wave_cap;
   int32_t nwall;
   void* v0;                        // R4 per snapshot entry

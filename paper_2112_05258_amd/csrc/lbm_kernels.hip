@@ -250,7 +250,7 @@ __device__ void zerod_update(BcDev& b, int64_t n, double Qp, double Pbar) {
 template <class S, bool ODD>
 __device__ __forceinline__ void reduce_block(const Dev& d, const int blk) {
   using R = typename Store<S>::R;
-  __shared__ double sq[RBLOCK], sp[RBLOCK], sq1[RBLOCK], sp1[RBLOCK], sq2[RBLOCK], sp2[RBLOCK];
+  __shared__ double sq[RBLOCK], sp[RBLOCK];
   __shared__ int last;
   const RedTab t = d.red[blk];
   // an instance that failed in an earlier step is frozen from this step on:
@@ -301,49 +301,60 @@ __device__ __forceinline__ void reduce_block(const Dev& d, const int blk) {
   if (!last) return;
 
   // ---- last block of this instance: finish the sums in a fixed order (a
-  // strided pass per lane, then the tree), all lanes loading partials at once
+  // strided pass per lane, then one tree per plane that has cells), all
+  // lanes loading partials at once
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   InstState* st = d.st + t.inst;
-  double q0 = 0.0, q1 = 0.0, q2 = 0.0, p0 = 0.0, p1 = 0.0, p2 = 0.0;
+  double qa[NPL], pa[NPL];
+#pragma unroll
+  for (int pl = 0; pl < NPL; ++pl) qa[pl] = pa[pl] = 0.0;
   for (int b = I.red0 + (int)threadIdx.x; b < I.red0 + I.nred; b += RBLOCK) {
     const double vq = __hip_atomic_load(&d.red_part[2 * b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const double vp = __hip_atomic_load(&d.red_part[2 * b + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const int pl = d.red[b].plane;
-    if (pl == 0) {
-      q0 += vq; p0 += vp;
-    } else if (pl == 1) {
-      q1 += vq; p1 += vp;
-    } else {
-      q2 += vq; p2 += vp;
-    }
+#pragma unroll
+    for (int q = 0; q < NPL; ++q)
+      if (pl == q) { qa[q] += vq; pa[q] += vp; }
   }
-  sq[threadIdx.x] = q0; sp[threadIdx.x] = p0;
-  sq1[threadIdx.x] = q1; sp1[threadIdx.x] = p1;
-  sq2[threadIdx.x] = q2; sp2[threadIdx.x] = p2;
-  __syncthreads();
-  for (int w = RBLOCK / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) {
-      sq[threadIdx.x] += sq[threadIdx.x + w];
-      sp[threadIdx.x] += sp[threadIdx.x + w];
-      sq1[threadIdx.x] += sq1[threadIdx.x + w];
-      sp1[threadIdx.x] += sp1[threadIdx.x + w];
-      sq2[threadIdx.x] += sq2[threadIdx.x + w];
-      sp2[threadIdx.x] += sp2[threadIdx.x + w];
+  double Q[NPL], P[NPL];
+#pragma unroll
+  for (int pl = 0; pl < NPL; ++pl) {
+    Q[pl] = P[pl] = 0.0;
+    if (I.lay_n[pl] == 0) continue;   // uniform over the block
+    sq[threadIdx.x] = qa[pl];
+    sp[threadIdx.x] = pa[pl];
+    __syncthreads();
+    for (int w = RBLOCK / 2; w > 0; w >>= 1) {
+      if (threadIdx.x < w) {
+        sq[threadIdx.x] += sq[threadIdx.x + w];
+        sp[threadIdx.x] += sp[threadIdx.x + w];
+      }
+      __syncthreads();
     }
+    Q[pl] = sq[0];
+    P[pl] = sp[0] / (double)I.lay_n[pl];
     __syncthreads();
   }
   if (threadIdx.x != 0) return;
-  // planes: inlet, outlet (coupled to the 0D models), mid-length (recorded)
-  double Q[3] = {sq[0], sq1[0], sq2[0]}, P[3] = {sp[0], sp1[0], sp2[0]};
-  for (int pl = 0; pl < 3; ++pl) P[pl] = I.lay_n[pl] ? P[pl] / (double)I.lay_n[pl] : 0.0;
-  if (!isfinite(Q[0]) || !isfinite(Q[1]) || !isfinite(P[0]) || !isfinite(P[1]))
-    atomicOr(d.err + t.inst, ERR_NONFINITE);
+  // planes: inlet, outlets (coupled to the 0D models), mid-length (recorded)
+  bool finite = isfinite(Q[0]) && isfinite(P[0]);
+#pragma unroll
+  for (int k = 0; k < NOUT; ++k) finite = finite && isfinite(Q[outlet_slot(k)]) && isfinite(P[outlet_slot(k)]);
+  if (!finite) atomicOr(d.err + t.inst, ERR_NONFINITE);
   const int64_t n = st->step;
-  BcDev* bc = d.bc + 3 * t.inst;
+  BcDev* bc = d.bc + NBC * t.inst;
   bc[0].area = (double)I.lay_n[0];
-  bc[1].area = (double)I.lay_n[1];
   zerod_update(bc[0], n, Q[0], P[0]);
-  zerod_update(bc[1], n, Q[1], P[1]);
+  double* ro = d.owave + ((int64_t)t.inst * d.wave_cap + (n % d.wave_cap)) * NOREC;
+#pragma unroll 1
+  for (int k = 0; k < NOUT; ++k) {
+    const int s = outlet_slot(k);
+    bc[s].area = (double)I.lay_n[s];
+    zerod_update(bc[s], n, Q[s], P[s]);
+    ro[3 * k] = Q[s];
+    ro[3 * k + 1] = P[s];
+    ro[3 * k + 2] = bc[s].kind == BC_WK3 ? bc[s].Pw : 0.0;
+  }
   zerod_update(bc[2], n, 0.0, 0.0);
   double* r = d.wave + ((int64_t)t.inst * d.wave_cap + (n % d.wave_cap)) * NREC;
   r[0] = (double)n;
@@ -513,8 +524,11 @@ __device__ __forceinline__ void collide_body(const Dev& d, const int inst, const
   // values need not stay live.
   R4 v0 = {0, 0, 0, 0};
   bool have_v0 = false;
-  auto ghost_value = [&](int i, uint32_t tg, R v) -> R {
-    const BcDev& B = d.bc[3 * inst + (tg - T_INLET)];
+  // 0D record of the ghost cell gc of type tg: an OUTLET ghost names its
+  // outlet in the high bits of its flag byte (loaded only for outlets)
+  auto ghost_value = [&](int i, uint32_t tg, uint32_t gc, R v) -> R {
+    const int slot = tg == T_INLET ? 0 : (tg == T_EXTP ? 2 : outlet_slot(d.flags[gc] >> OUT_SHIFT));
+    const BcDev& B = d.bc[NBC * inst + slot];
     if (B.vmode == 0) return v + wgt<R>(i) * (R(B.dstar - I.dref) - m.dl);
     R sx, s_y, s_z;
     if (B.vkind == VK_SNAPSHOT) {
@@ -556,7 +570,7 @@ __device__ __forceinline__ void collide_body(const Dev& d, const int inst, const
     const bool edge = i >= 7;
     if (nt(i) >= T_INLET &&
         !(NEE && edge && I.nee && (nt(edge_a(i)) == T_FLUID || nt(edge_b(i)) == T_FLUID))) {
-      const R out = ghost_value(i, nt(i), v);
+      const R out = ghost_value(i, nt(i), (uint32_t)(c - off[i]), v);
       if (!ODD) BufIO<S>::st(rs(OPP[i]), (uint32_t)(c - off[i]) * ES, out, d.scale);
       else BufIO<S>::st(rs(i), c * ES, out, d.scale);
     }
@@ -568,7 +582,7 @@ __device__ __forceinline__ void collide_body(const Dev& d, const int inst, const
         const int k = h == 0 ? edge_a(i) : edge_b(i);
         const int t = h == 0 ? edge_b(i) : edge_a(i);
         if (nt(k) >= T_INLET && nt(OPP[t]) == T_FLUID) {
-          const R out = ghost_value(i, nt(k), v);
+          const R out = ghost_value(i, nt(k), (uint32_t)(c - off[k]), v);
           if (!ODD) BufIO<S>::st(rs(OPP[i]), (uint32_t)(c - off[k]) * ES, out, d.scale);
           else BufIO<S>::st(rs(i), (uint32_t)(c + off[t]) * ES, out, d.scale);
         }
@@ -592,8 +606,11 @@ __device__ __forceinline__ void collide_cell(const Dev& d, const int inst, const
   // global cell index fits 32 bits (NT < 2^31); per-direction arrays are
   // addressed as uniform base + 32-bit lane offset
   const uint32_t c = (uint32_t)(I.cell0 + local);
+  // the instance's error word is loaded beside the cell's flags, so that
+  // the two latencies overlap; a frozen instance is left alone
   const uint8_t fl = d.flags[c];
-  if ((fl & TYPE_MASK) != T_FLUID) return;
+  const uint32_t ew = d.err[inst];
+  if ((fl & TYPE_MASK) != T_FLUID || (ew & ERR_FROZEN)) return;
   if (mode != COLLIDE_ALL && ((fl & F_BAND) != 0) != (mode == COLLIDE_BAND)) return;
   if (__any(fl & F_NEAR))
     collide_body<S, ODD, true, true, NEE>(d, inst, I, local, c, fl);
@@ -613,7 +630,6 @@ __device__ __forceinline__ void collide_cell(const Dev& d, const int inst, const
 template <class S, bool ODD, int BS, int CPT, bool NEE>
 __global__ __launch_bounds__(BS) void k_collide(Dev d, const CTile* __restrict__ tab, int mode) {
   const CTile t = tab[blockIdx.x];
-  if (d.err[t.inst] & ERR_FROZEN) return;   // whole block leaves
 #pragma unroll
   for (int q = 0; q < CPT; ++q) collide_cell<S, ODD, NEE>(d, t.inst, (int64_t)t.start + q * BS + (int)threadIdx.x, mode);
 }
@@ -845,6 +861,10 @@ __global__ __launch_bounds__(WBLOCK) void k_wall(Dev d, const int32_t* __restric
 
   // ---- interpolation of the unforced velocity over the 4x4x4 stencil ----
   if (staged) {
+    // the flag byte and the band velocity of a box cell are loaded together
+    // (the velocity array spans the instance's cells; only band cells hold a
+    // current value, the others are masked by the flag afterwards), so a
+    // lane's loads do not wait on each other
     for (int q = threadIdx.x; q < (int)vol; q += WBLOCK) {
       int x, y, z;
       box_cell(q, x, y, z);
@@ -853,14 +873,10 @@ __global__ __launch_bounds__(WBLOCK) void k_wall(Dev d, const int32_t* __restric
       if (in_box(x, y, z)) {
         const int64_t lc = x + (int64_t)I.nx * (y + (int64_t)I.ny * z);
         f = d.flags[I.cell0 + lc];
-        if ((f & TYPE_MASK) == T_FLUID) {
-          if (f & F_BAND) {
-            const R4 v = U[lc];   // written for band cells only
-            u = R4{v.x, v.y, v.z, R(0)};
-          } else {
-            u.w = R(1);
-          }
-        }
+        const R4 v = U[lc];
+        const bool fluid = (f & TYPE_MASK) == T_FLUID, band = (f & F_BAND) != 0;
+        u = R4{fluid && band ? v.x : R(0), fluid && band ? v.y : R(0), fluid && band ? v.z : R(0),
+               fluid && !band ? R(1) : R(0)};
       }
       sfl[q] = f;
       sbox[q] = u;
