@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--full-beat", action="store_true",
                     help="only cfg1 over one whole cardiac cycle in FP32 and FP16 storage")
     ap.add_argument("--no-full-beat", action="store_true", help="skip the whole-beat leg")
+    ap.add_argument("--contractility", action="store_true",
+                    help="only the wall-shear-stress sweep over normal and high LV contractility")
     ap.add_argument("--surrogate-only", action="store_true",
                     help="only the learned-surrogate leg (for profiling its kernels)")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble run")
@@ -268,6 +270,49 @@ def full_beat():
     return out
 
 
+def contractility_sweep(beats=2, every=250):
+    """Wall shear stress (lbm_wall_shear_stress) between the midpoint and the
+    outlet of the 128x128x512 elastic tube for normal and high LV
+    contractility (end-systolic elastance 1.76 and 2.75 mmHg/ml) at 60 beats
+    a minute with the Womersley number 16 (tau from nu = omega R^2 / Wo^2),
+    the paper's case study on the straight tube: the ring-mean WSS at three
+    quarters of the tube length over the last beat, its extremes, the share
+    of the beat with retrograde (negative) WSS, and the mean inlet flow."""
+    import numpy as np
+    import lbm_inputs as L
+    import paper_2112_05258_amd as amd
+    out = {}
+    R, Wo, beat = 48.0, 16.0, 25000
+    tau = 0.5 + 3.0 * (2.0 * np.pi / beat) * R * R / (Wo * Wo)
+    for name, emax in (("normal", 1.76), ("high", 2.75)):
+        c = L.cfg1(tau=tau)
+        sc = c["scales"]
+        c["inlet"] = (L.BC_LV_ELASTANCE, L.lv_params(emax, 0.06, 60.0, 8.0, 0.075, sc))
+        m = c["mesh"]
+        ring = int(round(0.75 * (m["n_z"] - 1)))
+        s = amd.solver_from_config(c, precision=amd.FP32, wave_cap=beats * beat)
+        t0 = time.perf_counter()
+        series = []
+        while s.t < beats * beat:
+            s.step(every)
+            s.sync()
+            if s.t > (beats - 1) * beat:
+                w = s.wall_shear_stress(dist=2.0).reshape(m["n_z"], m["n_theta"])[ring]
+                series.append(float(w.mean()))
+        wv = s.waveforms()[-beat:]
+        s.close()
+        ws = np.array(series) / sc["sigma_P"]     # lattice stress -> mmHg
+        out[name] = {"Emax_mmHg_per_ml": emax, "wss_mmHg_min": round(float(ws.min()), 5),
+                     "wss_mmHg_max": round(float(ws.max()), 5),
+                     "retrograde_share": round(float((ws < 0).mean()), 3),
+                     "mean_inlet_flow_lu": float(f"{wv[:, 1].mean():.4e}"),
+                     "peak_inlet_mmHg": round(float(wv[:, 2].max() / sc["sigma_P"]), 1),
+                     "samples": len(series), "s": round(time.perf_counter() - t0, 1)}
+        print(f"# contractility {name}: {out[name]}", file=sys.stderr, flush=True)
+    out.update(tau=round(float(tau), 6), heart_rate=60, beats=beats, ring_fraction=0.75)
+    return out
+
+
 def _band_cells(cfg):
     """Band cells of the wall (same rule as the library: stencil + 2-cell margin, fluid only)."""
     import numpy as np
@@ -413,6 +458,9 @@ def main():
         return
     if args.full_beat:
         print(json.dumps({"full_beat": full_beat()}), flush=True)
+        return
+    if args.contractility:
+        print(json.dumps({"contractility": contractility_sweep()}), flush=True)
         return
     cfg, desc = workload(args.workload)
     t_setup = time.perf_counter()

@@ -235,6 +235,20 @@ lbm_status lbm_set_wall(lbm_ctx* ctx, int32_t inst, const double* X, const doubl
 lbm_status lbm_read_wall(lbm_ctx* ctx, int32_t inst, double* X, double* Xprev, double* slip,
                          double* Vf, double* F);
 
+/* Wall shear stress at every point of instance inst's wall (the paper's
+ * case study, Sec. 3.2: WSS = mu dv1/dx3, the axial velocity's derivative
+ * normal to the wall, from the fluid next to the wall).  At a point X the
+ * mesh tangents give the inward unit normal n = -(t_theta x t_z)/|..| and the
+ * axial unit vector a = t_z/|t_z| (central differences; one-sided on the end
+ * rings); the fluid velocity sum e_i g_i is interpolated trilinearly over
+ * the FLUID cells around X + dist n (weights renormalised; NaN where none
+ * is FLUID), and WSS = mu ((v - V_wall) . a) / dist with V_wall = X^n -
+ * X^{n-1} and mu = (tau - 1/2)/3 (rho_0 = 1).  dist in lattice units,
+ * 0 < dist < 64 (2 reaches just past the delta kernel).  wss: host,
+ * n_points doubles.  Synchronises.  Errors: LBM_E_INVAL (no wall, NULL,
+ * dist out of range). */
+lbm_status lbm_wall_shear_stress(lbm_ctx* ctx, int32_t inst, double dist, double* wss);
+
 /* Overwrite the populations of instance inst: g (host, [cell][19] doubles,
  * shifted) for FLUID cells.  Only between an even number of steps.  Converts
  * to the storage precision (round to nearest even).  Synchronises. */

@@ -68,6 +68,7 @@ def lib(extended=False):
         L.orc_get_force.argtypes = [vp, dp]
         L.orc_get_waveforms.restype = C.c_long
         L.orc_get_waveforms.argtypes = [vp, dp, C.c_long]
+        L.orc_wss.argtypes = [vp, C.c_double, dp]
         L.orc_get_outlet_waveforms.restype = C.c_long
         L.orc_get_outlet_waveforms.argtypes = [vp, dp, C.c_long]
         L.orc_get_step.restype = C.c_long
@@ -278,6 +279,14 @@ class Oracle:
         F = np.zeros_like(X)
         self.L.orc_membrane_force(self.h, xp, F.ctypes.data_as(C.POINTER(C.c_double)))
         return F
+
+    def wss(self, dist=2.0):
+        """Wall shear stress at every wall point: mu times the axial velocity
+        difference between the fluid at dist along the inward normal and the
+        wall, over dist."""
+        out = np.zeros(self.np)
+        self.L.orc_wss(self.h, float(dist), out.ctypes.data_as(C.POINTER(C.c_double)))
+        return out
 
     def step(self, n=1):
         self.L.orc_step(self.h, int(n))

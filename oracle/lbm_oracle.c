@@ -962,6 +962,62 @@ void orc_step(void* ov, long nsteps) {
   for (long k = 0; k < nsteps; ++k) one_step(o);
 }
 
+/* Wall shear stress at every wall point (the paper's case study: WSS =
+ * mu dv1/dx3, the axial velocity's derivative along the wall normal, taken
+ * through the fluid next to the wall).  At point p with position X: the
+ * mesh tangents t_theta (central difference over the periodic ring) and t_z
+ * (central difference, one-sided on the end rings) give the inward unit
+ * normal n = -(t_theta x t_z)/|..| and the axial unit vector a = t_z/|t_z|;
+ * the fluid velocity v = sum e g (unforced, rho_0 = 1) is interpolated
+ * trilinearly over the FLUID cells among the 8 around Y = X + dist n
+ * (weights renormalised, NaN if none is FLUID), and
+ *   WSS_p = mu ((v(Y) - V_wall) . a) / dist,  mu = rho_0 (tau - 1/2) / 3,
+ * with V_wall = X^n - X^{n-1} the point's velocity. */
+void orc_wss(void* ov, double dist, double* out) {
+  orc_t* o = (orc_t*)ov;
+  const int nth = o->nth, nzl = o->nzl;
+  const real mu = RHO0 * (o->tau - (real)0.5) / 3;
+  for (long p = 0; p < o->np; ++p) {
+    const int jj = (int)(p % nth), k = (int)(p / nth);
+    real X[3], tt[3], tz[3], n[3], a[3], Vw[3];
+    const long pe = (jj + 1) % nth + (long)nth * k, pw = (jj + nth - 1) % nth + (long)nth * k;
+    const long pn = k < nzl - 1 ? p + nth : p, ps = k > 0 ? p - nth : p;
+    for (int q = 0; q < 3; ++q) {
+      X[q] = o->X0[3 * p + q] + o->Dn[3 * p + q];
+      tt[q] = (o->X0[3 * pe + q] + o->Dn[3 * pe + q]) - (o->X0[3 * pw + q] + o->Dn[3 * pw + q]);
+      tz[q] = (o->X0[3 * pn + q] + o->Dn[3 * pn + q]) - (o->X0[3 * ps + q] + o->Dn[3 * ps + q]);
+      Vw[q] = o->Dn[3 * p + q] - o->Dp[3 * p + q];
+    }
+    n[0] = -(tt[1] * tz[2] - tt[2] * tz[1]);
+    n[1] = -(tt[2] * tz[0] - tt[0] * tz[2]);
+    n[2] = -(tt[0] * tz[1] - tt[1] * tz[0]);
+    real nn = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]), na = sqrt(tz[0] * tz[0] + tz[1] * tz[1] + tz[2] * tz[2]);
+    for (int q = 0; q < 3; ++q) { n[q] /= nn; a[q] = tz[q] / na; }
+    real Y[3], v[3] = {0, 0, 0}, ws = 0;
+    int b[3];
+    for (int q = 0; q < 3; ++q) { Y[q] = X[q] + (real)dist * n[q]; b[q] = (int)floor(Y[q]); }
+    for (int cz = 0; cz < 2; ++cz)
+      for (int cy = 0; cy < 2; ++cy)
+        for (int cx = 0; cx < 2; ++cx) {
+          const int x = b[0] + cx, y = b[1] + cy, z = b[2] + cz;
+          if (x < 0 || y < 0 || z < 0 || x >= o->nx || y >= o->ny || z >= o->nz) continue;
+          const long c = cidx(o, x, y, z);
+          if (o->type[c] != T_FLUID) continue;
+          const real w = (cx ? Y[0] - b[0] : 1 - (Y[0] - b[0])) * (cy ? Y[1] - b[1] : 1 - (Y[1] - b[1])) *
+                         (cz ? Y[2] - b[2] : 1 - (Y[2] - b[2]));
+          real j[3] = {0, 0, 0};
+          for (int i = 0; i < NQ; ++i)
+            for (int q = 0; q < 3; ++q) j[q] += EV[i][q] * o->g[c * NQ + i];
+          for (int q = 0; q < 3; ++q) v[q] += w * j[q] / RHO0;
+          ws += w;
+        }
+    if (ws <= 0) { out[p] = NAN; continue; }
+    real s = 0;
+    for (int q = 0; q < 3; ++q) s += (v[q] / ws - Vw[q]) * a[q];
+    out[p] = (double)(mu * s / (real)dist);
+  }
+}
+
 /* gauge pressure p = c_s^2 sum g and first moment sum e_i g_i of every cell
  * (0 off-fluid) */
 void orc_get_fields(void* ov, double* p, double* u) {

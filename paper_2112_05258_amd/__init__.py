@@ -65,6 +65,7 @@ SYMBOLS = {
     "lbm_fsi_exchange": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(WallDesc), C.c_void_p, C.c_size_t]),
     "lbm_read_wall": (C.c_int, [C.c_void_p, C.c_int32] + [C.POINTER(C.c_double)] * 5),
     "lbm_set_wall": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "lbm_wall_shear_stress": (C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.POINTER(C.c_double)]),
     "lbm_write_populations": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_double)]),
     "lbm_set_rest": (C.c_int, [C.c_void_p, C.c_int32, C.c_double]),
     "lbm_read_populations": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_double)]),
@@ -276,6 +277,12 @@ class Solver:
         out = [np.zeros((n, 3)) for _ in range(5)]
         self._check(lib().lbm_read_wall(self.h, inst, *[_dp(o) for o in out]))
         return dict(X=out[0], Xprev=out[1], slip=out[2], Vf=out[3], F=out[4])
+
+    def wall_shear_stress(self, inst=0, dist=2.0):
+        """Wall shear stress at every wall point (lbm_wall_shear_stress)."""
+        out = np.zeros(self.fsi[inst][1])
+        self._check(lib().lbm_wall_shear_stress(self.h, inst, float(dist), _dp(out)))
+        return out
 
     def ncell(self, inst=0):
         return lib().lbm_num_cells(self.h, inst)

@@ -237,6 +237,7 @@ struct Wall {
   std::vector<int32_t> band;
   std::vector<double> X0;      // rest positions, xyz per point (host copy)
   std::vector<double> Xband;   // positions the band was last built around (host copy)
+  double* wss = nullptr;       // device, np doubles: wall shear stress read-back
 };
 
 // Instances of similar box volume share launch shapes, chosen by the
@@ -843,7 +844,7 @@ bool wall_band(const lbm_ctx* c, int k, const lbm_wall_desc* w, std::vector<int3
 int64_t band_capacity(int64_t nband) { return 2 * nband + 4096; }
 
 struct FsiLayout {
-  size_t u4, b4, X0, Xa, Xb, slip, Vf, Fp, band, Dref, total;
+  size_t u4, b4, X0, Xa, Xb, slip, Vf, Fp, band, Dref, wss, total;
 };
 FsiLayout fsi_plan(int64_t ncell, int64_t np, int64_t nband, int prec) {
   FsiLayout f;
@@ -859,6 +860,7 @@ FsiLayout fsi_plan(int64_t ncell, int64_t np, int64_t nband, int prec) {
   f.Fp = o; o = align256(o + np * 32);
   f.band = o; o = align256(o + band_capacity(nband) * 4);
   f.Dref = o; o = align256(o + np * 32);
+  f.wss = o; o = align256(o + np * 8);        // wall shear stress read-back
   f.total = o;
   return f;
 }
@@ -1347,6 +1349,7 @@ lbm_status lbm_fsi_exchange(lbm_ctx* c, int32_t k, const lbm_wall_desc* w, void*
   c->wall[k].margin = w->band_margin > 0 ? w->band_margin : 2;
   c->wall[k].band_cap = band_capacity((int64_t)band.size());
   c->wall[k].X0.assign(w->X0_host, w->X0_host + 3 * np);
+  c->wall[k].wss = (double*)(F + f.wss);
   c->wall[k].Xband = c->wall[k].X0;
   c->walls.clear();
   // launch grids sized for the largest band a wall may grow to (its list's
@@ -1438,6 +1441,19 @@ lbm_status lbm_read_wall(lbm_ctx* c, int32_t k, double* X, double* Xp, double* s
     return r;
   add_x0(X);
   add_x0(Xp);
+  return LBM_OK;
+}
+
+lbm_status lbm_wall_shear_stress(lbm_ctx* c, int32_t k, double dist, double* wss) {
+  if (!c || !wss || k < 0 || k >= c->n || !c->wall[k].on) return LBM_E_INVAL;
+  if (!(dist > 0.0 && dist < 64.0)) return fail(c, LBM_E_INVAL, "wall shear stress: dist outside (0, 64)");
+  const InstDesc& d = c->inst[k];
+  int64_t tk = 0;
+  if (lbm_status r = inst_step(c, k, &tk)) return r;   // the wall's state is at the instance's step
+  const double mu = (d.tau - 0.5) / 3.0;
+  HIPCHK(c, launch_wss(c->dev, c->prec, (int)(tk & 1), k, d.np, dist, mu, c->wall[k].wss, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipMemcpy(wss, c->wall[k].wss, (size_t)d.np * 8, hipMemcpyDeviceToHost));
   return LBM_OK;
 }
 

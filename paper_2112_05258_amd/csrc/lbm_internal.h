@@ -184,6 +184,11 @@ hipError_t launch_wall(const Dev& d, int prec, int parity, int tj, bool big, con
 constexpr int BCELLS = 1024;
 hipError_t launch_band_rebuild(const Dev& d, int parity, float thresh, const int maxlines[3], int maxblk,
                                hipStream_t s);
+// wall shear stress of the np points of instance inst's wall into out (np
+// doubles, device): fluid velocity at dist along the inward normal, mu the
+// dynamic viscosity
+hipError_t launch_wss(const Dev& d, int prec, int parity, int inst, int64_t np, double dist, double mu, double* out,
+                      hipStream_t s);
 // wall motion since the band was built, into the moved word (parity: the
 // current displacement's half of the ping-pong pair)
 hipError_t launch_motion(const Dev& d, int parity, hipStream_t s);

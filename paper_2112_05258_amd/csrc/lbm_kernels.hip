@@ -1036,6 +1036,72 @@ __global__ __launch_bounds__(WBLOCK) void k_motion(Dev d, int parity) {
 }
 
 // ---------------------------------------------------------------------------
+// k_wss: wall shear stress at every point of one wall (diagnostic, not on the
+// step's path).  The mesh tangents give the inward normal n and the axial
+// direction a; the fluid velocity sum e g of the FLUID cells around
+// Y = X + dist n is interpolated trilinearly (weights renormalised over the
+// FLUID cells; NaN if none), and WSS = mu ((v(Y) - V_wall) . a) / dist.
+// ---------------------------------------------------------------------------
+template <class S, bool ODD>
+__global__ __launch_bounds__(WBLOCK) void k_wss(Dev d, int inst, double dist, double mu, double* __restrict__ out) {
+  using R = typename Store<S>::R;
+  const InstDesc& I = d.inst[inst];
+  const int64_t p = (int64_t)blockIdx.x * WBLOCK + threadIdx.x;
+  if (p >= I.np) return;
+  const int nth = I.nth, nzl = I.nzl;
+  const int j = (int)(p % nth), k = (int)(p / nth);
+  const double* Dc = I.Xab[ODD ? 1 : 0];
+  const double* Dm = I.Xab[ODD ? 0 : 1];
+  auto pos = [&](int64_t q) {
+    const double3 a = ld3(I.X0, q), b = ld3(Dc, q);
+    return make_double3(a.x + b.x, a.y + b.y, a.z + b.z);
+  };
+  const double3 X = pos(p);
+  const double3 e = pos((j + 1) % nth + (int64_t)nth * k), w = pos((j + nth - 1) % nth + (int64_t)nth * k);
+  const double3 up = pos(k < nzl - 1 ? p + nth : p), dn = pos(k > 0 ? p - nth : p);
+  const double3 tt = make_double3(e.x - w.x, e.y - w.y, e.z - w.z);
+  const double3 tz = make_double3(up.x - dn.x, up.y - dn.y, up.z - dn.z);
+  double3 n = make_double3(-(tt.y * tz.z - tt.z * tz.y), -(tt.z * tz.x - tt.x * tz.z), -(tt.x * tz.y - tt.y * tz.x));
+  const double nn = sqrt(n.x * n.x + n.y * n.y + n.z * n.z), na = sqrt(tz.x * tz.x + tz.y * tz.y + tz.z * tz.z);
+  n.x /= nn; n.y /= nn; n.z /= nn;
+  const double3 a = make_double3(tz.x / na, tz.y / na, tz.z / na);
+  const double3 Dn = ld3(Dc, p), Dp = ld3(Dm, p);
+  const double Y[3] = {X.x + dist * n.x, X.y + dist * n.y, X.z + dist * n.z};
+  const int b[3] = {(int)floor(Y[0]), (int)floor(Y[1]), (int)floor(Y[2])};
+  int64_t off[NQ];
+  dir_offsets(I.nx, (int64_t)I.nx * I.ny, off);
+  const S* A = (const S*)d.pop;
+  double vx = 0, vy = 0, vz = 0, ws = 0;
+  for (int cz = 0; cz < 2; ++cz)
+    for (int cy = 0; cy < 2; ++cy)
+      for (int cx = 0; cx < 2; ++cx) {
+        const int x = b[0] + cx, y = b[1] + cy, z = b[2] + cz;
+        if (x < 0 || y < 0 || z < 0 || x >= I.nx || y >= I.ny || z >= I.nz) continue;
+        const int64_t c = I.cell0 + x + (int64_t)I.nx * (y + (int64_t)I.ny * z);
+        if ((d.flags[c] & TYPE_MASK) != T_FLUID) continue;
+        const double wt = (cx ? Y[0] - b[0] : 1.0 - (Y[0] - b[0])) * (cy ? Y[1] - b[1] : 1.0 - (Y[1] - b[1])) *
+                          (cz ? Y[2] - b[2] : 1.0 - (Y[2] - b[2]));
+        R g[NQ];
+        load_cell<S, ODD>(A, d.NT, c, off, d.inv_scale, g);
+        double jx = 0, jy = 0, jz = 0;
+#pragma unroll
+        for (int i = 1; i < NQ; ++i) {
+          jx += EX[i] * (double)g[i];
+          jy += EY[i] * (double)g[i];
+          jz += EZ[i] * (double)g[i];
+        }
+        vx += wt * jx; vy += wt * jy; vz += wt * jz;
+        ws += wt;
+      }
+  if (!(ws > 0.0)) {
+    out[p] = __builtin_nan("");
+    return;
+  }
+  const double s = (vx / ws - (Dn.x - Dp.x)) * a.x + (vy / ws - (Dn.y - Dp.y)) * a.y + (vz / ws - (Dn.z - Dp.z)) * a.z;
+  out[p] = mu * s / dist;
+}
+
+// ---------------------------------------------------------------------------
 // Band rebuild on the device (launched at each band check, gated on the
 // motion word).  The band of a wall is the FLUID cells within the margin m of
 // the 4x4x4 stencils of its points: the stencil bases b = floor(X) - 1
@@ -1441,6 +1507,17 @@ hipError_t launch_motion(const Dev& d, int parity, hipStream_t s) {
   if (d.nwall <= 0 || d.max_np <= 0) return hipSuccess;
   const dim3 g((unsigned)((d.max_np + WBLOCK - 1) / WBLOCK), d.nwall);
   return launch(k_motion, g, dim3(WBLOCK), s, Dev(d), int(parity));
+}
+hipError_t launch_wss(const Dev& d, int prec, int parity, int inst, int64_t np, double dist, double mu, double* out,
+                      hipStream_t s) {
+  if (np <= 0) return hipSuccess;
+  const dim3 g((unsigned)((np + WBLOCK - 1) / WBLOCK));
+#define F(T)                                                                                            \
+  return parity ? launch(k_wss<T, true>, g, dim3(WBLOCK), s, Dev(d), int(inst), dist, mu, out)          \
+                : launch(k_wss<T, false>, g, dim3(WBLOCK), s, Dev(d), int(inst), dist, mu, out);
+  LBM_DISPATCH(prec, F)
+#undef F
+  return hipErrorInvalidValue;
 }
 hipError_t launch_band_rebuild(const Dev& d, int parity, float thresh, const int maxlines[3], int maxblk,
                                hipStream_t s) {
