@@ -270,14 +270,20 @@ def full_beat():
     return out
 
 
-def contractility_sweep(beats=2, every=250):
+def contractility_sweep(beats=1, every=250):
     """Wall shear stress (lbm_wall_shear_stress) between the midpoint and the
     outlet of the 128x128x512 elastic tube for normal and high LV
     contractility (end-systolic elastance 1.76 and 2.75 mmHg/ml) at 60 beats
     a minute with the Womersley number 16 (tau from nu = omega R^2 / Wo^2),
-    the paper's case study on the straight tube: the ring-mean WSS at three
-    quarters of the tube length over the last beat, its extremes, the share
-    of the beat with retrograde (negative) WSS, and the mean inlet flow."""
+    the paper's case study on the straight tube, over the first beat from
+    the paper's initial state (fluid at rest at P0): the ring-mean WSS at
+    three quarters of the tube length, its extremes, the share of the beat
+    with retrograde (negative) WSS in systole and in diastole, and the beat's
+    valve timing, stroke volume and pressures.  Later beats are not used: the
+    closed tube's pressure oscillation after the first closure takes the
+    inlet pressure under the end-diastolic pressure when the next beat
+    starts, so the valve opens at once, closes on the oscillating flux and,
+    one opening per beat, stays shut while the ventricle contracts."""
     import numpy as np
     import lbm_inputs as L
     import paper_2112_05258_amd as amd
@@ -292,24 +298,38 @@ def contractility_sweep(beats=2, every=250):
         ring = int(round(0.75 * (m["n_z"] - 1)))
         s = amd.solver_from_config(c, precision=amd.FP32, wave_cap=beats * beat)
         t0 = time.perf_counter()
-        series = []
+        ts, series = [], []
         while s.t < beats * beat:
             s.step(every)
             s.sync()
             if s.t > (beats - 1) * beat:
                 w = s.wall_shear_stress(dist=2.0).reshape(m["n_z"], m["n_theta"])[ring]
+                ts.append(s.t)
                 series.append(float(w.mean()))
         wv = s.waveforms()[-beat:]
         s.close()
         ws = np.array(series) / sc["sigma_P"]     # lattice stress -> mmHg
+        valve = wv[:, 11] > 0.5
+        opened = np.flatnonzero(valve)
+        t_open, t_close = (int(wv[opened[0], 0]), int(wv[opened[-1], 0]) + 1) if len(opened) else (-1, -1)
+        syst = (np.array(ts) >= t_open) & (np.array(ts) <= t_close)
+        sv_ml = float(wv[valve, 1].sum()) / sc["sigma_V"]
         out[name] = {"Emax_mmHg_per_ml": emax, "wss_mmHg_min": round(float(ws.min()), 5),
                      "wss_mmHg_max": round(float(ws.max()), 5),
                      "retrograde_share": round(float((ws < 0).mean()), 3),
-                     "mean_inlet_flow_lu": float(f"{wv[:, 1].mean():.4e}"),
+                     "retrograde_share_systole": round(float((ws[syst] < 0).mean()), 3) if syst.any() else None,
+                     "retrograde_share_diastole": round(float((ws[~syst] < 0).mean()), 3) if (~syst).any() else None,
+                     "valve_open_step": t_open, "valve_close_step": t_close,
+                     "stroke_volume_ml": round(sv_ml, 2),
+                     "peak_Pv_mmHg": round(float(wv[:, 9].max() / sc["sigma_P"]), 1),
                      "peak_inlet_mmHg": round(float(wv[:, 2].max() / sc["sigma_P"]), 1),
-                     "samples": len(series), "s": round(time.perf_counter() - t0, 1)}
-        print(f"# contractility {name}: {out[name]}", file=sys.stderr, flush=True)
-    out.update(tau=round(float(tau), 6), heart_rate=60, beats=beats, ring_fraction=0.75)
+                     "min_inlet_mmHg": round(float(wv[:, 2].min() / sc["sigma_P"]), 1),
+                     "samples": len(series), "s": round(time.perf_counter() - t0, 1),
+                     "wss_series_mmHg": [round(float(v), 4) for v in ws]}
+        short = {k: v for k, v in out[name].items() if k != "wss_series_mmHg"}
+        print(f"# contractility {name}: {short}", file=sys.stderr, flush=True)
+    out.update(tau=round(float(tau), 6), heart_rate=60, beats=beats, ring_fraction=0.75,
+               sample_every_steps=every)
     return out
 
 
