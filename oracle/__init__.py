@@ -81,6 +81,7 @@ def lib(extended=False):
         L.orc_phicos.restype = C.c_double
         L.orc_phicos.argtypes = [C.c_double]
         L.orc_set_wall_options.argtypes = [vp, C.c_int, C.c_int]
+        L.orc_set_shell.argtypes = [vp, C.c_int, C.c_double]
         L.orc_set_nee_variant.argtypes = [vp, C.c_int]
         L.orc_set_wall.argtypes = [vp, dp, dp]
         L.orc_lattice.argtypes = [ip, dp]
@@ -242,6 +243,11 @@ class Oracle:
         """Delta kernel (0 Peskin 4-point, 1 cosine) and external-solid mode."""
         self.L.orc_set_wall_options(self.h, int(kernel), 1 if external else 0)
 
+    def set_shell(self, shell=True, poisson=0.5):
+        """Shell model: also the off-diagonal terms of Eq. structure (in-plane
+        shear with phi_12 = 1 / (2 (1 + poisson)), mixed bending)."""
+        self.L.orc_set_shell(self.h, 1 if shell else 0, float(poisson))
+
     def set_wall(self, X, V):
         """External-solid mode: positions at t_n and velocities (lu/step)."""
         X, xp = _d(X)
@@ -346,4 +352,6 @@ def from_config(cfg, pops=None, extended=False):
     if "mesh" in cfg:
         o.set_membrane(cfg["mesh"], cfg["k"], cfg["ei"], cfg["mass"], cfg["alpha"], cfg["beta"])
         o.set_wall_options(cfg.get("kernel", 0), cfg.get("wall_mode", 0) == 1)
+        if cfg.get("shell", 0):
+            o.set_shell(True, cfg.get("poisson", 0.5))
     return o

@@ -26,7 +26,8 @@
  *      extrapolation from 0D ghost nodes (Eq. Non-equilibrium3 with the
  *      pressure- or velocity-type coupling of Sec. 2.2)
  *   7. wall update by the staggered finite-difference operators
- *      (Eqs. tension, bending; central difference in time).
+ *      (Eqs. tension, bending; central difference in time), optionally with
+ *      the off-diagonal shear and mixed-bending terms of Eq. structure.
  *
  * Populations are stored shifted, g_i = f_i - w_i (an exact change of
  * variables: the equilibrium is linear in P and equals w_i at rest).  All
@@ -399,6 +400,8 @@ typedef struct {
   int nee_normal;          /* 1: NEE from the ghost's normal neighbour */
   int kernel;              /* 0 Peskin 4-point, 1 cosine 4-point */
   int external;            /* 1: the caller moves the points (no membrane forces) */
+  int shell;               /* 1: the off-diagonal (i != j) terms of Eq. structure too */
+  real phi12;              /* phi_12 = 1 / (2 (1 + Poisson's ratio)) */
   /* waveforms; per outlet k: flux, mean gauge pressure, Windkessel Pw */
   double* rec;
   double* orec;            /* [step][NOUT][3] */
@@ -521,6 +524,16 @@ void orc_set_wall_options(void* ov, int kernel, int external) {
   orc_t* o = (orc_t*)ov;
   o->kernel = kernel;
   o->external = external;
+}
+
+/* Shell model: with shell = 1 the membrane force takes the i != j terms of
+ * Eq. structure as well (in-plane shear with phi_12 = 1 / (2 (1 + nu)) and
+ * the mixed bending with gamma_12 = 1); 0 keeps the two coordinate
+ * directions only. */
+void orc_set_shell(void* ov, int shell, double poisson) {
+  orc_t* o = (orc_t*)ov;
+  o->shell = shell;
+  o->phi12 = 1 / (2 * (1 + (real)poisson));
 }
 
 /* Positions X (np*3) at t_n and velocities V (lattice units per step) of the
@@ -657,8 +670,9 @@ void orc_ib_spread(void* ov, long np, const double* X, const double* F, double a
   free(bb); free(xx); free(ff);
 }
 
-/* Membrane force per unit area on every point (Eq. structure restricted to the
- * two coordinate directions, Eqs. tension and bending): theta periodic, rings
+/* Membrane force per unit area on every point (Eq. structure along the two
+ * coordinate directions, Eqs. tension and bending, plus its off-diagonal
+ * terms when the shell model is on): theta periodic, rings
  * 0 and nzl-1 are simply supported fixed ends (curvature zero there).
  * Bending acts on the displacement D from the rest shape X0. */
 static void membrane_force(const orc_t* o, const real* D, real* Fel) {
@@ -708,6 +722,59 @@ static void membrane_force(const orc_t* o, const real* D, real* Fel) {
       }
       for (int a = 0; a < 3; ++a) Fel[3 * p + a] = f[a];
     }
+  if (o->shell) {
+    /* The i != j terms of Eq. structure.  In-plane shear: the strain
+     * S = X_theta . X_z (zero for the rest cylinder), with both tangents
+     * taken at the centre of each mesh cell as the mean of its two edges
+     * along that direction; the fluxes Eh phi12 S X_z (differentiated along
+     * theta) and Eh phi12 S X_theta (along z) live on the cell centres, and
+     * their divergence at a point is the difference of the two centre pairs
+     * on either side, each pair averaged.  Mixed bending: with gamma_12 =
+     * gamma_21 = 1 the two terms add to -2 EI D+D-_z (D+D-_theta D), the
+     * theta curvature of the displacement being zero on the end rings
+     * (simply supported). */
+    long nc = (long)nth * (nzl - 1);
+    real* cA = (real*)calloc((size_t)3 * nc + 1, sizeof(real));
+    real* cB = (real*)calloc((size_t)3 * nc + 1, sizeof(real));
+    real c = o->ks * o->phi12;
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < nzl - 1; ++k)
+      for (int jj = 0; jj < nth; ++jj) {
+        long p00 = jj + (long)nth * k, p10 = (jj + 1) % nth + (long)nth * k;
+        long p01 = p00 + nth, p11 = p10 + nth;
+        real e0[3], e1[3], xt[3], xz[3];
+        EDGE(p00, p10, e0);
+        EDGE(p01, p11, e1);
+        for (int a = 0; a < 3; ++a) xt[a] = (e0[a] + e1[a]) / (2 * o->ds_th);
+        EDGE(p00, p01, e0);
+        EDGE(p10, p11, e1);
+        for (int a = 0; a < 3; ++a) xz[a] = (e0[a] + e1[a]) / (2 * o->ds_z);
+        real S = xt[0] * xz[0] + xt[1] * xz[1] + xt[2] * xz[2];
+        long q = jj + (long)nth * k;
+        for (int a = 0; a < 3; ++a) {
+          cA[3 * q + a] = c * S * xz[a];
+          cB[3 * q + a] = c * S * xt[a];
+        }
+      }
+#pragma omp parallel for schedule(static)
+    for (int k = 1; k < nzl - 1; ++k)
+      for (int jj = 0; jj < nth; ++jj) {
+        long p = jj + (long)nth * k;
+        int jw = (jj + nth - 1) % nth;
+        /* centre (j + 1/2, k + 1/2) is entry j + nth k */
+        long ne = jj + (long)nth * k, se = jj + (long)nth * (k - 1);
+        long nw = jw + (long)nth * k, sw = jw + (long)nth * (k - 1);
+        for (int a = 0; a < 3; ++a) {
+          real shear = ((cA[3 * ne + a] + cA[3 * se + a]) - (cA[3 * nw + a] + cA[3 * sw + a])) / (2 * o->ds_th) +
+                       ((cB[3 * ne + a] + cB[3 * nw + a]) - (cB[3 * se + a] + cB[3 * sw + a])) / (2 * o->ds_z);
+          real kn = (k + 1 < nzl - 1) ? kt[3 * (p + nth) + a] : 0;
+          real ksth = (k - 1 > 0) ? kt[3 * (p - nth) + a] : 0;
+          real mixed = (kn - 2 * kt[3 * p + a] + ksth) / dz2;
+          Fel[3 * p + a] += shear - 2 * o->ei * mixed;
+        }
+      }
+    free(cA); free(cB);
+  }
 #undef EDGE
   free(kt); free(kz);
 }
