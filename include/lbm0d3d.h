@@ -205,6 +205,14 @@ typedef struct {
                        library interpolates, forms the penalty force and
                        spreads it; the force on the solid, -F, is read back
                        with lbm_read_wall */
+  int32_t shell;    /* 0 (default): Eq. structure along the two mesh
+                       directions only (phi, gamma diagonal); 1: the full
+                       shell model of Eq. structure, adding the off-diagonal
+                       terms -- in-plane shear with phi_12 = 1 / (2 (1 +
+                       poisson)) on the strain X_theta . X_z at the mesh-cell
+                       centres, and the mixed bending with gamma_12 = 1 (the
+                       bending operator becomes the discrete biharmonic) */
+  double poisson;   /* Poisson's ratio of the shell model, > -1 (shell = 1) */
 } lbm_wall_desc;
 
 /* Device bytes the wall of one instance needs (Lagrangian state + dense
@@ -311,11 +319,16 @@ lbm_status lbm_instance_status(lbm_ctx* ctx, int32_t inst);
 /* Steps taken so far. */
 int64_t lbm_steps(const lbm_ctx* ctx);
 
-/* Kernel timing with HIP events on the context's stream: when on, every
- * launch of the collide-stream kernel (id 0), the boundary/0D kernel (1), the
- * band-moment kernel (2) and the wall kernel (3) is bracketed by events.
- * lbm_kernel_time synchronises and returns launches and total milliseconds
- * since timing was switched on. */
+/* Kernel timing with HIP events on the context's stream: when on, the
+ * launches of each step are bracketed by events, per kind: the collide-stream
+ * kernel over the tiles without a 0D ghost of the normal-neighbour
+ * extrapolation nearby (id 0), the boundary/0D kernel (1), the band-moment
+ * kernel (2), the wall kernels (3: interpolation, force, spreading and the
+ * membrane step) and the collide-stream kernel over the tiles next to such
+ * ghosts (4; otherwise forked to a second stream beside id 0's launch, timed
+ * steps run them in sequence).  lbm_kernel_time synchronises and returns the
+ * bracketed intervals and their total milliseconds since timing was switched
+ * on. */
 lbm_status lbm_set_timing(lbm_ctx* ctx, int32_t on);
 lbm_status lbm_kernel_time(lbm_ctx* ctx, int32_t kernel, int64_t* launches, double* total_ms);
 

@@ -47,7 +47,7 @@ class WallDesc(C.Structure):
                 ("ds_theta", C.c_double), ("ds_z", C.c_double), ("area", C.c_double),
                 ("k_stretch", C.c_double), ("ei_bend", C.c_double), ("mass", C.c_double),
                 ("alpha", C.c_double), ("beta", C.c_double), ("band_margin", C.c_int32),
-                ("kernel", C.c_int32), ("mode", C.c_int32)]
+                ("kernel", C.c_int32), ("mode", C.c_int32), ("shell", C.c_int32), ("poisson", C.c_double)]
 
 
 class Launch(C.Structure):
@@ -247,16 +247,19 @@ class Solver:
         return dict(vmode=int(out[0]), pstar=out[1], S=out[2], Pv=out[3], Pw=out[4],
                     open=int(out[5]), Td=int(out[6]), vz=out[7])
 
-    def _wall_desc(self, mesh, k, ei, mass, alpha, beta, margin, kernel=0, mode=0):
+    def _wall_desc(self, mesh, k, ei, mass, alpha, beta, margin, kernel=0, mode=0, shell=0, poisson=0.5):
         X0 = np.ascontiguousarray(mesh["X0"], dtype=np.float64).reshape(-1)
         d = WallDesc(mesh["n_theta"], mesh["n_z"], _dp(X0), mesh["ds_theta"], mesh["ds_z"], mesh["area"],
-                     k, ei, mass, alpha, beta, margin, kernel, mode)
+                     k, ei, mass, alpha, beta, margin, kernel, mode, int(shell), float(poisson))
         return d, X0
 
-    def fsi_exchange(self, inst, mesh, k, ei, mass, alpha, beta, margin=2, kernel=0, mode=0):
+    def fsi_exchange(self, inst, mesh, k, ei, mass, alpha, beta, margin=2, kernel=0, mode=0,
+                     shell=0, poisson=0.5):
         """Attach the wall of instance inst: kernel 0 Peskin 4-point / 1
-        cosine; mode 0 built-in membrane / 1 external solid (set_wall)."""
-        d, X0 = self._wall_desc(mesh, k, ei, mass, alpha, beta, margin, kernel, mode)
+        cosine; mode 0 built-in membrane / 1 external solid (set_wall);
+        shell 1 adds the off-diagonal terms of the wall model (Poisson's
+        ratio poisson)."""
+        d, X0 = self._wall_desc(mesh, k, ei, mass, alpha, beta, margin, kernel, mode, shell, poisson)
         nb = C.c_size_t()
         self._check(lib().lbm_fsi_query_sizes(self.h, inst, C.byref(d), C.byref(nb)))
         buf = self.torch.empty(nb.value, dtype=self.torch.uint8, device=self.device)
@@ -434,7 +437,8 @@ def solver_from_config(cfg, precision=FP32, pops=None, store_scale=0.0, wave_cap
         s.set_rest(cfg["p_init"])
     if "mesh" in cfg:
         s.fsi_exchange(0, cfg["mesh"], cfg["k"], cfg["ei"], cfg["mass"], cfg["alpha"], cfg["beta"],
-                       margin=cfg.get("band_margin", 2), kernel=cfg.get("kernel", 0), mode=cfg.get("wall_mode", 0))
+                       margin=cfg.get("band_margin", 2), kernel=cfg.get("kernel", 0), mode=cfg.get("wall_mode", 0),
+                       shell=cfg.get("shell", 0), poisson=cfg.get("poisson", 0.5))
     return s
 
 
@@ -451,5 +455,6 @@ def solver_from_configs(cfgs, precision=FP32, store_scale=0.0, wave_cap=4096):
         if "mesh" in cfg:
             s.fsi_exchange(k, cfg["mesh"], cfg["k"], cfg["ei"], cfg["mass"], cfg["alpha"], cfg["beta"],
                            margin=cfg.get("band_margin", 2), kernel=cfg.get("kernel", 0),
-                           mode=cfg.get("wall_mode", 0))
+                           mode=cfg.get("wall_mode", 0), shell=cfg.get("shell", 0),
+                           poisson=cfg.get("poisson", 0.5))
     return s

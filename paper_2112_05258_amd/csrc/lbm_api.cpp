@@ -25,6 +25,7 @@ namespace {
 constexpr int EXh[NQ] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
 constexpr int EYh[NQ] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
 constexpr int EZh[NQ] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+constexpr int NTIMED = 5;   // kinds of timed launches (lbm_kernel_time ids)
 constexpr int OPPh[NQ] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
 constexpr double W[NQ] = {1.0 / 3,  1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18,
                           1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36,
@@ -298,8 +299,8 @@ struct lbm_ctx {
   bool timing = false;
   std::vector<EventPair> pool;
   std::vector<std::pair<int, EventPair>> recorded;
-  int64_t t_launch[4] = {0, 0, 0, 0};
-  double t_ms[4] = {0, 0, 0, 0};
+  int64_t t_launch[NTIMED] = {0, 0, 0, 0, 0};
+  double t_ms[NTIMED] = {0, 0, 0, 0, 0};
   // graph
   bool use_graph = true;
   hipGraphExec_t gexec = nullptr;
@@ -342,7 +343,7 @@ EventPair get_pair(lbm_ctx* c) {
 
 hipError_t enqueue_step(lbm_ctx* c, int parity, bool timed) {
   hipError_t e;
-  EventPair ev[4];
+  EventPair ev[NTIMED];
   auto pre = [&](int k) {
     if (timed) { ev[k] = get_pair(c); (void)hipEventRecord(ev[k].a, c->stream); }
   };
@@ -434,16 +435,27 @@ hipError_t enqueue_step(lbm_ctx* c, int parity, bool timed) {
       if (e != hipSuccess) return e;
     }
   if (forked && (e = hipEventRecord(c->ev_join, c->side)) != hipSuccess) return e;
-  for (const LaunchGroup& G : c->cgroups) {
-    if (fork && G.nee) continue;
-    EventPair p;
-    tpre(p);
-    e = launch_collide(c->dev, c->prec, parity, G.bs, G.cpt, G.nee, tab + G.off, G.count, COLLIDE_ALL, c->stream);
-    if (e != hipSuccess) return e;
-    tpost(p, G.cls, 0);
+  // timed steps: the tiles without extrapolation first (id 0), then the
+  // others (id 4)
+  for (int v = 0; v < 2; ++v) {
+    bool any = false;
+    for (const LaunchGroup& G : c->cgroups) {
+      if ((fork && G.nee) || G.nee != (v == 1)) continue;
+      if (!any && v == 1) pre(4);
+      any = true;
+      EventPair p;
+      tpre(p);
+      e = launch_collide(c->dev, c->prec, parity, G.bs, G.cpt, G.nee, tab + G.off, G.count, COLLIDE_ALL, c->stream);
+      if (e != hipSuccess) return e;
+      tpost(p, G.cls, 0);
+    }
+    if (v == 0) {
+      if (forked && (e = hipStreamWaitEvent(c->stream, c->ev_join, 0)) != hipSuccess) return e;
+      post(0);
+    } else if (any) {
+      post(4);
+    }
   }
-  if (forked && (e = hipStreamWaitEvent(c->stream, c->ev_join, 0)) != hipSuccess) return e;
-  post(0);
   return hipSuccess;
 }
 
@@ -872,8 +884,12 @@ bool valid_wall(const lbm_wall_desc* w, std::string& err) {
     err = "wall spacings, area and mass must be positive";
     return false;
   }
-  if (w->kernel < 0 || w->kernel > 1 || w->mode < 0 || w->mode > 1) {
-    err = "wall kernel and mode must be 0 or 1";
+  if (w->kernel < 0 || w->kernel > 1 || w->mode < 0 || w->mode > 1 || w->shell < 0 || w->shell > 1) {
+    err = "wall kernel, mode and shell must be 0 or 1";
+    return false;
+  }
+  if (w->shell == 1 && !(w->poisson > -1.0 && w->poisson < 1e6)) {
+    err = "the shell model needs a Poisson ratio above -1";
     return false;
   }
   return true;
@@ -1332,6 +1348,8 @@ lbm_status lbm_fsi_exchange(lbm_ctx* c, int32_t k, const lbm_wall_desc* w, void*
   d.ks = w->k_stretch; d.ei = w->ei_bend; d.mass = w->mass; d.alpha = w->alpha; d.beta = w->beta;
   d.kernel = w->kernel;
   d.ext = w->mode;
+  d.shell = w->shell;
+  d.phi12 = w->shell ? 1.0 / (2.0 * (1.0 + w->poisson)) : 0.0;
   d.band_margin = w->band_margin > 0 ? w->band_margin : 2;
   d.band_cap = (int32_t)band_capacity((int64_t)band.size());
   std::vector<double> X4((size_t)np * 4, 0.0);
@@ -1354,7 +1372,7 @@ lbm_status lbm_fsi_exchange(lbm_ctx* c, int32_t k, const lbm_wall_desc* w, void*
   c->walls.clear();
   // launch grids sized for the largest band a wall may grow to (its list's
   // capacity), so that bands rebuilt on the device need no new grid
-  int maxb = 0, maxmt = 0;
+  int maxb = 0, maxmt = 0, shell = 0;
   int64_t maxp = 0;
   c->maxlines[0] = c->maxlines[1] = c->maxlines[2] = 0;
   c->maxblk = 0;
@@ -1365,6 +1383,7 @@ lbm_status lbm_fsi_exchange(lbm_ctx* c, int32_t k, const lbm_wall_desc* w, void*
       maxb = std::max(maxb, (int)c->wall[q].band_cap);
       maxp = std::max(maxp, c->wall[q].np);
       maxmt = std::max(maxmt, membrane_tiles(e.nth, e.nzl));
+      shell |= e.shell;
       c->maxlines[0] = std::max(c->maxlines[0], e.ny * e.nz);
       c->maxlines[1] = std::max(c->maxlines[1], e.nx * e.nz);
       c->maxlines[2] = std::max(c->maxlines[2], e.nx * e.ny);
@@ -1375,6 +1394,7 @@ lbm_status lbm_fsi_exchange(lbm_ctx* c, int32_t k, const lbm_wall_desc* w, void*
   c->dev.max_band = maxb;
   c->dev.max_np = (int32_t)maxp;
   c->dev.max_mtile = maxmt;
+  c->dev.any_shell = shell;
   return build_groups(c, false);
 }
 
@@ -1596,13 +1616,13 @@ lbm_status lbm_set_timing(lbm_ctx* c, int32_t on) {
   if (!c) return LBM_E_INVAL;
   HIPCHK(c, hipStreamSynchronize(c->stream));
   collect_times(c);
-  for (int k = 0; k < 4; ++k) { c->t_ms[k] = 0; c->t_launch[k] = 0; }
+  for (int k = 0; k < NTIMED; ++k) { c->t_ms[k] = 0; c->t_launch[k] = 0; }
   c->timing = on != 0;
   return LBM_OK;
 }
 
 lbm_status lbm_kernel_time(lbm_ctx* c, int32_t kernel, int64_t* launches, double* ms) {
-  if (!c || kernel < 0 || kernel > 3 || !launches || !ms) return LBM_E_INVAL;
+  if (!c || kernel < 0 || kernel >= NTIMED || !launches || !ms) return LBM_E_INVAL;
   HIPCHK(c, hipStreamSynchronize(c->stream));
   collect_times(c);
   *launches = c->t_launch[kernel];

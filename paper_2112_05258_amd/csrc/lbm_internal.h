@@ -81,6 +81,7 @@ struct InstDesc {
   int32_t has_wall, nth, nzl, nband;
   int32_t kernel;          // delta kernel: 0 Peskin 4-point, 1 cosine 4-point
   int32_t ext;             // 1: external solid (points moved by the caller)
+  int32_t shell;           // 1: off-diagonal terms of the wall model (shear, mixed bending)
   int32_t nee;             // 1: normal-neighbour x_f in the extrapolation at ghosts
   int64_t np;
   void* u4;                // R4 per local cell: unforced velocity (band cells)
@@ -96,6 +97,7 @@ struct InstDesc {
   int64_t cblk0;           // first block count of this instance (band rebuild)
   double* Dref;            // double4 per point: displacement when the band was built
   double ds_th, ds_z, area, ks, ei, mass, alpha, beta;
+  double phi12;            // 1 / (2 (1 + Poisson's ratio)), shell model
 };
 
 struct InstState {
@@ -139,6 +141,7 @@ struct Dev {
   int32_t max_band, max_np;
   int32_t any_nee;                 // some instance uses the normal-neighbour extrapolation
   int32_t max_mtile;               // largest membrane tile count of a wall (membrane_tiles)
+  int32_t any_shell;               // some wall takes the shell model's off-diagonal terms
 };
 
 // membrane step tiles: MEM_TJ x MEM_TK points (theta x z) per workgroup

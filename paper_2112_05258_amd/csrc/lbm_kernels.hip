@@ -1020,19 +1020,28 @@ __global__ __launch_bounds__(WBLOCK) void k_wall(Dev d, const int32_t* __restric
 // (max norm; positive floats order as their bit patterns) into the moved
 // word, launched right before the host's wall-motion test rather than in
 // every step.  D is the current displacement (Xab of the step parity).
+// Each workgroup strides over the points (MOTION_BLOCKS workgroups per wall)
+// and reduces in LDS, so that one atomic per workgroup reaches the moved
+// word: one per wave made the atomics on that single word the kernel's cost.
+constexpr int MOTION_BLOCKS = 256;
 __global__ __launch_bounds__(WBLOCK) void k_motion(Dev d, int parity) {
+  __shared__ uint32_t red[WBLOCK / 64];
   const int inst = d.walls[blockIdx.y];
-  if (d.err[inst] != 0u) return;   // failed instances take no part in the test
+  if (d.err[inst] != 0u) return;   // failed instances take no part in the test (whole block)
   const InstDesc& I = d.inst[inst];
-  if ((int64_t)blockIdx.x * WBLOCK >= I.np) return;  // whole block leaves
-  const int64_t p = (int64_t)blockIdx.x * WBLOCK + threadIdx.x;
   uint32_t mv = 0u;
-  if (p < I.np) {
+  for (int64_t p = (int64_t)blockIdx.x * WBLOCK + threadIdx.x; p < I.np; p += (int64_t)gridDim.x * WBLOCK) {
     const double3 D = ld3(I.Xab[parity], p), Dr = ld3(I.Dref, p);
-    mv = __float_as_uint((float)fmax(fabs(D.x - Dr.x), fmax(fabs(D.y - Dr.y), fabs(D.z - Dr.z))));
+    mv = max(mv, __float_as_uint((float)fmax(fabs(D.x - Dr.x), fmax(fabs(D.y - Dr.y), fabs(D.z - Dr.z)))));
   }
   mv = __ockl_wfred_max_u32(mv);   // all lanes of the wave are active here
-  if ((threadIdx.x & 63) == 0 && mv != 0u) atomicMax(d.moved, mv);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mv;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t m = red[0];
+    for (int w = 1; w < WBLOCK / 64; ++w) m = max(m, red[w]);
+    if (m != 0u) atomicMax(d.moved, m);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1273,7 +1282,8 @@ __global__ __launch_bounds__(WBLOCK) void k_band_write(Dev d) {
     }
 }
 
-// k_membrane: membrane forces (Eqs. tension and bending along theta and z)
+// k_membrane: membrane forces (Eqs. tension and bending along theta and z,
+// and with the shell model the off-diagonal terms of Eq. structure)
 // and the wall's central-difference step, one lane per point, after k_wall
 // has produced this step's penalty force.  A workgroup takes a tile of
 // MJ x MK points (theta x z) and stages X0 and D of the tile and its 2-point
@@ -1281,6 +1291,9 @@ __global__ __launch_bounds__(WBLOCK) void k_band_write(Dev d) {
 // neighbour values from L2.
 constexpr int MJ = MEM_TJ, MK = MEM_TK, MH = 2;
 constexpr int MLJ = MJ + 2 * MH, MLK = MK + 2 * MH;
+// SHELL: the build with the shell model's terms, taken when some wall asks
+// for them (they cost the plain membrane registers even when skipped).
+template <bool SHELL>
 __global__ __launch_bounds__(WBLOCK) void k_membrane(Dev d, int parity) {
   const int inst = d.walls[blockIdx.y];
   if (d.err[inst] & ERR_FROZEN) return;
@@ -1355,6 +1368,48 @@ __global__ __launch_bounds__(WBLOCK) void k_membrane(Dev d, int parity) {
     f.x -= I.ei * (kp.x - 2.0 * kc.x + km.x) / dz2;
     f.y -= I.ei * (kp.y - 2.0 * kc.y + km.y) / dz2;
     f.z -= I.ei * (kp.z - 2.0 * kc.z + km.z) / dz2;
+    if (SHELL && I.shell) {
+      // The off-diagonal terms of Eq. structure.  In-plane shear: on each of
+      // the four mesh cells around the point, the tangents X_theta and X_z
+      // at the cell centre (means of the cell's two edges along each
+      // direction), the strain S = X_theta . X_z and the fluxes
+      // A = Eh phi12 S X_z (differentiated along theta) and
+      // B = Eh phi12 S X_theta (along z); their divergence at the point
+      // differences the centre pairs on either side.
+      const double c = I.ks * I.phi12;
+      auto flux = [&](int dj, int dk, double3& A, double3& B) {
+        const double3 e0 = edge(dj, dk, dj + 1, dk), e1 = edge(dj, dk + 1, dj + 1, dk + 1);
+        const double3 e2 = edge(dj, dk, dj, dk + 1), e3 = edge(dj + 1, dk, dj + 1, dk + 1);
+        const double3 xt = make_double3((e0.x + e1.x) / (2.0 * I.ds_th), (e0.y + e1.y) / (2.0 * I.ds_th),
+                                        (e0.z + e1.z) / (2.0 * I.ds_th));
+        const double3 xz = make_double3((e2.x + e3.x) / (2.0 * I.ds_z), (e2.y + e3.y) / (2.0 * I.ds_z),
+                                        (e2.z + e3.z) / (2.0 * I.ds_z));
+        const double cs = c * (xt.x * xz.x + xt.y * xz.y + xt.z * xz.z);
+        A = make_double3(cs * xz.x, cs * xz.y, cs * xz.z);
+        B = make_double3(cs * xt.x, cs * xt.y, cs * xt.z);
+      };
+      double3 Ane, Bne, Ase, Bse, Anw, Bnw, Asw, Bsw;
+      flux(0, 0, Ane, Bne);
+      flux(0, -1, Ase, Bse);
+      flux(-1, 0, Anw, Bnw);
+      flux(-1, -1, Asw, Bsw);
+      const double ht = 2.0 * I.ds_th, hz = 2.0 * I.ds_z;
+      f.x += ((Ane.x + Ase.x) - (Anw.x + Asw.x)) / ht + ((Bne.x + Bnw.x) - (Bse.x + Bsw.x)) / hz;
+      f.y += ((Ane.y + Ase.y) - (Anw.y + Asw.y)) / ht + ((Bne.y + Bnw.y) - (Bse.y + Bsw.y)) / hz;
+      f.z += ((Ane.z + Ase.z) - (Anw.z + Asw.z)) / ht + ((Bne.z + Bnw.z) - (Bse.z + Bsw.z)) / hz;
+      // mixed bending (gamma_12 = gamma_21 = 1): -2 EI times the second z
+      // difference of the theta curvature, zero on the end rings
+      auto kth = [&](int dk) -> double3 {
+        if (k + dk <= 0 || k + dk >= nzl - 1) return make_double3(0.0, 0.0, 0.0);
+        const double3 a = DD(-1, dk), b = DD(0, dk), e = DD(1, dk);
+        return make_double3((e.x - 2.0 * b.x + a.x) / dt2, (e.y - 2.0 * b.y + a.y) / dt2,
+                            (e.z - 2.0 * b.z + a.z) / dt2);
+      };
+      const double3 qm = kth(-1), qc = kth(0), qp = kth(1);
+      f.x -= 2.0 * I.ei * (qp.x - 2.0 * qc.x + qm.x) / dz2;
+      f.y -= 2.0 * I.ei * (qp.y - 2.0 * qc.y + qm.y) / dz2;
+      f.z -= 2.0 * I.ei * (qp.z - 2.0 * qc.z + qm.z) / dz2;
+    }
   }
 
   // central difference in time; the wall receives -F.  An external solid
@@ -1505,7 +1560,7 @@ hipError_t launch_wall(const Dev& d, int prec, int parity, int tj, bool big, con
 
 hipError_t launch_motion(const Dev& d, int parity, hipStream_t s) {
   if (d.nwall <= 0 || d.max_np <= 0) return hipSuccess;
-  const dim3 g((unsigned)((d.max_np + WBLOCK - 1) / WBLOCK), d.nwall);
+  const dim3 g((unsigned)std::min<int64_t>(MOTION_BLOCKS, (d.max_np + WBLOCK - 1) / WBLOCK), d.nwall);
   return launch(k_motion, g, dim3(WBLOCK), s, Dev(d), int(parity));
 }
 hipError_t launch_wss(const Dev& d, int prec, int parity, int inst, int64_t np, double dist, double mu, double* out,
@@ -1541,7 +1596,8 @@ hipError_t launch_band_rebuild(const Dev& d, int parity, float thresh, const int
 hipError_t launch_membrane(const Dev& d, int parity, hipStream_t s) {
   if (d.nwall <= 0 || d.max_np <= 0 || d.max_mtile <= 0) return hipSuccess;
   const dim3 g2((unsigned)d.max_mtile, d.nwall);
-  return launch(k_membrane, g2, dim3(WBLOCK), s, Dev(d), int(parity));
+  return d.any_shell ? launch(k_membrane<true>, g2, dim3(WBLOCK), s, Dev(d), int(parity))
+                     : launch(k_membrane<false>, g2, dim3(WBLOCK), s, Dev(d), int(parity));
 }
 
 hipError_t launch_fill_rest(const Dev& d, int prec, int64_t cell0, int64_t ncell, double dshift, hipStream_t s) {
