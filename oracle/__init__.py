@@ -17,6 +17,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lbm_oracle.c")
+_SRCS = [_SRC, os.path.join(_HERE, "axi_oracle.c")]   # the 3D solver, the axisymmetric one
 _LIBS = {False: os.path.join(_HERE, "liblbm_oracle.so"),       # real = double
          True: os.path.join(_HERE, "liblbm_oracle_ext.so")}    # real = long double
 NREC = 14
@@ -28,11 +29,11 @@ def build(force=True):
     """Compile the oracle with gcc (-O2, OpenMP, no fast-math), in FP64 and
     in extended precision (long double, the reference for the FP64 bar)."""
     for ext, path in _LIBS.items():
-        if not force and os.path.exists(path) and os.path.getmtime(path) >= os.path.getmtime(_SRC):
+        if not force and os.path.exists(path) and os.path.getmtime(path) >= max(map(os.path.getmtime, _SRCS)):
             continue
         tmp = path + ".tmp"
         cmd = ["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared", "-Wall",
-               "-Wno-unused-function", "-o", tmp, _SRC, "-lm"]
+               "-Wno-unused-function", "-o", tmp] + _SRCS + ["-lm"]
         if ext:
             cmd.insert(1, "-DORC_EXTENDED")
         subprocess.check_call(cmd)
@@ -94,6 +95,18 @@ def lib(extended=False):
         L.orc_filament_force.argtypes = [C.c_int, dp, C.c_double, C.c_double, C.c_double, dp]
         L.orc_num_threads.restype = C.c_int
         L.orc_is_extended.restype = C.c_int
+        L.axo_create.restype = vp
+        L.axo_create.argtypes = [C.c_int, C.c_int, C.c_double, u8p, C.c_int]
+        L.axo_destroy.argtypes = [vp]
+        L.axo_set_bc.argtypes = [vp, C.c_int, C.c_int, dp, C.c_int, dp, C.c_int]
+        L.axo_set_body_force.argtypes = [vp, C.c_double, C.c_double]
+        L.axo_set_rest.argtypes = [vp, C.c_double]
+        L.axo_set_pops.argtypes = [vp, dp]
+        L.axo_get_pops.argtypes = [vp, dp]
+        L.axo_step.argtypes = [vp, C.c_long]
+        L.axo_get_fields.argtypes = [vp, dp, dp, dp]
+        L.axo_get_waveforms.restype = C.c_long
+        L.axo_get_waveforms.argtypes = [vp, dp, C.c_long]
         _lib[extended] = L
     return _lib[extended]
 
@@ -354,4 +367,76 @@ def from_config(cfg, pops=None, extended=False):
         o.set_wall_options(cfg.get("kernel", 0), cfg.get("wall_mode", 0) == 1)
         if cfg.get("shell", 0):
             o.set_shell(True, cfg.get("poisson", 0.5))
+    return o
+
+
+# ----------------------------------------------------------------------------
+# axisymmetric D2Q9 solver (axi_oracle.c)
+# ----------------------------------------------------------------------------
+
+class Axi:
+    """Axisymmetric D2Q9 oracle on an nr x nx grid of node types (row j at
+    r = j + 1/2, the axis half way below row 0, rows past nr-1 wall; column 0
+    INLET ghosts, column nx-1 OUTLET ghosts, or periodic along x)."""
+
+    def __init__(self, flags, tau, periodic_x=False, extended=False):
+        self.L = lib(extended)
+        self.flags = np.ascontiguousarray(flags, dtype=np.uint8)
+        self.nr, self.nx = self.flags.shape
+        self.h = self.L.axo_create(self.nx, self.nr, float(tau),
+                                   self.flags.ctypes.data_as(C.POINTER(C.c_uint8)), 1 if periodic_x else 0)
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            self.L.axo_destroy(self.h)
+            self.h = None
+
+    def set_bc(self, boundary, kind, par, state=()):
+        par, pp = _d(np.asarray(par, dtype=np.float64))
+        st, sp = _dn(np.asarray(state, dtype=np.float64) if len(state) else None)
+        self.L.axo_set_bc(self.h, boundary, kind, pp, len(par), sp, 0 if st is None else len(st))
+
+    def set_body_force(self, G0, omega=0.0):
+        self.L.axo_set_body_force(self.h, float(G0), float(omega))
+
+    def set_rest(self, p):
+        self.L.axo_set_rest(self.h, float(p))
+
+    def set_pops(self, g):
+        g, gp = _d(g)
+        self.L.axo_set_pops(self.h, gp)
+
+    def get_pops(self):
+        g = np.zeros((self.nr * self.nx, 9))
+        self.L.axo_get_pops(self.h, g.ctypes.data_as(C.POINTER(C.c_double)))
+        return g
+
+    def step(self, n):
+        self.L.axo_step(self.h, int(n))
+
+    def fields(self):
+        """Gauge pressure and the forced velocity (u_x, u_r), each (nr, nx)."""
+        out = [np.zeros((self.nr, self.nx)) for _ in range(3)]
+        self.L.axo_get_fields(self.h, *[o.ctypes.data_as(C.POINTER(C.c_double)) for o in out])
+        return out[0], out[1], out[2]
+
+    def waveforms(self):
+        n = self.L.axo_get_waveforms(self.h, None, 0)
+        out = np.zeros((n, NREC))
+        self.L.axo_get_waveforms(self.h, out.ctypes.data_as(C.POINTER(C.c_double)), n)
+        return out
+
+
+def axi_from_config(cfg, extended=False):
+    """Axisymmetric oracle for a workload dict of lbm_inputs (axi_* builders)."""
+    o = Axi(cfg["flags"], cfg["tau"], periodic_x=cfg.get("periodic_x", False), extended=extended)
+    for b, key in ((0, "inlet"), (1, "outlet")):
+        if key in cfg:
+            kind, par = cfg[key][0], cfg[key][1]
+            st = cfg[key][2] if len(cfg[key]) > 2 else ()
+            o.set_bc(b, kind, par, st)
+    if cfg.get("body_force"):
+        o.set_body_force(*cfg["body_force"])
+    if cfg.get("p_init", 0.0):
+        o.set_rest(cfg["p_init"])
     return o

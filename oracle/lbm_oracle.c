@@ -337,6 +337,13 @@ void orc_bc_update(void* cv, long n, double Qp, double Pbar, double* out) {
   out[4] = (double)c->Pw; out[5] = c->open; out[6] = c->snap; out[7] = (double)c->Td;
 }
 
+/* v* of a velocity-type update: the constant axial velocity, or the axial
+ * correction dv of the pressure-driven Windkessel */
+double orc_bc_vconst(void* cv) { return (double)((orc_bc*)cv)->vconst; }
+/* boundary area (cells, or the summed ring areas of an axisymmetric layer)
+ * that turns the pressure-driven Windkessel's flux deficit into dv */
+void orc_bc_set_area(void* cv, double area) { ((orc_bc*)cv)->area = area; }
+
 /* ------------------------------------------------------------------------ */
 /* wall (membrane) finite-difference operators                               */
 /* ------------------------------------------------------------------------ */
