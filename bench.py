@@ -50,6 +50,9 @@ def parse():
     ap.add_argument("--no-full-beat", action="store_true", help="skip the whole-beat leg")
     ap.add_argument("--contractility", action="store_true",
                     help="only the wall-shear-stress sweep over normal and high LV contractility")
+    ap.add_argument("--axi-refinement", action="store_true",
+                    help="only the axisymmetric straight-aorta refinement study (D = 20 ... 128)")
+    ap.add_argument("--no-axi", action="store_true", help="skip the axisymmetric refinement study")
     ap.add_argument("--surrogate-only", action="store_true",
                     help="only the learned-surrogate leg (for profiling its kernels)")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the batched-ensemble run")
@@ -343,6 +346,53 @@ def contractility_sweep(beats=1, every=250):
     return out
 
 
+def axi_refinement(Ds=(20, 32, 64, 100, 128), beats=4, nphase=256):
+    """The paper's straight-aorta refinement study on the axisymmetric solver
+    (rigid wall, LV-elastance inlet, Windkessel outlet, Wo = 16, length 25 D,
+    FP64): diameters of D = 20, 32, 64, 100 and 128 cells (dx = D_phys / D)
+    under acoustic scaling (lbm_inputs.axi_aorta), four beats each.  The last beat's inlet pressure,
+    inlet flow and mid-length pressure, in mmHg and ml/s, are sampled at
+    nphase phases (linear interpolation in the per-step record); the L-inf
+    error of each against the finest run, over that run's range, and the
+    observed order between successive resolutions are reported."""
+    import numpy as np
+    import lbm_inputs as L
+    import paper_2112_05258_amd as amd
+    runs, curves = {}, {}
+    for D in Ds:
+        c = L.axi_aorta(D, beats=beats)
+        sc = c["scales"]
+        s = amd.axi_solver_from_config(c, precision=amd.FP64)
+        t0 = time.perf_counter()
+        s.step(c["steps"])
+        s.sync()
+        dt = time.perf_counter() - t0
+        w = s.waveforms()
+        s.close()
+        T = c["beat"]
+        ph = (beats - 1) * T + T * np.arange(nphase) / nphase
+        qs = sc["sigma_V"] / sc["sigma_t"]
+        curves[D] = {"P_in": np.interp(ph, w[:, 0], w[:, 2]) / sc["sigma_P"],
+                     "Q_in": np.interp(ph, w[:, 0], w[:, 1]) / qs,
+                     "P_mid": np.interp(ph, w[:, 0], w[:, 13]) / sc["sigma_P"]}
+        nfluid = int((c["flags"] == L.FLUID).sum())
+        runs[D] = {"nodes": int(c["flags"].size), "steps": c["steps"], "s": round(dt, 2),
+                   "mlups": round(nfluid * c["steps"] / dt / 1e6, 1),
+                   "peak_P_in_mmHg": round(float(curves[D]["P_in"].max()), 3),
+                   "peak_Q_in_ml_s": round(float(curves[D]["Q_in"].max()), 2)}
+        print(f"# axi D={D}: {runs[D]}", file=sys.stderr, flush=True)
+    ref = curves[Ds[-1]]
+    errs, orders = {}, {}
+    for key in ("P_in", "Q_in", "P_mid"):
+        span = float(np.ptp(ref[key]))
+        e = [float(np.abs(curves[D][key] - ref[key]).max() / span) for D in Ds[:-1]]
+        errs[key] = [float(f"{v:.4e}") for v in e]
+        orders[key] = [round(float(np.log(e[k] / e[k + 1]) / np.log(Ds[k + 1] / Ds[k])), 2)
+                       for k in range(len(e) - 1)]
+    return {"D": list(Ds), "beats": beats, "runs": runs,
+            "linf_error_vs_finest_over_its_range": errs, "observed_order": orders}
+
+
 def _band_mask(cfg):
     """Band cells of the wall at its rest shape (same rule as the library:
     stencil + 2-cell margin, fluid only)."""
@@ -521,6 +571,9 @@ def main():
     if args.full_beat:
         print(json.dumps({"full_beat": full_beat()}), flush=True)
         return
+    if args.axi_refinement:
+        print(json.dumps({"axi_refinement": axi_refinement()}), flush=True)
+        return
     if args.contractility:
         print(json.dumps({"contractility": contractility_sweep()}), flush=True)
         return
@@ -576,6 +629,8 @@ def main():
         out["full_beat"] = full_beat()
     if not args.no_surrogate and args.workload == "cfg1" and args.precision == "fp32":
         out["surrogate"] = run_surrogate()
+    if not args.no_axi and args.workload == "cfg1" and args.precision == "fp32":
+        out["axi_refinement"] = axi_refinement()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cfg)
     print(json.dumps(out), flush=True)

@@ -421,29 +421,34 @@ def axi_pipe(nr, nx, periodic=False, stenosis=None):
 AXI_D_REF = 20
 
 
-def axi_aorta(D=20, beats=4, Wo=16.0, tau=0.51, length_D=25, Z=0.005):
+def axi_aorta(D=20, beats=4, Wo=16.0, tau20=0.51, length_D=25, Z=0.005):
     """The straight-aorta refinement workload: a rigid axisymmetric tube of
     diameter D cells and length 25 D between an LV-elastance inlet (E_es 2.2,
     E_min 0.06 mmHg/ml, HR 60, P_ed 8 mmHg) and a flux-driven Windkessel outlet
     (Z, C 1.5, R 1.0), Womersley number 16.  Every resolution is the same
-    continuous problem under diffusive scaling from D = 20 (tau fixed, so
-    dx ~ 1/D and dt ~ 1/D^2): with s = D / 20 the beat takes T_20 s^2 steps,
-    a volume of 1 ml is 0.7 s^3 cells and 1 mmHg is 1e-4 / s^2 in lattice
-    pressure; T_20 = 2 pi R^2 / (Wo^2 nu) at R = 10.  The lattice's flows are
-    slow (Reynolds number ~ 3: the physiological ~4 000 with Wo = 16 is
-    beyond BGK at D = 20), and Z = 0.005 mmHg s/ml keeps the flux-driven
-    Windkessel coupling inside its stable range at every resolution."""
+    continuous problem under acoustic scaling from D = 20 (dx and dt both
+    ~ 1/D, so the lattice's sound speed, its Mach number and its pressures
+    stay what they are at D = 20, and nu grows with D): with s = D / 20,
+    tau = 1/2 + (tau20 - 1/2) s, the beat takes T_20 s steps, 1 ml is
+    0.7 s^3 cells and 1 mmHg is 1e-4 in lattice pressure; T_20 =
+    2 pi R^2 / (Wo^2 nu) at R = 10.  The rigid tube's only compliance is the
+    lattice's own compressibility (sound speed c_s), part of the problem
+    being refined.  The flows are slow (Reynolds number ~ 3: the
+    physiological ~4 000 with Wo = 16 is beyond BGK at D = 20), and
+    Z = 0.005 mmHg s/ml keeps the flux-driven Windkessel coupling inside its
+    stable range at every resolution."""
     if D % 2:
         raise ValueError("D must be even")
     R = D // 2
     s = D / AXI_D_REF
-    nu = (tau - 0.5) / 3.0
-    T20 = 2.0 * math.pi * (AXI_D_REF / 2) ** 2 / (Wo * Wo * nu)
-    sc = scales(T20 * s * s, 0.7 * s ** 3, 1e-4 / (s * s))
+    nu20 = (tau20 - 0.5) / 3.0
+    T20 = 2.0 * math.pi * (AXI_D_REF / 2) ** 2 / (Wo * Wo * nu20)
+    tau = 0.5 + (tau20 - 0.5) * s
+    sc = scales(T20 * s, 0.7 * s ** 3, 1e-4)
     nx = length_D * D + 2
     p0 = 80.0 * sc["sigma_P"]
     return dict(
         name=f"axi_aorta_D{D}", nr=R, nx=nx, tau=tau, flags=axi_pipe(R, nx),
         inlet=(BC_LV_ELASTANCE, lv_params(2.2, 0.06, 60.0, 8.0, 0.075, sc)),
         outlet=(BC_WINDKESSEL3, wk_params(Z, 1.5, 1.0, sc, coupling=0.0), [p0]),
-        p_init=p0, scales=sc, beat=T20 * s * s, steps=int(math.ceil(beats * T20 * s * s)), D=D)
+        p_init=p0, scales=sc, beat=T20 * s, steps=int(math.ceil(beats * T20 * s)), D=D)

@@ -17,17 +17,21 @@
  * it exists for -- the difference between the axisymmetric incompressible
  * Navier-Stokes equations and what the planar D2Q9 model recovers with the
  * mass source -- enter as a body force with Guo's forcing term:
- *   F_x = -u_x u_r / r + (nu / r) (d_r u_x + d_x u_r) - d_x u_r / (6 r)
+ *   F_x = -u_x u_r / r + (nu / r) (d_r u_x + d_x u_r)
  *   F_r = -u_r^2 / r + (2 nu / r) d_r u_r - 2 nu u_r / r^2
- *         - (d_r u_r / r - u_r / r^2) / 6
  * (the planar model with the source recovers d_t u + div(u u) = -grad p +
  * nu div(grad u + grad u^T); the axisymmetric equations have u . grad u,
  * nu lap u + (nu / r) d_r u - nu u_r e_r / r^2 instead, and
- * div u = -u_r / r makes up the rest).  The last terms, -grad(u_r / r) / 6,
- * undo what the explicit source adds to the momentum flux at second order:
- * its isotropic second moment (1/3) S with S = -u_r / r, half of which
- * survives the time discretisation as a spurious pressure S / 6 (the
- * velocity field does not see a gradient, the pressure does).  Derivatives: central differences of
+ * div u = -u_r / r makes up the rest).
+ *
+ * Pressure.  The explicit source's isotropic second moment (1/3) S, with
+ * S = -u_r / r, survives the time discretisation at half strength as a
+ * pressure: the lattice's D / 3 is the flow's pressure minus S / 6, a
+ * gradient the velocity field does not see.  Every pressure read from the
+ * lattice (the column means handed to the 0D models, the field output) is
+ * therefore p = D / 3 - j_r / (6 r).  (Entering +grad(S) / 6 as a force
+ * instead removes the shift but makes the first row's u_r feed itself at
+ * small nu: unstable at tau = 0.51.)  Derivatives: central differences of
  * the unforced velocity; at the axis the mirror values (u_x even, u_r odd);
  * next to a wall the quadratic through the two nearest nodes and the wall's
  * zero (the wall sits half way, as bounce-back places it); next to an
@@ -41,7 +45,8 @@
  * 3 p (p gauge), j = sum e g; rho_0 = 1.
  *
  * One step (Algorithm 1's order): moments; flux Q = sum 2 pi r u_x (u_x =
- * j_x / sum f, as in the 3D solver) and ring-area-weighted mean pressure of
+ * j_x / sum f, as in the 3D solver) and ring-area-weighted mean pressure (as
+ * below) of
  * the inlet column 1, the outlet column nx-2 and the mid column nx/2; the 0D
  * updates; the axisymmetric force from the unforced velocities; collision
  * with F_i (Guo) and H_i = -w_i u_r / r (u the forced velocity) and pull
@@ -245,7 +250,7 @@ static void column(const axo_t* o, int col, real* Q, real* P) {
     if (o->type[c] != A_FLUID) continue;
     real dA = 2 * API * rj(j);
     q += dA * o->jx[c] / (1 + o->D[c]);
-    pa += dA * o->D[c] / 3;
+    pa += dA * (o->D[c] / 3 - o->jr[c] / (6 * rj(j)));
     a += dA;
   }
   *Q = q;
@@ -258,8 +263,8 @@ static void axforce(const axo_t* o, int i, int j, real G, real* Fx, real* Fr) {
   long c = NI(o, i, j);
   real r = rj(j), ux = o->jx[c], ur = o->jr[c], nu = o->nu;
   real dux_dr = ddr(o, o->jx, 0, i, j), dur_dr = ddr(o, o->jr, 1, i, j), dur_dx = ddx(o, o->jr, i, j);
-  *Fx = -ux * ur / r + nu / r * (dux_dr + dur_dx) - dur_dx / (6 * r) + G;
-  *Fr = -ur * ur / r + 2 * nu / r * dur_dr - 2 * nu * ur / (r * r) - (dur_dr / r - ur / (r * r)) / 6;
+  *Fx = -ux * ur / r + nu / r * (dux_dr + dur_dx) + G;
+  *Fr = -ur * ur / r + 2 * nu / r * dur_dr - 2 * nu * ur / (r * r);
 }
 
 /* post-collision value of direction k at fluid node c: BGK with Guo's term
@@ -392,7 +397,7 @@ void axo_get_fields(void* ov, double* p, double* ux, double* ur) {
   for (int j = 0; j < o->nr; ++j)
     for (int i = 0; i < o->nx; ++i) {
       long c = NI(o, i, j);
-      p[c] = (double)(o->D[c] / 3);
+      p[c] = (double)(o->D[c] / 3 - (o->type[c] == A_FLUID ? o->jr[c] / (6 * rj(j)) : 0));
       if (o->type[c] != A_FLUID) { ux[c] = ur[c] = 0; continue; }
       real fx, fr;
       axforce(o, i, j, G, &fx, &fr);

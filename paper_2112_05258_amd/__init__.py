@@ -126,6 +126,30 @@ SUR_SYMBOLS = {
     "lbm_sur_destroy": (C.c_int, [C.c_void_p]),
 }
 
+class AxiConfig(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("nr", C.c_int32), ("tau", C.c_double), ("precision", C.c_int32),
+                ("flags", C.POINTER(C.c_uint8)), ("periodic_x", C.c_int32), ("wave_cap", C.c_int32),
+                ("p_ref", C.c_double)]
+
+
+# axisymmetric solver (include/lbm_axi.h)
+AXI_SYMBOLS = {
+    "lbm_axi_query_size": (C.c_int, [C.POINTER(AxiConfig), C.POINTER(C.c_size_t)]),
+    "lbm_axi_init": (C.c_int, [C.POINTER(AxiConfig), C.c_void_p, C.c_size_t, C.c_void_p, C.POINTER(C.c_void_p)]),
+    "lbm_axi_couple_0d": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_double), C.c_int32,
+                                    C.POINTER(C.c_double), C.c_int32]),
+    "lbm_axi_set_body_force": (C.c_int, [C.c_void_p, C.c_double, C.c_double]),
+    "lbm_axi_set_rest": (C.c_int, [C.c_void_p, C.c_double]),
+    "lbm_axi_write_populations": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
+    "lbm_axi_read_populations": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
+    "lbm_axi_step": (C.c_int, [C.c_void_p, C.c_int64]),
+    "lbm_axi_read_fields": (C.c_int, [C.c_void_p] + [C.POINTER(C.c_double)] * 3),
+    "lbm_axi_read_waveforms": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_int64, C.POINTER(C.c_int64)]),
+    "lbm_axi_sync": (C.c_int, [C.c_void_p]),
+    "lbm_axi_last_error": (C.c_char_p, [C.c_void_p]),
+    "lbm_axi_destroy": (C.c_int, [C.c_void_p]),
+}
+
 _lib = None
 
 
@@ -140,7 +164,7 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is not built; run python -m paper_2112_05258_amd.build")
         L = C.CDLL(LIB_PATH)
-        for name, (res, args) in list(SYMBOLS.items()) + list(SUR_SYMBOLS.items()):
+        for name, (res, args) in list(SYMBOLS.items()) + list(SUR_SYMBOLS.items()) + list(AXI_SYMBOLS.items()):
             f = getattr(L, name)
             f.restype = res
             f.argtypes = args
@@ -457,4 +481,105 @@ def solver_from_configs(cfgs, precision=FP32, store_scale=0.0, wave_cap=4096):
                            margin=cfg.get("band_margin", 2), kernel=cfg.get("kernel", 0),
                            mode=cfg.get("wall_mode", 0), shell=cfg.get("shell", 0),
                            poisson=cfg.get("poisson", 0.5))
+    return s
+
+
+# ----------------------------------------------------------------------------
+# axisymmetric solver
+# ----------------------------------------------------------------------------
+
+class AxiSolver:
+    """Axisymmetric D2Q9 context (include/lbm_axi.h) on the current GPU: node
+    types (nr, nx), row j at r = j + 1/2; boundaries 0 (inlet) and 1 (outlet)."""
+
+    def __init__(self, flags, tau, precision=FP64, periodic_x=False, wave_cap=4096, p_ref=0.0, device="cuda:0"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self._flags = np.ascontiguousarray(flags, dtype=np.uint8)
+        self.nr, self.nx = self._flags.shape
+        self.cfg = AxiConfig(self.nx, self.nr, float(tau), precision,
+                             self._flags.ctypes.data_as(C.POINTER(C.c_uint8)), 1 if periodic_x else 0, wave_cap,
+                             float(p_ref))
+        self.h = None
+        nb = C.c_size_t()
+        self._check(lib().lbm_axi_query_size(C.byref(self.cfg), C.byref(nb)))
+        self.buf = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.Stream(device=self.device)
+        h = C.c_void_p()
+        self._check(lib().lbm_axi_init(C.byref(self.cfg), C.c_void_p(self.buf.data_ptr()), nb.value,
+                                       C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.h = h
+        self.t = 0
+
+    def _check(self, code):
+        if code != 0:
+            raise LbmError(code, lib().lbm_axi_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().lbm_axi_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def couple_0d(self, boundary, kind, params, state=()):
+        p = np.ascontiguousarray(params, dtype=np.float64)
+        st = np.ascontiguousarray(state, dtype=np.float64) if len(state) else None
+        self._check(lib().lbm_axi_couple_0d(self.h, boundary, kind, _dp(p), len(p), _dp(st),
+                                            0 if st is None else len(st)))
+
+    def set_body_force(self, G0, omega=0.0):
+        self._check(lib().lbm_axi_set_body_force(self.h, float(G0), float(omega)))
+
+    def set_rest(self, p):
+        self._check(lib().lbm_axi_set_rest(self.h, float(p)))
+
+    def write_populations(self, g):
+        g = np.ascontiguousarray(g, dtype=np.float64)
+        if g.size != self.nr * self.nx * 9:
+            raise ValueError("populations must be (nr * nx, 9)")
+        self._check(lib().lbm_axi_write_populations(self.h, _dp(g)))
+
+    def read_populations(self):
+        g = np.zeros((self.nr * self.nx, 9))
+        self._check(lib().lbm_axi_read_populations(self.h, _dp(g)))
+        return g
+
+    def step(self, n):
+        self._check(lib().lbm_axi_step(self.h, int(n)))
+        self.t += int(n)
+
+    def sync(self):
+        self._check(lib().lbm_axi_sync(self.h))
+
+    def fields(self):
+        """Gauge pressure and forced velocity (u_x, u_r), each (nr, nx)."""
+        out = [np.zeros((self.nr, self.nx)) for _ in range(3)]
+        self._check(lib().lbm_axi_read_fields(self.h, *[_dp(o) for o in out]))
+        return out[0], out[1], out[2]
+
+    def waveforms(self, cap=1 << 30):
+        m = min(cap, self.t, self.cfg.wave_cap if self.cfg.wave_cap > 0 else 4096)
+        out = np.zeros((m, 14))
+        n = C.c_int64()
+        self._check(lib().lbm_axi_read_waveforms(self.h, _dp(out), m, C.byref(n)))
+        return out[:n.value]
+
+
+def axi_solver_from_config(cfg, precision=FP64, wave_cap=None):
+    """Axisymmetric context for a workload dict of lbm_inputs (axi_* builders)."""
+    s = AxiSolver(cfg["flags"], cfg["tau"], precision=precision, periodic_x=cfg.get("periodic_x", False),
+                  wave_cap=wave_cap or max(4096, int(cfg.get("steps", 0)) + 1),
+                  p_ref=cfg.get("p_ref", cfg.get("p_init", 0.0)))
+    for b, key in ((0, "inlet"), (1, "outlet")):
+        if key in cfg:
+            kind, par = cfg[key][0], cfg[key][1]
+            st = cfg[key][2] if len(cfg[key]) > 2 else ()
+            s.couple_0d(b, kind, par, st)
+    if cfg.get("body_force"):
+        s.set_body_force(*cfg["body_force"])
+    if cfg.get("p_init", 0.0):
+        s.set_rest(cfg["p_init"])
     return s

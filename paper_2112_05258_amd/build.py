@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbm0d3d.so")
-SOURCES = ["lbm_kernels.hip", "lbm_api.cpp", "sur.hip"]
+SOURCES = ["lbm_kernels.hip", "lbm_api.cpp", "sur.hip", "axi.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -23,7 +23,8 @@ def test_header_declares_the_boundary_calls():
 def test_library_exports_every_declared_symbol():
     import paper_2112_05258_amd as amd
     lib = ctypes.CDLL(amd.LIB_PATH)
-    for header, table in (("lbm0d3d.h", amd.SYMBOLS), ("lbm_surrogate.h", amd.SUR_SYMBOLS)):
+    for header, table in (("lbm0d3d.h", amd.SYMBOLS), ("lbm_surrogate.h", amd.SUR_SYMBOLS),
+                          ("lbm_axi.h", amd.AXI_SYMBOLS)):
         missing = [n for n in declared_symbols(header) if not hasattr(lib, n)]
         assert not missing, (header, missing)
         # the binding covers the same set
@@ -70,3 +71,26 @@ def test_size_query_and_argument_checks_on_cpu():
     for v, want in ((1, 0), (2, -1), (-1, -1)):  # extrapolation variant: 0 or 1 only
         cfg.nee_variant = v
         assert amd.lib().lbm_query_sizes(ctypes.byref(cfg), 1, ctypes.byref(pb), ctypes.byref(wb)) == want, v
+
+
+def test_axisymmetric_size_query_and_checks_on_cpu():
+    """lbm_axi_query_size validates the node types without a device."""
+    import numpy as np
+    import lbm_inputs as L
+    import paper_2112_05258_amd as amd
+    f = L.axi_pipe(8, 40)
+    cfg = amd.AxiConfig(40, 8, 0.8, amd.FP64, f.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), 0, 64, 0.0)
+    nb = ctypes.c_size_t()
+    assert amd.lib().lbm_axi_query_size(ctypes.byref(cfg), ctypes.byref(nb)) == 0 and nb.value > 9 * 8 * 40 * 8
+    for bad_flags in (lambda g: g.__setitem__((3, 0), L.FLUID),      # fluid in the inlet column
+                      lambda g: g.__setitem__((3, 5), L.INLET),      # inlet off column 0
+                      lambda g: g.__setitem__((3, 5), 7)):           # no such type
+        g = f.copy()
+        bad_flags(g)
+        c2 = amd.AxiConfig(40, 8, 0.8, amd.FP64, g.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), 0, 64, 0.0)
+        assert amd.lib().lbm_axi_query_size(ctypes.byref(c2), ctypes.byref(nb)) == -1
+    c3 = amd.AxiConfig(40, 8, 0.5, amd.FP64, f.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), 0, 64, 0.0)
+    assert amd.lib().lbm_axi_query_size(ctypes.byref(c3), ctypes.byref(nb)) == -1
+    c4 = amd.AxiConfig(40, 8, 0.8, amd.FP16S, f.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), 0, 64, 0.0)
+    assert amd.lib().lbm_axi_query_size(ctypes.byref(c4), ctypes.byref(nb)) == -1
+    assert np.all(f[:, 1:-1] == L.FLUID)

@@ -149,7 +149,9 @@ def _stokes_mode(R, kR=4.0, tau=0.8, nsamp=120):
     ur = -k * (A * special.iv(1, k * r) + B * special.jv(1, beta * r)) * np.cos(k * x)
     p = s * A * special.iv(0, k * r) * np.cos(k * x)
     eu = ux.reshape(-1, 1) * _E[:, 0] + ur.reshape(-1, 1) * _E[:, 1]
-    geq = _W * (3 * p.reshape(-1, 1) + 3 * eu + 4.5 * eu ** 2 - 1.5 * (ux ** 2 + ur ** 2).reshape(-1, 1))
+    # the lattice holds D = 3 p + u_r / (2 r): its pressure reading subtracts u_r / (6 r)
+    D0 = 3 * p + ur / (2 * r)
+    geq = _W * (D0.reshape(-1, 1) + 3 * eu + 4.5 * eu ** 2 - 1.5 * (ux ** 2 + ur ** 2).reshape(-1, 1))
     o = oracle.Axi(L.axi_pipe(R, nx, periodic=True), tau, periodic_x=True)
     o.set_pops(geq)
     ts = np.linspace(0.2 / -s, 1.5 / -s, nsamp).astype(int)
@@ -168,8 +170,9 @@ def test_radial_stokes_mode():
     """The pin with u_r != 0 in the momentum equation: an axisymmetric Stokes
     mode decays at the exact rate (the radial terms -u_r^2 / r,
     (2 nu / r) d_r u_r - 2 nu u_r / r^2 and the mass source), and it carries
-    its exact pressure (the sound left by the start falls at second order;
-    without the -grad(u_r / r) / 6 term it falls at first order only)."""
+    its exact pressure (the start from the exact pressure, held as
+    D = 3 p + u_r / (2 r), leaves sound that falls at second order; read
+    without the u_r / (6 r) term it falls at first order only)."""
     res = [_stokes_mode(R) for R in (8, 16, 32)]
     rate, spread = [a for a, _ in res], [b for _, b in res]
     print({"rate": rate, "spread": spread})
