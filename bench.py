@@ -478,13 +478,35 @@ def run_ensemble(n=256, seed=3):
     cycles = float(np.floor(total / beats)[live].sum())
     finite = all(bool(np.isfinite(s.waveforms(k, cap=2)[:, 1:5]).all()) for k in range(n) if live[k])
     classes = s.classes()
+    # a short timed pass after the beat (kernels in sequence, HIP events):
+    # per-step kernel times and the bulk collide's achieved bandwidth
+    s.set_timing(True)
+    s.step(24)
+    s.sync()
+    kt = {k: s.kernel_time(k) for k in range(5)}
+    s.set_timing(False)
     s.close()
+    bulk_bytes = 0
+    for k, c in enumerate(cfgs):
+        if not live[k]:
+            continue
+        fl = (c["flags"] == L.FLUID).ravel()
+        bulk = ~_nee_tiles(c)
+        bulk_bytes += int((fl & bulk).sum()) * 153 + int((_band_mask(c).ravel() & bulk).sum()) * 16
+    n0, ms0 = kt[0]
+    coll_ms = ms0 / max(n0, 1)
+    names = ["collide", "reduce_0d", "band", "wall", "collide_0d_plane_tiles"]
     return {"instances": n, "cells": int(sum(c["nx"] * c["ny"] * c["nz"] for c in cfgs)), "fluid_cells": nfluid,
             "wall_points": int(sum(c["mesh"]["X0"].shape[0] for c in cfgs)),
             "value": round(nfluid * ran / el / 1e6, 1), "unit": "MLUPS",
             "ms_per_step": round(el / ran * 1e3, 4), "steps": total, "s": round(el, 2),
             "waveforms_per_s": round(cycles / el, 3), "cycles_completed": int(cycles),
             "failed_members": failed, "finite": finite, "setup_s": round(t_setup, 1),
+            "kernels_ms_per_step": {names[k]: round(kt[k][1] / max(kt[k][0], 1), 4) for k in range(5)},
+            "collide_roofline": {"bound": "hbm", "bytes_per_launch": bulk_bytes, "avg_launch_us": round(coll_ms * 1e3, 1),
+                                 "achieved": round(bulk_bytes / (coll_ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
+                                 "unit": "GB/s",
+                                 "frac": round(bulk_bytes / (coll_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
             "autotune": {"steps": tuned_steps, "s": round(t_tune, 2),
                          "classes": [{k: c[k] for k in ("instances", "cells", "block", "cells_per_lane",
                                                         "wall_tile_theta")} for c in classes]}}
