@@ -63,6 +63,11 @@ def test_cfg1_fp32_full_size_matches_oracle(cfg1_runs):
     print({a: f"{b:.2e}" for a, b in e.items()}, flush=True)
     for a, b in e.items():
         assert b <= 1e-5, (a, b)
+    # error-vs-step curve of the boundary records (flux, pressure per step)
+    curve = [max(_rel(ws[k, (1, 3, 12)], wo[k, (1, 3, 12)]), _rel(ws[k, (2, 4, 13)], wo[k, (2, 4, 13)]))
+             for k in range(len(wo))]
+    print({"error_vs_step": [f"{v:.1e}" for v in curve]}, flush=True)
+    assert max(curve) <= 1e-5
 
 
 def test_cfg1_fp16s_full_size_within_storage_bound(cfg1_runs):
