@@ -23,6 +23,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "lbm_surrogate.h"
@@ -383,19 +384,24 @@ __global__ void k_adam(float* __restrict__ w, float* __restrict__ m1, float* __r
 // input in LDS between two barriers.
 constexpr int MR = 128, MWID = 512, APITCH = MWID + 8;
 
-// weights in MFMA fragment order: element ((nt K/16 + ks) 64 + lane) 8 + e of
+// weights in MFMA fragment order: element ((ks N/32 + nt) 64 + lane) 8 + e of
 // layer l (N outputs, depth K = kp) is W[32 nt + lane % 32][16 ks + 8 (lane / 32) + e],
-// so the 64 lanes of a wave read one tile's k-step as 1 KB in a row
+// so the 64 lanes of a wave read one tile's k-step as 1 KB in a row, and the
+// N/32 tiles of one k-step lie side by side: the waves of every workgroup,
+// which read the same k-step of different tiles at about the same time,
+// spread over all L2 channels instead of meeting in the few that addresses
+// a power-of-two distance apart share
 __global__ void k_frag(const uint16_t* __restrict__ wb, LayerMap L, int64_t n, uint16_t* __restrict__ wf) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
   int l = 0;
   while (l + 1 < L.nl && p >= L.woff[l + 1]) ++l;
   const int64_t q = p - L.woff[l];
-  const int K = L.kp[l], KS = K / 16;
+  const int K = L.kp[l];
   const int e = (int)(q & 7), lane = (int)((q >> 3) & 63);
   const int64_t t = q >> 9;
-  const int ks = (int)(t % KS), nt = (int)(t / KS);
+  const int NT = L.out[l] / 32;
+  const int nt = (int)(t % NT), ks = (int)(t / NT);
   wf[p] = wb[L.woff[l] + (int64_t)(nt * 32 + (lane & 31)) * K + ks * 16 + (lane >> 5) * 8 + e];
 }
 
@@ -409,10 +415,10 @@ __global__ void k_frag_f32(const float* __restrict__ w, LayerMap L, int64_t n, u
   int l = 0;
   while (l + 1 < L.nl && p >= L.woff[l + 1]) ++l;
   const int64_t q = p - L.woff[l];
-  const int K = L.kp[l], KS = K / 16;
   const int e = (int)(q & 7), lane = (int)((q >> 3) & 63);
   const int64_t t = q >> 9;
-  const int ks = (int)(t % KS), nt = (int)(t / KS);
+  const int NT = L.out[l] / 32;
+  const int nt = (int)(t % NT), ks = (int)(t / NT);
   const int row = nt * 32 + (lane & 31), col = ks * 16 + (lane >> 5) * 8 + e;
   wf[p] = col < L.in[l] ? f2bf(w[L.off[l] + (int64_t)row * L.in[l] + col]) : (uint16_t)0;
 }
@@ -437,6 +443,114 @@ struct MlpArgs {
   float* y;             // m x 512 physical outputs
 };
 
+// GELU for the inference epilogue, the same A&S 7.1.26 tail as phi_cdf
+// rearranged: with q = (1 - erf(|z| / sqrt 2)) / 2 the upper tail,
+// z Phi(z) = max(z, 0) - |z| q for either sign of z, so no select is needed;
+// the constants absorb 1 / sqrt 2, the 1/2 of q and log2 e (v_exp_f32 is a
+// power of two).  Eleven VALU instructions and two transcendentals.
+__device__ __forceinline__ float gelu_epi(float z) {
+  const float t = __builtin_amdgcn_rcpf(fmaf(fabsf(z), 0.3275911f * 0.70710678118654752f, 1.0f));
+  const float poly =
+      0.5f * 0.254829592f +
+      t * (0.5f * -0.284496736f + t * (0.5f * 1.421413741f + t * (0.5f * -1.453152027f + t * (0.5f * 1.061405429f))));
+  const float e = __builtin_amdgcn_exp2f((z * -0.72134752044448170f) * z);   // exp(-z^2 / 2)
+  // max(z, 0) as a median: one instruction, where fmaxf adds a canonicalising max
+  return fmaf(-(fabsf(z) * t) * poly, e, __builtin_amdgcn_fmed3f(z, 0.0f, 3.0e38f));
+}
+
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+// The workgroup's 128 rows are two halves of 64, each a pipeline of its own
+// through the layers: one phase multiplies one half's layer while the same
+// waves, between those products, run the other half's GELU epilogue of the
+// layer before, so the vector ALUs work while the matrix cores do.
+// Activations stay in LDS and are overwritten in place; the two halves
+// touch disjoint rows and one barrier separates the phases.
+
+// compile-time loop: f(integral_constant<int, k>) for k = B .. E - 1
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+
+// GELU of accumulator n (0..63, in (i, j, v) order) of a half's (column,
+// row) tiles; every fourth one stores the group of four as one 8-byte LDS
+// write (lane l: row i 32 + l % 32, columns 8 (v / 4) + 4 (l / 32) .. + 3 of
+// tile j).
+template <int N>
+__device__ __forceinline__ void epi_value(const f32x16 (&acc)[2][2], float (&gv)[4], uint16_t* act, int wv,
+                                          int lane) {
+  constexpr int i = N >> 5, j = (N >> 4) & 1, v = N & 15;
+  gv[N & 3] = gelu_epi(acc[i][j][v]);
+  if ((N & 3) == 3) {
+    const int row = i * 32 + (lane & 31), col = (2 * wv + j) * 32 + 8 * (v >> 2) + 4 * (lane >> 5);
+    // hardware round-to-nearest-even conversion, two values at a time
+    const bf16x2 lo = __builtin_convertvector((f32x2){gv[0], gv[1]}, bf16x2);
+    const bf16x2 hi = __builtin_convertvector((f32x2){gv[2], gv[3]}, bf16x2);
+    *(uint2*)(act + row * APITCH + col) = make_uint2(__builtin_bit_cast(uint32_t, lo), __builtin_bit_cast(uint32_t, hi));
+  }
+}
+
+template <int N0, int PER>
+__device__ __forceinline__ void epi_values(const f32x16 (&acc)[2][2], float (&gv)[4], uint16_t* act, int wv, int lane) {
+  if constexpr (PER > 0) {
+    epi_value<N0>(acc, gv, act, wv, lane);
+    epi_values<N0 + 1, PER - 1>(acc, gv, act, wv, lane);
+  }
+}
+
+// One phase: the products of one layer (depth 16 KS) for one half (two
+// 32-row blocks, rows at actM) and this wave's 64 output columns into accM,
+// the first k-step taking the bias tiles bt as its accumulator input; with
+// DRAIN the epilogue of the other half (accE, rows at actE) is spread over
+// the k-steps.  TR: the weights are the A operand and the activations the B
+// operand, so a tile holds (output column, row) and lane l has row l % 32
+// and four consecutive columns per group of four accumulators.  !TR: (row,
+// output column), lane l has column l % 32 (the output layer, whose FP32
+// rows leave in 128-byte runs).
+template <bool TR, int KS, bool DRAIN>
+__device__ __forceinline__ void mlp_phase(f32x16 (&accM)[2][2], const f32x16 (&bt)[2], const uint16_t* actM,
+                                          const uint16_t* wf, const f32x16 (&accE)[2][2], uint16_t* actE, int wv,
+                                          int lane) {
+  const int fr = lane & 31, fk = (lane >> 5) * 8;
+  constexpr int NT = MWID / 32;   // column tiles of a layer
+  const bf16x8* W0 = (const bf16x8*)wf + (2 * wv) * 64 + lane;
+  const bf16x8* W1 = W0 + 64;
+  const uint16_t* arow = actM + fr * APITCH + fk;
+  bf16x8 b0[2], b1[2], af[2][2];
+  float gv[4];
+  b0[0] = W0[0];
+  b1[0] = W1[0];
+  af[0][0] = *(const bf16x8*)arow;
+  af[0][1] = *(const bf16x8*)(arow + 32 * APITCH);
+  static_for<0, KS>([&](auto cc) {
+    constexpr int c = decltype(cc)::value;
+    if constexpr (c + 1 < KS) {   // next k-step's fragments in flight
+      b0[(c + 1) & 1] = W0[(c + 1) * NT * 64];
+      b1[(c + 1) & 1] = W1[(c + 1) * NT * 64];
+      af[(c + 1) & 1][0] = *(const bf16x8*)(arow + (c + 1) * 16);
+      af[(c + 1) & 1][1] = *(const bf16x8*)(arow + 32 * APITCH + (c + 1) * 16);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const f32x16 c0 = c == 0 ? bt[0] : accM[i][0], c1 = c == 0 ? bt[1] : accM[i][1];
+      const bf16x8 x = af[c & 1][i];
+      if (TR) {
+        accM[i][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b0[c & 1], x, c0, 0, 0, 0);
+        accM[i][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b1[c & 1], x, c1, 0, 0, 0);
+      } else {
+        accM[i][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x, b0[c & 1], c0, 0, 0, 0);
+        accM[i][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x, b1[c & 1], c1, 0, 0, 0);
+      }
+    }
+    if constexpr (DRAIN) epi_values<c * (64 / KS), 64 / KS>(accE, gv, actE, wv, lane);
+  });
+}
+
 __global__ __launch_bounds__(512) void k_mlp_fwd(MlpArgs a) {
   __shared__ __attribute__((aligned(16))) uint16_t act[MR * APITCH];
   const int tid = (int)threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -450,94 +564,89 @@ __global__ __launch_bounds__(512) void k_mlp_fwd(MlpArgs a) {
     act[r * APITCH + j] = f2bf(v);
   }
   __syncthreads();
-  const int fr = lane & 31, fk = (lane >> 5) * 8;
-  f32x16 acc[4][2];
-  // acc = act (128 x K) W_l^T for this wave's two column tiles
-  auto layer = [&](int l) {
-    const int KS = a.L.kp[l] / 16;   // 2 for the first layer, 32 after
-    const bf16x8* W0 = (const bf16x8*)(a.wf + a.L.woff[l]) + (int64_t)(2 * wv) * KS * 64 + lane;
-    const bf16x8* W1 = W0 + (int64_t)KS * 64;
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j)
-#pragma unroll
-        for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
-    // k-steps in pairs; the next pair's weight fragments are in flight while
-    // the current pair is multiplied (KS is even)
-    bf16x8 b0[2], b1[2];
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      b0[q] = W0[q * 64];
-      b1[q] = W1[q * 64];
-    }
-    for (int c = 0; c < KS; c += 2) {
-      bf16x8 n0[2], n1[2];
-      const bool more = c + 2 < KS;
-      if (more) {
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-          n0[q] = W0[(c + 2 + q) * 64];
-          n1[q] = W1[(c + 2 + q) * 64];
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        const int k = (c + q) * 16 + fk;
-        bf16x8 af[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) af[i] = *(const bf16x8*)(act + (i * 32 + fr) * APITCH + k);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          acc[i][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[i], b0[q], acc[i][0], 0, 0, 0);
-          acc[i][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[i], b1[q], acc[i][1], 0, 0, 0);
-        }
-      }
-      if (more) {
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-          b0[q] = n0[q];
-          b1[q] = n1[q];
-        }
-      }
-    }
-    __syncthreads();   // every wave has read this layer's input
-  };
+  const int fr = lane & 31, fh = lane >> 5;
+  uint16_t* const actA = act;
+  uint16_t* const actB = act + 64 * APITCH;
   auto bias_of = [&](int l) { return a.w + a.L.off[l] + (int64_t)a.L.out[l] * a.L.in[l]; };
-  // accumulator v of lane l: row 8 (v / 4) + 4 (l / 32) + v % 4 of its
-  // 32 x 32 tile, column l % 32
-  const int nl = a.L.nl;
-  for (int l = 0; l + 1 < nl; ++l) {
-    layer(l);
+  // hidden-layer bias tiles: accumulator v of lane l is column
+  // 8 (v / 4) + 4 (l / 32) + v % 4 of the (column, row) tile
+  auto bias_tr = [&](int l, f32x16 (&bt)[2]) {
     const float* bias = bias_of(l);
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const float4 bv = *(const float4*)(bias + (2 * wv + j) * 32 + 8 * g + 4 * fh);
+        bt[j][4 * g + 0] = bv.x;
+        bt[j][4 * g + 1] = bv.y;
+        bt[j][4 * g + 2] = bv.z;
+        bt[j][4 * g + 3] = bv.w;
+      }
+  };
+  // output-layer bias tiles: column l % 32 of the (row, column) tile
+  auto bias_out = [&](f32x16 (&bt)[2]) {
+    const float* bias = bias_of(a.L.nl - 1);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const float bj = bias[(2 * wv + j) * 32 + fr];
+#pragma unroll
+      for (int v = 0; v < 16; ++v) bt[j][v] = bj;
+    }
+  };
+  auto wf_of = [&](int l) { return a.wf + a.L.woff[l]; };
+  const int nl = a.L.nl;
+  f32x16 accA[2][2], accB[2][2];
+  constexpr int K0 = KPAD / 16, KH = MWID / 16;
+  // phase 2l: half A's products of layer l beside half B's epilogue of
+  // layer l - 1; phase 2l + 1: half B's products of layer l beside half A's
+  // epilogue of layer l.  A barrier ends every phase: the rows a phase
+  // drains into were read by the products of the phase before, and the rows
+  // it multiplies were drained into by the phase before.
+  {
+    f32x16 bt[2];
+    bias_tr(0, bt);
+    mlp_phase<true, K0, false>(accA, bt, actA, wf_of(0), accB, actB, wv, lane);
+    __syncthreads();
+    mlp_phase<true, K0, true>(accB, bt, actB, wf_of(0), accA, actA, wv, lane);
+    __syncthreads();
+  }
+  for (int l = 1; l + 1 < nl; ++l) {
+    f32x16 bt[2];
+    bias_tr(l, bt);
+    mlp_phase<true, KH, true>(accA, bt, actA, wf_of(l), accB, actB, wv, lane);
+    __syncthreads();
+    mlp_phase<true, KH, true>(accB, bt, actB, wf_of(l), accA, actA, wv, lane);
+    __syncthreads();
+  }
+  {
+    f32x16 bt[2];
+    bias_out(bt);
+    mlp_phase<false, KH, true>(accA, bt, actA, wf_of(nl - 1), accB, actB, wv, lane);
+    __syncthreads();
+    mlp_phase<false, KH, false>(accB, bt, actB, wf_of(nl - 1), accA, actA, wv, lane);
+  }
+  const bool full = r0 + MR <= a.m;   // uniform: only the last workgroup may be ragged
+  auto store = [&](const f32x16 (&acc)[2][2], int rb, auto checked) {
+    float* yb = a.y + (int64_t)(r0 + rb) * MWID;
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       const int col = (2 * wv + j) * 32 + fr;
-      const float bj = bias[col];
+      const float mj = a.mu[col], sj = a.sigma[col];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
-          const int row = i * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
-          // hardware round-to-nearest-even conversion (v_cvt_pk_bf16_f32)
-          act[row * APITCH + col] = __builtin_bit_cast(uint16_t, (__bf16)gelu(acc[i][j][v] + bj));
+          const int row = i * 32 + (v >> 2) * 8 + fh * 4 + (v & 3);
+          if (!decltype(checked)::value || r0 + rb + row < a.m) yb[row * MWID + col] = fmaf(sj, acc[i][j][v], mj);
         }
     }
-    __syncthreads();
-  }
-  layer(nl - 1);
-  const float* bias = bias_of(nl - 1);
-#pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const int col = (2 * wv + j) * 32 + fr;
-    const float bj = bias[col], mj = a.mu[col], sj = a.sigma[col];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int row = i * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
-        if (r0 + row < a.m) a.y[(int64_t)(r0 + row) * MWID + col] = mj + sj * (acc[i][j][v] + bj);
-      }
+  };
+  if (full) {
+    store(accA, 0, std::false_type{});
+    store(accB, 64, std::false_type{});
+  } else {
+    store(accA, 0, std::true_type{});
+    store(accB, 64, std::true_type{});
   }
 }
 
