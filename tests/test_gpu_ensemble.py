@@ -73,8 +73,17 @@ def test_elastic_batch_equals_single_runs(amd, precision, tol):
         ps_, us = s.fields()
         fl = c["flags"] == L.FLUID
         assert rel_l2(ub[fl], us[fl]) <= tol and rel_l2(pb[fl], ps_[fl]) <= tol, k
+        # the wall: the two runs' spread forces differ by the order of their
+        # atomic additions, a rounding that the slip integral and the
+        # displacement recursion sum over the n steps like a random walk
+        # (sqrt(n) tol), and X is read back in absolute coordinates, so the
+        # displacement X - X0 carries eps |X| / |D| on top
         wb, ws = b.read_wall(k), s.read_wall()
-        assert rel_l2(wb["X"] - c["mesh"]["X0"], ws["X"] - c["mesh"]["X0"]) <= tol * 10, k
+        D = ws["X"] - c["mesh"]["X0"]
+        floor = np.finfo(float).eps * np.linalg.norm(ws["X"]) / np.linalg.norm(D)
+        e_x = rel_l2(wb["X"] - c["mesh"]["X0"], D)
+        print({"member": k, "wall_X": f"{e_x:.2e}", "bar": f"{tol * np.sqrt(41) + floor:.2e}"}, flush=True)
+        assert e_x <= tol * np.sqrt(41) + floor, k
         s.close()
 
 
