@@ -509,7 +509,7 @@ def run_ensemble(n=256, seed=3):
                                  "frac": round(bulk_bytes / (coll_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
             "autotune": {"steps": tuned_steps, "s": round(t_tune, 2),
                          "classes": [{k: c[k] for k in ("instances", "cells", "block", "cells_per_lane",
-                                                        "wall_tile_theta")} for c in classes]}}
+                                                        "wall_tile_theta", "wall_tile_z")} for c in classes]}}
 
 
 def _oracle_rate(cfg, budget_s, max_steps):

@@ -352,13 +352,23 @@ lbm_status lbm_set_overlap(lbm_ctx* ctx, int32_t on);
  * cell count into size classes (quartiles from 8 instances on, else one
  * class); each class has its own collide-stream launch (workgroup size and
  * cells per lane, over a table of tiles of consecutive cells of one
- * instance) and wall launch (tiles of wall_tile_theta x 256/wall_tile_theta
- * mesh points).  Results do not depend on the shapes, except for the
- * rounding order of the wall force's float additions. */
+ * instance) and wall launch (tiles of wall_tile_theta x wall_tile_z mesh
+ * points, one 256-lane workgroup each).  Defaults: workgroups of 256 lanes,
+ * one cell per lane, 16 x 16 wall tiles -- or, when a wall is attached whose
+ * 16 x 16 stencil boxes would fill more than 60 % of the standard LDS
+ * staging (coarse meshes), the first of 16 x 8, 8 x 16, 8 x 8 whose boxes
+ * do not, unless the class's shapes were set.  Results do not depend on the shapes, except for
+ * the rounding order of the wall force's float additions. */
 typedef struct {
   int32_t block;            /* collide workgroup: 128, 256 or 512 lanes */
   int32_t cells_per_lane;   /* 1 or 2 */
   int32_t wall_tile_theta;  /* 8, 16 or 32 mesh points along theta */
+  int32_t wall_tile_z;      /* mesh points along z: 0 = 256 / wall_tile_theta
+                               (tiles of 256 points: 8 x 32, 16 x 16, 32 x 8),
+                               or the smaller tiles 8 x 16, 16 x 8, 8 x 8, whose
+                               stencil boxes fit the staging memory on coarse
+                               meshes (one lane per point, the other lanes idle
+                               while the points are processed) */
 } lbm_launch;
 
 int32_t lbm_num_classes(lbm_ctx* ctx);
@@ -370,7 +380,7 @@ lbm_status lbm_get_launch(lbm_ctx* ctx, int32_t cls, lbm_launch* out);
 lbm_status lbm_set_launch(lbm_ctx* ctx, int32_t cls, const lbm_launch* launch);
 
 /* Autotuner: times the current shapes and every collide shape (6), then
- * the current and every wall tile (3, if walls are registered), over
+ * the current and every wall tile (6, if walls are registered), over
  * trial_steps steps each (rounded up to even, after 2 untimed steps), per
  * class with HIP events; a class changes shape only for a candidate at
  * least 2 % faster than its current one.  The trial steps are ordinary steps of the method: the state

@@ -51,7 +51,8 @@ class WallDesc(C.Structure):
 
 
 class Launch(C.Structure):
-    _fields_ = [("block", C.c_int32), ("cells_per_lane", C.c_int32), ("wall_tile_theta", C.c_int32)]
+    _fields_ = [("block", C.c_int32), ("cells_per_lane", C.c_int32), ("wall_tile_theta", C.c_int32),
+                ("wall_tile_z", C.c_int32)]
 
 
 SYMBOLS = {
@@ -372,7 +373,7 @@ class Solver:
     # ---- launch shapes per size class (autotuner) ----------------------
     def classes(self):
         """Per size class: dict(instances, cells, wall_points, block,
-        cells_per_lane, wall_tile_theta)."""
+        cells_per_lane, wall_tile_theta, wall_tile_z)."""
         out = []
         for q in range(lib().lbm_num_classes(self.h)):
             ni, nc, npt = C.c_int32(), C.c_int64(), C.c_int64()
@@ -380,11 +381,13 @@ class Solver:
             la = Launch()
             self._check(lib().lbm_get_launch(self.h, q, C.byref(la)))
             out.append(dict(instances=ni.value, cells=nc.value, wall_points=npt.value, block=la.block,
-                            cells_per_lane=la.cells_per_lane, wall_tile_theta=la.wall_tile_theta))
+                            cells_per_lane=la.cells_per_lane, wall_tile_theta=la.wall_tile_theta,
+                            wall_tile_z=la.wall_tile_z))
         return out
 
-    def set_launch(self, cls, block, cells_per_lane, wall_tile_theta):
-        la = Launch(block, cells_per_lane, wall_tile_theta)
+    def set_launch(self, cls, block, cells_per_lane, wall_tile_theta, wall_tile_z=0):
+        """wall_tile_z = 0: the 256-point tile, 256 / wall_tile_theta along z."""
+        la = Launch(block, cells_per_lane, wall_tile_theta, wall_tile_z)
         self._check(lib().lbm_set_launch(self.h, cls, C.byref(la)))
 
     def _class_keys(self):
@@ -414,7 +417,7 @@ class Solver:
         if keys and all(k in table for k in keys):
             for q, k in enumerate(keys):
                 e = table[k]
-                self.set_launch(q, e["block"], e["cells_per_lane"], e["wall_tile_theta"])
+                self.set_launch(q, e["block"], e["cells_per_lane"], e["wall_tile_theta"], e.get("wall_tile_z", 0))
             return 0
         adv = C.c_int64()
         self._check(lib().lbm_autotune(self.h, int(trial_steps), C.byref(adv)))
@@ -428,8 +431,8 @@ class Solver:
         for q, k in enumerate(keys):
             c = cls[pick[k]]
             if pick[k] != q:
-                self.set_launch(q, c["block"], c["cells_per_lane"], c["wall_tile_theta"])
-            table[k] = {a: c[a] for a in ("block", "cells_per_lane", "wall_tile_theta")}
+                self.set_launch(q, c["block"], c["cells_per_lane"], c["wall_tile_theta"], c["wall_tile_z"])
+            table[k] = {a: c[a] for a in ("block", "cells_per_lane", "wall_tile_theta", "wall_tile_z")}
         if cache:
             tmp = cache + ".tmp"
             with open(tmp, "w") as f:

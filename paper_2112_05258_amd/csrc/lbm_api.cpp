@@ -242,16 +242,17 @@ struct Wall {
 };
 
 // Instances of similar box volume share launch shapes, chosen by the
-// autotuner: collide workgroup size and cells per lane, wall tile width.
+// autotuner: collide workgroup size and cells per lane, wall tile shape.
 struct SizeClass {
   std::vector<int32_t> inst;   // instance ids, ascending (memory order)
-  int bs = 256, cpt = 1, tj = 16;
+  int bs = 256, cpt = 1, tj = 16, tk = 16;
+  bool shaped = false;         // shapes set by lbm_set_launch or the autotuner
 };
 
 // One launch: the classes that share a shape (or one class while tuning),
 // with their slice of the packed tile table or wall list.
 struct LaunchGroup {
-  int bs = 256, cpt = 1, tj = 16;
+  int bs = 256, cpt = 1, tj = 16, tk = 16;
   bool nee = false;            // collide tiles holding cells next to a 0D ghost of an
                                // instance with the normal-neighbour extrapolation
   bool bigbox = false;         // wall tiles staged by the large-box kernel
@@ -367,7 +368,7 @@ hipError_t enqueue_step(lbm_ctx* c, int parity, bool timed) {
     if ((e = hipStreamWaitEvent(s2, c->ev_fork, 0)) != hipSuccess) return e;
     if ((e = launch_band(c->dev, c->prec, parity, s2)) != hipSuccess) return e;
     for (const LaunchGroup& G : c->wgroups)
-      if ((e = launch_wall(c->dev, c->prec, parity, G.tj, G.bigbox, cw + G.off, G.count, G.wall_tiles, s2)) != hipSuccess)
+      if ((e = launch_wall(c->dev, c->prec, parity, G.tj, G.tk, G.bigbox, cw + G.off, G.count, G.wall_tiles, s2)) != hipSuccess)
         return e;
     if ((e = hipEventRecord(c->ev_wall, s2)) != hipSuccess) return e;
     if ((e = launch_membrane(c->dev, parity, s2)) != hipSuccess) return e;
@@ -407,7 +408,7 @@ hipError_t enqueue_step(lbm_ctx* c, int parity, bool timed) {
     for (const LaunchGroup& G : c->wgroups) {
       EventPair p;
       tpre(p);
-      e = launch_wall(c->dev, c->prec, parity, G.tj, G.bigbox, cw + G.off, G.count, G.wall_tiles, c->stream);
+      e = launch_wall(c->dev, c->prec, parity, G.tj, G.tk, G.bigbox, cw + G.off, G.count, G.wall_tiles, c->stream);
       if (e != hipSuccess) return e;
       tpost(p, G.cls, 1);
     }
@@ -492,19 +493,18 @@ void make_classes(lbm_ctx* c) {
 // (workgroup, cells per lane) and one wall launch per distinct tile width,
 // or one of each per class (per_class, for timing them apart).  Packs and
 // uploads the tile table and the wall list.
-// Whether wall i's tiles of tj x 256/tj points need the large-box wall
-// kernel: some stencil box, at the positions the band was last built
-// around, exceeds 90 % of the standard staging capacity (coarse meshes, or
-// a wall whose motion has stretched its tiles; the margin leaves room for
-// the motion until the next band build).  One tile on the unstaged path
-// (stencils read and spread in global memory) sets the whole launch's
-// duration, so a single one is enough to switch.
-bool wall_needs_bigbox(const lbm_ctx* c, int i, int tj) {
+// Largest stencil box (cells) of wall i's tiles of tj x tk points at the
+// positions its band was last built around, and whether that needs the
+// large-box wall kernel: some box exceeds 90 % of the standard staging
+// capacity (coarse meshes, or a wall whose motion has stretched its tiles;
+// the margin leaves room for the motion until the next band build).  One
+// tile on the unstaged path (stencils read and spread in global memory) sets
+// the whole launch's duration, so a single one is enough to switch.
+int64_t wall_max_box(const lbm_ctx* c, int i, int tj, int tk) {
   const InstDesc& d = c->inst[i];
   const std::vector<double>& X = c->wall[i].Xband;
-  const int tk = 256 / tj, nth = d.nth, nzl = d.nzl;
-  const int64_t cap = wall_boxcap(c->prec == 0 ? 8 : 4, tj) * 9 / 10;
-  int64_t over = 0;
+  const int nth = d.nth, nzl = d.nzl;
+  int64_t most = 0;
   for (int k0 = 0; k0 < nzl; k0 += tk)
     for (int j0 = 0; j0 < nth; j0 += tj) {
       int lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
@@ -517,9 +517,13 @@ bool wall_needs_bigbox(const lbm_ctx* c, int i, int tj) {
           }
       int64_t vol = 1;
       for (int a = 0; a < 3; ++a) vol *= (int64_t)(hi[a] - lo[a] + 4);
-      over += vol > cap;
+      most = std::max(most, vol);
     }
-  return over > 0;
+  return most;
+}
+
+bool wall_needs_bigbox(const lbm_ctx* c, int i, int tj, int tk) {
+  return wall_max_box(c, i, tj, tk) > wall_boxcap(c->prec == 0 ? 8 : 4, tj) * 9 / 10;
 }
 
 lbm_status refresh_bands(lbm_ctx* c);
@@ -570,18 +574,19 @@ lbm_status build_groups(lbm_ctx* c, bool per_class) {
     if (wdone[q]) continue;
     LaunchGroup G;
     G.tj = c->cls[q].tj;
+    G.tk = c->cls[q].tk;
     G.cls = q;
     G.off = walls.size();
-    const int tk = 256 / G.tj;
+    const int tk = G.tk;
     for (int r = q; r < nc; ++r) {
-      if (wdone[r] || (r != q && (per_class || c->cls[r].tj != G.tj))) continue;
+      if (wdone[r] || (r != q && (per_class || c->cls[r].tj != G.tj || c->cls[r].tk != G.tk))) continue;
       wdone[r] = true;
       for (int32_t i : c->cls[r].inst)
         if (c->wall[i].on) {
           walls.push_back(i);
           const InstDesc& d = c->inst[i];
           G.wall_tiles = std::max(G.wall_tiles, ((d.nth + G.tj - 1) / G.tj) * ((d.nzl + tk - 1) / tk));
-          G.bigbox = G.bigbox || wall_needs_bigbox(c, i, G.tj);
+          G.bigbox = G.bigbox || wall_needs_bigbox(c, i, G.tj, G.tk);
         }
     }
     G.count = (int)(walls.size() - G.off);
@@ -1148,14 +1153,23 @@ lbm_status lbm_get_launch(lbm_ctx* c, int32_t q, lbm_launch* out) {
   out->block = c->cls[q].bs;
   out->cells_per_lane = c->cls[q].cpt;
   out->wall_tile_theta = c->cls[q].tj;
+  out->wall_tile_z = c->cls[q].tk;
   return LBM_OK;
 }
 
 namespace {
+// the wall tile shapes (theta x z mesh points) the kernel is built for
+constexpr int WALL_TILES[6][2] = {{8, 32}, {16, 16}, {32, 8}, {8, 16}, {16, 8}, {8, 8}};
+
+int tile_z(const lbm_launch* l) { return l->wall_tile_z ? l->wall_tile_z : (l->wall_tile_theta ? 256 / l->wall_tile_theta : 0); }
+
 bool valid_launch(const lbm_launch* l) {
-  return l && (l->block == 128 || l->block == 256 || l->block == 512) &&
-         (l->cells_per_lane == 1 || l->cells_per_lane == 2) &&
-         (l->wall_tile_theta == 8 || l->wall_tile_theta == 16 || l->wall_tile_theta == 32);
+  if (!l || !(l->block == 128 || l->block == 256 || l->block == 512) ||
+      !(l->cells_per_lane == 1 || l->cells_per_lane == 2))
+    return false;
+  for (const auto& t : WALL_TILES)
+    if (l->wall_tile_theta == t[0] && tile_z(l) == t[1]) return true;
+  return false;
 }
 
 void apply_launch(lbm_ctx* c, int q, const lbm_launch& l) {
@@ -1163,12 +1177,15 @@ void apply_launch(lbm_ctx* c, int q, const lbm_launch& l) {
   K.bs = l.block;
   K.cpt = l.cells_per_lane;
   K.tj = l.wall_tile_theta;
+  K.tk = tile_z(&l);
+  K.shaped = true;
 }
 }  // namespace
 
 lbm_status lbm_set_launch(lbm_ctx* c, int32_t q, const lbm_launch* l) {
   if (!c || q < 0 || q >= (int)c->cls.size()) return LBM_E_INVAL;
-  if (!valid_launch(l)) return fail(c, LBM_E_INVAL, "block 128/256/512, 1-2 cells per lane, wall tile 8/16/32");
+  if (!valid_launch(l)) return fail(c, LBM_E_INVAL,
+                "block 128/256/512, 1-2 cells per lane, wall tile 8x32, 16x16, 32x8, 8x16, 16x8 or 8x8");
   HIPCHK(c, hipStreamSynchronize(c->stream));
   drop_graph(c);
   apply_launch(c, q, *l);
@@ -1193,7 +1210,10 @@ lbm_status lbm_autotune(lbm_ctx* c, int32_t trial_steps, int64_t* advanced) {
     for (int q = 0; q < nc; ++q) {
       lbm_launch l = best[q];
       if (cand && kind == 0) { l.block = cand->block; l.cells_per_lane = cand->cells_per_lane; }
-      if (cand && kind == 1) l.wall_tile_theta = cand->wall_tile_theta;
+      if (cand && kind == 1) {
+        l.wall_tile_theta = cand->wall_tile_theta;
+        l.wall_tile_z = cand->wall_tile_z;
+      }
       apply_launch(c, q, l);
     }
     lbm_status s = build_groups(c, true);   // one launch per class, timed apart
@@ -1247,15 +1267,23 @@ lbm_status lbm_autotune(lbm_ctx* c, int32_t trial_steps, int64_t* advanced) {
       for (int32_t i : c->cls[q].inst) has_wall[q] = has_wall[q] || c->wall[i].on;
     st = trial(nullptr, 1, bms);
     if (st != LBM_OK) return st;
-    for (int tj : {8, 16, 32}) {
+    for (const auto& t : WALL_TILES) {
       lbm_launch cand = best[0];
-      cand.wall_tile_theta = tj;
+      cand.wall_tile_theta = t[0];
+      cand.wall_tile_z = t[1];
       st = trial(&cand, 1, ms);
       if (st != LBM_OK) return st;
       for (int q = 0; q < nc; ++q)
-        if (has_wall[q] && ms[q] < bms[q] * gain) { bms[q] = ms[q]; pick[q].wall_tile_theta = tj; }
+        if (has_wall[q] && ms[q] < bms[q] * gain) {
+          bms[q] = ms[q];
+          pick[q].wall_tile_theta = t[0];
+          pick[q].wall_tile_z = t[1];
+        }
     }
-    for (int q = 0; q < nc; ++q) best[q].wall_tile_theta = pick[q].wall_tile_theta;
+    for (int q = 0; q < nc; ++q) {
+      best[q].wall_tile_theta = pick[q].wall_tile_theta;
+      best[q].wall_tile_z = pick[q].wall_tile_z;
+    }
   }
   for (int q = 0; q < nc; ++q) apply_launch(c, q, best[q]);
   lbm_status s = build_groups(c, false);
@@ -1395,6 +1423,26 @@ lbm_status lbm_fsi_exchange(lbm_ctx* c, int32_t k, const lbm_wall_desc* w, void*
   c->dev.max_np = (int32_t)maxp;
   c->dev.max_mtile = maxmt;
   c->dev.any_shell = shell;
+  // default wall tile of the instance's size class (unless its shapes were
+  // set): the square 256-point tile, or, on meshes too coarse for it, the
+  // first smaller tile whose stencil boxes all fill at most 60 % of the
+  // standard staging, so that they stay there while the wall deforms (band
+  // rebuilds on the device keep the launch as it was built)
+  for (SizeClass& K : c->cls) {
+    if (K.shaped || std::find(K.inst.begin(), K.inst.end(), k) == K.inst.end()) continue;
+    static const int pref[4][2] = {{16, 16}, {16, 8}, {8, 16}, {8, 8}};
+    for (const auto& t : pref) {
+      bool fits = true;
+      for (int32_t i : K.inst)
+        fits = fits && !(c->wall[i].on &&
+                         wall_max_box(c, i, t[0], t[1]) > wall_boxcap(c->prec == 0 ? 8 : 4, t[0]) * 6 / 10);
+      if (fits) {
+        K.tj = t[0];
+        K.tk = t[1];
+        break;
+      }
+    }
+  }
   return build_groups(c, false);
 }
 

@@ -170,13 +170,14 @@ hipError_t launch_collide(const Dev& d, int prec, int parity, int bs, int cpt, b
 hipError_t launch_band(const Dev& d, int prec, int parity, hipStream_t s);
 // the boundary reductions and the band moments in one launch
 hipError_t launch_reduce_band(const Dev& d, int prec, int parity, int nred, hipStream_t s);
-// wall exchange over the walls of a size class, tiles of tj x (256 / tj)
-// points (tj = 8, 16, 32); tiles = tile count of the class's largest wall
 // LDS staging capacity of a wall tile's stencil box (cells), standard and
 // large-box kernels; element size 8 (FP64) or 4 (FP32 velocities)
 constexpr int wall_boxcap(int elem, int tj) { return elem == 8 ? 1024 : (tj == 32 ? 2048 : 1792); }
 constexpr int wall_boxcap_big(int elem) { return elem == 8 ? 2560 : 4096; }
-hipError_t launch_wall(const Dev& d, int prec, int parity, int tj, bool big, const int32_t* walls, int nwall,
+// wall exchange over the walls of a size class, tiles of tj x tk points
+// (8 x 32, 16 x 16, 32 x 8, 8 x 16, 16 x 8, 8 x 8); tiles = tile count of the
+// class's largest wall
+hipError_t launch_wall(const Dev& d, int prec, int parity, int tj, int tk, bool big, const int32_t* walls, int nwall,
                        int tiles, hipStream_t s);
 // Band rebuild on the device: the gate opens once the motion word reaches
 // thresh; then every wall's band is rebuilt around the current positions

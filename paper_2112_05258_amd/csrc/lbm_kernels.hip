@@ -655,22 +655,26 @@ template <> struct FixOf<double> {
 // there for the interpolation, and the same LDS then accumulates the spread
 // force with LDS atomics before one flush of the box's non-zero cells with
 // global atomics (instead of 64 x 3 global atomics per point).
-// The tile shape TJ x TK (TJ * TK = 256) is chosen per size class by the
-// autotuner: wide in theta (32 x 8), square (16 x 16) or long in z (8 x 32).
+// The tile shape TJ x TK is chosen per size class by the autotuner: 256
+// points wide in theta (32 x 8), square (16 x 16) or long in z (8 x 32), or
+// the smaller 8 x 16, 16 x 8 and 8 x 8 tiles, whose stencil boxes still fit
+// the staging memory on coarse meshes (there the 256 lanes stage and flush
+// the box, and a lane per point takes the stencils while the others idle).
 // In the staged path the 4 x 4 x 4 stencil loops are unrolled and free of
 // branches: each staged cell holds (u, m) with u = 0 outside the band and
 // m = 1 at a fluid cell outside the band, so one 16-byte LDS read per
 // stencil cell serves both the interpolation and the band check; tile-wide
 // extents and maxima are reduced within each wave first, so only one lane
 // per wave touches the shared LDS word.
-template <class R, int TJ, bool BIG>
+template <class R, int TJ, int TK, bool BIG>
 __global__ __launch_bounds__(WBLOCK) void k_wall(Dev d, const int32_t* __restrict__ walls, int parity) {
-  constexpr int TK = (WBLOCK / 64) * 64 / TJ;
+  static_assert(TJ * TK <= WBLOCK && TJ % 2 == 0 && TK % 2 == 0, "one lane per point of the tile");
   using R4 = typename V4<R>::T;
   using Fix = typename FixOf<R>::T;
-  // box cells: at 0.5 lu spacing a 16 x 16 or 8 x 32 tile spans <= ~1000,
-  // a 32 x 8 tile <= ~1600; BIG (coarser meshes, ~0.9 lu: up to ~3300 for
-  // 16 x 16) trades occupancy for staging; a larger box takes the unstaged path
+  // box cells: at 0.5 lu spacing a 16 x 16 or 8 x 32 tile spans <= ~1100,
+  // a 32 x 8 tile <= ~1700; at ~0.9 lu a 16 x 16 tile up to ~3500 (BIG,
+  // which trades occupancy for staging), an 8 x 16 tile ~1500 and an 8 x 8
+  // tile ~900; a larger box takes the unstaged path
   constexpr int BOXCAP = BIG ? wall_boxcap_big(sizeof(R)) : wall_boxcap(sizeof(R), TJ);
   static_assert(3 * sizeof(Fix) <= sizeof(R4), "the spread accumulators reuse the staging box");
   __shared__ R4 sbox[BOXCAP];
@@ -691,7 +695,7 @@ __global__ __launch_bounds__(WBLOCK) void k_wall(Dev d, const int32_t* __restric
   const int wv = (int)threadIdx.x >> 6, ln = (int)threadIdx.x & 63;
   const int j = (bx % ntj) * TJ + 2 * (ln % (TJ / 2)) + (wv & 1);
   const int k = (bx / ntj) * TK + 2 * (ln / (TJ / 2)) + (wv >> 1);
-  const bool point = j < nth && k < nzl;
+  const bool point = ln < (TJ / 2) * (TK / 2) && j < nth && k < nzl;
   const int64_t p = point ? j + (int64_t)nth * k : 0;
   // the wall is carried as displacement D = X - X0 (ping-pong D^n / D^{n-1})
   const double* Dc = I.Xab[parity];
@@ -1437,26 +1441,24 @@ hipError_t launch_band(const Dev& d, int prec, int parity, hipStream_t s) {
 
 namespace {
 template <class R>
-hipError_t wall_t(const Dev& d, int parity, int tj, bool big, const int32_t* walls, dim3 grid, hipStream_t s) {
+hipError_t wall_t(const Dev& d, int parity, int tj, int tk, bool big, const int32_t* walls, dim3 grid, hipStream_t s) {
   const dim3 b(WBLOCK);
-  switch (tj * 2 + (big ? 1 : 0)) {
-    case 16: return launch(k_wall<R, 8, false>, grid, b, s, Dev(d), walls, int(parity));
-    case 17: return launch(k_wall<R, 8, true>, grid, b, s, Dev(d), walls, int(parity));
-    case 32: return launch(k_wall<R, 16, false>, grid, b, s, Dev(d), walls, int(parity));
-    case 33: return launch(k_wall<R, 16, true>, grid, b, s, Dev(d), walls, int(parity));
-    case 64: return launch(k_wall<R, 32, false>, grid, b, s, Dev(d), walls, int(parity));
-    case 65: return launch(k_wall<R, 32, true>, grid, b, s, Dev(d), walls, int(parity));
-    default: return hipErrorInvalidValue;
-  }
+#define W(J, K)                                                                                      \
+  if (tj == J && tk == K)                                                                           \
+    return big ? launch(k_wall<R, J, K, true>, grid, b, s, Dev(d), walls, int(parity))             \
+               : launch(k_wall<R, J, K, false>, grid, b, s, Dev(d), walls, int(parity));
+  W(8, 32) W(16, 16) W(32, 8) W(8, 16) W(16, 8) W(8, 8)
+#undef W
+  return hipErrorInvalidValue;
 }
 }  // namespace
 
-hipError_t launch_wall(const Dev& d, int prec, int parity, int tj, bool big, const int32_t* walls, int nwall,
+hipError_t launch_wall(const Dev& d, int prec, int parity, int tj, int tk, bool big, const int32_t* walls, int nwall,
                        int tiles, hipStream_t s) {
   if (nwall <= 0 || tiles <= 0) return hipSuccess;
   const dim3 grid((unsigned)tiles, (unsigned)nwall);
-  return prec == 0 ? wall_t<double>(d, parity, tj, big, walls, grid, s)
-                   : wall_t<float>(d, parity, tj, big, walls, grid, s);
+  return prec == 0 ? wall_t<double>(d, parity, tj, tk, big, walls, grid, s)
+                   : wall_t<float>(d, parity, tj, tk, big, walls, grid, s);
 }
 
 hipError_t launch_motion(const Dev& d, int parity, hipStream_t s) {

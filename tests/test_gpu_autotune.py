@@ -1,8 +1,8 @@
 """Launch shapes per size class and the autotuner.
 
 The collide-stream result is independent of the workgroup size and cells
-per lane (bitwise); the wall tile changes only the rounding order of the
-spread force's float additions.  The autotuner's trial steps are ordinary
+per lane (bitwise); the wall tile (any of the six shapes) changes only the
+rounding order of the spread force's float additions.  The autotuner's trial steps are ordinary
 steps of the method, and its choices round-trip through the JSON cache.
 """
 import json
@@ -20,6 +20,10 @@ def amd():
     import paper_2112_05258_amd as amd
     amd.lib()
     return amd
+
+
+# the wall tile shapes (theta x z mesh points)
+TILES = [(8, 32), (16, 16), (32, 8), (8, 16), (16, 8), (8, 8)]
 
 
 def _rigid(n, seed):
@@ -60,10 +64,10 @@ def test_wall_tiles_agree_to_rounding(amd):
         p["L"] = min(p["L"], 40)
     cfgs = [L.ensemble_config(p) for p in ps]
     out = []
-    for tj in (8, 16, 32):
+    for tj, tk in TILES:
         s = amd.solver_from_configs(cfgs, precision=amd.FP64)
         for q in range(len(s.classes())):
-            s.set_launch(q, 256, 1, tj)
+            s.set_launch(q, 256, 1, tj, tk)
         s.step(31)
         s.sync()
         out.append([s.read_wall(k)["X"] - c["mesh"]["X0"] for k, c in enumerate(cfgs)])
@@ -101,10 +105,10 @@ def test_autotune_with_walls_and_bad_shapes(amd):
         p["L"] = min(p["L"], 40)
     s = amd.solver_from_configs([L.ensemble_config(p) for p in ps], precision=amd.FP32)
     adv = s.autotune(trial_steps=2)
-    assert adv == (7 + 4) * (2 + 2)           # current + 6 shapes, current + 3 tiles
+    assert adv == (7 + 7) * (2 + 2)           # current + 6 shapes, current + 6 tiles
     for c in s.classes():
         assert c["block"] in (128, 256, 512) and c["cells_per_lane"] in (1, 2)
-        assert c["wall_tile_theta"] in (8, 16, 32)
+        assert (c["wall_tile_theta"], c["wall_tile_z"]) in TILES
     s.step(10)
     s.sync()
     with pytest.raises(amd.LbmError):
@@ -113,3 +117,7 @@ def test_autotune_with_walls_and_bad_shapes(amd):
         s.set_launch(0, 256, 3, 16)
     with pytest.raises(amd.LbmError):
         s.set_launch(0, 256, 1, 12)
+    with pytest.raises(amd.LbmError):
+        s.set_launch(0, 256, 1, 32, 16)      # 512 points: more than a workgroup's lanes
+    with pytest.raises(amd.LbmError):
+        s.set_launch(0, 256, 1, 8, 4)

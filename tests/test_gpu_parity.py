@@ -208,19 +208,24 @@ def test_external_solid_prescribed_motion(oracle_mod, amd, precision, tol):
             t.close()
 
 
-@pytest.mark.parametrize("h,tj", [(0.7, 16), (0.7, 32), (1.4, 16)])
-def test_wall_staging_paths(oracle_mod, amd, h, tj):
+@pytest.mark.parametrize("h,tj,tk", [(0.7, 16, 0), (0.7, 32, 0), (1.4, 16, 0), (0.7, 8, 8), (0.7, 16, 8),
+                                     (1.4, 8, 16), (1.4, 8, 8)])
+def test_wall_staging_paths(oracle_mod, amd, h, tj, tk):
     """The wall exchange's three ways of handling a tile's stencil box, each
     against the oracle (the library picks the kernel from the rest shape; the
     box sizes below follow from the mesh).  h = 0.7, 16 x 16 tiles: boxes of
     600-1694 cells, the large-box kernel stages them all; h = 0.7, 32 x 8:
     1188-1782 cells, the standard kernel stages them all; h = 1.4, 16 x 16:
     3060-4950 cells, the large-box kernel stages those up to 4096 and the
-    rest take the unstaged path (stencils read and spread in global memory)."""
+    rest take the unstaged path (stencils read and spread in global memory).
+    The smaller tiles: h = 0.7, 8 x 8: 252-486 cells and 16 x 8: 600-1089,
+    the standard kernel (lanes without a point idle); h = 1.4, 8 x 16:
+    1700-2750 and 8 x 8: 600-1540, the large-box kernel."""
     c = L.small_fsi(h=h)
     o = oracle_mod.from_config(c, extended=True)
     s = amd.solver_from_config(c, precision=amd.FP64)
-    s.set_launch(0, 256, 1, tj)
+    s.set_launch(0, 256, 1, tj, tk)
+    assert s.classes()[0]["wall_tile_z"] == (tk or 256 // tj)
     o.step(60)
     s.step(60)
     s.sync()
