@@ -397,13 +397,29 @@ hipError_t enqueue_step(lbm_ctx* c, int parity, bool timed) {
     if (e != hipSuccess) return e;
     post(1);
   }
+  if (c->dev.nwall > 0 && !fused) {
+    pre(2);
+    e = launch_band(c->dev, c->prec, parity, c->stream);
+    if (e != hipSuccess) return e;
+    post(2);
+  }
+  // Untimed, untuned steps with a side stream fork after the wall exchange:
+  // the wall's time step (k_membrane: reads the wall state and the force just
+  // spread, writes the next displacements, which no collide reads) and the few
+  // tiles next to a 0D ghost (the normal-neighbour build; in the AA pattern
+  // every cell reads and writes only its own slots) run there beside the bulk
+  // collide, which would otherwise wait for their latency.  The main stream
+  // joins them before the step ends.  Timed and tuning steps keep everything
+  // in sequence.
+  const bool fork = !timed && !c->tuning && c->side != nullptr;
+  bool forked = false;
+  auto fork_side = [&]() -> hipError_t {
+    if (forked) return hipSuccess;
+    forked = true;
+    hipError_t r = hipEventRecord(c->ev_fork, c->stream);
+    return r != hipSuccess ? r : hipStreamWaitEvent(c->side, c->ev_fork, 0);
+  };
   if (c->dev.nwall > 0) {
-    if (!fused) {
-      pre(2);
-      e = launch_band(c->dev, c->prec, parity, c->stream);
-      if (e != hipSuccess) return e;
-      post(2);
-    }
     pre(3);
     for (const LaunchGroup& G : c->wgroups) {
       EventPair p;
@@ -412,26 +428,20 @@ hipError_t enqueue_step(lbm_ctx* c, int parity, bool timed) {
       if (e != hipSuccess) return e;
       tpost(p, G.cls, 1);
     }
-    e = launch_membrane(c->dev, parity, c->stream);
+    if (fork) {
+      if ((e = fork_side()) != hipSuccess) return e;
+      e = launch_membrane(c->dev, parity, c->side);
+    } else {
+      e = launch_membrane(c->dev, parity, c->stream);
+    }
     if (e != hipSuccess) return e;
     post(3);
   }
   pre(0);
-  // The few tiles next to a 0D ghost (the normal-neighbour build) run on the
-  // side stream beside the bulk launch: in the AA pattern every cell reads
-  // and writes only its own slots, so the two launches are independent, and
-  // the small one would otherwise add its own latency to the step.  Timed
-  // and tuning steps keep them in sequence.
-  const bool fork = !timed && !c->tuning && c->side != nullptr;
-  bool forked = false;
   if (fork)
     for (const LaunchGroup& G : c->cgroups) {
       if (!G.nee) continue;
-      if (!forked) {
-        if ((e = hipEventRecord(c->ev_fork, c->stream)) != hipSuccess) return e;
-        if ((e = hipStreamWaitEvent(c->side, c->ev_fork, 0)) != hipSuccess) return e;
-        forked = true;
-      }
+      if ((e = fork_side()) != hipSuccess) return e;
       e = launch_collide(c->dev, c->prec, parity, G.bs, G.cpt, true, tab + G.off, G.count, COLLIDE_ALL, c->side);
       if (e != hipSuccess) return e;
     }
