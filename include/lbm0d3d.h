@@ -348,6 +348,21 @@ lbm_status lbm_set_graph(lbm_ctx* ctx, int32_t on);
  * Synchronises and drops the captured step graph. */
 lbm_status lbm_set_overlap(lbm_ctx* ctx, int32_t on);
 
+/* Deterministic spreading (Eq. EulForce): the wall tiles are launched in
+ * six colour classes one after another -- (theta tile index parity) +
+ * 2 (z tile index parity), and two more for the last theta column of a ring
+ * with an odd tile count -- so that tiles whose stencil boxes meet are never
+ * in the same launch.  Each tile's sums are exact (fixed point in LDS), and a
+ * cell then receives them in colour order: two runs from the same state give
+ * bitwise equal results, where the default single launch sums the tiles in
+ * the order the hardware runs them (equal to rounding).  Holds while every
+ * tile's box is staged in LDS (the unstaged path for oversized boxes spreads
+ * point by point with float atomics) and tiles two apart along theta or z do
+ * not reach the same cell (tiles spanning more than the 4-cell stencil, as
+ * the defaults do).  Costs the wall exchange its single launch's occupancy.
+ * Default off.  Synchronises and drops the captured step graph. */
+lbm_status lbm_set_deterministic(lbm_ctx* ctx, int32_t on);
+
 /* Launch shapes per size class.  The instances of a context are grouped by
  * cell count into size classes (quartiles from 8 instances on, else one
  * class); each class has its own collide-stream launch (workgroup size and

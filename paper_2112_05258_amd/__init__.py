@@ -82,6 +82,7 @@ SYMBOLS = {
     "lbm_kernel_time": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
     "lbm_set_graph": (C.c_int, [C.c_void_p, C.c_int32]),
     "lbm_set_overlap": (C.c_int, [C.c_void_p, C.c_int32]),
+    "lbm_set_deterministic": (C.c_int, [C.c_void_p, C.c_int32]),
     "lbm_set_band_check": (C.c_int, [C.c_void_p, C.c_int32]),
     "lbm_num_classes": (C.c_int32, [C.c_void_p]),
     "lbm_class_info": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int64),
@@ -366,6 +367,10 @@ class Solver:
 
     def set_overlap(self, on):
         self._check(lib().lbm_set_overlap(self.h, 1 if on else 0))
+
+    def set_deterministic(self, on):
+        """Wall tiles launched colour by colour (lbm_set_deterministic)."""
+        self._check(lib().lbm_set_deterministic(self.h, 1 if on else 0))
 
     def set_band_check(self, every):
         self._check(lib().lbm_set_band_check(self.h, int(every)))

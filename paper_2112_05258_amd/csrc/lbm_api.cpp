@@ -289,6 +289,7 @@ struct lbm_ctx {
   // overlap of the wall exchange with the bulk collide: a side stream, the
   // band-cell tile table (256-cell tiles holding a band cell) and events
   bool overlap = false;
+  bool deterministic = false;   // wall tiles launched colour by colour
   int64_t band_check = 32;     // steps between wall-motion tests (0: never)
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_wall = nullptr, ev_join = nullptr;
@@ -342,6 +343,19 @@ EventPair get_pair(lbm_ctx* c) {
   return p;
 }
 
+// the wall exchange of every launch group on stream s: one launch per group,
+// or in the deterministic mode one per tile colour, in colour order
+hipError_t enqueue_wall(lbm_ctx* c, int parity, hipStream_t s) {
+  const int32_t* cw = (const int32_t*)(c->work + c->L.cwalls);
+  for (const LaunchGroup& G : c->wgroups)
+    for (int col = c->deterministic ? 0 : -1; col < (c->deterministic ? WALL_COLOURS : 0); ++col) {
+      hipError_t e = launch_wall(c->dev, c->prec, parity, G.tj, G.tk, G.bigbox, cw + G.off, G.count, G.wall_tiles,
+                                 col, s);
+      if (e != hipSuccess) return e;
+    }
+  return hipSuccess;
+}
+
 hipError_t enqueue_step(lbm_ctx* c, int parity, bool timed) {
   hipError_t e;
   EventPair ev[NTIMED];
@@ -367,9 +381,7 @@ hipError_t enqueue_step(lbm_ctx* c, int parity, bool timed) {
     if ((e = hipEventRecord(c->ev_fork, c->stream)) != hipSuccess) return e;
     if ((e = hipStreamWaitEvent(s2, c->ev_fork, 0)) != hipSuccess) return e;
     if ((e = launch_band(c->dev, c->prec, parity, s2)) != hipSuccess) return e;
-    for (const LaunchGroup& G : c->wgroups)
-      if ((e = launch_wall(c->dev, c->prec, parity, G.tj, G.tk, G.bigbox, cw + G.off, G.count, G.wall_tiles, s2)) != hipSuccess)
-        return e;
+    if ((e = enqueue_wall(c, parity, s2)) != hipSuccess) return e;
     if ((e = hipEventRecord(c->ev_wall, s2)) != hipSuccess) return e;
     if ((e = launch_membrane(c->dev, parity, s2)) != hipSuccess) return e;
     if ((e = hipEventRecord(c->ev_join, s2)) != hipSuccess) return e;
@@ -424,8 +436,11 @@ hipError_t enqueue_step(lbm_ctx* c, int parity, bool timed) {
     for (const LaunchGroup& G : c->wgroups) {
       EventPair p;
       tpre(p);
-      e = launch_wall(c->dev, c->prec, parity, G.tj, G.tk, G.bigbox, cw + G.off, G.count, G.wall_tiles, c->stream);
-      if (e != hipSuccess) return e;
+      for (int col = c->deterministic ? 0 : -1; col < (c->deterministic ? WALL_COLOURS : 0); ++col) {
+        e = launch_wall(c->dev, c->prec, parity, G.tj, G.tk, G.bigbox, cw + G.off, G.count, G.wall_tiles, col,
+                        c->stream);
+        if (e != hipSuccess) return e;
+      }
       tpost(p, G.cls, 1);
     }
     if (fork) {
@@ -1697,6 +1712,14 @@ lbm_status lbm_set_graph(lbm_ctx* c, int32_t on) {
 lbm_status lbm_set_band_check(lbm_ctx* c, int32_t every) {
   if (!c || every < 0) return LBM_E_INVAL;
   c->band_check = every;
+  return LBM_OK;
+}
+
+lbm_status lbm_set_deterministic(lbm_ctx* c, int32_t on) {
+  if (!c) return LBM_E_INVAL;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  drop_graph(c);
+  c->deterministic = on != 0;
   return LBM_OK;
 }
 

@@ -176,9 +176,11 @@ constexpr int wall_boxcap(int elem, int tj) { return elem == 8 ? 1024 : (tj == 3
 constexpr int wall_boxcap_big(int elem) { return elem == 8 ? 2560 : 4096; }
 // wall exchange over the walls of a size class, tiles of tj x tk points
 // (8 x 32, 16 x 16, 32 x 8, 8 x 16, 16 x 8, 8 x 8); tiles = tile count of the
-// class's largest wall
+// class's largest wall; colour >= 0 takes only the tiles of that colour
+// (WALL_COLOURS classes, tiles of one colour two tiles apart in theta and in z)
+constexpr int WALL_COLOURS = 6;
 hipError_t launch_wall(const Dev& d, int prec, int parity, int tj, int tk, bool big, const int32_t* walls, int nwall,
-                       int tiles, hipStream_t s);
+                       int tiles, int colour, hipStream_t s);
 // Band rebuild on the device: the gate opens once the motion word reaches
 // thresh; then every wall's band is rebuilt around the current positions
 // (parity) by marking the stencil bases, dilating the marks along x, y and

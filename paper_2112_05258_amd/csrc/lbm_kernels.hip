@@ -666,8 +666,13 @@ template <> struct FixOf<double> {
 // stencil cell serves both the interpolation and the band check; tile-wide
 // extents and maxima are reduced within each wave first, so only one lane
 // per wave touches the shared LDS word.
+// colour >= 0 (the deterministic spreading mode): only the tiles of that
+// colour, (theta tile parity) + 2 (z tile parity), or 4 + (z tile parity) for
+// the last theta column of an odd ring (theta is periodic); the host launches
+// the colours one after another, so a cell receives the tiles' sums in colour
+// order wherever tiles of one colour do not share a cell.
 template <class R, int TJ, int TK, bool BIG>
-__global__ __launch_bounds__(WBLOCK) void k_wall(Dev d, const int32_t* __restrict__ walls, int parity) {
+__global__ __launch_bounds__(WBLOCK) void k_wall(Dev d, const int32_t* __restrict__ walls, int parity, int colour) {
   static_assert(TJ * TK <= WBLOCK && TJ % 2 == 0 && TK % 2 == 0, "one lane per point of the tile");
   using R4 = typename V4<R>::T;
   using Fix = typename FixOf<R>::T;
@@ -688,6 +693,11 @@ __global__ __launch_bounds__(WBLOCK) void k_wall(Dev d, const int32_t* __restric
   const int ntj = (nth + TJ - 1) / TJ;
   const int bx = (int)blockIdx.x;
   if (bx >= ntj * ((nzl + TK - 1) / TK)) return;  // whole block leaves
+  if (colour >= 0) {
+    const int jt = bx % ntj, kt = bx / ntj;
+    const int col = ((ntj & 1) && jt == ntj - 1) ? 4 + (kt & 1) : (jt & 1) + 2 * (kt & 1);
+    if (col != colour) return;   // whole block leaves
+  }
   // wave w takes the parity sub-lattice (w & 1, w >> 1) of the TJ x TK patch:
   // its (TJ/2) x (TK/2) points are >= 1 lu apart, so for a given stencil
   // offset the 64 lanes mostly hit distinct cells and the LDS atomics do not
@@ -1445,12 +1455,13 @@ hipError_t launch_band(const Dev& d, int prec, int parity, hipStream_t s) {
 
 namespace {
 template <class R>
-hipError_t wall_t(const Dev& d, int parity, int tj, int tk, bool big, const int32_t* walls, dim3 grid, hipStream_t s) {
+hipError_t wall_t(const Dev& d, int parity, int tj, int tk, bool big, const int32_t* walls, dim3 grid, int colour,
+                  hipStream_t s) {
   const dim3 b(WBLOCK);
 #define W(J, K)                                                                                      \
   if (tj == J && tk == K)                                                                           \
-    return big ? launch(k_wall<R, J, K, true>, grid, b, s, Dev(d), walls, int(parity))             \
-               : launch(k_wall<R, J, K, false>, grid, b, s, Dev(d), walls, int(parity));
+    return big ? launch(k_wall<R, J, K, true>, grid, b, s, Dev(d), walls, int(parity), int(colour)) \
+               : launch(k_wall<R, J, K, false>, grid, b, s, Dev(d), walls, int(parity), int(colour));
   W(8, 32) W(16, 16) W(32, 8) W(8, 16) W(16, 8) W(8, 8)
 #undef W
   return hipErrorInvalidValue;
@@ -1458,11 +1469,11 @@ hipError_t wall_t(const Dev& d, int parity, int tj, int tk, bool big, const int3
 }  // namespace
 
 hipError_t launch_wall(const Dev& d, int prec, int parity, int tj, int tk, bool big, const int32_t* walls, int nwall,
-                       int tiles, hipStream_t s) {
+                       int tiles, int colour, hipStream_t s) {
   if (nwall <= 0 || tiles <= 0) return hipSuccess;
   const dim3 grid((unsigned)tiles, (unsigned)nwall);
-  return prec == 0 ? wall_t<double>(d, parity, tj, tk, big, walls, grid, s)
-                   : wall_t<float>(d, parity, tj, tk, big, walls, grid, s);
+  return prec == 0 ? wall_t<double>(d, parity, tj, tk, big, walls, grid, colour, s)
+                   : wall_t<float>(d, parity, tj, tk, big, walls, grid, colour, s);
 }
 
 hipError_t launch_motion(const Dev& d, int parity, hipStream_t s) {

@@ -21,7 +21,7 @@ hipError_t launch_collide(const Dev&, int, int, int, int, bool, const CTile*, in
 }
 hipError_t launch_band(const Dev&, int, int, hipStream_t) { return hipErrorNotSupported; }
 hipError_t launch_reduce_band(const Dev&, int, int, int, hipStream_t) { return hipErrorNotSupported; }
-hipError_t launch_wall(const Dev&, int, int, int, int, bool, const int32_t*, int, int, hipStream_t) {
+hipError_t launch_wall(const Dev&, int, int, int, int, bool, const int32_t*, int, int, int, hipStream_t) {
   return hipErrorNotSupported;
 }
 hipError_t launch_band_rebuild(const Dev&, int, float, const int[3], int, hipStream_t) { return hipErrorNotSupported; }
