@@ -121,3 +121,27 @@ def test_autotune_with_walls_and_bad_shapes(amd):
         s.set_launch(0, 256, 1, 32, 16)      # 512 points: more than a workgroup's lanes
     with pytest.raises(amd.LbmError):
         s.set_launch(0, 256, 1, 8, 4)
+
+
+def test_default_wall_tile_follows_the_mesh(amd):
+    """Without shapes set, attaching a wall picks the square 256-point tile
+    unless its stencil boxes would fill more than 60 % of the standard
+    staging; then the first of 16 x 8, 8 x 16, 8 x 8 whose boxes do not.
+    Largest boxes at rest (cells; standard staging 1 792): cfg1 at 0.5 lu,
+    16 x 16: 990, kept; at 0.9 lu: 16 x 16 3 276, 16 x 8 2 002, 8 x 16
+    1 296, 8 x 8 792 -> 8 x 8; the small tube at 0.7 lu: 16 x 16 1 694,
+    16 x 8 1 089, 8 x 16 756 -> 8 x 16.  Shapes set by the caller stay."""
+    cases = [(L.cfg1(h=0.5), (16, 16)), (L.cfg1(h=0.9), (8, 8)), (L.small_fsi(h=0.7), (8, 16))]
+    for c, want in cases:
+        s = amd.solver_from_config(c, precision=amd.FP32)
+        k = s.classes()[0]
+        assert (k["wall_tile_theta"], k["wall_tile_z"]) == want, (c["name"], k)
+        s.close()
+    c = L.small_fsi(h=0.7)
+    s = amd.solver_from_config(c, precision=amd.FP32)
+    s.set_launch(0, 256, 1, 32)
+    s.step(2)
+    s.sync()
+    k = s.classes()[0]
+    assert (k["wall_tile_theta"], k["wall_tile_z"]) == (32, 8)
+    s.close()
