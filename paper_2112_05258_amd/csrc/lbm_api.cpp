@@ -292,7 +292,7 @@ struct lbm_ctx {
   bool deterministic = false;   // wall tiles launched colour by colour
   int64_t band_check = 32;     // steps between wall-motion tests (0: never)
   hipStream_t side = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_wall = nullptr, ev_join = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_wall = nullptr, ev_join = nullptr, ev_red = nullptr;
   int nbtile = 0;
   // per-class kernel events while tuning: (class, kind 0 collide / 1 wall)
   bool tuning = false;
@@ -396,11 +396,35 @@ hipError_t enqueue_step(lbm_ctx* c, int parity, bool timed) {
       return e;
     return hipStreamWaitEvent(c->stream, c->ev_join, 0);
   }
-  // With a wall, untimed steps run the 0D reductions and the band moments as
-  // one launch (the reductions hide behind the band's memory traffic);
-  // timed and tuning steps keep them apart, so that each has its own time.
-  const bool fused = c->dev.nwall > 0 && !timed && !c->tuning;
-  if (fused) {
+  // Untimed, untuned steps with a side stream and a wall run there, from the
+  // step's start, the 0D reductions (beside the band moments and the wall
+  // exchange: their chain of dependent memory operations stretches under the
+  // band's traffic and would otherwise set the length of a shared launch),
+  // then, once the force is spread, the wall's time step (k_membrane: reads
+  // the wall state and the force, writes the next displacements, which no
+  // collide reads) and the few tiles next to a 0D ghost (the normal-neighbour
+  // build; in the AA pattern every cell reads and writes only its own slots)
+  // beside the bulk collide.  The bulk collide, which overwrites the
+  // mid-length layer the reductions read and, without the normal-neighbour
+  // build, reads the 0D state they update, waits for the reductions; the main
+  // stream joins the side stream before the step ends.  Without a side
+  // stream, untimed steps with a wall run the reductions and the band moments
+  // as one launch; timed and tuning steps keep everything in sequence.
+  const bool fork = !timed && !c->tuning && c->side != nullptr;
+  const bool red_side = fork && c->dev.nwall > 0;
+  const bool fused = c->dev.nwall > 0 && !timed && !c->tuning && !red_side;
+  bool forked = false;
+  auto fork_side = [&]() -> hipError_t {
+    if (forked) return hipSuccess;
+    forked = true;
+    hipError_t r = hipEventRecord(c->ev_fork, c->stream);
+    return r != hipSuccess ? r : hipStreamWaitEvent(c->side, c->ev_fork, 0);
+  };
+  if (red_side) {
+    if ((e = fork_side()) != hipSuccess) return e;
+    if ((e = launch_reduce(c->dev, c->prec, parity, c->L.nred, c->side)) != hipSuccess) return e;
+    if ((e = hipEventRecord(c->ev_red, c->side)) != hipSuccess) return e;
+  } else if (fused) {
     e = launch_reduce_band(c->dev, c->prec, parity, c->L.nred, c->stream);
     if (e != hipSuccess) return e;
   } else {
@@ -415,22 +439,6 @@ hipError_t enqueue_step(lbm_ctx* c, int parity, bool timed) {
     if (e != hipSuccess) return e;
     post(2);
   }
-  // Untimed, untuned steps with a side stream fork after the wall exchange:
-  // the wall's time step (k_membrane: reads the wall state and the force just
-  // spread, writes the next displacements, which no collide reads) and the few
-  // tiles next to a 0D ghost (the normal-neighbour build; in the AA pattern
-  // every cell reads and writes only its own slots) run there beside the bulk
-  // collide, which would otherwise wait for their latency.  The main stream
-  // joins them before the step ends.  Timed and tuning steps keep everything
-  // in sequence.
-  const bool fork = !timed && !c->tuning && c->side != nullptr;
-  bool forked = false;
-  auto fork_side = [&]() -> hipError_t {
-    if (forked) return hipSuccess;
-    forked = true;
-    hipError_t r = hipEventRecord(c->ev_fork, c->stream);
-    return r != hipSuccess ? r : hipStreamWaitEvent(c->side, c->ev_fork, 0);
-  };
   if (c->dev.nwall > 0) {
     pre(3);
     for (const LaunchGroup& G : c->wgroups) {
@@ -444,7 +452,8 @@ hipError_t enqueue_step(lbm_ctx* c, int parity, bool timed) {
       tpost(p, G.cls, 1);
     }
     if (fork) {
-      if ((e = fork_side()) != hipSuccess) return e;
+      if ((e = hipEventRecord(c->ev_wall, c->stream)) != hipSuccess) return e;
+      if ((e = hipStreamWaitEvent(c->side, c->ev_wall, 0)) != hipSuccess) return e;
       e = launch_membrane(c->dev, parity, c->side);
     } else {
       e = launch_membrane(c->dev, parity, c->stream);
@@ -461,6 +470,7 @@ hipError_t enqueue_step(lbm_ctx* c, int parity, bool timed) {
       if (e != hipSuccess) return e;
     }
   if (forked && (e = hipEventRecord(c->ev_join, c->side)) != hipSuccess) return e;
+  if (red_side && (e = hipStreamWaitEvent(c->stream, c->ev_red, 0)) != hipSuccess) return e;
   // timed steps: the tiles without extrapolation first (id 0), then the
   // others (id 4)
   for (int v = 0; v < 2; ++v) {
@@ -1085,7 +1095,8 @@ lbm_status lbm_init(const lbm_config* cfgs, int32_t n, const lbm_buffers* buf, v
   if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev_wall, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_red, hipEventDisableTiming) != hipSuccess) {
     g_init_err = "side stream or event creation failed";
     (void)hipStreamSynchronize(c->stream);
     delete c;
@@ -1978,7 +1989,7 @@ void lbm_destroy(lbm_ctx* c) {
     (void)hipEventDestroy(p.b);
   }
   drop_graph(c);
-  for (hipEvent_t e : {c->ev_fork, c->ev_wall, c->ev_join})
+  for (hipEvent_t e : {c->ev_fork, c->ev_wall, c->ev_join, c->ev_red})
     if (e) (void)hipEventDestroy(e);
   if (c->side) (void)hipStreamDestroy(c->side);
   delete c;
