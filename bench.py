@@ -60,6 +60,9 @@ def parse():
     ap.add_argument("--single-stream", action="store_true",
                     help="eager launches on the solver stream throughout, with per-kernel events "
                          "and no HIP graph (the launch pattern hardware-counter collection is taken on)")
+    ap.add_argument("--window-start", type=int, default=None,
+                    help="steps into the beat before the timed window (default %d; a short run for counter passes)"
+                    % PREP_STEPS)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device copy of 1 GiB (calibration of the HBM byte counters)")
     return ap.parse_args()
@@ -575,8 +578,10 @@ def traffic_from_profile(precision):
 
 def main():
     args = parse()
-    global SINGLE_STREAM
+    global SINGLE_STREAM, PREP_STEPS
     SINGLE_STREAM = args.single_stream
+    if args.window_start is not None:
+        PREP_STEPS = max(0, args.window_start)
     if args.copy_probe:
         copy_probe()
         return
