@@ -72,3 +72,32 @@ def test_deterministic_mode_meets_the_oracle(oracle_mod, amd, precision, tol):
     floor = np.finfo(float).eps * np.linalg.norm(X) / np.linalg.norm(Do)
     assert e_x <= wall_bar(precision, tol, 120) + floor, (e_x, floor)
     s.close()
+
+
+@pytest.mark.parametrize("precision,nee", [("FP32", 0), ("FP16S", 0), ("FP32", 1)])
+def test_stream_orders_agree_bitwise(amd, precision, nee):
+    """With deterministic spreading every kernel of a step is deterministic,
+    so the step's three orders must give bitwise equal states: the replayed
+    graph (0D reductions on the second stream beside the band moments and the
+    wall exchange, membrane and 0D-plane tiles there beside the bulk
+    collide), the same launches without a graph, and the timed step (every
+    launch in sequence on one stream).  A missing wait between the streams
+    would show here as a difference.  nee = 1: the normal-neighbour build,
+    whose 0D-plane tiles have a launch of their own (on the second stream)."""
+    c = dict(L.small_fsi(), nee_variant=nee)
+    out = []
+    for mode in ("graph", "eager", "sequential"):
+        s = amd.solver_from_config(c, precision=getattr(amd, precision))
+        s.set_deterministic(True)
+        if mode == "eager":
+            s.set_graph(False)
+        if mode == "sequential":
+            s.set_timing(True)
+        s.step(150)
+        s.sync()
+        w = s.read_wall()
+        out.append((s.read_populations(), s.waveforms(), w["X"], w["F"]))
+        s.close()
+    for o in out[1:]:
+        for a, b in zip(out[0], o):
+            assert np.array_equal(a, b)
