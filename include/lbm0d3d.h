@@ -363,6 +363,20 @@ lbm_status lbm_set_overlap(lbm_ctx* ctx, int32_t on);
  * Default off.  Synchronises and drops the captured step graph. */
 lbm_status lbm_set_deterministic(lbm_ctx* ctx, int32_t on);
 
+/* Race check of the AA streaming (a debug aid, not part of a step): runs the
+ * FP32 collide-stream of the given parity (0 even, 1 odd) over every cell
+ * with each population store replaced by an atomic count of the slot it
+ * targets, and copies the counts to counts (host, 19 * N uint32, N = the
+ * context's total cell count, slot i of global cell c at i * N + c).  The
+ * populations are left unchanged.  In a race-free step every count is 0 or
+ * 1, and every slot a fluid cell reads in the following step (parity 0:
+ * slot opp(i) of c - e_i; parity 1: slot i of c) counts 1.  Synchronises;
+ * allocates its counters for the call.  Errors: LBM_E_INVAL (NULL, parity,
+ * a context that is not FP32), LBM_E_STATE (a store aimed past the
+ * population arrays, which the step's bounded stores would drop),
+ * LBM_E_DEVICE. */
+lbm_status lbm_debug_slot_writes(lbm_ctx* ctx, int32_t parity, uint32_t* counts);
+
 /* Launch shapes per size class.  The instances of a context are grouped by
  * cell count into size classes (quartiles from 8 instances on, else one
  * class); each class has its own collide-stream launch (workgroup size and

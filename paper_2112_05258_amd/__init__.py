@@ -83,6 +83,7 @@ SYMBOLS = {
     "lbm_set_graph": (C.c_int, [C.c_void_p, C.c_int32]),
     "lbm_set_overlap": (C.c_int, [C.c_void_p, C.c_int32]),
     "lbm_set_deterministic": (C.c_int, [C.c_void_p, C.c_int32]),
+    "lbm_debug_slot_writes": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_uint32)]),
     "lbm_set_band_check": (C.c_int, [C.c_void_p, C.c_int32]),
     "lbm_num_classes": (C.c_int32, [C.c_void_p]),
     "lbm_class_info": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int64),
@@ -367,6 +368,15 @@ class Solver:
 
     def set_overlap(self, on):
         self._check(lib().lbm_set_overlap(self.h, 1 if on else 0))
+
+    def debug_slot_writes(self, parity):
+        """Store counts per population slot of one collide-stream pass of the
+        given parity, shape (19, total cells), populations left unchanged
+        (lbm_debug_slot_writes; FP32 contexts)."""
+        n = sum(self.ncell(k) for k in range(self.n))
+        out = np.zeros((NQ, n), dtype=np.uint32)
+        self._check(lib().lbm_debug_slot_writes(self.h, int(parity), out.ctypes.data_as(C.POINTER(C.c_uint32))))
+        return out
 
     def set_deterministic(self, on):
         """Wall tiles launched colour by colour (lbm_set_deterministic)."""

@@ -1029,6 +1029,7 @@ lbm_status lbm_init(const lbm_config* cfgs, int32_t n, const lbm_buffers* buf, v
   d.err = (uint32_t*)(c->work + c->L.err);
   d.owave = (double*)(c->work + c->L.owave);
   d.moved = (uint32_t*)(c->work + c->L.moved);
+  d.slotcnt = nullptr;
   d.bmark = (uint8_t*)(c->work + c->L.bmark);
   d.btmp = (uint8_t*)(c->work + c->L.btmp);
   d.bcnt = (int32_t*)(c->work + c->L.bcnt);
@@ -1723,6 +1724,36 @@ lbm_status lbm_set_graph(lbm_ctx* c, int32_t on) {
 lbm_status lbm_set_band_check(lbm_ctx* c, int32_t every) {
   if (!c || every < 0) return LBM_E_INVAL;
   c->band_check = every;
+  return LBM_OK;
+}
+
+lbm_status lbm_debug_slot_writes(lbm_ctx* c, int32_t parity, uint32_t* counts) {
+  if (!c || !counts || (parity != 0 && parity != 1)) return LBM_E_INVAL;
+  if (c->prec != LBM_FP32) return fail(c, LBM_E_INVAL, "the slot-write check runs on FP32 contexts");
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  std::vector<CTile> tiles;
+  for (int i = 0; i < c->n; ++i)
+    for (int64_t s0 = 0; s0 < c->inst[i].ncell; s0 += 256) tiles.push_back(CTile{i, (int32_t)s0});
+  const size_t n = (size_t)NQ * (size_t)c->L.NT;
+  uint32_t* cnt = nullptr;
+  CTile* tab = nullptr;
+  uint32_t outside = 0;   // stores past the arrays, counted after the slots
+  hipError_t e = hipMalloc((void**)&cnt, (n + 1) * 4);
+  if (e == hipSuccess) e = hipMalloc((void**)&tab, tiles.size() * sizeof(CTile));
+  if (e == hipSuccess) e = hipMemset(cnt, 0, (n + 1) * 4);
+  if (e == hipSuccess) e = hipMemcpy(tab, tiles.data(), tiles.size() * sizeof(CTile), hipMemcpyHostToDevice);
+  if (e == hipSuccess) {
+    Dev d = c->dev;
+    d.slotcnt = cnt;
+    e = launch_collide_count(d, parity, c->dev.any_nee != 0, tab, (int)tiles.size(), c->stream);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e == hipSuccess) e = hipMemcpy(counts, cnt, n * 4, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(&outside, cnt + n, 4, hipMemcpyDeviceToHost);
+  if (tab) (void)hipFree(tab);
+  if (cnt) (void)hipFree(cnt);
+  HIPCHK(c, e);
+  if (outside) return fail(c, LBM_E_STATE, "a population store outside the arrays");
   return LBM_OK;
 }
 

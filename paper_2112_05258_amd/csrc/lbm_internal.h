@@ -133,6 +133,7 @@ struct Dev {
   uint32_t* moved;                 // max wall motion since the band was built (float bits)
   // band rebuild on the device: cell marks (two byte arrays over all cells),
   // band cells per block of BCELLS cells, and the gate word (1: rebuild now)
+  uint32_t* slotcnt;   // slot-writer check only: 19 * NT store counts (else null)
   uint8_t* bmark;
   uint8_t* btmp;
   int32_t* bcnt;
@@ -168,6 +169,9 @@ enum { COLLIDE_ALL = 0, COLLIDE_BULK = 1, COLLIDE_BAND = 2 };
 hipError_t launch_collide(const Dev& d, int prec, int parity, int bs, int cpt, bool nee, const CTile* tab,
                           int ntile, int mode, hipStream_t s);
 hipError_t launch_band(const Dev& d, int prec, int parity, hipStream_t s);
+// the slot-writer check: the FP32 collide counting its stores (d.slotcnt)
+// over tiles of 256 cells
+hipError_t launch_collide_count(const Dev& d, int parity, bool nee, const CTile* tab, int ntile, hipStream_t s);
 // the boundary reductions and the band moments in one launch
 hipError_t launch_reduce_band(const Dev& d, int prec, int parity, int nred, hipStream_t s);
 // LDS staging capacity of a wall tile's stencil box (cells), standard and

@@ -364,7 +364,7 @@ __device__ __forceinline__ R relax(int i, const Mom<R>& m, R g, R om) {
 // types are looked up);
 // BAND: the wave holds a cell of the wall's band (the IB force enters, zero
 // at the wave's other cells).  The plain body has neither.
-template <class S, bool ODD, bool NEAR, bool BAND, bool NEE>
+template <class S, bool ODD, bool NEAR, bool BAND, bool NEE, bool COUNT = false>
 __device__ __forceinline__ void collide_body(const Dev& d, const int inst, const InstDesc& I, const int64_t local,
                                              const uint32_t c, const uint8_t fl) {
   using R = typename Store<S>::R;
@@ -395,6 +395,18 @@ __device__ __forceinline__ void collide_body(const Dev& d, const int inst, const
   constexpr uint32_t ES = sizeof(S);
   const uint32_t dir_bytes = (uint32_t)(NT * ES);
   auto rs = [&](int i) { return dir_rsrc(A + i * NT, dir_bytes); };
+  // a store of direction dir at byte offset o; the counting build (the
+  // slot-writer check) counts it in d.slotcnt instead of storing -- an
+  // offset past the direction's array (which the buffer store would drop)
+  // in the extra counter after the 19 * NT slots
+  auto put = [&](int dir, uint32_t o, typename Store<S>::R v) {
+    if constexpr (COUNT) {
+      const uint64_t k = o / ES;
+      atomicAdd(d.slotcnt + (k < (uint64_t)NT ? (uint64_t)dir * (uint64_t)NT + k : (uint64_t)NQ * (uint64_t)NT), 1u);
+    } else {
+      BufIO<S>::st(rs(dir), o, v, d.scale);
+    }
+  };
   R g[NQ];
 #pragma unroll
   for (int i = 0; i < NQ; ++i) {
@@ -455,8 +467,8 @@ __device__ __forceinline__ void collide_body(const Dev& d, const int inst, const
 #pragma unroll
   for (int i = 0; i < NQ; ++i) {
     const R v = relax<R, BAND>(i, m, g[i], om);
-    if (!ODD) BufIO<S>::st(rs(OPP[i]), c * ES, v, d.scale);
-    else BufIO<S>::st(rs(i), (uint32_t)(c + off[i]) * ES, v, d.scale);
+    if (!ODD) put(OPP[i], c * ES, v);
+    else put(i, (uint32_t)(c + off[i]) * ES, v);
     // halfway bounce-back: g*_i toward a SOLID cell x = c + e_i returns to c
     // as direction opp i.  It goes to the slot the next step's plain load of
     // that direction reads: x's A[i][x] after an even step, the own A[opp i][c]
@@ -464,16 +476,16 @@ __device__ __forceinline__ void collide_body(const Dev& d, const int inst, const
     // then lands in a slot nobody reads (the solid's, or the own slot whose
     // reader would be the solid).
     if (NEAR && i > 0 && nt(OPP[i]) == T_SOLID) {
-      if (!ODD) BufIO<S>::st(rs(i), (uint32_t)(c + off[i]) * ES, v, d.scale);
-      else BufIO<S>::st(rs(OPP[i]), c * ES, v, d.scale);
+      if (!ODD) put(i, (uint32_t)(c + off[i]) * ES, v);
+      else put(OPP[i], c * ES, v);
     }
     if (!NEAR || i == 0) continue;
     const bool edge = i >= 7;
     if (nt(i) >= T_INLET &&
         !(NEE && edge && I.nee && (nt(edge_a(i)) == T_FLUID || nt(edge_b(i)) == T_FLUID))) {
       const R out = ghost_value(i, nt(i), (uint32_t)(c - off[i]), v);
-      if (!ODD) BufIO<S>::st(rs(OPP[i]), (uint32_t)(c - off[i]) * ES, out, d.scale);
-      else BufIO<S>::st(rs(i), c * ES, out, d.scale);
+      if (!ODD) put(OPP[i], (uint32_t)(c - off[i]) * ES, out);
+      else put(i, c * ES, out);
     }
     if (NEE && edge && I.nee) {
       // this cell as the normal neighbour of the ghost c - e_k, handing
@@ -484,8 +496,8 @@ __device__ __forceinline__ void collide_body(const Dev& d, const int inst, const
         const int t = h == 0 ? edge_b(i) : edge_a(i);
         if (nt(k) >= T_INLET && nt(OPP[t]) == T_FLUID) {
           const R out = ghost_value(i, nt(k), (uint32_t)(c - off[k]), v);
-          if (!ODD) BufIO<S>::st(rs(OPP[i]), (uint32_t)(c - off[k]) * ES, out, d.scale);
-          else BufIO<S>::st(rs(i), (uint32_t)(c + off[t]) * ES, out, d.scale);
+          if (!ODD) put(OPP[i], (uint32_t)(c - off[k]) * ES, out);
+          else put(i, (uint32_t)(c + off[t]) * ES, out);
         }
       }
     }
@@ -500,7 +512,7 @@ __device__ __forceinline__ void collide_body(const Dev& d, const int inst, const
 // the two partial passes touch disjoint memory and the bulk pass may run
 // while the wall exchange still reads the band cells' populations.  The body is chosen per wave (a vote over its
 // active lanes), so the choice never splits a wave.
-template <class S, bool ODD, bool NEE>
+template <class S, bool ODD, bool NEE, bool COUNT = false>
 __device__ __forceinline__ void collide_cell(const Dev& d, const int inst, const int64_t local, const int mode) {
   const InstDesc& I = d.inst[inst];
   if (local >= I.ncell) return;
@@ -514,11 +526,11 @@ __device__ __forceinline__ void collide_cell(const Dev& d, const int inst, const
   if ((fl & TYPE_MASK) != T_FLUID || (ew & ERR_FROZEN)) return;
   if (mode != COLLIDE_ALL && ((fl & F_BAND) != 0) != (mode == COLLIDE_BAND)) return;
   if (__any(fl & F_NEAR))
-    collide_body<S, ODD, true, true, NEE>(d, inst, I, local, c, fl);
+    collide_body<S, ODD, true, true, NEE, COUNT>(d, inst, I, local, c, fl);
   else if (__any(fl & F_BAND))
-    collide_body<S, ODD, false, true, NEE>(d, inst, I, local, c, fl);
+    collide_body<S, ODD, false, true, NEE, COUNT>(d, inst, I, local, c, fl);
   else
-    collide_body<S, ODD, false, false, NEE>(d, inst, I, local, c, fl);
+    collide_body<S, ODD, false, false, NEE, COUNT>(d, inst, I, local, c, fl);
 }
 
 // One workgroup of BS lanes per tile of BS * CPT consecutive cells of one
@@ -533,6 +545,17 @@ __global__ __launch_bounds__(BS) void k_collide(Dev d, const CTile* __restrict__
   const CTile t = tab[blockIdx.x];
 #pragma unroll
   for (int q = 0; q < CPT; ++q) collide_cell<S, ODD, NEE>(d, t.inst, (int64_t)t.start + q * BS + (int)threadIdx.x, mode);
+}
+
+// The slot-writer check of the AA pattern: the FP32 collide with every
+// population store replaced by an atomic count of its slot in d.slotcnt
+// (19 * NT counters), over tiles of 256 cells; the populations are left as
+// they are.  A race-free step writes each slot at most once, and every slot
+// a fluid cell reads in the next step exactly once.
+template <bool ODD, bool NEE>
+__global__ __launch_bounds__(256) void k_collide_count(Dev d, const CTile* __restrict__ tab) {
+  const CTile t = tab[blockIdx.x];
+  collide_cell<float, ODD, NEE, true>(d, t.inst, (int64_t)t.start + (int)threadIdx.x, COLLIDE_ALL);
 }
 
 // ---------------------------------------------------------------------------
@@ -1427,6 +1450,16 @@ hipError_t launch_collide(const Dev& d, int prec, int parity, int bs, int cpt, b
   LBM_DISPATCH(prec, F)
 #undef F
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_collide_count(const Dev& d, int parity, bool nee, const CTile* tab, int ntile, hipStream_t s) {
+  if (ntile <= 0) return hipSuccess;
+  const dim3 g((unsigned)ntile), b(256);
+  if (nee)
+    return parity ? launch(k_collide_count<true, true>, g, b, s, Dev(d), tab)
+                  : launch(k_collide_count<false, true>, g, b, s, Dev(d), tab);
+  return parity ? launch(k_collide_count<true, false>, g, b, s, Dev(d), tab)
+                : launch(k_collide_count<false, false>, g, b, s, Dev(d), tab);
 }
 
 hipError_t launch_reduce_band(const Dev& d, int prec, int parity, int nred, hipStream_t s) {

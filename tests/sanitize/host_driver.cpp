@@ -20,6 +20,7 @@ hipError_t launch_collide(const Dev&, int, int, int, int, bool, const CTile*, in
   return hipErrorNotSupported;
 }
 hipError_t launch_band(const Dev&, int, int, hipStream_t) { return hipErrorNotSupported; }
+hipError_t launch_collide_count(const Dev&, int, bool, const CTile*, int, hipStream_t) { return hipErrorNotSupported; }
 hipError_t launch_reduce_band(const Dev&, int, int, int, hipStream_t) { return hipErrorNotSupported; }
 hipError_t launch_wall(const Dev&, int, int, int, int, bool, const int32_t*, int, int, int, hipStream_t) {
   return hipErrorNotSupported;
