@@ -734,6 +734,8 @@ __global__ __launch_bounds__(WBLOCK) void k_wall(Dev d, const int32_t* __restric
   const double* Dc = I.Xab[parity];
   double* Dn = I.Xab[parity ^ 1];
   const double3 X0 = ld3(I.X0, p), D = ld3(Dc, p), Dm = ld3(Dn, p);
+  double4* SL = (double4*)I.slip;
+  double4 sl = SL[p];   // the slip integral, loaded with the rest of the point's state
   // A point that is not finite or has left the lattice box (a run that has
   // blown up) cannot be in its band: it is flagged and takes no part, so
   // that no stencil index is ever formed from it (the comparisons are false
@@ -870,8 +872,6 @@ __global__ __launch_bounds__(WBLOCK) void k_wall(Dev d, const int32_t* __restric
     const double dxv = (double)Vx - (D.x - Dm.x);
     const double dyv = (double)Vy - (D.y - Dm.y);
     const double dzv = (double)Vz - (D.z - Dm.z);
-    double4* SL = (double4*)I.slip;
-    double4 sl = SL[p];
     sl.x += dxv; sl.y += dyv; sl.z += dzv;
     SL[p] = sl;
     Fx = I.alpha * sl.x + I.beta * dxv;
