@@ -374,14 +374,14 @@ __global__ void k_adam(float* __restrict__ w, float* __restrict__ m1, float* __r
 // ---------------------------------------------------------------------------
 // Fused inference for width 512 and 512 outputs (the surrogate's shape)
 // ---------------------------------------------------------------------------
-// One 512-lane workgroup (8 waves) per 128 rows holds the rows' activations
-// in LDS (128 x 512 BF16, row pitch padded by 16 bytes) from the input
-// normalisation to the output layer, so hidden activations never travel to
-// HBM.  Wave w computes output columns 64 w .. 64 w + 63 of every layer
-// (4 x 2 MFMA tiles of 32 x 32): A fragments come from LDS, B fragments
-// (weights) stream from L2 in fragment order, two k-steps ahead of the
-// MFMAs that use them.  The GELU epilogue writes the layer's output over its
-// input in LDS between two barriers.
+// One 1024-lane workgroup (16 waves, four per SIMD) per 128 rows holds the
+// rows' activations in LDS (128 x 512 BF16, row pitch padded by 16 bytes)
+// from the input normalisation to the output layer, so hidden activations
+// never travel to HBM.  Wave w computes output columns 32 w .. 32 w + 31 of
+// every layer (4 x 1 MFMA tiles of 32 x 32): activation fragments come from
+// LDS one k-step ahead, weight fragments stream from L2 in fragment order two
+// k-steps ahead of the MFMAs that use them.  The GELU epilogue writes the
+// layer's output over its input in LDS between two barriers.
 constexpr int MR = 128, MWID = 512, APITCH = MWID + 8;
 
 // weights in MFMA fragment order: element ((ks N/32 + nt) 64 + lane) 8 + e of
@@ -477,17 +477,17 @@ __device__ __forceinline__ void static_for(F&& f) {
   }
 }
 
-// GELU of accumulator n (0..63, in (i, j, v) order) of a half's (column,
+// GELU of accumulator n (0..32 NJ - 1, in (i, j, v) order) of a half's (column,
 // row) tiles; every fourth one stores the group of four as one 8-byte LDS
 // write (lane l: row i 32 + l % 32, columns 8 (v / 4) + 4 (l / 32) .. + 3 of
 // tile j).
-template <int N>
-__device__ __forceinline__ void epi_value(const f32x16 (&acc)[2][2], float (&gv)[4], uint16_t* act, int wv,
+template <int NJ, int N>
+__device__ __forceinline__ void epi_value(const f32x16 (&acc)[2][NJ], float (&gv)[4], uint16_t* act, int wv,
                                           int lane) {
-  constexpr int i = N >> 5, j = (N >> 4) & 1, v = N & 15;
+  constexpr int i = N / (16 * NJ), j = (N / 16) % NJ, v = N & 15;
   gv[N & 3] = gelu_epi(acc[i][j][v]);
   if ((N & 3) == 3) {
-    const int row = i * 32 + (lane & 31), col = (2 * wv + j) * 32 + 8 * (v >> 2) + 4 * (lane >> 5);
+    const int row = i * 32 + (lane & 31), col = (NJ * wv + j) * 32 + 8 * (v >> 2) + 4 * (lane >> 5);
     // hardware round-to-nearest-even conversion, two values at a time
     const bf16x2 lo = __builtin_convertvector((f32x2){gv[0], gv[1]}, bf16x2);
     const bf16x2 hi = __builtin_convertvector((f32x2){gv[2], gv[3]}, bf16x2);
@@ -495,16 +495,16 @@ __device__ __forceinline__ void epi_value(const f32x16 (&acc)[2][2], float (&gv)
   }
 }
 
-template <int N0, int PER>
-__device__ __forceinline__ void epi_values(const f32x16 (&acc)[2][2], float (&gv)[4], uint16_t* act, int wv, int lane) {
+template <int NJ, int N0, int PER>
+__device__ __forceinline__ void epi_values(const f32x16 (&acc)[2][NJ], float (&gv)[4], uint16_t* act, int wv, int lane) {
   if constexpr (PER > 0) {
-    epi_value<N0>(acc, gv, act, wv, lane);
-    epi_values<N0 + 1, PER - 1>(acc, gv, act, wv, lane);
+    epi_value<NJ, N0>(acc, gv, act, wv, lane);
+    epi_values<NJ, N0 + 1, PER - 1>(acc, gv, act, wv, lane);
   }
 }
 
 // One phase: the products of one layer (depth 16 KS) for one half (two
-// 32-row blocks, rows at actM) and this wave's 64 output columns into accM,
+// 32-row blocks, rows at actM) and this wave's 32 NJ output columns into accM,
 // the first k-step taking the bias tiles bt as its accumulator input; with
 // DRAIN the epilogue of the other half (accE, rows at actE) is spread over
 // the k-steps.  TR: the weights are the A operand and the activations the B
@@ -512,51 +512,68 @@ __device__ __forceinline__ void epi_values(const f32x16 (&acc)[2][2], float (&gv
 // and four consecutive columns per group of four accumulators.  !TR: (row,
 // output column), lane l has column l % 32 (the output layer, whose FP32
 // rows leave in 128-byte runs).
-template <bool TR, int KS, bool DRAIN>
-__device__ __forceinline__ void mlp_phase(f32x16 (&accM)[2][2], const f32x16 (&bt)[2], const uint16_t* actM,
-                                          const uint16_t* wf, const f32x16 (&accE)[2][2], uint16_t* actE, int wv,
+template <int NJ, bool TR, int KS, bool DRAIN>
+__device__ __forceinline__ void mlp_phase(f32x16 (&accM)[2][NJ], const f32x16 (&bt)[NJ], const uint16_t* actM,
+                                          const uint16_t* wf, const f32x16 (&accE)[2][NJ], uint16_t* actE, int wv,
                                           int lane) {
   const int fr = lane & 31, fk = (lane >> 5) * 8;
   constexpr int NT = MWID / 32;   // column tiles of a layer
-  const bf16x8* W0 = (const bf16x8*)wf + (2 * wv) * 64 + lane;
-  const bf16x8* W1 = W0 + 64;
+  // weight fragments through a buffer resource over this layer's fragments
+  // (out of range reads return zero): the lane's byte offset in a VGPR, the
+  // k-step's in the scalar offset, so the unrolled k-steps need no 64-bit
+  // address registers of their own (dword 3: 32-bit data format)
+  const __amdgpu_buffer_rsrc_t W = __builtin_amdgcn_make_buffer_rsrc((void*)wf, (short)0, NT * 64 * 16 * KS, 0x00020000);
+  const int wlane = ((NJ * wv) * 64 + lane) * 16;
+  auto ldw = [&](int off) { return __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(W, wlane, off, 0)); };
   const uint16_t* arow = actM + fr * APITCH + fk;
-  bf16x8 b0[2], b1[2], af[2][2];
+  bf16x8 b[3][NJ], af[2][2];
   float gv[4];
-  b0[0] = W0[0];
-  b1[0] = W1[0];
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) b[0][j] = ldw(j * 64 * 16);
+  if constexpr (KS > 1) {
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) b[1][j] = ldw((NT * 64 + j * 64) * 16);
+  }
   af[0][0] = *(const bf16x8*)arow;
   af[0][1] = *(const bf16x8*)(arow + 32 * APITCH);
   static_for<0, KS>([&](auto cc) {
     constexpr int c = decltype(cc)::value;
-    if constexpr (c + 1 < KS) {   // next k-step's fragments in flight
-      b0[(c + 1) & 1] = W0[(c + 1) * NT * 64];
-      b1[(c + 1) & 1] = W1[(c + 1) * NT * 64];
+    if constexpr (c + 2 < KS) {   // weights two k-steps ahead
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) b[(c + 2) % 3][j] = ldw(((c + 2) * NT * 64 + j * 64) * 16);
+    }
+    if constexpr (c + 1 < KS) {   // next k-step's activations in flight
+
       af[(c + 1) & 1][0] = *(const bf16x8*)(arow + (c + 1) * 16);
       af[(c + 1) & 1][1] = *(const bf16x8*)(arow + 32 * APITCH + (c + 1) * 16);
     }
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-      const f32x16 c0 = c == 0 ? bt[0] : accM[i][0], c1 = c == 0 ? bt[1] : accM[i][1];
       const bf16x8 x = af[c & 1][i];
-      if (TR) {
-        accM[i][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b0[c & 1], x, c0, 0, 0, 0);
-        accM[i][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b1[c & 1], x, c1, 0, 0, 0);
-      } else {
-        accM[i][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x, b0[c & 1], c0, 0, 0, 0);
-        accM[i][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x, b1[c & 1], c1, 0, 0, 0);
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        const f32x16 c0 = c == 0 ? bt[j] : accM[i][j];
+        if (TR)
+          accM[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b[c % 3][j], x, c0, 0, 0, 0);
+        else
+          accM[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x, b[c % 3][j], c0, 0, 0, 0);
       }
     }
-    if constexpr (DRAIN) epi_values<c * (64 / KS), 64 / KS>(accE, gv, actE, wv, lane);
+    if constexpr (DRAIN) epi_values<NJ, c * (32 * NJ / KS), 32 * NJ / KS>(accE, gv, actE, wv, lane);
   });
 }
 
-__global__ __launch_bounds__(512) void k_mlp_fwd(MlpArgs a) {
+// column tiles per wave: 1 (16 waves, at most 128 VGPRs each) runs the
+// network in 178-182 us per 65 536 rows, 2 (8 waves with twice the
+// accumulators) in 190
+constexpr int FWD_NJ = 1, FWD_THREADS = 64 * (MWID / 32) / FWD_NJ;
+__global__ __launch_bounds__(FWD_THREADS) void k_mlp_fwd(MlpArgs a) {
+  constexpr int NJ = FWD_NJ;
   __shared__ __attribute__((aligned(16))) uint16_t act[MR * APITCH];
   const int tid = (int)threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int r0 = (int)blockIdx.x * MR;
   // inputs normalised as k_prep_x does; padding columns and rows are zero
-  for (int e = tid; e < MR * KPAD; e += 512) {
+  for (int e = tid; e < MR * KPAD; e += FWD_THREADS) {
     const int r = e / KPAD, j = e % KPAD;
     float v = 0.0f;
     if (j < a.nin && r0 + r < a.m)
@@ -570,13 +587,13 @@ __global__ __launch_bounds__(512) void k_mlp_fwd(MlpArgs a) {
   auto bias_of = [&](int l) { return a.w + a.L.off[l] + (int64_t)a.L.out[l] * a.L.in[l]; };
   // hidden-layer bias tiles: accumulator v of lane l is column
   // 8 (v / 4) + 4 (l / 32) + v % 4 of the (column, row) tile
-  auto bias_tr = [&](int l, f32x16 (&bt)[2]) {
+  auto bias_tr = [&](int l, f32x16 (&bt)[NJ]) {
     const float* bias = bias_of(l);
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < NJ; ++j)
 #pragma unroll
       for (int g = 0; g < 4; ++g) {
-        const float4 bv = *(const float4*)(bias + (2 * wv + j) * 32 + 8 * g + 4 * fh);
+        const float4 bv = *(const float4*)(bias + (NJ * wv + j) * 32 + 8 * g + 4 * fh);
         bt[j][4 * g + 0] = bv.x;
         bt[j][4 * g + 1] = bv.y;
         bt[j][4 * g + 2] = bv.z;
@@ -584,18 +601,18 @@ __global__ __launch_bounds__(512) void k_mlp_fwd(MlpArgs a) {
       }
   };
   // output-layer bias tiles: column l % 32 of the (row, column) tile
-  auto bias_out = [&](f32x16 (&bt)[2]) {
+  auto bias_out = [&](f32x16 (&bt)[NJ]) {
     const float* bias = bias_of(a.L.nl - 1);
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const float bj = bias[(2 * wv + j) * 32 + fr];
+    for (int j = 0; j < NJ; ++j) {
+      const float bj = bias[(NJ * wv + j) * 32 + fr];
 #pragma unroll
       for (int v = 0; v < 16; ++v) bt[j][v] = bj;
     }
   };
   auto wf_of = [&](int l) { return a.wf + a.L.woff[l]; };
   const int nl = a.L.nl;
-  f32x16 accA[2][2], accB[2][2];
+  f32x16 accA[2][NJ], accB[2][NJ];
   constexpr int K0 = KPAD / 16, KH = MWID / 16;
   // phase 2l: half A's products of layer l beside half B's epilogue of
   // layer l - 1; phase 2l + 1: half B's products of layer l beside half A's
@@ -603,34 +620,42 @@ __global__ __launch_bounds__(512) void k_mlp_fwd(MlpArgs a) {
   // drains into were read by the products of the phase before, and the rows
   // it multiplies were drained into by the phase before.
   {
-    f32x16 bt[2];
+    f32x16 bt[NJ];
     bias_tr(0, bt);
-    mlp_phase<true, K0, false>(accA, bt, actA, wf_of(0), accB, actB, wv, lane);
+    mlp_phase<NJ, true, K0, false>(accA, bt, actA, wf_of(0), accB, actB, wv, lane);
     __syncthreads();
-    mlp_phase<true, K0, true>(accB, bt, actB, wf_of(0), accA, actA, wv, lane);
+    bias_tr(0, bt);
+    mlp_phase<NJ, true, K0, true>(accB, bt, actB, wf_of(0), accA, actA, wv, lane);
     __syncthreads();
   }
   for (int l = 1; l + 1 < nl; ++l) {
-    f32x16 bt[2];
-    bias_tr(l, bt);
-    mlp_phase<true, KH, true>(accA, bt, actA, wf_of(l), accB, actB, wv, lane);
+    {
+      f32x16 bt[NJ];
+      bias_tr(l, bt);
+      mlp_phase<NJ, true, KH, true>(accA, bt, actA, wf_of(l), accB, actB, wv, lane);
+    }
     __syncthreads();
-    mlp_phase<true, KH, true>(accB, bt, actB, wf_of(l), accA, actA, wv, lane);
+    {
+      f32x16 bt[NJ];
+      bias_tr(l, bt);
+      mlp_phase<NJ, true, KH, true>(accB, bt, actB, wf_of(l), accA, actA, wv, lane);
+    }
     __syncthreads();
   }
   {
-    f32x16 bt[2];
+    f32x16 bt[NJ];
     bias_out(bt);
-    mlp_phase<false, KH, true>(accA, bt, actA, wf_of(nl - 1), accB, actB, wv, lane);
+    mlp_phase<NJ, false, KH, true>(accA, bt, actA, wf_of(nl - 1), accB, actB, wv, lane);
     __syncthreads();
-    mlp_phase<false, KH, false>(accB, bt, actB, wf_of(nl - 1), accA, actA, wv, lane);
+    bias_out(bt);
+    mlp_phase<NJ, false, KH, false>(accB, bt, actB, wf_of(nl - 1), accA, actA, wv, lane);
   }
   const bool full = r0 + MR <= a.m;   // uniform: only the last workgroup may be ragged
-  auto store = [&](const f32x16 (&acc)[2][2], int rb, auto checked) {
+  auto store = [&](const f32x16 (&acc)[2][NJ], int rb, auto checked) {
     float* yb = a.y + (int64_t)(r0 + rb) * MWID;
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int col = (2 * wv + j) * 32 + fr;
+    for (int j = 0; j < NJ; ++j) {
+      const int col = (NJ * wv + j) * 32 + fr;
       const float mj = a.mu[col], sj = a.sigma[col];
 #pragma unroll
       for (int i = 0; i < 2; ++i)
@@ -931,7 +956,7 @@ lbm_status predict_fused(lbm_sur_ctx* c, const float* x, int m, float* y) {
   g.wf = c->wf; g.w = c->w; g.L = c->L; g.mu = c->mu; g.sigma = c->sigma; g.y = y;
   const bool t = c->timing && c->nev + 2 <= (int)c->ev.size();
   if (t) SURCHK(c, hipEventRecord(c->ev[c->nev], c->stream));
-  hipLaunchKernelGGL(k_mlp_fwd, dim3(blocks(m, MR)), dim3(512), 0, c->stream, g);
+  hipLaunchKernelGGL(k_mlp_fwd, dim3(blocks(m, MR)), dim3(FWD_THREADS), 0, c->stream, g);
   SURCHK(c, hipGetLastError());
   if (t) {
     SURCHK(c, hipEventRecord(c->ev[c->nev + 1], c->stream));
@@ -1181,7 +1206,7 @@ lbm_status lbm_sur_predict_static(const lbm_sur_config* cfg, const float* theta,
   MlpArgs g;
   g.x = x; g.m = m; g.nin = cfg->n_in; g.lo = lo; g.hi = hi;
   g.wf = wf; g.w = theta; g.L = L; g.mu = mu; g.sigma = sigma; g.y = y;
-  hipLaunchKernelGGL(k_mlp_fwd, dim3(blocks(m, MR)), dim3(512), 0, s, g);
+  hipLaunchKernelGGL(k_mlp_fwd, dim3(blocks(m, MR)), dim3(FWD_THREADS), 0, s, g);
   if (hipGetLastError() != hipSuccess) return bad(LBM_E_DEVICE, "inference kernel launch failed");
   return LBM_OK;
 }
