@@ -380,7 +380,8 @@ __global__ void k_adam(float* __restrict__ w, float* __restrict__ m1, float* __r
 // never travel to HBM.  Wave w computes output columns 32 w .. 32 w + 31 of
 // every layer (4 x 1 MFMA tiles of 32 x 32): activation fragments come from
 // LDS one k-step ahead, weight fragments stream from L2 in fragment order two
-// k-steps ahead of the MFMAs that use them.  The GELU epilogue writes the
+// k-steps ahead of the MFMAs that use them (a phase's first two before the
+// barrier that ends the phase before).  The GELU epilogue writes the
 // layer's output over its input in LDS between two barriers.
 constexpr int MR = 128, MWID = 512, APITCH = MWID + 8;
 
@@ -503,19 +504,36 @@ __device__ __forceinline__ void epi_values(const f32x16 (&acc)[2][NJ], float (&g
   }
 }
 
+// the weight fragments of a phase's first two k-steps (depth 16 NKS >= 2),
+// loaded before the barrier that precedes the phase: weights do not depend
+// on the activations the barrier orders
+template <int NJ, int NKS>
+__device__ __forceinline__ void mlp_pre(bf16x8 (&pre)[2][NJ], const uint16_t* wf, int wv, int lane) {
+  constexpr int NT = MWID / 32;
+  const __amdgpu_buffer_rsrc_t W = __builtin_amdgcn_make_buffer_rsrc((void*)wf, (short)0, NT * 64 * 16 * NKS, 0x00020000);
+  const int wlane = ((NJ * wv) * 64 + lane) * 16;
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    pre[0][j] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(W, wlane, j * 64 * 16, 0));
+    pre[1][j] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(W, wlane, (NT * 64 + j * 64) * 16, 0));
+  }
+}
+
 // One phase: the products of one layer (depth 16 KS) for one half (two
 // 32-row blocks, rows at actM) and this wave's 32 NJ output columns into accM,
 // the first k-step taking the bias tiles bt as its accumulator input; with
 // DRAIN the epilogue of the other half (accE, rows at actE) is spread over
-// the k-steps.  TR: the weights are the A operand and the activations the B
+// the k-steps.  pre holds the weight fragments of the first two k-steps on
+// entry and, with NKS > 0, those of the next phase (weights wf_next, depth
+// 16 NKS) on exit.  TR: the weights are the A operand and the activations the B
 // operand, so a tile holds (output column, row) and lane l has row l % 32
 // and four consecutive columns per group of four accumulators.  !TR: (row,
 // output column), lane l has column l % 32 (the output layer, whose FP32
 // rows leave in 128-byte runs).
-template <int NJ, bool TR, int KS, bool DRAIN>
+template <int NJ, bool TR, int KS, bool DRAIN, int NKS>
 __device__ __forceinline__ void mlp_phase(f32x16 (&accM)[2][NJ], const f32x16 (&bt)[NJ], const uint16_t* actM,
                                           const uint16_t* wf, const f32x16 (&accE)[2][NJ], uint16_t* actE, int wv,
-                                          int lane) {
+                                          int lane, bf16x8 (&pre)[2][NJ], const uint16_t* wf_next) {
   const int fr = lane & 31, fk = (lane >> 5) * 8;
   constexpr int NT = MWID / 32;   // column tiles of a layer
   // weight fragments through a buffer resource over this layer's fragments
@@ -529,10 +547,9 @@ __device__ __forceinline__ void mlp_phase(f32x16 (&accM)[2][NJ], const f32x16 (&
   bf16x8 b[3][NJ], af[2][2];
   float gv[4];
 #pragma unroll
-  for (int j = 0; j < NJ; ++j) b[0][j] = ldw(j * 64 * 16);
-  if constexpr (KS > 1) {
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) b[1][j] = ldw((NT * 64 + j * 64) * 16);
+  for (int j = 0; j < NJ; ++j) {   // the first two k-steps' weights came with the phase before
+    b[0][j] = pre[0][j];
+    b[1][j] = pre[1][j];
   }
   af[0][0] = *(const bf16x8*)arow;
   af[0][1] = *(const bf16x8*)(arow + 32 * APITCH);
@@ -543,7 +560,6 @@ __device__ __forceinline__ void mlp_phase(f32x16 (&accM)[2][NJ], const f32x16 (&
       for (int j = 0; j < NJ; ++j) b[(c + 2) % 3][j] = ldw(((c + 2) * NT * 64 + j * 64) * 16);
     }
     if constexpr (c + 1 < KS) {   // next k-step's activations in flight
-
       af[(c + 1) & 1][0] = *(const bf16x8*)(arow + (c + 1) * 16);
       af[(c + 1) & 1][1] = *(const bf16x8*)(arow + 32 * APITCH + (c + 1) * 16);
     }
@@ -561,11 +577,12 @@ __device__ __forceinline__ void mlp_phase(f32x16 (&accM)[2][NJ], const f32x16 (&
     }
     if constexpr (DRAIN) epi_values<NJ, c * (32 * NJ / KS), 32 * NJ / KS>(accE, gv, actE, wv, lane);
   });
+  if constexpr (NKS > 0) mlp_pre<NJ, NKS>(pre, wf_next, wv, lane);
 }
 
-// column tiles per wave: 1 (16 waves, at most 128 VGPRs each) runs the
+// column tiles per wave: 1 (16 waves, at most 128 VGPRs each) ran the
 // network in 178-182 us per 65 536 rows, 2 (8 waves with twice the
-// accumulators) in 190
+// accumulators) in 190, both before the cross-barrier weight loads
 constexpr int FWD_NJ = 1, FWD_THREADS = 64 * (MWID / 32) / FWD_NJ;
 __global__ __launch_bounds__(FWD_THREADS) void k_mlp_fwd(MlpArgs a) {
   constexpr int NJ = FWD_NJ;
@@ -619,36 +636,38 @@ __global__ __launch_bounds__(FWD_THREADS) void k_mlp_fwd(MlpArgs a) {
   // epilogue of layer l.  A barrier ends every phase: the rows a phase
   // drains into were read by the products of the phase before, and the rows
   // it multiplies were drained into by the phase before.
+  bf16x8 pre[2][NJ];
+  mlp_pre<NJ, K0>(pre, wf_of(0), wv, lane);
   {
     f32x16 bt[NJ];
     bias_tr(0, bt);
-    mlp_phase<NJ, true, K0, false>(accA, bt, actA, wf_of(0), accB, actB, wv, lane);
+    mlp_phase<NJ, true, K0, false, K0>(accA, bt, actA, wf_of(0), accB, actB, wv, lane, pre, wf_of(0));
     __syncthreads();
     bias_tr(0, bt);
-    mlp_phase<NJ, true, K0, true>(accB, bt, actB, wf_of(0), accA, actA, wv, lane);
+    mlp_phase<NJ, true, K0, true, KH>(accB, bt, actB, wf_of(0), accA, actA, wv, lane, pre, wf_of(1));
     __syncthreads();
   }
   for (int l = 1; l + 1 < nl; ++l) {
     {
       f32x16 bt[NJ];
       bias_tr(l, bt);
-      mlp_phase<NJ, true, KH, true>(accA, bt, actA, wf_of(l), accB, actB, wv, lane);
+      mlp_phase<NJ, true, KH, true, KH>(accA, bt, actA, wf_of(l), accB, actB, wv, lane, pre, wf_of(l));
     }
     __syncthreads();
     {
       f32x16 bt[NJ];
       bias_tr(l, bt);
-      mlp_phase<NJ, true, KH, true>(accB, bt, actB, wf_of(l), accA, actA, wv, lane);
+      mlp_phase<NJ, true, KH, true, KH>(accB, bt, actB, wf_of(l), accA, actA, wv, lane, pre, wf_of(l + 1));
     }
     __syncthreads();
   }
   {
     f32x16 bt[NJ];
     bias_out(bt);
-    mlp_phase<NJ, false, KH, true>(accA, bt, actA, wf_of(nl - 1), accB, actB, wv, lane);
+    mlp_phase<NJ, false, KH, true, KH>(accA, bt, actA, wf_of(nl - 1), accB, actB, wv, lane, pre, wf_of(nl - 1));
     __syncthreads();
     bias_out(bt);
-    mlp_phase<NJ, false, KH, false>(accB, bt, actB, wf_of(nl - 1), accA, actA, wv, lane);
+    mlp_phase<NJ, false, KH, false, 0>(accB, bt, actB, wf_of(nl - 1), accA, actA, wv, lane, pre, wf_of(nl - 1));
   }
   const bool full = r0 + MR <= a.m;   // uniform: only the last workgroup may be ragged
   auto store = [&](const f32x16 (&acc)[2][NJ], int rb, auto checked) {
