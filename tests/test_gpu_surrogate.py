@@ -87,6 +87,29 @@ def test_fused_inference_full_size_ragged_batch_and_weight_updates(sur):
     s.close()
 
 
+@pytest.mark.parametrize("n_hidden", [1, 2, 7])
+def test_fused_inference_other_depths(sur, n_hidden):
+    """The fused kernel's phase sequence for networks of 1, 2 and 7 hidden
+    layers of width 512 (no hidden-to-hidden layer, one, the most the
+    allocation-free entry takes): 200 rows, a full block of 128 and a
+    ragged one, against the FP64 network.  Each product adds ~2e-3 of BF16
+    rounding; 8 chained products stay well under the bar."""
+    rng = np.random.default_rng(40 + n_hidden)
+    theta = L.mlp_init([7] + [512] * n_hidden + [512], seed=50 + n_hidden)
+    lo, hi, mu, sigma = _scaling(512, rng)
+    s = sur.Surrogate(7, 512, n_hidden, 512, max_batch=200, train_batch=16)
+    s.set_params(theta)
+    s.set_scaling(lo, hi, mu, sigma)
+    X = L.surrogate_params(200, seed=60 + n_hidden)
+    y = s.predict(X).cpu().numpy()
+    yo, _, _ = mlp.forward(theta, mlp.layer_shapes(7, 512, n_hidden, 512), mlp.normalise_inputs(X, lo, hi))
+    e = _rel((y - mu) / sigma, yo)
+    tail = _rel((y[128:] - mu) / sigma, yo[128:])
+    print({"n_hidden": n_hidden, "forward_rel_l2": f"{e:.2e}", "ragged_block": f"{tail:.2e}"}, flush=True)
+    assert e <= 2e-2 and tail <= 2e-2
+    s.close()
+
+
 def _full_case(seed, m):
     rng = np.random.default_rng(seed)
     theta = L.mlp_init([7] + [512] * 4 + [512], seed=seed)
