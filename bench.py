@@ -231,6 +231,7 @@ def run_surrogate(n_check=128, reps=20, batch=65536):
     flop = 2.0 * batch * (nin * w + (nh - 1) * w * w + w * nout)
     achieved = flop * reps / (gms * 1e-3) / 1e12
     s.close()
+    train = [train_rate(tb) for tb in (256, 4096)]
     return {"value": round(batch / (ms * 1e-3), 1), "unit": "waveforms/s", "batch": batch,
             "ms_per_batch": round(ms, 4),
             "held_out": n_check, "pressure_pulse_rel_l2_mean": round(float(dP.mean()), 5),
@@ -240,7 +241,43 @@ def run_surrogate(n_check=128, reps=20, batch=65536):
             "roofline": {"bound": "mfma", "kernel": "k_mlp_fwd (whole network per launch)",
                          "achieved": round(achieved, 1), "peak": 2500.0, "unit": "TFLOP/s",
                          "frac": round(achieved / 2500.0, 4), "launches": n,
-                         "avg_launch_us": round(gms / max(n, 1) * 1e3, 2)}}
+                         "avg_launch_us": round(gms / max(n, 1) * 1e3, 2)},
+            "training": train}
+
+
+def train_rate(tb, steps=50):
+    """Adam training steps of the 7 -> 512 x 4 -> 512 network (forward,
+    backward and update by the library's kernels) on shuffled mini-batches of
+    tb rows drawn from 4096 seeded samples: time per step (HIP events on the
+    context's stream) and the products' algorithmic rate (forward, data
+    gradients of every layer but the first, weight gradients)."""
+    import numpy as np
+    import torch
+    import lbm_inputs as L
+    from paper_2112_05258_amd import surrogate as S
+    s = S.Surrogate(train_batch=tb, max_batch=tb)
+    s.set_params(L.mlp_init([7] + [512] * 4 + [512], seed=3))
+    s.set_scaling(L.SURROGATE_LO, L.SURROGATE_HI, np.zeros(512), np.ones(512))
+    rng = np.random.default_rng(4)
+    xd = s._dev(L.surrogate_params(4096, seed=5))
+    td = s._dev(rng.normal(size=(4096, 512)))
+    idx = s._dev(np.stack([rng.permutation(4096)[:tb] for _ in range(steps + 5)]).astype(np.int32), torch.int32)
+    s.stream.wait_stream(torch.cuda.current_stream(s.device))
+    for k in range(5):
+        s.train_step(xd, td, idx[k], 1e-4)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s.stream)
+    for k in range(steps):
+        s.train_step(xd, td, idx[5 + k], 1e-4)
+    e1.record(s.stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    w, nh, nin, nout = s.cfg.width, s.cfg.n_hidden, s.cfg.n_in, s.cfg.n_out
+    fwd = 2.0 * (nin * w + (nh - 1) * w * w + w * nout)
+    flop = tb * (2 * fwd + 2.0 * ((nh - 1) * w * w + w * nout))
+    s.close()
+    return {"batch": tb, "us_per_step": round(ms * 1e3, 1), "samples_per_s": round(tb / (ms * 1e-3), 1),
+            "tflops": round(flop / (ms * 1e-3) / 1e12, 1)}
 
 
 def full_beat():

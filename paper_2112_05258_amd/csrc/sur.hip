@@ -40,12 +40,14 @@ constexpr int KPAD = 32;     // input width of the first layer is padded to this
 
 enum { EPI_FWD_GELU = 0, EPI_FWD_OUT = 1, EPI_BWD_GELU = 2, EPI_WGRAD = 3 };
 
-// FP32 -> BF16, round to nearest even (NaN kept quiet)
+// FP32 -> BF16, round to nearest even (NaN kept quiet); both results are
+// formed and one selected, so an epilogue of many conversions stays
+// straight-line code
 __device__ __forceinline__ uint16_t f2bf(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
+  const uint32_t u = __float_as_uint(f);
+  const uint32_t rne = (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+  const uint32_t qnan = (u >> 16) | 0x40u;
+  return (uint16_t)((u & 0x7fffffffu) > 0x7f800000u ? qnan : rne);
 }
 
 // Phi(z) = (1 + erf(z / sqrt 2)) / 2, the standard normal CDF, with erf from
@@ -86,25 +88,57 @@ struct GemmArgs {
   int64_t ldo;
   const float* mu;      // EPI_FWD_OUT: output de-standardisation (may be null)
   const float* sigma;
+  int ksplit;           // EPI_WGRAD: depth split over ksplit workgroups (1: none)
+  float* part;          // their partial products, ksplit x M x N
 };
 
-// Stage a 128 x 32 tile (rows r0.., depth k0..) into LDS as S[r][k].
+// out[m ldo + n] = sum over z of part[z][m][n], in z order
+__global__ void k_sum_parts(const float* __restrict__ part, int ksplit, int M, int N, float* __restrict__ out,
+                            int64_t ldo) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)M * N) return;
+  float s = 0.0f;
+#pragma unroll 16
+  for (int z = 0; z < ksplit; ++z) s += part[(int64_t)z * M * N + e];
+  out[(e / N) * ldo + e % N] = s;
+}
+
+// A 128 x 32 tile (rows r0.., depth k0..) in two steps: its 512 16-byte
+// chunks into registers (two per lane), then into LDS as S[r][k].  KC:
+// G[r * ld + k], a chunk is 8 k of one row; otherwise G[k * ld + r], a chunk
+// is 8 rows of one k, transposed on the way into LDS.  Every chunk is loaded
+// from an index clamped into the matrix (ext >= 1 rows, resp. a multiple of
+// 8; K a positive multiple of 8) and the ones outside it are zeroed only
+// when stored, so no load sits in a branch and nothing waits for the loads
+// before the store.
 template <bool KC>
-__device__ __forceinline__ void load_tile(uint16_t* S, const uint16_t* G, int64_t ld, int ext, int r0, int k0,
-                                          int K, int tid) {
-  if (KC) {  // G[r * ld + k]: one 16-byte chunk of 8 k per load
-    for (int c = tid; c < 128 * (BK / 8); c += 256) {
-      const int r = c / (BK / 8), kc = (c % (BK / 8)) * 8;
-      uint4 v = make_uint4(0, 0, 0, 0);
-      if (r0 + r < ext && k0 + kc + 8 <= K) v = *(const uint4*)(G + (int64_t)(r0 + r) * ld + k0 + kc);
-      *(uint4*)(S + r * LDK + kc) = v;
+__device__ __forceinline__ void tile_gload(uint4 (&v)[2], bool (&ok)[2], const uint16_t* G, int64_t ld, int ext,
+                                           int r0, int k0, int K, int tid) {
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int c = tid + 256 * q;
+    if (KC) {
+      const int r = r0 + c / (BK / 8), k = k0 + (c % (BK / 8)) * 8;
+      ok[q] = r < ext && k + 8 <= K;
+      v[q] = *(const uint4*)(G + (int64_t)min(r, ext - 1) * ld + min(k, K - 8));
+    } else {
+      const int k = k0 + c / 16, r = r0 + (c % 16) * 8;
+      ok[q] = k < K && r + 8 <= ext;
+      v[q] = *(const uint4*)(G + (int64_t)min(k, K - 1) * ld + min(r, ext - 8));
     }
-  } else {   // G[k * ld + r]: 8 consecutive r per load, transposed into LDS
-    for (int c = tid; c < BK * 16; c += 256) {
+  }
+}
+template <bool KC>
+__device__ __forceinline__ void tile_sstore(uint16_t* S, const uint4 (&v)[2], const bool (&ok)[2], int tid) {
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int c = tid + 256 * q;
+    const uint4 w = ok[q] ? v[q] : make_uint4(0, 0, 0, 0);
+    if (KC) {
+      *(uint4*)(S + (c / (BK / 8)) * LDK + (c % (BK / 8)) * 8) = w;
+    } else {
       const int k = c / 16, rc = (c % 16) * 8;
-      uint4 v = make_uint4(0, 0, 0, 0);
-      if (k0 + k < K && r0 + rc + 8 <= ext) v = *(const uint4*)(G + (int64_t)(k0 + k) * ld + r0 + rc);
-      const uint16_t* e = (const uint16_t*)&v;
+      const uint16_t* e = (const uint16_t*)&w;
 #pragma unroll
       for (int j = 0; j < 8; ++j) S[(rc + j) * LDK + k] = e[j];
     }
@@ -113,10 +147,16 @@ __device__ __forceinline__ void load_tile(uint16_t* S, const uint16_t* G, int64_
 
 template <bool AKC, bool BKC, int EPI>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
-  __shared__ __attribute__((aligned(16))) uint16_t As[BM * LDK];
-  __shared__ __attribute__((aligned(16))) uint16_t Bs[BN * LDK];
+  __shared__ __attribute__((aligned(16))) uint16_t As[2][BM * LDK];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[2][BN * LDK];
   const int tid = (int)threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int m0 = (int)blockIdx.y * BM, n0 = (int)blockIdx.x * BN;
+  // split over the depth (weight gradients of a large batch): workgroup z
+  // takes depth kb .. ke and writes its partial product to slice z of
+  // g.part, which k_sum_parts adds up in slice order
+  const int kz = (int)blockIdx.z;
+  const int kc = g.ksplit > 1 ? (g.K + g.ksplit - 1) / g.ksplit / BK * BK + BK : g.K;
+  const int kb = kz * kc, ke = min(g.K, kb + kc);
   const int wm = (wv >> 1) * 64, wn = (wv & 1) * 64;
   f32x16 acc[2][2];
 #pragma unroll
@@ -126,54 +166,104 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
 
-  // operand fragments: lane l supplies row (l % 32) and the 8 k of half (l / 32)
+  // operand fragments: lane l supplies row (l % 32) and the 8 k of half (l / 32).
+  // The next k-step's tiles are fetched into registers while the current one
+  // is multiplied out of LDS, then stored into the other LDS buffer.
   const int fr = lane & 31, fk = (lane >> 5) * 8;
-  for (int k0 = 0; k0 < g.K; k0 += BK) {
-    load_tile<AKC>(As, g.A, g.lda, g.a_ext, m0, k0, g.K, tid);
-    load_tile<BKC>(Bs, g.B, g.ldb, g.b_ext, n0, k0, g.K, tid);
-    __syncthreads();
+  uint4 ra[2], rb[2];
+  bool oa[2], ob[2];
+  if (kb < ke) {
+    tile_gload<AKC>(ra, oa, g.A, g.lda, g.a_ext, m0, kb, ke, tid);
+    tile_gload<BKC>(rb, ob, g.B, g.ldb, g.b_ext, n0, kb, ke, tid);
+    tile_sstore<AKC>(As[0], ra, oa, tid);
+    tile_sstore<BKC>(Bs[0], rb, ob, tid);
+  }
+  __syncthreads();
+  const int nk = kb < ke ? (ke - kb + BK - 1) / BK : 0;
+  for (int st = 0; st < nk; ++st) {
+    const int cur = st & 1;
+    const bool more = st + 1 < nk;
+    if (more) {
+      tile_gload<AKC>(ra, oa, g.A, g.lda, g.a_ext, m0, kb + (st + 1) * BK, ke, tid);
+      tile_gload<BKC>(rb, ob, g.B, g.ldb, g.b_ext, n0, kb + (st + 1) * BK, ke, tid);
+    }
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 16) {
       bf16x8 a[2], b[2];
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
-        a[t] = *(const bf16x8*)(As + (wm + t * 32 + fr) * LDK + kk + fk);
-        b[t] = *(const bf16x8*)(Bs + (wn + t * 32 + fr) * LDK + kk + fk);
+        a[t] = *(const bf16x8*)(As[cur] + (wm + t * 32 + fr) * LDK + kk + fk);
+        b[t] = *(const bf16x8*)(Bs[cur] + (wn + t * 32 + fr) * LDK + kk + fk);
       }
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
     }
+    if (more) {
+      tile_sstore<AKC>(As[cur ^ 1], ra, oa, tid);
+      tile_sstore<BKC>(Bs[cur ^ 1], rb, ob, tid);
+    }
     __syncthreads();
   }
 
   // accumulator v of lane l holds row 8 (v / 4) + 4 (l / 32) + v % 4 and
-  // column l % 32 of its 32 x 32 tile
+  // column l % 32 of its 32 x 32 tile.  The epilogue's operand loads (bias,
+  // pre-activations) are all issued before the first is used, at indices
+  // clamped into the matrix, so they do not wait on each other one by one
+  // behind the per-element bounds test.
+  auto row_of = [&](int i, int v) { return m0 + wm + i * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3); };
+  auto col_of = [&](int j) { return n0 + wn + j * 32 + (lane & 31); };
+  float zb[2][2][16];
+  if (EPI == EPI_BWD_GELU) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int v = 0; v < 16; ++v)
+          zb[i][j][v] = g.zin[(int64_t)min(row_of(i, v), g.M - 1) * g.ldo + min(col_of(j), g.N - 1)];
+  }
+  float bj[2] = {0.0f, 0.0f};
+  if (EPI == EPI_FWD_GELU || EPI == EPI_FWD_OUT) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) bj[j] = g.bias[min(col_of(j), g.N - 1)];
+  }
+  // a tile inside the matrix stores without per-element tests (straight-line
+  // code: no waits for earlier stores between the elements)
+  const bool full = m0 + BM <= g.M && n0 + BN <= g.N;
+  auto epi = [&](auto checked) {
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
-        const int m = m0 + wm + i * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
-        const int n = n0 + wn + j * 32 + (lane & 31);
-        if (m >= g.M || n >= g.N) continue;
+        const int m = row_of(i, v);
+        const int n = col_of(j);
+        if (decltype(checked)::value && (m >= g.M || n >= g.N)) continue;
         const float s = acc[i][j][v];
         const int64_t o = (int64_t)m * g.ldo + n;
         if (EPI == EPI_FWD_GELU) {
-          const float z = s + g.bias[n];
+          const float z = s + bj[j];
           if (g.zout) g.zout[o] = z;
           g.outh[o] = f2bf(gelu(z));
         } else if (EPI == EPI_FWD_OUT) {
-          const float y = s + g.bias[n];
+          const float y = s + bj[j];
           g.outf[o] = g.mu ? g.mu[n] + g.sigma[n] * y : y;
         } else if (EPI == EPI_BWD_GELU) {
-          g.outh[o] = f2bf(s * gelu_grad(g.zin[o]));
+          g.outh[o] = f2bf(s * gelu_grad(zb[i][j][v]));
+        } else if (g.ksplit > 1) {
+          g.part[((int64_t)kz * g.M + m) * g.N + n] = s;
         } else {
           g.outf[o] = s;
         }
       }
+  };
+  if (full)
+    epi(std::false_type{});
+  else
+    epi(std::true_type{});
 }
 
 // Forward product C = A B^T with both operands k-contiguous (activations h and
@@ -251,6 +341,22 @@ __global__ __launch_bounds__(256, 2) void k_gemm_fwd(GemmArgs g) {
     if (more) sstore(cur ^ 1);
     __syncthreads();
   }
+  // per-column operands loaded once, before the element loop (clamped
+  // indices; out-of-range elements are not stored)
+  float bj[4], mj[4], sj[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int n = min(n0 + wn + j * 32 + (lane & 31), g.N - 1);
+    bj[j] = g.bias[n];
+    mj[j] = EPI == EPI_FWD_OUT && g.mu ? g.mu[n] : 0.0f;
+    sj[j] = EPI == EPI_FWD_OUT && g.mu ? g.sigma[n] : 1.0f;
+  }
+  // a tile inside the matrix stores without per-element tests, and the
+  // optional output (pre-activations, resp. de-standardisation) is chosen
+  // once: straight-line code, no waits for earlier stores between elements
+  const bool full = m0 + FBM <= g.M && n0 + FBN <= g.N;
+  const bool opt = EPI == EPI_FWD_GELU ? g.zout != nullptr : g.mu != nullptr;
+  auto epi = [&](auto checked, auto with) {
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -259,16 +365,25 @@ __global__ __launch_bounds__(256, 2) void k_gemm_fwd(GemmArgs g) {
       for (int v = 0; v < 16; ++v) {
         const int m = m0 + wm + i * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
         const int n = n0 + wn + j * 32 + (lane & 31);
-        if (m >= g.M || n >= g.N) continue;
-        const float s = acc[i][j][v] + g.bias[n];
+        if (decltype(checked)::value && (m >= g.M || n >= g.N)) continue;
+        const float s = acc[i][j][v] + bj[j];
         const int64_t o = (int64_t)m * g.ldo + n;
         if (EPI == EPI_FWD_GELU) {
-          if (g.zout) g.zout[o] = s;
+          if (decltype(with)::value) g.zout[o] = s;
           g.outh[o] = f2bf(gelu(s));
         } else {
-          g.outf[o] = g.mu ? g.mu[n] + g.sigma[n] * s : s;
+          g.outf[o] = decltype(with)::value ? mj[j] + sj[j] * s : s;
         }
       }
+  };
+  if (full && opt)
+    epi(std::false_type{}, std::true_type{});
+  else if (full)
+    epi(std::false_type{}, std::false_type{});
+  else if (opt)
+    epi(std::true_type{}, std::true_type{});
+  else
+    epi(std::true_type{}, std::false_type{});
 }
 
 // inputs: X0[r][j] = 2 (x - lo) / (hi - lo) - 1 for r < m and j < n_in; 0 for
@@ -305,12 +420,13 @@ __global__ void k_prep_t(const float* __restrict__ t, int nrows, const int32_t* 
 __global__ __launch_bounds__(256) void k_loss(const float* __restrict__ y, const float* __restrict__ tn, int64_t n,
                                               uint16_t* __restrict__ dy, double* __restrict__ loss) {
   __shared__ double part[256];
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  // grid-stride over the elements: a capped grid keeps the atomics on the
+  // one loss word few
   double s = 0.0;
-  if (e < n) {
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
     const float d = y[e] - tn[e];
     dy[e] = f2bf(2.0f * d / (float)n);
-    s = (double)d * (double)d;
+    s += (double)d * (double)d;
   }
   part[threadIdx.x] = s;
   __syncthreads();
@@ -321,12 +437,33 @@ __global__ __launch_bounds__(256) void k_loss(const float* __restrict__ y, const
   if (threadIdx.x == 0) atomicAdd(loss, part[0] / (double)n);
 }
 
-// db[j] = sum_r dz[r][j]
-__global__ void k_colsum(const uint16_t* __restrict__ dz, int m, int n, float* __restrict__ db) {
+// Bias gradients db[j] = sum_r dz[r][j] in two deterministic passes: the
+// rows in chunks of CROWS, one workgroup row per chunk (so a large batch
+// spreads over many workgroups instead of one column-thread walking every
+// row), then the chunks' partial sums added in chunk order.
+constexpr int CROWS = 64;
+__global__ void k_colsum_part(const uint16_t* __restrict__ dz, int m, int n, float* __restrict__ part) {
+  const int j = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (j >= n) return;
+  const int r0 = (int)blockIdx.y * CROWS, r1 = min(m, r0 + CROWS);
+  float s = 0.0f;
+  if (r1 - r0 == CROWS) {   // a whole chunk: all its loads in flight at once
+    uint16_t v[CROWS];
+#pragma unroll
+    for (int r = 0; r < CROWS; ++r) v[r] = dz[(int64_t)(r0 + r) * n + j];
+#pragma unroll
+    for (int r = 0; r < CROWS; ++r) s += __uint_as_float((uint32_t)v[r] << 16);
+  } else {
+    for (int r = r0; r < r1; ++r) s += __uint_as_float((uint32_t)dz[(int64_t)r * n + j] << 16);
+  }
+  part[(int64_t)blockIdx.y * n + j] = s;
+}
+__global__ void k_colsum_fin(const float* __restrict__ part, int nchunk, int n, float* __restrict__ db) {
   const int j = (int)(blockIdx.x * blockDim.x + threadIdx.x);
   if (j >= n) return;
   float s = 0.0f;
-  for (int r = 0; r < m; ++r) s += __uint_as_float((uint32_t)dz[(int64_t)r * n + j] << 16);
+#pragma unroll 16
+  for (int q = 0; q < nchunk; ++q) s += part[(int64_t)q * n + j];
   db[j] = s;
 }
 
@@ -710,6 +847,8 @@ struct lbm_sur_ctx {
   int64_t np, nwb;
   // device regions
   float *w, *m1, *m2, *g, *lo, *hi, *mu, *sigma, *Y, *Tn;
+  float* cpart;         // partial column sums of the bias gradients
+  float* wpart;         // partial weight gradients of a depth-split product
   uint16_t *wb, *wf, *X0, *dz[2];
   int64_t wgen, fgen;   // weight updates so far; the update wf was last built from
   uint16_t* H[8];
@@ -769,8 +908,12 @@ LayerMap layer_map(const lbm_sur_config& c, int64_t& np, int64_t& nwb) {
 }
 
 struct Plan {
-  size_t w, m1, m2, g, wb, wf, lo, hi, mu, sigma, X0, H[8], Z[8], Y, Tn, dz[2], loss, errw, total;
+  size_t w, m1, m2, g, wb, wf, lo, hi, mu, sigma, X0, H[8], Z[8], Y, Tn, dz[2], cpart, wpart, loss, errw, total;
 };
+
+// depth split of a weight-gradient product over the batch rows: one slice
+// per 256 rows, at most 16 (a product of 512 x 512 outputs has only 16 tiles)
+int wgrad_split(int K) { return std::min(16, std::max(1, K / 256)); }
 
 size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -806,6 +949,12 @@ Plan plan(const lbm_sur_config& c) {
   const size_t wmax = (size_t)(c.width > c.n_out ? c.width : c.n_out);
   p.dz[0] = take(rows_tr * wmax * 2);
   p.dz[1] = take(rows_tr * wmax * 2);
+  p.cpart = take((rows_tr + CROWS - 1) / CROWS * wmax * 4);
+  {
+    const int s = wgrad_split((int)((rows_tr + 7) / 8 * 8));
+    const size_t win = (size_t)(c.width > KPAD ? c.width : KPAD);
+    p.wpart = take(s > 1 ? (size_t)s * wmax * win * 4 : 4);
+  }
   p.loss = take(8);
   p.errw = take(4);
   p.total = o;
@@ -826,8 +975,15 @@ lbm_status gemm(lbm_sur_ctx* c, const GemmArgs& a) {
     dim3 grid((a.N + FBN - 1) / FBN, (a.M + FBM - 1) / FBM);
     hipLaunchKernelGGL((k_gemm_fwd<EPI>), grid, dim3(256), 0, c->stream, a);
   } else {
-    dim3 grid((a.N + BN - 1) / BN, (a.M + BM - 1) / BM);
-    hipLaunchKernelGGL((k_gemm<AKC, BKC, EPI>), grid, dim3(256), 0, c->stream, a);
+    GemmArgs b = a;
+    b.ksplit = EPI == EPI_WGRAD ? wgrad_split(a.K) : 1;
+    b.part = c->wpart;
+    dim3 grid((a.N + BN - 1) / BN, (a.M + BM - 1) / BM, b.ksplit);
+    hipLaunchKernelGGL((k_gemm<AKC, BKC, EPI>), grid, dim3(256), 0, c->stream, b);
+    SURCHK(c, hipGetLastError());
+    if (b.ksplit > 1)
+      hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)(((int64_t)a.M * a.N + 255) / 256)), dim3(256), 0, c->stream, c->wpart,
+                         b.ksplit, a.M, a.N, a.outf, a.ldo);
   }
   SURCHK(c, hipGetLastError());
   if (t) {
@@ -901,7 +1057,7 @@ lbm_status grad_pass(lbm_sur_ctx* c, const float* x, const float* t, int nrows, 
   SURCHK(c, hipGetLastError());
   TRY(forward(c, m, true, nullptr));
   SURCHK(c, hipMemsetAsync(c->loss, 0, 8, c->stream));
-  hipLaunchKernelGGL(k_loss, dim3(blocks((int64_t)m * C.n_out, 256)), dim3(256), 0, c->stream, c->Y, c->Tn,
+  hipLaunchKernelGGL(k_loss, dim3(std::min(blocks((int64_t)m * C.n_out, 256), 512u)), dim3(256), 0, c->stream, c->Y, c->Tn,
                      (int64_t)m * C.n_out, c->dz[0], c->loss);
   SURCHK(c, hipGetLastError());
   int cur = 0;
@@ -917,7 +1073,11 @@ lbm_status grad_pass(lbm_sur_ctx* c, const float* x, const float* t, int nrows, 
     a.M = nout; a.N = nin; a.K = mp;
     a.outf = c->g + c->L.off[l]; a.ldo = nin;
     TRY((gemm<false, false, EPI_WGRAD>(c, a)));
-    hipLaunchKernelGGL(k_colsum, dim3(blocks(nout, 256)), dim3(256), 0, c->stream, c->dz[cur], m, nout,
+    const int nchunk = (m + CROWS - 1) / CROWS;
+    hipLaunchKernelGGL(k_colsum_part, dim3(blocks(nout, 256), nchunk), dim3(256), 0, c->stream, c->dz[cur], m, nout,
+                       c->cpart);
+    SURCHK(c, hipGetLastError());
+    hipLaunchKernelGGL(k_colsum_fin, dim3(blocks(nout, 256)), dim3(256), 0, c->stream, c->cpart, nchunk, nout,
                        c->g + c->L.off[l] + (int64_t)nout * nin);
     SURCHK(c, hipGetLastError());
     if (l == 0) break;
@@ -1026,6 +1186,8 @@ lbm_status lbm_sur_init(const lbm_sur_config* cfg, void* mem, size_t bytes, void
   }
   c->Y = (float*)(b + p.Y); c->Tn = (float*)(b + p.Tn);
   c->dz[0] = (uint16_t*)(b + p.dz[0]); c->dz[1] = (uint16_t*)(b + p.dz[1]);
+  c->cpart = (float*)(b + p.cpart);
+  c->wpart = (float*)(b + p.wpart);
   c->loss = (double*)(b + p.loss);
   c->errw = (int*)(b + p.errw);
   c->step = 0;
