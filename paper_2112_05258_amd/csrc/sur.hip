@@ -33,9 +33,13 @@ namespace sur {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-// block tile BM x BN, k-step BK; 4 waves, each 64 x 64 = 2 x 2 MFMA tiles
-constexpr int BM = 128, BN = 128, BK = 32;
-constexpr int LDK = BK + 8;  // LDS row pitch in bf16 (80 B: 16-B aligned, staggers banks)
+// block tile BM x BN, k-step BK; 4 waves, each 64 x 64 = 2 x 2 MFMA tiles.
+// The training products are small (a few hundred rows) and their k-loops
+// wait on memory once per k-step, so the k-step is deep: 64.
+constexpr int BM = 128, BN = 128, BK = 64;
+constexpr int LDK = BK + 8;  // LDS row pitch in bf16 (144 B: 16-B aligned, rows 36 banks apart)
+constexpr int TQ = BK / 16;  // 16-byte chunks per lane of a 128 x BK tile
+static_assert(BK % 32 == 0, "transposed tiles are stored as pairs of k");
 constexpr int KPAD = 32;     // input width of the first layer is padded to this
 
 enum { EPI_FWD_GELU = 0, EPI_FWD_OUT = 1, EPI_BWD_GELU = 2, EPI_WGRAD = 3 };
@@ -103,44 +107,54 @@ __global__ void k_sum_parts(const float* __restrict__ part, int ksplit, int M, i
   out[(e / N) * ldo + e % N] = s;
 }
 
-// A 128 x 32 tile (rows r0.., depth k0..) in two steps: its 512 16-byte
-// chunks into registers (two per lane), then into LDS as S[r][k].  KC:
+// A 128 x BK tile (rows r0.., depth k0..) in two steps: its 16 BK 16-byte
+// chunks into registers (TQ per lane), then into LDS as S[r][k].  KC:
 // G[r * ld + k], a chunk is 8 k of one row; otherwise G[k * ld + r], a chunk
-// is 8 rows of one k, transposed on the way into LDS.  Every chunk is loaded
+// is 8 rows of one k, transposed on the way into LDS: a lane takes the chunks
+// of two adjacent k (2p, 2p + 1) over the same 8 rows and writes each row's
+// pair as one 4-byte word, the 32 pairs of a wave's half side by side (rows
+// 8 apart fall 32 banks apart: no bank conflicts).  Every chunk is loaded
 // from an index clamped into the matrix (ext >= 1 rows, resp. a multiple of
 // 8; K a positive multiple of 8) and the ones outside it are zeroed only
 // when stored, so no load sits in a branch and nothing waits for the loads
 // before the store.
 template <bool KC>
-__device__ __forceinline__ void tile_gload(uint4 (&v)[2], bool (&ok)[2], const uint16_t* G, int64_t ld, int ext,
+__device__ __forceinline__ void tile_gload(uint4 (&v)[TQ], bool (&ok)[TQ], const uint16_t* G, int64_t ld, int ext,
                                            int r0, int k0, int K, int tid) {
 #pragma unroll
-  for (int q = 0; q < 2; ++q) {
+  for (int q = 0; q < TQ; ++q) {
     const int c = tid + 256 * q;
     if (KC) {
       const int r = r0 + c / (BK / 8), k = k0 + (c % (BK / 8)) * 8;
       ok[q] = r < ext && k + 8 <= K;
       v[q] = *(const uint4*)(G + (int64_t)min(r, ext - 1) * ld + min(k, K - 8));
     } else {
-      const int k = k0 + c / 16, r = r0 + (c % 16) * 8;
+      const int u = tid + 256 * (q >> 1);          // pair unit: k pair u % (BK / 2), 8 rows u / (BK / 2)
+      const int k = k0 + 2 * (u % (BK / 2)) + (q & 1), r = r0 + (u / (BK / 2)) * 8;
       ok[q] = k < K && r + 8 <= ext;
       v[q] = *(const uint4*)(G + (int64_t)min(k, K - 1) * ld + min(r, ext - 8));
     }
   }
 }
 template <bool KC>
-__device__ __forceinline__ void tile_sstore(uint16_t* S, const uint4 (&v)[2], const bool (&ok)[2], int tid) {
+__device__ __forceinline__ void tile_sstore(uint16_t* S, const uint4 (&v)[TQ], const bool (&ok)[TQ], int tid) {
+  if (KC) {
 #pragma unroll
-  for (int q = 0; q < 2; ++q) {
-    const int c = tid + 256 * q;
-    const uint4 w = ok[q] ? v[q] : make_uint4(0, 0, 0, 0);
-    if (KC) {
-      *(uint4*)(S + (c / (BK / 8)) * LDK + (c % (BK / 8)) * 8) = w;
-    } else {
-      const int k = c / 16, rc = (c % 16) * 8;
-      const uint16_t* e = (const uint16_t*)&w;
+    for (int q = 0; q < TQ; ++q) {
+      const int c = tid + 256 * q;
+      *(uint4*)(S + (c / (BK / 8)) * LDK + (c % (BK / 8)) * 8) = ok[q] ? v[q] : make_uint4(0, 0, 0, 0);
+    }
+  } else {
 #pragma unroll
-      for (int j = 0; j < 8; ++j) S[(rc + j) * LDK + k] = e[j];
+    for (int q = 0; q < TQ; q += 2) {
+      const int u = tid + 256 * (q >> 1);
+      const int p = u % (BK / 2), rc = (u / (BK / 2)) * 8;
+      const uint4 w0 = ok[q] ? v[q] : make_uint4(0, 0, 0, 0), w1 = ok[q + 1] ? v[q + 1] : make_uint4(0, 0, 0, 0);
+      const uint16_t* e0 = (const uint16_t*)&w0;
+      const uint16_t* e1 = (const uint16_t*)&w1;
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        *(uint32_t*)(S + (rc + j) * LDK + 2 * p) = (uint32_t)e0[j] | ((uint32_t)e1[j] << 16);
     }
   }
 }
@@ -170,8 +184,8 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
   // The next k-step's tiles are fetched into registers while the current one
   // is multiplied out of LDS, then stored into the other LDS buffer.
   const int fr = lane & 31, fk = (lane >> 5) * 8;
-  uint4 ra[2], rb[2];
-  bool oa[2], ob[2];
+  uint4 ra[TQ], rb[TQ];
+  bool oa[TQ], ob[TQ];
   if (kb < ke) {
     tile_gload<AKC>(ra, oa, g.A, g.lda, g.a_ext, m0, kb, ke, tid);
     tile_gload<BKC>(rb, ob, g.B, g.ldb, g.b_ext, n0, kb, ke, tid);
@@ -269,13 +283,13 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
 // Forward product C = A B^T with both operands k-contiguous (activations h and
 // weights W): training's forward pass, and inference for other shapes.  Block tile 128 x 256, each of the 4
 // waves 64 x 128 (2 x 4 MFMA tiles: 6 fragment reads from LDS per 8 MFMAs),
-// k-step 32.  The next k-step's tiles are fetched into registers while the
+// k-step BK.  The next k-step's tiles are fetched into registers while the
 // current one is multiplied out of LDS, and stored into the other half of a
 // double-buffered LDS after it: one barrier per k-step.
 constexpr int FBM = 128, FBN = 256;
 
 template <int EPI>
-__global__ __launch_bounds__(256, 2) void k_gemm_fwd(GemmArgs g) {
+__global__ __launch_bounds__(256) void k_gemm_fwd(GemmArgs g) {
   __shared__ __attribute__((aligned(16))) uint16_t As[2][FBM * LDK];
   __shared__ __attribute__((aligned(16))) uint16_t Bs[2][FBN * LDK];
   const int tid = (int)threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -288,33 +302,37 @@ __global__ __launch_bounds__(256, 2) void k_gemm_fwd(GemmArgs g) {
     for (int j = 0; j < 4; ++j)
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
-  // 16-byte chunks of 8 k: A tile 128 x 32 = 512 chunks (2 per lane), B tile
-  // 256 x 32 = 1024 chunks (4 per lane); out-of-range chunks are zero
-  uint4 ra[2], rb[4];
+  // 16-byte chunks of 8 k: A tile 128 x BK = 16 BK chunks (TQ per lane), B
+  // tile 256 x BK (2 TQ per lane); out-of-range chunks are zero
+  // (loads from indices clamped into the matrices, zeroed when stored: no
+  // load in a branch, no wait before the store)
+  constexpr int CR = BK / 8;   // chunks per row
+  uint4 ra[TQ], rb[2 * TQ];
+  bool oa[TQ], ob[2 * TQ];
   auto gload = [&](int k0) {
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int c = tid + 256 * q, r = c >> 2, kc = (c & 3) * 8;
-      ra[q] = make_uint4(0, 0, 0, 0);
-      if (m0 + r < g.a_ext && k0 + kc + 8 <= g.K) ra[q] = *(const uint4*)(g.A + (int64_t)(m0 + r) * g.lda + k0 + kc);
+    for (int q = 0; q < TQ; ++q) {
+      const int c = tid + 256 * q, r = m0 + c / CR, k = k0 + (c % CR) * 8;
+      oa[q] = r < g.a_ext && k + 8 <= g.K;
+      ra[q] = *(const uint4*)(g.A + (int64_t)min(r, g.a_ext - 1) * g.lda + min(k, g.K - 8));
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int c = tid + 256 * q, r = c >> 2, kc = (c & 3) * 8;
-      rb[q] = make_uint4(0, 0, 0, 0);
-      if (n0 + r < g.b_ext && k0 + kc + 8 <= g.K) rb[q] = *(const uint4*)(g.B + (int64_t)(n0 + r) * g.ldb + k0 + kc);
+    for (int q = 0; q < 2 * TQ; ++q) {
+      const int c = tid + 256 * q, r = n0 + c / CR, k = k0 + (c % CR) * 8;
+      ob[q] = r < g.b_ext && k + 8 <= g.K;
+      rb[q] = *(const uint4*)(g.B + (int64_t)min(r, g.b_ext - 1) * g.ldb + min(k, g.K - 8));
     }
   };
   auto sstore = [&](int buf) {
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
+    for (int q = 0; q < TQ; ++q) {
       const int c = tid + 256 * q;
-      *(uint4*)(As[buf] + (c >> 2) * LDK + (c & 3) * 8) = ra[q];
+      *(uint4*)(As[buf] + (c / CR) * LDK + (c % CR) * 8) = oa[q] ? ra[q] : make_uint4(0, 0, 0, 0);
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < 2 * TQ; ++q) {
       const int c = tid + 256 * q;
-      *(uint4*)(Bs[buf] + (c >> 2) * LDK + (c & 3) * 8) = rb[q];
+      *(uint4*)(Bs[buf] + (c / CR) * LDK + (c % CR) * 8) = ob[q] ? rb[q] : make_uint4(0, 0, 0, 0);
     }
   };
   const int fr = lane & 31, fk = (lane >> 5) * 8;
