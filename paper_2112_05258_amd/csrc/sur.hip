@@ -238,15 +238,25 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
         for (int v = 0; v < 16; ++v)
           zb[i][j][v] = g.zin[(int64_t)min(row_of(i, v), g.M - 1) * g.ldo + min(col_of(j), g.N - 1)];
   }
-  float bj[2] = {0.0f, 0.0f};
+  float bj[2] = {0.0f, 0.0f}, mj[2] = {0.0f, 0.0f}, sj[2] = {1.0f, 1.0f};
   if (EPI == EPI_FWD_GELU || EPI == EPI_FWD_OUT) {
 #pragma unroll
-    for (int j = 0; j < 2; ++j) bj[j] = g.bias[min(col_of(j), g.N - 1)];
+    for (int j = 0; j < 2; ++j) {
+      const int n = min(col_of(j), g.N - 1);
+      bj[j] = g.bias[n];
+      if (EPI == EPI_FWD_OUT && g.mu) {
+        mj[j] = g.mu[n];
+        sj[j] = g.sigma[n];
+      }
+    }
   }
   // a tile inside the matrix stores without per-element tests (straight-line
   // code: no waits for earlier stores between the elements)
+  // the optional output (pre-activations, de-standardisation, the split's
+  // partial slice) is chosen once, outside the element loop
   const bool full = m0 + BM <= g.M && n0 + BN <= g.N;
-  auto epi = [&](auto checked) {
+  const bool opt = EPI == EPI_FWD_GELU ? g.zout != nullptr : EPI == EPI_FWD_OUT ? g.mu != nullptr : g.ksplit > 1;
+  auto epi = [&](auto checked, auto with) {
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -260,24 +270,28 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
         const int64_t o = (int64_t)m * g.ldo + n;
         if (EPI == EPI_FWD_GELU) {
           const float z = s + bj[j];
-          if (g.zout) g.zout[o] = z;
+          if (decltype(with)::value) g.zout[o] = z;
           g.outh[o] = f2bf(gelu(z));
         } else if (EPI == EPI_FWD_OUT) {
           const float y = s + bj[j];
-          g.outf[o] = g.mu ? g.mu[n] + g.sigma[n] * y : y;
+          g.outf[o] = decltype(with)::value ? mj[j] + sj[j] * y : y;
         } else if (EPI == EPI_BWD_GELU) {
           g.outh[o] = f2bf(s * gelu_grad(zb[i][j][v]));
-        } else if (g.ksplit > 1) {
+        } else if (decltype(with)::value) {
           g.part[((int64_t)kz * g.M + m) * g.N + n] = s;
         } else {
           g.outf[o] = s;
         }
       }
   };
-  if (full)
-    epi(std::false_type{});
+  if (full && opt)
+    epi(std::false_type{}, std::true_type{});
+  else if (full)
+    epi(std::false_type{}, std::false_type{});
+  else if (opt)
+    epi(std::true_type{}, std::true_type{});
   else
-    epi(std::true_type{});
+    epi(std::true_type{}, std::false_type{});
 }
 
 // Forward product C = A B^T with both operands k-contiguous (activations h and
@@ -287,6 +301,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
 // current one is multiplied out of LDS, and stored into the other half of a
 // double-buffered LDS after it: one barrier per k-step.
 constexpr int FBM = 128, FBN = 256;
+constexpr int FWD_SMALL_M = 1024;   // at most this many rows: the 128 x 128 kernel
 
 template <int EPI>
 __global__ __launch_bounds__(256) void k_gemm_fwd(GemmArgs g) {
@@ -989,9 +1004,16 @@ lbm_status gemm(lbm_sur_ctx* c, const GemmArgs& a) {
     return fail(c, LBM_E_INVAL, "matrix product shape or alignment not supported");
   const bool t = c->timing && c->nev + 2 <= (int)c->ev.size();
   if (t) SURCHK(c, hipEventRecord(c->ev[c->nev], c->stream));
-  if constexpr (AKC && BKC && (EPI == EPI_FWD_GELU || EPI == EPI_FWD_OUT)) {
-    dim3 grid((a.N + FBN - 1) / FBN, (a.M + FBM - 1) / FBM);
-    hipLaunchKernelGGL((k_gemm_fwd<EPI>), grid, dim3(256), 0, c->stream, a);
+  // forward products of few rows take the 128 x 128 tiles: twice the
+  // workgroups, half the epilogue each (a latency-bound chain either way)
+  constexpr bool fwd_form = AKC && BKC && (EPI == EPI_FWD_GELU || EPI == EPI_FWD_OUT);
+  bool use_fwd = false;
+  if constexpr (fwd_form) use_fwd = a.M > FWD_SMALL_M;
+  if (use_fwd) {
+    if constexpr (fwd_form) {
+      dim3 grid((a.N + FBN - 1) / FBN, (a.M + FBM - 1) / FBM);
+      hipLaunchKernelGGL((k_gemm_fwd<EPI>), grid, dim3(256), 0, c->stream, a);
+    }
   } else {
     GemmArgs b = a;
     b.ksplit = EPI == EPI_WGRAD ? wgrad_split(a.K) : 1;
