@@ -301,7 +301,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
 // current one is multiplied out of LDS, and stored into the other half of a
 // double-buffered LDS after it: one barrier per k-step.
 constexpr int FBM = 128, FBN = 256;
-constexpr int FWD_SMALL_M = 1024;   // at most this many rows: the 128 x 128 kernel
+constexpr int FWD_SMALL_M = 8192;   // at most this many rows: the 128 x 128 kernel
 
 template <int EPI>
 __global__ __launch_bounds__(256) void k_gemm_fwd(GemmArgs g) {
