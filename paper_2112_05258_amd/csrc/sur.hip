@@ -96,6 +96,19 @@ struct GemmArgs {
   float* part;          // their partial products, ksplit x M x N
 };
 
+// the backward data product of a depth split: the slices added in order,
+// then the GELU derivative, BF16 out (as the product's own epilogue does)
+__global__ void k_sum_parts_bwd(const float* __restrict__ part, int ksplit, int M, int N,
+                                const float* __restrict__ zin, uint16_t* __restrict__ outh, int64_t ldo) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)M * N) return;
+  float s = 0.0f;
+#pragma unroll 4
+  for (int z = 0; z < ksplit; ++z) s += part[(int64_t)z * M * N + e];
+  const int64_t o = (e / N) * ldo + e % N;
+  outh[o] = f2bf(s * gelu_grad(zin[o]));
+}
+
 // out[m ldo + n] = sum over z of part[z][m][n], in z order
 __global__ void k_sum_parts(const float* __restrict__ part, int ksplit, int M, int N, float* __restrict__ out,
                             int64_t ldo) {
@@ -165,11 +178,12 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
   __shared__ __attribute__((aligned(16))) uint16_t Bs[2][BN * LDK];
   const int tid = (int)threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int m0 = (int)blockIdx.y * BM, n0 = (int)blockIdx.x * BN;
-  // split over the depth (weight gradients of a large batch): workgroup z
-  // takes depth kb .. ke and writes its partial product to slice z of
-  // g.part, which k_sum_parts adds up in slice order
+  // split over the depth (weight gradients of a large batch, backward data
+  // products of few rows): workgroup z takes depth kb .. ke and writes its
+  // partial product to slice z of g.part, which k_sum_parts (resp.
+  // k_sum_parts_bwd, with the GELU derivative) adds up in slice order
   const int kz = (int)blockIdx.z;
-  const int kc = g.ksplit > 1 ? (g.K + g.ksplit - 1) / g.ksplit / BK * BK + BK : g.K;
+  const int kc = g.ksplit > 1 ? ((g.K + g.ksplit - 1) / g.ksplit + BK - 1) / BK * BK : g.K;
   const int kb = kz * kc, ke = min(g.K, kb + kc);
   const int wm = (wv >> 1) * 64, wn = (wv & 1) * 64;
   f32x16 acc[2][2];
@@ -229,7 +243,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
   auto row_of = [&](int i, int v) { return m0 + wm + i * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3); };
   auto col_of = [&](int j) { return n0 + wn + j * 32 + (lane & 31); };
   float zb[2][2][16];
-  if (EPI == EPI_BWD_GELU) {
+  if (EPI == EPI_BWD_GELU && g.ksplit <= 1) {
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -276,7 +290,10 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
           const float y = s + bj[j];
           g.outf[o] = decltype(with)::value ? mj[j] + sj[j] * y : y;
         } else if (EPI == EPI_BWD_GELU) {
-          g.outh[o] = f2bf(s * gelu_grad(zb[i][j][v]));
+          if (decltype(with)::value)
+            g.part[((int64_t)kz * g.M + m) * g.N + n] = s;
+          else
+            g.outh[o] = f2bf(s * gelu_grad(zb[i][j][v]));
         } else if (decltype(with)::value) {
           g.part[((int64_t)kz * g.M + m) * g.N + n] = s;
         } else {
@@ -947,6 +964,10 @@ struct Plan {
 // depth split of a weight-gradient product over the batch rows: one slice
 // per 256 rows, at most 16 (a product of 512 x 512 outputs has only 16 tiles)
 int wgrad_split(int K) { return std::min(16, std::max(1, K / 256)); }
+// depth split of a backward data product (depth 512) of few rows, whose few
+// workgroups would each walk all 8 k-steps
+constexpr int BWD_SPLIT = 4, BWD_SPLIT_ROWS = 1024;
+int bwd_split(int M) { return M <= BWD_SPLIT_ROWS ? BWD_SPLIT : 1; }
 
 size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -984,9 +1005,13 @@ Plan plan(const lbm_sur_config& c) {
   p.dz[1] = take(rows_tr * wmax * 2);
   p.cpart = take((rows_tr + CROWS - 1) / CROWS * wmax * 4);
   {
+    // partial products of a depth split: weight gradients (nout x nin) or
+    // backward data products (rows x width)
     const int s = wgrad_split((int)((rows_tr + 7) / 8 * 8));
     const size_t win = (size_t)(c.width > KPAD ? c.width : KPAD);
-    p.wpart = take(s > 1 ? (size_t)s * wmax * win * 4 : 4);
+    const size_t wg = s > 1 ? (size_t)s * wmax * win : 0;
+    const size_t bw = (size_t)BWD_SPLIT * std::min(rows_tr, (size_t)BWD_SPLIT_ROWS) * (size_t)c.width;
+    p.wpart = take((wg > bw ? wg : bw) * 4);
   }
   p.loss = take(8);
   p.errw = take(4);
@@ -1016,14 +1041,17 @@ lbm_status gemm(lbm_sur_ctx* c, const GemmArgs& a) {
     }
   } else {
     GemmArgs b = a;
-    b.ksplit = EPI == EPI_WGRAD ? wgrad_split(a.K) : 1;
+    b.ksplit = EPI == EPI_WGRAD ? wgrad_split(a.K) : EPI == EPI_BWD_GELU ? bwd_split(a.M) : 1;
     b.part = c->wpart;
     dim3 grid((a.N + BN - 1) / BN, (a.M + BM - 1) / BM, b.ksplit);
     hipLaunchKernelGGL((k_gemm<AKC, BKC, EPI>), grid, dim3(256), 0, c->stream, b);
     SURCHK(c, hipGetLastError());
-    if (b.ksplit > 1)
-      hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)(((int64_t)a.M * a.N + 255) / 256)), dim3(256), 0, c->stream, c->wpart,
-                         b.ksplit, a.M, a.N, a.outf, a.ldo);
+    const dim3 eg((unsigned)(((int64_t)a.M * a.N + 255) / 256));
+    if (b.ksplit > 1 && EPI == EPI_WGRAD)
+      hipLaunchKernelGGL(k_sum_parts, eg, dim3(256), 0, c->stream, c->wpart, b.ksplit, a.M, a.N, a.outf, a.ldo);
+    if (b.ksplit > 1 && EPI == EPI_BWD_GELU)
+      hipLaunchKernelGGL(k_sum_parts_bwd, eg, dim3(256), 0, c->stream, c->wpart, b.ksplit, a.M, a.N, a.zin, a.outh,
+                         a.ldo);
   }
   SURCHK(c, hipGetLastError());
   if (t) {
