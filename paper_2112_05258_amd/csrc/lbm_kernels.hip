@@ -645,6 +645,17 @@ __device__ __forceinline__ R phicos(R r) {
   return r < R(2) ? v : R(0);
 }
 
+// Add to device memory with a global (not flat) atomic and no returned
+// value: a flat atomic also counts as an LDS operation, so the wait of the
+// next LDS read (or of any later load) would wait for it to complete; this
+// one nothing waits for.
+__device__ __forceinline__ void gadd(float* p, float v) {
+  (void)__builtin_amdgcn_global_atomic_fadd_f32((__attribute__((address_space(1))) float*)p, v);
+}
+__device__ __forceinline__ void gadd(double* p, double v) {
+  (void)__builtin_amdgcn_global_atomic_fadd_f64((__attribute__((address_space(1))) double*)p, v);
+}
+
 __device__ __forceinline__ double3 ld3(const double* p, int64_t k) {
   const double4 v = ((const double4*)p)[k];
   return make_double3(v.x, v.y, v.z);
@@ -795,7 +806,9 @@ __global__ __launch_bounds__(WBLOCK) void k_wall(Dev d, const int32_t* __restric
     y = oy + yq;
     z = oz + zq;
   };
-  auto in_box = [&](int x, int y, int z) { return x >= 0 && y >= 0 && z >= 0 && x < I.nx && y < I.ny && z < I.nz; };
+  const int inx = I.nx, iny = I.ny, inz = I.nz;
+  const int64_t icell0 = I.cell0;
+  auto in_box = [&](int x, int y, int z) { return x >= 0 && y >= 0 && z >= 0 && x < inx && y < iny && z < inz; };
   // first box index of a point's stencil
   const int q0 = valid && staged ? (bx0 - ox) + ex * ((by0 - oy) + ey * (bz0 - oz)) : 0;
 
@@ -883,6 +896,10 @@ __global__ __launch_bounds__(WBLOCK) void k_wall(Dev d, const int32_t* __restric
 
   // ---- spreading (Eq. EulForce): b(node) += F area delta ----
   R* B = (R*)I.b4;
+  // strides held in registers: read through I after an atomic on B (which
+  // might alias it) they would be reloaded, and the load waited for, every
+  // time
+  const int64_t snx = I.nx, snxy = (int64_t)I.nx * I.ny;
   const R fx = (R)(Fx * I.area), fy = (R)(Fy * I.area), fz = (R)(Fz * I.area);
   // Spreading into the LDS box in fixed point: integer LDS atomics run at
   // full rate where float ones do not, and an integer sum is exact, so the
@@ -935,8 +952,7 @@ __global__ __launch_bounds__(WBLOCK) void k_wall(Dev d, const int32_t* __restric
       if (a == 0) continue;
       int x, y, z;
       box_cell(q, x, y, z);
-      const int64_t lc = x + (int64_t)I.nx * (y + (int64_t)I.ny * z);
-      atomicAdd(B + 4 * lc + c3, (R)a * invS);
+      gadd(B + 4 * (x + snx * y + snxy * z) + c3, (R)a * invS);
     }
   } else if (valid) {
     for (int cz = 0; cz < 4; ++cz)
@@ -945,14 +961,14 @@ __global__ __launch_bounds__(WBLOCK) void k_wall(Dev d, const int32_t* __restric
         for (int cx = 0; cx < 4; ++cx) {
           const int x = bx0 + cx, y = by0 + cy, z = bz0 + cz;
           if (!in_box(x, y, z)) continue;
-          const int64_t lc = x + (int64_t)I.nx * (y + (int64_t)I.ny * z);
-          const uint8_t f = d.flags[I.cell0 + lc];
+          const int64_t lc = x + snx * y + snxy * z;
+          const uint8_t f = d.flags[icell0 + lc];
           if ((f & TYPE_MASK) != T_FLUID || !(f & F_BAND)) continue;
           const R w = wx[cx] * wyz;
           if (w == R(0)) continue;
-          atomicAdd(B + 4 * lc + 0, fx * w);
-          atomicAdd(B + 4 * lc + 1, fy * w);
-          atomicAdd(B + 4 * lc + 2, fz * w);
+          gadd(B + 4 * lc + 0, fx * w);
+          gadd(B + 4 * lc + 1, fy * w);
+          gadd(B + 4 * lc + 2, fz * w);
         }
       }
   }
