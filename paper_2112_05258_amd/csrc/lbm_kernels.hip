@@ -746,6 +746,14 @@ __global__ __launch_bounds__(WBLOCK) void k_wall(Dev d, const int32_t* __restric
   double* Dn = I.Xab[parity ^ 1];
   const double3 X0 = ld3(I.X0, p), D = ld3(Dc, p), Dm = ld3(Dn, p);
   double4* SL = (double4*)I.slip;
+  // the instance fields used after this kernel's first global stores, read
+  // now: read through I after a store that might alias it, each would be a
+  // vector load waited for together with the stores before it
+  const double ialpha = I.alpha, ibeta = I.beta, iarea = I.area;
+  R4* const IVf = (R4*)I.Vf;
+  double4* const IFp = (double4*)I.Fp;
+  R* const B = (R*)I.b4;
+  const int64_t snx = I.nx, snxy = (int64_t)I.nx * I.ny;
   double4 sl = SL[p];   // the slip integral, loaded with the rest of the point's state
   // A point that is not finite or has left the lattice box (a run that has
   // blown up) cannot be in its band: it is flagged and takes no part, so
@@ -887,20 +895,17 @@ __global__ __launch_bounds__(WBLOCK) void k_wall(Dev d, const int32_t* __restric
     const double dzv = (double)Vz - (D.z - Dm.z);
     sl.x += dxv; sl.y += dyv; sl.z += dzv;
     SL[p] = sl;
-    Fx = I.alpha * sl.x + I.beta * dxv;
-    Fy = I.alpha * sl.y + I.beta * dyv;
-    Fz = I.alpha * sl.z + I.beta * dzv;
-    ((R4*)I.Vf)[p] = R4{Vx, Vy, Vz, R(0)};
-    ((double4*)I.Fp)[p] = double4{Fx, Fy, Fz, 0.0};
+    Fx = ialpha * sl.x + ibeta * dxv;
+    Fy = ialpha * sl.y + ibeta * dyv;
+    Fz = ialpha * sl.z + ibeta * dzv;
+    IVf[p] = R4{Vx, Vy, Vz, R(0)};
+    IFp[p] = double4{Fx, Fy, Fz, 0.0};
   }
 
   // ---- spreading (Eq. EulForce): b(node) += F area delta ----
-  R* B = (R*)I.b4;
-  // strides held in registers: read through I after an atomic on B (which
-  // might alias it) they would be reloaded, and the load waited for, every
-  // time
-  const int64_t snx = I.nx, snxy = (int64_t)I.nx * I.ny;
-  const R fx = (R)(Fx * I.area), fy = (R)(Fy * I.area), fz = (R)(Fz * I.area);
+  // (B, snx, snxy: read up front, as above; read through I after an atomic
+  // on B they would be reloaded, and waited for, in every flush iteration)
+  const R fx = (R)(Fx * iarea), fy = (R)(Fy * iarea), fz = (R)(Fz * iarea);
   // Spreading into the LDS box in fixed point: integer LDS atomics run at
   // full rate where float ones do not, and an integer sum is exact, so the
   // result does not depend on the order of the tile's contributions.  The
